@@ -1,0 +1,184 @@
+/*
+ * dsp.h -- C ABI of libdsp.so, the MI355X patch engine for ideal MHD with
+ * local time steps (the DISPATCH method: Nordlund et al. 2018, MNRAS).
+ *
+ * A patch set is the paper's task list of patch tasks (Sec. 2.1-2.2): each
+ * patch is a cube of n^3 cells whose state is kept as a ring of time slices
+ * (Sec. 3A).  Advancing the set to a time repeatedly updates every patch that
+ * is ready in the sense of Eq. (1) with grace g = 0 (Sec. 3B), until every
+ * patch has reached that time (the task list "execute" of Sec. 2.2).  One
+ * patch update
+ *   1. fills the patch's guard zones from its neighbours, interpolating
+ *      linearly in time between the two stored slices that bracket the
+ *      patch time, and in space (conservative prolongation / restriction)
+ *      where the neighbour has another resolution (Sec. 3A);
+ *   2. takes one second-order MUSCL-Hancock step with HLLD fluxes and
+ *      constrained transport of face-centred B (Sec. 4.1, 4.3), with its own
+ *      Courant time step quantised to dt_base * 2^-k (local time steps,
+ *      Sec. 1, Sec. 5.2);
+ *   3. publishes the new slice over the oldest one (Sec. 3A).
+ * All of it runs in HIP kernels on the GPU; the host only validates
+ * arguments, builds the static neighbour tables and launches.
+ *
+ * Conventions for every call:
+ *  - returns 0 (DSP_OK) or a negative DSP_E* code; nothing is thrown across
+ *    the ABI; dsp_last_error() gives a message for the calling thread;
+ *  - "host" pointers are ordinary CPU memory owned by the caller; "device"
+ *    pointers are GPU memory owned by the caller;
+ *  - a set owns all the device memory it allocates and frees it in
+ *    dsp_destroy(); a set is not thread-safe, distinct sets are independent.
+ *
+ * Host layout of a state (dsp_init, dsp_read_state): patches in id order,
+ * per patch rho, mx, my, mz, E each [n][n][n] (z, y, x; x fastest), then
+ * Bx [n][n][n+1], By [n][n+1][n], Bz [n+1][n][n]; every patch stores both of
+ * its boundary faces.  Values per patch: 5 n^3 + 3 n^2 (n+1).  Always FP64
+ * on the host; FP32 sets round on upload.  Units: mu0 = 1, so the magnetic
+ * pressure is |B|^2 / 2.
+ */
+#ifndef DSP_H
+#define DSP_H
+#include <stddef.h>
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  DSP_OK = 0,
+  DSP_EINVAL = -1,      /* invalid argument or configuration */
+  DSP_ENOMEM = -2,      /* device allocation failed */
+  DSP_EHIP = -3,        /* a HIP runtime call failed */
+  DSP_EKMAX = -4,       /* a patch needs a time-step level k > kmax */
+  DSP_EALIGN = -5,      /* time not a multiple of dt_base (LOCAL / GLOBAL_QUANT) */
+  DSP_ENONFINITE = -6,  /* non-finite state or signal speed */
+  DSP_ENEGATIVE = -7,   /* non-positive density, or pressure without a floor */
+  DSP_ESTATE = -8       /* call not valid in the set's current state */
+};
+
+typedef enum { DSP_F32 = 1, DSP_F64 = 2 } dsp_prec;
+
+/* How time steps are chosen (Sec. 1, Sec. 5.2):
+ *  LOCAL        each patch its own level k (dt = dt_base 2^-k), Eq. (1) dispatch
+ *  GLOBAL_QUANT every patch takes the smallest quantised step of the set
+ *  GLOBAL_EXACT every patch takes courant / max Courant rate (last step clipped)
+ *  FIXED        every patch takes dt_fixed (last step clipped) */
+typedef enum {
+  DSP_DT_LOCAL = 0,
+  DSP_DT_GLOBAL_QUANT = 1,
+  DSP_DT_GLOBAL_EXACT = 2,
+  DSP_DT_FIXED = 3
+} dsp_dt_mode;
+
+typedef struct {
+  double gamma;    /* ratio of specific heats, > 1 */
+  double courant;  /* Courant number C of the rate sum_d (|v_d| + c_f,d)/dx */
+  double dt_base;  /* coarsest quantised step (LOCAL, GLOBAL_QUANT) */
+  double dt_fixed; /* step of the FIXED mode */
+  double grace;    /* g of Eq. (1); must be 0 */
+  double p_floor;  /* 0: non-positive pressure is DSP_ENEGATIVE; > 0: floor (counted) */
+  int32_t kmax;    /* finest level, 0..40; times are integer ticks dt_base 2^-kmax */
+  int32_t nslots;  /* time slices kept per patch, >= 2 (3 recommended) */
+  int32_t nguard;  /* guard layers of the patch model, 2 or 3; the stencil reads 2 */
+  int32_t limiter; /* 0 = van Leer (the only one) */
+  dsp_prec prec;   /* stencil precision; times, weights and sums stay FP64 */
+  dsp_dt_mode dt_mode;
+  int32_t periodic[3]; /* must be 1, 1, 1 */
+  double box_lo[3], box_hi[3];
+} dsp_config;
+
+/* One cubic patch: origin, edge length (size[0] == size[1] == size[2]),
+ * interior cells n per edge (n >= 4), refinement level (informational).
+ * Origins and sizes must lie on a common lattice: n/size integral and every
+ * origin a multiple of 1/(2 lcm(n/size)). */
+typedef struct {
+  double origin[3], size[3];
+  int32_t n, level;
+} dsp_patch_desc;
+
+/* Optional device allocator (e.g. a framework's caching allocator).
+ * NULL in dsp_create means hipMalloc / hipFree. */
+typedef struct {
+  void* ctx;
+  void* (*alloc)(void* ctx, size_t bytes);
+  void (*free)(void* ctx, void* p);
+} dsp_allocator;
+
+typedef struct dsp_set dsp_set;
+
+/* Create a set of npatch patches (host arrays, copied).  Builds the
+ * neighbour tables (symmetric closure of "reads guard data from", Eq. (1))
+ * and allocates the time slices and work memory on the current device.
+ * hip_stream: a hipStream_t to run on, or NULL for the default stream.
+ * Errors: DSP_EINVAL (bad configuration or geometry), DSP_ENOMEM, DSP_EHIP. */
+int dsp_create(const dsp_config* cfg, const dsp_patch_desc* patches, int32_t npatch,
+               void* hip_stream, const dsp_allocator* alloc, dsp_set** out);
+
+/* Upload a full state (host, FP64, n_values = total values of the layout
+ * above) as the only valid slice of every patch, at time t0 (a multiple of
+ * dt_base in LOCAL / GLOBAL_QUANT: restart).  Resets schedule and counters.
+ * Errors: DSP_EINVAL (size), DSP_ENONFINITE, DSP_EALIGN, DSP_EHIP. */
+int dsp_init(dsp_set* set, const double* U_host, size_t n_values, double t0);
+
+/* Same as dsp_init, from a device array (host layout, in the set's precision,
+ * caller-owned): a device-to-device copy, for re-running from a resident
+ * initial state.  Errors: DSP_EINVAL, DSP_EALIGN, DSP_EHIP (no finiteness check). */
+int dsp_init_device(dsp_set* set, const void* U_dev, double t0);
+
+/* Advance every patch to t_end (Sec. 2.2 "execute").  Stream-ordered; returns
+ * after completion.  Errors: DSP_EALIGN, DSP_EKMAX, DSP_ENONFINITE,
+ * DSP_ENEGATIVE, DSP_EHIP; on error each patch is left at its last completed
+ * step (dsp_read_state then returns those slices). */
+int dsp_advance_to(dsp_set* set, double t_end);
+
+/* Same as dsp_advance_to, but as the plain baseline: a host loop picks the
+ * oldest ready patch (Sec. 3B mode (i)) and launches its update alone, one
+ * patch per launch sequence, with a host round trip per update. */
+int dsp_advance_to_plain(dsp_set* set, double t_end);
+
+/* Download the latest slice of every patch (host, FP64, n_values as in
+ * dsp_init).  t_out (nullable) receives the earliest patch time. */
+int dsp_read_state(const dsp_set* set, double* U_host, size_t n_values, double* t_out);
+
+/* Schedule record since dsp_init (host arrays of npatch entries): number of
+ * updates per patch and an FNV-1a hash of its sequence of levels k (one byte
+ * per update, k & 0xff, -1 in GLOBAL_EXACT / FIXED).  klog (nullable) receives
+ * the first klog_cap levels per patch ([npatch][klog_cap], -2 past the end). */
+int dsp_read_schedule(const dsp_set* set, int64_t* steps, uint64_t* khash, int32_t* klog,
+                      size_t klog_cap);
+
+/* Counters and FP64 diagnostics of the current state:
+ *  [0] cell updates since init  [1] sum rho dV   [2..4] sum m dV   [5] sum E dV
+ *  [6..8] sum B dV (cell means of faces)  [9] max |div B| (per unit length)
+ *  [10] pressure-floor hits  [11] first-order fallback faces
+ *  [12] GPU time of the last advance (ms)  [13] rounds (launch sequences)
+ *  [14] earliest patch time  [15] latest patch time */
+int dsp_stats(const dsp_set* set, double out[16]);
+
+/* Time (ms, HIP events on the set's stream) of the dominant stencil kernel
+ * summed over the last advance, and the number of its launches. */
+int dsp_kernel_time(const dsp_set* set, double* ms, int64_t* launches);
+
+/* Fixed-dt forward run for differentiation (all patches step together with
+ * dt_fixed, nsteps steps).  U0_dev, UT_dev: device arrays in the host layout
+ * and the set's precision (caller-owned).  ckpt_dev (nullable): device array of
+ * (nsteps/8 + 1) states receiving the state every 8 steps (checkpointing). */
+int dsp_fixed_steps_fwd(dsp_set* set, const void* U0_dev, void* UT_dev, int32_t nsteps,
+                        void* ckpt_dev);
+
+/* Reverse (adjoint) of nsteps fixed-dt steps: given lamT_dev = dJ/dU_T
+ * (device, host layout, set precision), writes lam0_dev = dJ/dU_0, recomputing
+ * forward states from the checkpoints written by dsp_fixed_steps_fwd.
+ * seg: steps per checkpoint segment (must be 8). */
+int dsp_fixed_steps_adj(dsp_set* set, const void* ckpt_dev, const void* lamT_dev,
+                        void* lam0_dev, int32_t nsteps, int32_t seg);
+
+/* Free every device allocation of the set (NULL is a no-op). */
+void dsp_destroy(dsp_set* set);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* dsp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

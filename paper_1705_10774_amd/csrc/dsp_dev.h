@@ -1,0 +1,99 @@
+// dsp_dev.h -- device-visible descriptions of a patch set and of the work
+// buffers of one launch sequence.  Plain structs of device pointers, passed
+// to kernels by value.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dsp {
+
+enum : int { ERR_NONFINITE = 1, ERR_NEGATIVE = 2, ERR_KMAX = 4, ERR_STATE = 8 };
+
+// A box of guard elements of one patch that take their values from one
+// source patch.  Indices are the patch's own padded indices (inclusive);
+// same = 1: equal resolution, source index = own index + shift; same = 0:
+// resampled across resolutions, wrap = lattice shift of the periodic image.
+struct GBox {
+  int lo[3], hi[3];
+  int q;
+  int same;
+  int shift[3];
+  int pad_;
+  int64_t wrap[3];
+};
+
+struct DevSet {
+  int npatch, nslots, kmax, dt_mode, exact_time, klog_cap;
+  double gamma, courant, dt_base, dt_fixed, p_floor;
+  // geometry
+  const int* n;           // interior cells per edge
+  const double* dx;       // cell size
+  const int64_t* lo;      // lattice origin [3 * npatch]
+  const int64_t* len;     // lattice edge length
+  const int64_t* dxl;     // lattice cell size
+  const int64_t* slot_off;   // element offset of slot 0 of each patch
+  const int64_t* slice_len;  // values per slice
+  // time bookkeeping (FP64 + integer ticks)
+  int* cur;
+  int64_t* ticks;
+  double* tcur;
+  int64_t* sticks;  // [npatch * nslots]
+  double* stime;
+  int8_t* svalid;
+  // schedule record
+  int64_t* steps;
+  uint64_t* khash;
+  int8_t* klog;  // [npatch * klog_cap]
+  // neighbours (Eq. (1)) and guard boxes
+  const int* nb_off;
+  const int* nb_idx;
+  const int* rbox_off;  // [npatch * 108 + 1]: boxes of (patch, component + 1, region)
+  const GBox* boxes;
+  // counters and error bits
+  int* err;
+  unsigned long long* floor_hits;
+  unsigned long long* fallback;
+  unsigned long long* updates;
+};
+
+// Work buffers of a batch of patch slots (stride = values per slot).
+template <class T> struct WorkPtr {
+  T* pad;   // guard-filled padded patch: 5 N^3 + 3 N^2 (N + 1)
+  int64_t pad_stride;
+  T* w;     // primitives, 8 N^3
+  T* h;     // half-step primitives, 8 N^3
+  int64_t w_stride;
+  T* s;     // slopes, 3 x 8 N^3
+  int64_t s_stride;
+  T* f;     // fluxes, 3 x 8 (N+1)^3
+  int64_t f_stride;
+  int64_t fm3;  // (N+1)^3
+  T* e;     // edge EMFs, 3 (N+1)^3
+  int64_t e_stride;
+  double* smax;  // Courant rate per slot
+};
+
+// Step of each list entry.
+struct StepPtr {
+  int* k;
+  int64_t* dtk;
+  double* dt;
+};
+
+template <class T>
+void launch_update(const DevSet& S, const int* list, int count, int nmax, T* slots, const WorkPtr<T>& W,
+                   const StepPtr& st, hipStream_t s, int dt_kind, double t_end, int clip,
+                   hipEvent_t ev0, hipEvent_t ev1);
+void launch_publish(const DevSet& S, const int* list, int count, const StepPtr& st, hipStream_t s);
+void launch_scan(const DevSet& S, int64_t T_end, int* list, int* counters, hipStream_t s);
+template <class T> void launch_stats(const DevSet& S, const T* slots, double* out, hipStream_t s);
+template <class T>
+void launch_gather(const DevSet& S, const T* slots, double* dst, const int64_t* host_off, hipStream_t s);
+template <class T>
+void launch_scatter(const DevSet& S, T* slots, const double* src, const int64_t* host_off, hipStream_t s);
+template <class T>
+void launch_pack(const DevSet& S, const T* slots, T* dst, const int64_t* host_off, hipStream_t s);
+template <class T>
+void launch_unpack(const DevSet& S, T* slots, const T* src, const int64_t* host_off, hipStream_t s);
+
+}  // namespace dsp

@@ -1,0 +1,893 @@
+// dsp_kernels.hip -- HIP kernels of the patch engine (gfx950).
+//
+// One update of a set of ready patches (Sec. 3A/3B of the paper) is a short
+// sequence of kernels over a batch of patch slots b = 0..count-1, patch
+// p = list[b]:
+//   k_fill     guard-filled padded copy of the patch (2 guard layers), guard
+//              values interpolated linearly in time between the neighbour's
+//              two bracketing slices (or copied at an exact slice time), and
+//              conservatively prolonged / restricted across resolutions;
+//   k_prim     primitive variables and the Courant rate of every padded cell,
+//              reduced per patch with wavefront + workgroup maxima;
+//   k_dt_*     the quantised step (FP64 + integer ticks);
+//   k_pred     van Leer slopes and the Hancock half-step predictor;
+//   k_flux     HLLD fluxes on every face the update and the edge EMFs need;
+//   k_emf      upwinded edge EMFs (constrained transport);
+//   k_update   conservative update of the cell variables and CT update of B,
+//              written into the patch's next ring slot;
+//   k_publish  new slot, ticks, step count and level hash (after the whole
+//              round, so every read of the round saw the old metadata).
+// Kernels that read per-patch data take a list of patch ids; a patch's
+// interior size n may differ between patches (uneven sets).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dsp_dev.h"
+#include "mhd_dev.h"
+
+namespace dsp {
+
+// ---------------------------------------------------------------------------
+// small helpers
+
+__device__ __forceinline__ int64_t pcell(int N, int v, int i, int j, int k) {
+  return (int64_t)v * N * N * N + ((int64_t)(k + 2) * N + (j + 2)) * N + (i + 2);
+}
+// padded face array of component d inside the padded patch buffer
+__device__ __forceinline__ int64_t pface(int N, int d, int i, int j, int k) {
+  const int sx = N + (d == 0), sy = N + (d == 1);
+  return 5LL * N * N * N + (int64_t)d * N * N * (N + 1) + ((int64_t)(k + 2) * sy + (j + 2)) * sx + (i + 2);
+}
+// slice (interior) layout
+__device__ __forceinline__ int64_t scell(int n, int v, int i, int j, int k) {
+  return (int64_t)v * n * n * n + ((int64_t)k * n + j) * n + i;
+}
+__device__ __forceinline__ int64_t sface(int n, int d, int i, int j, int k) {
+  const int sx = n + (d == 0), sy = n + (d == 1);
+  return 5LL * n * n * n + (int64_t)d * n * n * (n + 1) + ((int64_t)k * sy + j) * sx + i;
+}
+// work arrays indexed by padded cell coordinates [-2, n+1]^3 (stride N^3 per
+// component) and face/edge arrays over [-2, n+2]^3 (stride (N+1)^3)
+__device__ __forceinline__ int64_t wcell(int N, int v, int i, int j, int k) {
+  return (int64_t)v * N * N * N + ((int64_t)(k + 2) * N + (j + 2)) * N + (i + 2);
+}
+__device__ __forceinline__ int64_t wface(int N, int v, int i, int j, int k) {
+  const int M = N + 1;
+  return (int64_t)v * M * M * M + ((int64_t)(k + 2) * M + (j + 2)) * M + (i + 2);
+}
+
+// ordered bit patterns of non-negative floating-point numbers
+__device__ __forceinline__ void atomic_max_pos(double* a, double v) {
+  atomicMax((unsigned long long*)a, (unsigned long long)__double_as_longlong(v));
+}
+
+// time-slice bracket of patch q for time (tk, tt): exact slice or a < t < b
+struct Bracket {
+  int64_t oa, ob;  // element offsets of the two slices
+  double w;        // weight of b (0 for an exact copy)
+};
+__device__ Bracket bracket(const DevSet& S, int q, int64_t tk, double tt) {
+  Bracket br;
+  const int ns = S.nslots;
+  int ia = -1, ib = -1, ie = -1;
+  for (int s = 0; s < ns; ++s) {
+    const int64_t e = (int64_t)q * ns + s;
+    if (!S.svalid[e]) continue;
+    const bool eq = S.exact_time ? (S.stime[e] == tt) : (S.sticks[e] == tk);
+    if (eq) ie = s;
+    if (S.exact_time) {
+      if (S.stime[e] < tt && (ia < 0 || S.stime[e] > S.stime[(int64_t)q * ns + ia])) ia = s;
+      if (S.stime[e] > tt && (ib < 0 || S.stime[e] < S.stime[(int64_t)q * ns + ib])) ib = s;
+    } else {
+      if (S.sticks[e] < tk && (ia < 0 || S.sticks[e] > S.sticks[(int64_t)q * ns + ia])) ia = s;
+      if (S.sticks[e] > tk && (ib < 0 || S.sticks[e] < S.sticks[(int64_t)q * ns + ib])) ib = s;
+    }
+  }
+  const int64_t base = S.slot_off[q];
+  const int64_t V = S.slice_len[q];
+  if (ie >= 0) {
+    br.oa = br.ob = base + ie * V;
+    br.w = 0.0;
+    return br;
+  }
+  if (ia < 0 || ib < 0) {
+    atomicOr(S.err, ERR_STATE);
+    br.oa = br.ob = base;
+    br.w = 0.0;
+    return br;
+  }
+  br.oa = base + ia * V;
+  br.ob = base + ib * V;
+  const int64_t e_a = (int64_t)q * ns + ia, e_b = (int64_t)q * ns + ib;
+  if (S.exact_time)
+    br.w = (tt - S.stime[e_a]) / (S.stime[e_b] - S.stime[e_a]);
+  else
+    br.w = (double)(tk - S.sticks[e_a]) / (double)(S.sticks[e_b] - S.sticks[e_a]);
+  return br;
+}
+
+template <class T>
+__device__ __forceinline__ T tlerp(const T* slots, const Bracket& br, int64_t e) {
+  const T a = slots[br.oa + e];
+  if (br.oa == br.ob) return a;
+  const T b = slots[br.ob + e];
+  return a + (T)br.w * (b - a);
+}
+
+// Cross-resolution guard value: mean over the target box of the source's
+// piecewise-linear, minmod-limited reconstruction (source-interior slopes,
+// one-sided in the source's edge cells).  comp < 0: cell variable var over
+// the target cell [X - h, X + h] per axis; comp = d: face field d over the
+// target face (the source field is linear along d between its faces).
+template <class T>
+__device__ T cross_value(const DevSet& S, const T* slots, const Bracket& br, int q, int comp,
+                         int var, const int64_t* X, int64_t tdx) {
+  const int n = S.n[q];
+  const int64_t sdx = S.dxl[q];
+  const int64_t* lo = S.lo + 3 * q;
+  const int64_t len = S.len[q];
+  int64_t a[3], b[3];
+  for (int d = 0; d < 3; ++d) {
+    int64_t A = (d == comp) ? X[d] : X[d] - tdx / 2;
+    int64_t B = (d == comp) ? X[d] : X[d] + tdx / 2;
+    A -= lo[d];
+    B -= lo[d];
+    a[d] = A < 0 ? 0 : (A > len ? len : A);
+    b[d] = B < 0 ? 0 : (B > len ? len : B);
+  }
+  auto get = [&](int i, int j, int k) -> T {
+    const int64_t e = (comp < 0) ? scell(n, var, i, j, k) : sface(n, comp, i, j, k);
+    return tlerp(slots, br, e);
+  };
+  auto minmod = [](T x, T y) -> T {
+    if (x * y <= T(0)) return T(0);
+    return (fabs(x) < fabs(y)) ? x : y;
+  };
+  // slope of the (cell or face) sample at idx along axis d, in source cells
+  auto slope = [&](int* idx, int d, int hi, T v0) -> T {
+    const int c = idx[d];
+    T s = T(0);
+    if (c - 1 >= 0 && c + 1 <= hi) {
+      idx[d] = c - 1; T vm = get(idx[0], idx[1], idx[2]);
+      idx[d] = c + 1; T vp = get(idx[0], idx[1], idx[2]);
+      s = minmod(v0 - vm, vp - v0);
+    } else if (c + 1 <= hi) {
+      idx[d] = c + 1; s = get(idx[0], idx[1], idx[2]) - v0;
+    } else if (c - 1 >= 0) {
+      idx[d] = c - 1; s = v0 - get(idx[0], idx[1], idx[2]);
+    }
+    idx[d] = c;
+    return s;
+  };
+  if (comp < 0) {
+    int i0[3], i1[3];
+    for (int d = 0; d < 3; ++d) {
+      i0[d] = (int)(a[d] / sdx);
+      i1[d] = (int)((b[d] - 1) / sdx);
+      i0[d] = i0[d] < 0 ? 0 : (i0[d] > n - 1 ? n - 1 : i0[d]);
+      i1[d] = i1[d] < 0 ? 0 : (i1[d] > n - 1 ? n - 1 : i1[d]);
+    }
+    T acc = T(0);
+    double vol = 0.0;
+    for (int k = i0[2]; k <= i1[2]; ++k)
+      for (int j = i0[1]; j <= i1[1]; ++j)
+        for (int i = i0[0]; i <= i1[0]; ++i) {
+          int ci[3] = {i, j, k};
+          double ov = 1.0, off[3];
+          for (int d = 0; d < 3; ++d) {
+            int64_t x0 = a[d] > (int64_t)ci[d] * sdx ? a[d] : (int64_t)ci[d] * sdx;
+            int64_t x1 = b[d] < (int64_t)(ci[d] + 1) * sdx ? b[d] : (int64_t)(ci[d] + 1) * sdx;
+            ov *= (double)(x1 - x0);
+            off[d] = (0.5 * (double)(x0 + x1) - ((double)ci[d] + 0.5) * (double)sdx) / (double)sdx;
+          }
+          if (ov <= 0.0) continue;
+          const T v0 = get(i, j, k);
+          T vv = v0;
+          for (int d = 0; d < 3; ++d) vv = vv + (T)off[d] * slope(ci, d, n - 1, v0);
+          acc = acc + (T)ov * vv;
+          vol += ov;
+        }
+    return acc / (T)vol;
+  }
+  // face field
+  const int d = comp, t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+  int f0 = (int)(a[d] / sdx);
+  int64_t rem = a[d] - (int64_t)f0 * sdx;
+  if (f0 >= n) { f0 = n; rem = 0; }
+  const double wn = (double)rem / (double)sdx;
+  int u0 = (int)(a[t1] / sdx), u1 = (int)((b[t1] - 1) / sdx);
+  int v0_ = (int)(a[t2] / sdx), v1 = (int)((b[t2] - 1) / sdx);
+  u0 = u0 < 0 ? 0 : (u0 > n - 1 ? n - 1 : u0);
+  u1 = u1 < 0 ? 0 : (u1 > n - 1 ? n - 1 : u1);
+  v0_ = v0_ < 0 ? 0 : (v0_ > n - 1 ? n - 1 : v0_);
+  v1 = v1 < 0 ? 0 : (v1 > n - 1 ? n - 1 : v1);
+  T acc = T(0);
+  double area = 0.0;
+  for (int u = u0; u <= u1; ++u)
+    for (int v = v0_; v <= v1; ++v) {
+      const int ti[2] = {u, v};
+      const int ax[2] = {t1, t2};
+      double ov = 1.0, off[2];
+      for (int m = 0; m < 2; ++m) {
+        const int dd = ax[m];
+        int64_t x0 = a[dd] > (int64_t)ti[m] * sdx ? a[dd] : (int64_t)ti[m] * sdx;
+        int64_t x1 = b[dd] < (int64_t)(ti[m] + 1) * sdx ? b[dd] : (int64_t)(ti[m] + 1) * sdx;
+        ov *= (double)(x1 - x0);
+        off[m] = (0.5 * (double)(x0 + x1) - ((double)ti[m] + 0.5) * (double)sdx) / (double)sdx;
+      }
+      if (ov <= 0.0) continue;
+      T vv = T(0);
+      for (int side = 0; side < 2; ++side) {
+        const double ws = side == 0 ? 1.0 - wn : wn;
+        if (ws == 0.0) continue;
+        int idx[3];
+        idx[d] = f0 + side;
+        idx[t1] = u;
+        idx[t2] = v;
+        const T c0 = get(idx[0], idx[1], idx[2]);
+        T lin = c0;
+        for (int m = 0; m < 2; ++m) lin = lin + (T)off[m] * slope(idx, ax[m], n - 1, c0);
+        vv = vv + (T)ws * lin;
+      }
+      acc = acc + (T)ov * vv;
+      area += ov;
+    }
+  return acc / (T)area;
+}
+
+// ---------------------------------------------------------------------------
+// k_fill: one thread per padded element (5 N^3 cell values, then 3 face
+// arrays) of patch list[b].
+
+template <class T>
+__global__ void k_fill(DevSet S, const int* __restrict__ list, int count, T* __restrict__ slots,
+                       WorkPtr<T> W) {
+  const int b = blockIdx.y;
+  if (b >= count) return;
+  const int p = list[b];
+  const int n = S.n[p], N = n + 4;
+  const int64_t ncell = (int64_t)N * N * N, nface = (int64_t)N * N * (N + 1);
+  const int64_t total = 5 * ncell + 3 * nface;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  int comp, var, i, j, k;
+  if (e < 5 * ncell) {
+    comp = -1;
+    var = (int)(e / ncell);
+    int64_t r = e - var * ncell;
+    i = (int)(r % N) - 2;
+    r /= N;
+    j = (int)(r % N) - 2;
+    k = (int)(r / N) - 2;
+  } else {
+    int64_t r = e - 5 * ncell;
+    comp = (int)(r / nface);
+    var = 0;
+    r -= comp * nface;
+    const int sx = N + (comp == 0), sy = N + (comp == 1);
+    i = (int)(r % sx) - 2;
+    r /= sx;
+    j = (int)(r % sy) - 2;
+    k = (int)(r / sy) - 2;
+  }
+  T* Pd = W.pad + (int64_t)b * W.pad_stride;
+  const int idx[3] = {i, j, k};
+  int rg[3];
+  bool interior = true;
+  for (int d = 0; d < 3; ++d) {
+    const int hi = n + (d == comp ? 1 : 0);
+    rg[d] = idx[d] < 0 ? 0 : (idx[d] < hi ? 1 : 2);
+    interior = interior && rg[d] == 1;
+  }
+  if (interior) {
+    const int64_t own = S.slot_off[p] + (int64_t)S.cur[p] * S.slice_len[p];
+    const int64_t se = (comp < 0) ? scell(n, var, i, j, k) : sface(n, comp, i, j, k);
+    Pd[e] = slots[own + se];
+    return;
+  }
+  // guard element: find its box among the boxes of (patch, component, region)
+  const int region = (rg[2] * 3 + rg[1]) * 3 + rg[0];
+  const int key = p * 108 + (comp + 1) * 27 + region;
+  const int b0 = S.rbox_off[key], b1 = S.rbox_off[key + 1];
+  for (int m = b0; m < b1; ++m) {
+    const GBox& G = S.boxes[m];
+    if (i < G.lo[0] || i > G.hi[0] || j < G.lo[1] || j > G.hi[1] || k < G.lo[2] || k > G.hi[2])
+      continue;
+    const int q = G.q;
+    const Bracket br = bracket(S, q, S.ticks[p], S.tcur[p]);
+    T val;
+    if (G.same) {
+      const int qi = i + G.shift[0], qj = j + G.shift[1], qk = k + G.shift[2];
+      const int64_t se = (comp < 0) ? scell(S.n[q], var, qi, qj, qk) : sface(S.n[q], comp, qi, qj, qk);
+      val = tlerp(slots, br, se);
+    } else {
+      // lattice position of the element, shifted into the source's periodic image
+      const int64_t dxl = S.dxl[p];
+      int64_t X[3];
+      for (int d = 0; d < 3; ++d) {
+        X[d] = S.lo[3 * p + d] + (int64_t)idx[d] * dxl + (d == comp ? 0 : dxl / 2) + G.wrap[d];
+      }
+      val = cross_value(S, slots, br, q, comp, var, X, dxl);
+    }
+    Pd[e] = val;
+    return;
+  }
+  atomicOr(S.err, ERR_STATE);  // no source: the plan is inconsistent
+}
+
+// ---------------------------------------------------------------------------
+// k_prim: primitives and Courant rate over the padded cells [-2, n+1]^3.
+
+template <class T>
+__global__ void k_prim(DevSet S, const int* __restrict__ list, int count, WorkPtr<T> W) {
+  const int b = blockIdx.y;
+  if (b >= count) return;
+  const int p = list[b];
+  const int n = S.n[p], N = n + 4;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ncell = (int64_t)N * N * N;
+  double s = 0.0;
+  if (c < ncell) {
+    const int i = (int)(c % N) - 2, j = (int)((c / N) % N) - 2, k = (int)(c / ((int64_t)N * N)) - 2;
+    const T* Pd = W.pad + (int64_t)b * W.pad_stride;
+    T* Wp = W.w + (int64_t)b * W.w_stride;
+    const T rho = Pd[pcell(N, 0, i, j, k)];
+    const T mx = Pd[pcell(N, 1, i, j, k)], my = Pd[pcell(N, 2, i, j, k)], mz = Pd[pcell(N, 3, i, j, k)];
+    const T en = Pd[pcell(N, 4, i, j, k)];
+    const T bx = T(0.5) * (Pd[pface(N, 0, i, j, k)] + Pd[pface(N, 0, i + 1, j, k)]);
+    const T by = T(0.5) * (Pd[pface(N, 1, i, j, k)] + Pd[pface(N, 1, i, j + 1, k)]);
+    const T bz = T(0.5) * (Pd[pface(N, 2, i, j, k)] + Pd[pface(N, 2, i, j, k + 1)]);
+    const T ir = T(1) / rho;
+    const T vx = mx * ir, vy = my * ir, vz = mz * ir;
+    const T ke = T(0.5) * (mx * mx + my * my + mz * mz) * ir;
+    const T bb = bx * bx + by * by + bz * bz;
+    T pr = (T(S.gamma) - T(1)) * (en - ke - T(0.5) * bb);
+    if (!isfinite(rho) || !isfinite(pr)) {
+      atomicOr(S.err, ERR_NONFINITE);
+      pr = T(1);
+    }
+    if (!(rho > T(0))) {
+      atomicOr(S.err, ERR_NEGATIVE);
+    } else if (S.p_floor > 0.0) {
+      if (pr < T(S.p_floor)) {
+        pr = T(S.p_floor);
+        atomicAdd(S.floor_hits, 1ULL);
+      }
+    } else if (!(pr > T(0))) {
+      atomicOr(S.err, ERR_NEGATIVE);
+    }
+    const int64_t o = wcell(N, 0, i, j, k), st = ncell;
+    Wp[o] = rho;
+    Wp[o + st] = vx;
+    Wp[o + 2 * st] = vy;
+    Wp[o + 3 * st] = vz;
+    Wp[o + 4 * st] = pr;
+    Wp[o + 5 * st] = bx;
+    Wp[o + 6 * st] = by;
+    Wp[o + 7 * st] = bz;
+    // Courant rate sum_d (|v_d| + c_f,d) / dx in stencil precision
+    if (rho > T(0) && pr > T(0)) {
+      const T a2 = T(S.gamma) * pr * ir, b2 = bb * ir;
+      T sum = fabs(vx) + fast_speed(a2, b2, (by * by + bz * bz) * ir);
+      sum = sum + (fabs(vy) + fast_speed(a2, b2, (bz * bz + bx * bx) * ir));
+      sum = sum + (fabs(vz) + fast_speed(a2, b2, (bx * bx + by * by) * ir));
+      s = (double)sum / S.dx[p];
+      if (!isfinite(s)) atomicOr(S.err, ERR_NONFINITE);
+    }
+  }
+  // wavefront maximum, then one atomic per wavefront
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_xor(s, off, 64);
+    s = o > s ? o : s;
+  }
+  if ((threadIdx.x & 63) == 0 && s > 0.0) atomic_max_pos(W.smax + b, s);
+}
+
+// ---------------------------------------------------------------------------
+// time-step choice
+
+__device__ int level_for(const DevSet& S, double smax, int64_t ticks) {
+  // k_c = 0 if r <= 1 else ceil(log2 r) exactly (frexp), r = dt_base smax / C;
+  // raised so that the step keeps the patch time a multiple of the step
+  const double r = S.dt_base * smax / S.courant;
+  int kc = 0;
+  if (r > 1.0) {
+    int e;
+    const double m = frexp(r, &e);
+    kc = (m == 0.5) ? e - 1 : e;
+  }
+  int k = kc;
+  if (ticks != 0) {
+    const int tz = __ffsll((unsigned long long)ticks) - 1;
+    const int al = S.kmax - tz;
+    k = k > al ? k : al;
+  }
+  return k;
+}
+
+__global__ void k_dt_local(DevSet S, const int* __restrict__ list, int count, StepPtr st,
+                           const double* smax) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= count) return;
+  const int p = list[b];
+  const int k = level_for(S, smax[b], S.ticks[p]);
+  if (k > S.kmax) {
+    atomicOr(S.err, ERR_KMAX);
+    st.k[b] = S.kmax;
+  } else {
+    st.k[b] = k;
+  }
+  st.dtk[b] = (int64_t)1 << (S.kmax - st.k[b]);
+  st.dt[b] = S.dt_base * ldexp(1.0, -st.k[b]);
+}
+
+// GLOBAL modes: one step for the whole set (single workgroup reduction).
+// mode 1: k = max of the per-patch levels; mode 2: courant / max rate,
+// clipped to t_end; mode 3: dt_fixed, clipped to t_end unless nsteps mode.
+__global__ void k_dt_global(DevSet S, const int* __restrict__ list, int count, StepPtr st,
+                            const double* smax, double t_end, int clip) {
+  __shared__ double red[256];
+  __shared__ int redk[256];
+  double m = 0.0;
+  int km = 0;
+  for (int b = threadIdx.x; b < count; b += blockDim.x) {
+    m = smax[b] > m ? smax[b] : m;
+    if (S.dt_mode == 1) {
+      const int k = level_for(S, smax[b], S.ticks[list[b]]);
+      km = k > km ? k : km;
+    }
+  }
+  red[threadIdx.x] = m;
+  redk[threadIdx.x] = km;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      red[threadIdx.x] = red[threadIdx.x + s] > red[threadIdx.x] ? red[threadIdx.x + s] : red[threadIdx.x];
+      redk[threadIdx.x] = redk[threadIdx.x + s] > redk[threadIdx.x] ? redk[threadIdx.x + s] : redk[threadIdx.x];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  double dt;
+  int64_t dtk = 0;
+  int k = -1;
+  const double t0 = S.tcur[list[0]];
+  if (S.dt_mode == 1) {
+    k = redk[0];
+    if (k > S.kmax) {
+      atomicOr(S.err, ERR_KMAX);
+      k = S.kmax;
+    }
+    dtk = (int64_t)1 << (S.kmax - k);
+    dt = S.dt_base * ldexp(1.0, -k);
+  } else {
+    dt = (S.dt_mode == 2) ? S.courant / red[0] : S.dt_fixed;
+    if (clip && t0 + dt > t_end) dt = t_end - t0;
+  }
+  for (int b = 0; b < count; ++b) {
+    st.k[b] = k;
+    st.dtk[b] = dtk;
+    st.dt[b] = dt;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_pred: slopes (per direction) and half-step predictor on [-1, n]^3.
+
+template <class T>
+__global__ void k_pred(DevSet S, const int* __restrict__ list, int count, WorkPtr<T> W, StepPtr st) {
+  const int b = blockIdx.y;
+  if (b >= count) return;
+  const int p = list[b];
+  const int n = S.n[p], N = n + 4, M = n + 2;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= (int64_t)M * M * M) return;
+  const int i = (int)(c % M) - 1, j = (int)((c / M) % M) - 1, k = (int)(c / ((int64_t)M * M)) - 1;
+  const T* Wp = W.w + (int64_t)b * W.w_stride;
+  T* Sp = W.s + (int64_t)b * W.s_stride;
+  T* Hp = W.h + (int64_t)b * W.w_stride;
+  const int64_t NC = (int64_t)N * N * N;
+  T w[8];
+  for (int v = 0; v < 8; ++v) w[v] = Wp[wcell(N, v, i, j, k)];
+  const T ir = T(1) / w[0];
+  const T g = T(S.gamma);
+  T sum[8] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+  for (int d = 0; d < 3; ++d) {
+    const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+    int im = i, jm = j, km = k, ip = i, jp = j, kp = k;
+    if (d == 0) { im--; ip++; } else if (d == 1) { jm--; jp++; } else { km--; kp++; }
+    T sl[8];
+    for (int v = 0; v < 8; ++v) {
+      if (v == 5 + d) {
+        sl[v] = T(0);
+        continue;
+      }
+      const T a = Wp[wcell(N, v, im, jm, km)], cc = Wp[wcell(N, v, ip, jp, kp)];
+      sl[v] = van_leer(w[v] - a, cc - w[v]);
+    }
+    for (int v = 0; v < 8; ++v) Sp[(int64_t)(d * 8 + v) * NC + wcell(N, 0, i, j, k)] = sl[v];
+    // primitive Jacobian of the 1-D problem along d, normal field constant
+    const T un = w[1 + d];
+    const T bn = w[5 + d], b1 = w[5 + t1], b2 = w[5 + t2];
+    sum[0] = sum[0] + (un * sl[0] + w[0] * sl[1 + d]);
+    sum[1 + d] = sum[1 + d] + (un * sl[1 + d] + (sl[4] + b1 * sl[5 + t1] + b2 * sl[5 + t2]) * ir);
+    sum[1 + t1] = sum[1 + t1] + (un * sl[1 + t1] - bn * sl[5 + t1] * ir);
+    sum[1 + t2] = sum[1 + t2] + (un * sl[1 + t2] - bn * sl[5 + t2] * ir);
+    sum[4] = sum[4] + (un * sl[4] + g * w[4] * sl[1 + d]);
+    sum[5 + t1] = sum[5 + t1] + (un * sl[5 + t1] + b1 * sl[1 + d] - bn * sl[1 + t1]);
+    sum[5 + t2] = sum[5 + t2] + (un * sl[5 + t2] + b2 * sl[1 + d] - bn * sl[1 + t2]);
+  }
+  const T hdtdx = (T)(0.5 * st.dt[b] / S.dx[p]);
+  for (int v = 0; v < 8; ++v) Hp[wcell(N, v, i, j, k)] = w[v] - hdtdx * sum[v];
+}
+
+// ---------------------------------------------------------------------------
+// k_flux: HLLD on faces along d (face index [0, n]) with the other indices in
+// [-1, n].  Thread layout: the three directions concatenated.
+
+template <class T>
+__global__ void k_flux(DevSet S, const int* __restrict__ list, int count, WorkPtr<T> W) {
+  const int b = blockIdx.y;
+  if (b >= count) return;
+  const int p = list[b];
+  const int n = S.n[p], N = n + 4, M = n + 2;
+  const int64_t per = (int64_t)(n + 1) * M * M;
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= 3 * per) return;
+  const int d = (int)(c / per);
+  c -= d * per;
+  // index order: face index fastest along d's own axis layout
+  int idx[3];
+  const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+  idx[d] = (int)(c % (n + 1));
+  idx[t1] = (int)((c / (n + 1)) % M) - 1;
+  idx[t2] = (int)(c / ((int64_t)(n + 1) * M)) - 1;
+  int ia[3] = {idx[0], idx[1], idx[2]};
+  ia[d] -= 1;
+  const T* Wp = W.w + (int64_t)b * W.w_stride;
+  const T* Hp = W.h + (int64_t)b * W.w_stride;
+  const T* Sp = W.s + (int64_t)b * W.s_stride;
+  const T* Pd = W.pad + (int64_t)b * W.pad_stride;
+  const int64_t NC = (int64_t)N * N * N;
+  const int64_t ca = wcell(N, 0, ia[0], ia[1], ia[2]), cb = wcell(N, 0, idx[0], idx[1], idx[2]);
+  const int order[7] = {0, 1 + d, 1 + t1, 1 + t2, 4, 5 + t1, 5 + t2};
+  T l[7], r[7];
+  for (int m = 0; m < 7; ++m) {
+    const int v = order[m];
+    l[m] = Hp[v * NC + ca] + T(0.5) * Sp[(int64_t)(d * 8 + v) * NC + ca];
+    r[m] = Hp[v * NC + cb] - T(0.5) * Sp[(int64_t)(d * 8 + v) * NC + cb];
+  }
+  const T bface = Pd[pface(N, d, idx[0], idx[1], idx[2])];
+  T bn = bface + T(0.5) * ((Hp[(5 + d) * NC + ca] - Wp[(5 + d) * NC + ca]) +
+                           (Hp[(5 + d) * NC + cb] - Wp[(5 + d) * NC + cb]));
+  if (!(l[0] > T(0)) || !(l[4] > T(0)) || !(r[0] > T(0)) || !(r[4] > T(0))) {
+    for (int m = 0; m < 7; ++m) {
+      l[m] = Wp[order[m] * NC + ca];
+      r[m] = Wp[order[m] * NC + cb];
+    }
+    bn = bface;
+    atomicAdd(S.fallback, 1ULL);
+  }
+  T f[7];
+  hlld_flux(l, r, bn, T(S.gamma), f);
+  T* Fp = W.f + (int64_t)b * W.f_stride + (int64_t)d * 8 * W.fm3;
+  const int64_t o = wface(N, 0, idx[0], idx[1], idx[2]);
+  const int64_t fs = W.fm3;
+  Fp[o] = f[0];
+  Fp[(1 + d) * fs + o] = f[1];
+  Fp[(1 + t1) * fs + o] = f[2];
+  Fp[(1 + t2) * fs + o] = f[3];
+  Fp[4 * fs + o] = f[4];
+  Fp[(5 + d) * fs + o] = T(0);
+  Fp[(5 + t1) * fs + o] = f[5];
+  Fp[(5 + t2) * fs + o] = f[6];
+}
+
+// ---------------------------------------------------------------------------
+// k_emf: edge EMF E_a on edges along a (a-index a cell index in [0, n-1], the
+// other two face indices in [0, n]), (a, b, c) cyclic.  Face EMFs come from
+// the induction fluxes: on b-faces E_a = -F_b[B_c], on c-faces E_a = +F_c[B_b];
+// the cell reference value is E = -v x B of the half-step state; corrections
+// are upwinded by the sign of the mass flux (Gardiner & Stone 2005).
+
+template <class T>
+__global__ void k_emf(DevSet S, const int* __restrict__ list, int count, WorkPtr<T> W) {
+  const int blk = blockIdx.y;
+  if (blk >= count) return;
+  const int p = list[blk];
+  const int n = S.n[p], N = n + 4;
+  const int64_t per = (int64_t)n * (n + 1) * (n + 1);
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= 3 * per) return;
+  const int a = (int)(c / per);
+  c -= a * per;
+  const int bax = (a + 1) % 3, cax = (a + 2) % 3;
+  int e[3];
+  e[a] = (int)(c % n);
+  e[bax] = (int)((c / n) % (n + 1));
+  e[cax] = (int)(c / ((int64_t)n * (n + 1)));
+  const T* Hp = W.h + (int64_t)blk * W.w_stride;
+  const T* Fb = W.f + (int64_t)blk * W.f_stride + (int64_t)bax * 8 * W.fm3;
+  const T* Fc = W.f + (int64_t)blk * W.f_stride + (int64_t)cax * 8 * W.fm3;
+  const int64_t fs = W.fm3;
+  const int64_t NC = (int64_t)N * N * N;
+  int pA[3] = {e[0], e[1], e[2]}, pB[3] = {e[0], e[1], e[2]};
+  pB[cax] -= 1;
+  int pC[3] = {e[0], e[1], e[2]}, pD[3] = {e[0], e[1], e[2]};
+  pD[bax] -= 1;
+  const int64_t oA = wface(N, 0, pA[0], pA[1], pA[2]), oB = wface(N, 0, pB[0], pB[1], pB[2]);
+  const int64_t oC = wface(N, 0, pC[0], pC[1], pC[2]), oD = wface(N, 0, pD[0], pD[1], pD[2]);
+  const T A = -Fb[(5 + cax) * fs + oA], B = -Fb[(5 + cax) * fs + oB];
+  const T C = Fc[(5 + bax) * fs + oC], D = Fc[(5 + bax) * fs + oD];
+  const T mA = Fb[oA], mB = Fb[oB], mC = Fc[oC], mD = Fc[oD];
+  auto ecc = [&](int db, int dc) -> T {
+    int q[3] = {e[0], e[1], e[2]};
+    q[bax] += db;
+    q[cax] += dc;
+    const int64_t o = wcell(N, 0, q[0], q[1], q[2]);
+    // E_a = v_c B_b - v_b B_c
+    return Hp[(1 + cax) * NC + o] * Hp[(5 + bax) * NC + o] - Hp[(1 + bax) * NC + o] * Hp[(5 + cax) * NC + o];
+  };
+  const T c00 = ecc(-1, -1), c10 = ecc(0, -1), c01 = ecc(-1, 0), c11 = ecc(0, 0);
+  auto up = [](T m, T x, T y) -> T {
+    if (m > T(0)) return x;
+    if (m < T(0)) return y;
+    return T(0.5) * (x + y);
+  };
+  const T dc14 = up(mA, c01 - D, c11 - C);
+  const T dc34 = up(mB, D - c00, C - c10);
+  const T db14 = up(mC, c10 - B, c11 - A);
+  const T db34 = up(mD, B - c00, A - c01);
+  T* Ep = W.e + (int64_t)blk * W.e_stride + (int64_t)a * W.fm3;
+  Ep[wface(N, 0, e[0], e[1], e[2])] =
+      T(0.25) * (A + B + C + D) + T(0.25) * ((dc34 - dc14) + (db34 - db14));
+}
+
+// ---------------------------------------------------------------------------
+// k_update: new slice = conservative update of the cells + CT update of the
+// faces, written into the patch's next ring slot.
+
+template <class T>
+__global__ void k_update(DevSet S, const int* __restrict__ list, int count, T* __restrict__ slots,
+                         WorkPtr<T> W, StepPtr st) {
+  const int blk = blockIdx.y;
+  if (blk >= count) return;
+  const int p = list[blk];
+  const int n = S.n[p], N = n + 4;
+  const int64_t n3 = (int64_t)n * n * n, nf = (int64_t)n * n * (n + 1);
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n3 + 3 * nf) return;
+  const T* Pd = W.pad + (int64_t)blk * W.pad_stride;
+  const int nxt = (S.cur[p] + 1) % S.nslots;
+  T* out = slots + S.slot_off[p] + (int64_t)nxt * S.slice_len[p];
+  const T dtdx = (T)(st.dt[blk] / S.dx[p]);
+  const int64_t fs = W.fm3;
+  if (c < n3) {
+    const int i = (int)(c % n), j = (int)((c / n) % n), k = (int)(c / ((int64_t)n * n));
+    T du[5] = {T(0), T(0), T(0), T(0), T(0)};
+    for (int d = 0; d < 3; ++d) {
+      const T* Fd = W.f + (int64_t)blk * W.f_stride + (int64_t)d * 8 * fs;
+      int r[3] = {i, j, k};
+      r[d] += 1;
+      const int64_t ol = wface(N, 0, i, j, k), orr = wface(N, 0, r[0], r[1], r[2]);
+      for (int v = 0; v < 5; ++v) du[v] = du[v] + (Fd[v * fs + orr] - Fd[v * fs + ol]);
+    }
+    for (int v = 0; v < 5; ++v)
+      out[scell(n, v, i, j, k)] = Pd[pcell(N, v, i, j, k)] - dtdx * du[v];
+    return;
+  }
+  c -= n3;
+  const int d = (int)(c / nf);
+  c -= d * nf;
+  const int sx = n + (d == 0), sy = n + (d == 1);
+  const int i = (int)(c % sx), j = (int)((c / sx) % sy), k = (int)(c / ((int64_t)sx * sy));
+  const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+  const T* E1 = W.e + (int64_t)blk * W.e_stride + (int64_t)t1 * fs;
+  const T* E2 = W.e + (int64_t)blk * W.e_stride + (int64_t)t2 * fs;
+  int p1[3] = {i, j, k}, p2[3] = {i, j, k};
+  p1[t1] += 1;
+  p2[t2] += 1;
+  const int64_t o0 = wface(N, 0, i, j, k);
+  const T curl = (E2[wface(N, 0, p1[0], p1[1], p1[2])] - E2[o0]) - (E1[wface(N, 0, p2[0], p2[1], p2[2])] - E1[o0]);
+  out[sface(n, d, i, j, k)] = Pd[pface(N, d, i, j, k)] - dtdx * curl;
+}
+
+// ---------------------------------------------------------------------------
+// k_publish: the new slice becomes current (Sec. 3A), ticks advance.
+
+__global__ void k_publish(DevSet S, const int* __restrict__ list, int count, StepPtr st) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= count) return;
+  const int p = list[b];
+  const int ns = S.nslots;
+  const int nxt = (S.cur[p] + 1) % ns;
+  const int64_t e = (int64_t)p * ns + nxt;
+  if (S.exact_time) {
+    S.tcur[p] = S.tcur[p] + st.dt[b];
+    S.stime[e] = S.tcur[p];
+  } else {
+    S.ticks[p] += st.dtk[b];
+    S.sticks[e] = S.ticks[p];
+    S.tcur[p] = ldexp((double)S.ticks[p], -S.kmax) * S.dt_base;
+  }
+  S.svalid[e] = 1;
+  S.cur[p] = nxt;
+  const int k = st.k[b];
+  const int64_t m = S.steps[p];
+  if (m < S.klog_cap) S.klog[(int64_t)p * S.klog_cap + m] = (int8_t)k;
+  S.steps[p] = m + 1;
+  uint64_t h = S.khash[p];
+  h ^= (uint64_t)(uint8_t)(k & 0xff);
+  h *= 1099511628211ULL;
+  S.khash[p] = h;
+  const int n = S.n[p];
+  atomicAdd(S.updates, (unsigned long long)n * n * n);
+}
+
+// ---------------------------------------------------------------------------
+// k_scan: readiness of every patch (Eq. (1), g = 0) and the ready list.
+
+__global__ void k_scan(DevSet S, int64_t T_end, int* __restrict__ list, int* __restrict__ counters) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= S.npatch) return;
+  const int64_t t = S.ticks[p];
+  if (t >= T_end) return;
+  atomicAdd(counters + 1, 1);  // not yet done
+  for (int m = S.nb_off[p]; m < S.nb_off[p + 1]; ++m)
+    if (S.ticks[S.nb_idx[m]] < t) return;
+  const int slot = atomicAdd(counters, 1);
+  list[slot] = p;
+}
+
+// ---------------------------------------------------------------------------
+// diagnostics: per-patch FP64 sums (one workgroup per patch, fixed-order tree
+// reduction, so the result does not depend on scheduling)
+
+template <class T>
+__global__ void k_stats(DevSet S, const T* __restrict__ slots, double* __restrict__ out) {
+  const int p = blockIdx.x;
+  const int n = S.n[p];
+  const int64_t n3 = (int64_t)n * n * n;
+  const T* u = slots + S.slot_off[p] + (int64_t)S.cur[p] * S.slice_len[p];
+  const double dv = S.dx[p] * S.dx[p] * S.dx[p];
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double dmax = 0.0;
+  for (int64_t c = threadIdx.x; c < n3; c += blockDim.x) {
+    const int i = (int)(c % n), j = (int)((c / n) % n), k = (int)(c / ((int64_t)n * n));
+    for (int v = 0; v < 5; ++v) acc[v] += (double)u[scell(n, v, i, j, k)] * dv;
+    const double bl[3] = {(double)u[sface(n, 0, i, j, k)], (double)u[sface(n, 1, i, j, k)],
+                          (double)u[sface(n, 2, i, j, k)]};
+    const double br[3] = {(double)u[sface(n, 0, i + 1, j, k)], (double)u[sface(n, 1, i, j + 1, k)],
+                          (double)u[sface(n, 2, i, j, k + 1)]};
+    for (int d = 0; d < 3; ++d) acc[5 + d] += 0.5 * (bl[d] + br[d]) * dv;
+    const double dvg = fabs((br[0] - bl[0]) + (br[1] - bl[1]) + (br[2] - bl[2])) / S.dx[p];
+    dmax = dvg > dmax ? dvg : dmax;
+  }
+  __shared__ double red[256];
+  for (int q = 0; q < 9; ++q) {
+    red[threadIdx.x] = (q < 8) ? acc[q] : dmax;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s)
+        red[threadIdx.x] = (q < 8) ? red[threadIdx.x] + red[threadIdx.x + s]
+                                   : (red[threadIdx.x + s] > red[threadIdx.x] ? red[threadIdx.x + s] : red[threadIdx.x]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[(int64_t)p * 9 + q] = red[0];
+    __syncthreads();
+  }
+}
+
+// host layout <-> ring slot (the host layout is the concatenation of slices)
+template <class T>
+__global__ void k_gather(DevSet S, const T* __restrict__ slots, double* __restrict__ dst,
+                         const int64_t* __restrict__ host_off) {
+  const int p = blockIdx.y;
+  const int64_t V = S.slice_len[p];
+  const T* src = slots + S.slot_off[p] + (int64_t)S.cur[p] * V;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < V; e += (int64_t)gridDim.x * blockDim.x)
+    dst[host_off[p] + e] = (double)src[e];
+}
+
+template <class T>
+__global__ void k_scatter(DevSet S, T* __restrict__ slots, const double* __restrict__ src,
+                          const int64_t* __restrict__ host_off) {
+  const int p = blockIdx.y;
+  const int64_t V = S.slice_len[p];
+  T* dst = slots + S.slot_off[p];  // slot 0
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < V; e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = (T)src[host_off[p] + e];
+}
+
+// copy between the host-layout (contiguous) representation and slot 0 / the
+// current slot in the set's precision, device to device (fixed-step entry)
+template <class T>
+__global__ void k_pack(DevSet S, const T* __restrict__ slots, T* __restrict__ dst,
+                       const int64_t* __restrict__ host_off) {
+  const int p = blockIdx.y;
+  const int64_t V = S.slice_len[p];
+  const T* src = slots + S.slot_off[p] + (int64_t)S.cur[p] * V;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < V; e += (int64_t)gridDim.x * blockDim.x)
+    dst[host_off[p] + e] = src[e];
+}
+template <class T>
+__global__ void k_unpack(DevSet S, T* __restrict__ slots, const T* __restrict__ src,
+                         const int64_t* __restrict__ host_off) {
+  const int p = blockIdx.y;
+  const int64_t V = S.slice_len[p];
+  T* dst = slots + S.slot_off[p];
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < V; e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = src[host_off[p] + e];
+}
+
+// ---------------------------------------------------------------------------
+// launchers (explicit instantiation for float and double)
+
+template <class T>
+void launch_update(const DevSet& S, const int* list, int count, int nmax, T* slots, const WorkPtr<T>& W,
+                   const StepPtr& st, hipStream_t s, int dt_kind, double t_end, int clip,
+                   hipEvent_t ev0, hipEvent_t ev1) {
+  const int N = nmax + 4, M = nmax + 2;
+  const int TPB = 256;
+  auto blocks = [&](int64_t elems) { return (unsigned)((elems + TPB - 1) / TPB); };
+  (void)hipMemsetAsync(W.smax, 0, sizeof(double) * count, s);
+  const int64_t fill_elems = 5LL * N * N * N + 3LL * N * N * (N + 1);
+  hipLaunchKernelGGL(k_fill<T>, dim3(blocks(fill_elems), count), dim3(TPB), 0, s, S, list, count, slots, W);
+  hipLaunchKernelGGL(k_prim<T>, dim3(blocks((int64_t)N * N * N), count), dim3(TPB), 0, s, S, list, count, W);
+  if (dt_kind == 0)
+    hipLaunchKernelGGL(k_dt_local, dim3((count + 255) / 256), dim3(256), 0, s, S, list, count, st, W.smax);
+  else
+    hipLaunchKernelGGL(k_dt_global, dim3(1), dim3(256), 0, s, S, list, count, st, W.smax, t_end, clip);
+  hipLaunchKernelGGL(k_pred<T>, dim3(blocks((int64_t)M * M * M), count), dim3(TPB), 0, s, S, list, count, W, st);
+  if (ev0) (void)hipEventRecord(ev0, s);
+  hipLaunchKernelGGL(k_flux<T>, dim3(blocks(3LL * (nmax + 1) * M * M), count), dim3(TPB), 0, s, S, list, count, W);
+  if (ev1) (void)hipEventRecord(ev1, s);
+  hipLaunchKernelGGL(k_emf<T>, dim3(blocks(3LL * nmax * (nmax + 1) * (nmax + 1)), count), dim3(TPB), 0, s, S, list,
+                     count, W);
+  hipLaunchKernelGGL(k_update<T>, dim3(blocks((int64_t)nmax * nmax * nmax + 3LL * nmax * nmax * (nmax + 1)), count),
+                     dim3(TPB), 0, s, S, list, count, slots, W, st);
+}
+
+void launch_publish(const DevSet& S, const int* list, int count, const StepPtr& st, hipStream_t s) {
+  hipLaunchKernelGGL(k_publish, dim3((count + 255) / 256), dim3(256), 0, s, S, list, count, st);
+}
+
+void launch_scan(const DevSet& S, int64_t T_end, int* list, int* counters, hipStream_t s) {
+  (void)hipMemsetAsync(counters, 0, 2 * sizeof(int), s);
+  hipLaunchKernelGGL(k_scan, dim3((S.npatch + 255) / 256), dim3(256), 0, s, S, T_end, list, counters);
+}
+
+template <class T>
+void launch_stats(const DevSet& S, const T* slots, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_stats<T>, dim3(S.npatch), dim3(256), 0, s, S, slots, out);
+}
+
+template <class T>
+void launch_gather(const DevSet& S, const T* slots, double* dst, const int64_t* host_off, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather<T>, dim3(64, S.npatch), dim3(256), 0, s, S, slots, dst, host_off);
+}
+template <class T>
+void launch_scatter(const DevSet& S, T* slots, const double* src, const int64_t* host_off, hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter<T>, dim3(64, S.npatch), dim3(256), 0, s, S, slots, src, host_off);
+}
+template <class T>
+void launch_pack(const DevSet& S, const T* slots, T* dst, const int64_t* host_off, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack<T>, dim3(64, S.npatch), dim3(256), 0, s, S, slots, dst, host_off);
+}
+template <class T>
+void launch_unpack(const DevSet& S, T* slots, const T* src, const int64_t* host_off, hipStream_t s) {
+  hipLaunchKernelGGL(k_unpack<T>, dim3(64, S.npatch), dim3(256), 0, s, S, slots, src, host_off);
+}
+
+#define DSP_INST(T)                                                                                    \
+  template void launch_update<T>(const DevSet&, const int*, int, int, T*, const WorkPtr<T>&,          \
+                                 const StepPtr&, hipStream_t, int, double, int, hipEvent_t, hipEvent_t); \
+  template void launch_stats<T>(const DevSet&, const T*, double*, hipStream_t);                        \
+  template void launch_gather<T>(const DevSet&, const T*, double*, const int64_t*, hipStream_t);       \
+  template void launch_scatter<T>(const DevSet&, T*, const double*, const int64_t*, hipStream_t);      \
+  template void launch_pack<T>(const DevSet&, const T*, T*, const int64_t*, hipStream_t);              \
+  template void launch_unpack<T>(const DevSet&, T*, const T*, const int64_t*, hipStream_t);
+DSP_INST(float)
+DSP_INST(double)
+
+}  // namespace dsp

@@ -1,0 +1,939 @@
+// dsp_runtime.hip -- host side of libdsp.so: argument checks, patch geometry
+// on an exact integer lattice, neighbour and guard-box tables, device memory,
+// the round driver of the dispatcher, and the C ABI declared in dsp.h.
+//
+// Dispatcher (Sec. 3B): a round scans every patch for readiness (Eq. (1)
+// with g = 0: no neighbour lags behind it), then updates the whole ready set
+// in one launch sequence and publishes it.  With g = 0 the updates of one
+// round never read a slot that another update of the round writes, so the
+// result does not depend on how the ready set is split or ordered.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <memory>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "../../include/dsp.h"
+#include "dsp_dev.h"
+
+using namespace dsp;
+
+namespace {
+
+thread_local std::string g_err;
+int fail(int code, const std::string& m) {
+  g_err = m;
+  return code;
+}
+
+int64_t gcd_i64(int64_t a, int64_t b) {
+  while (b) {
+    int64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a < 0 ? -a : a;
+}
+int64_t floordiv(int64_t a, int64_t b) {  // b > 0
+  int64_t q = a / b;
+  if ((a % b) != 0 && (a < 0)) --q;
+  return q;
+}
+int64_t ceildiv(int64_t a, int64_t b) { return -floordiv(-a, b); }
+
+struct HPatch {
+  int n, level;
+  double dx;
+  int64_t lo[3], len, dxl;
+  int64_t V, slot_off;
+};
+
+}  // namespace
+
+struct dsp_set {
+  dsp_config cfg;
+  int np = 0;
+  std::vector<HPatch> P;
+  int64_t box_lo[3], box_len[3];
+  int64_t bsize = 1;
+  int nb[3] = {1, 1, 1};
+  std::vector<std::vector<int>> bucket;
+  std::vector<std::vector<int>> nbors;  // host copy (plain path)
+  hipStream_t stream = nullptr;
+  bool use_alloc = false;
+  dsp_allocator alloc{};
+  std::vector<void*> allocs;
+  bool f32 = false;
+  int nmax = 0;
+  int B = 0;  // batch capacity (patch slots of work memory)
+  int klog_cap = 256;
+  int64_t total_values = 0;
+  std::vector<int64_t> host_off;
+  // device memory
+  void* slots = nullptr;
+  DevSet D{};
+  void* work_pad = nullptr;
+  void *work_w = nullptr, *work_h = nullptr, *work_s = nullptr, *work_f = nullptr, *work_e = nullptr;
+  int64_t pad_stride = 0, w_stride = 0, s_stride = 0, f_stride = 0, e_stride = 0, fm3 = 0;
+  double* smax = nullptr;
+  int* d_list = nullptr;
+  int* d_counters = nullptr;
+  int* d_single = nullptr;
+  StepPtr st{};
+  double* d_hostbuf = nullptr;
+  int64_t* d_host_off = nullptr;
+  double* d_stats = nullptr;
+  // device-side mutable pointers (same memory as in D, non-const views)
+  int* d_err = nullptr;
+  unsigned long long* d_cnt = nullptr;  // floor, fallback, updates
+  bool initialised = false;
+  double last_ms = 0.0;
+  int64_t rounds = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  size_t ev_used = 0;
+  double kern_ms = 0.0;
+  int64_t kern_launches = 0;
+
+  ~dsp_set() { release(); }
+
+  bool alloc_failed = false;
+  void* dalloc(size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    void* p = nullptr;
+    if (use_alloc) {
+      p = alloc.alloc(alloc.ctx, bytes);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+      p = nullptr;
+    }
+    if (p)
+      allocs.push_back(p);
+    else
+      alloc_failed = true;
+    return p;
+  }
+  void release() {
+    for (void* p : allocs) {
+      if (use_alloc)
+        alloc.free(alloc.ctx, p);
+      else
+        (void)hipFree(p);
+    }
+    allocs.clear();
+    for (auto& e : ev) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+    ev.clear();
+  }
+
+  // ---- geometry -------------------------------------------------------------
+  int locate(int64_t X[3], const int mode[3]) const {
+    for (int d = 0; d < 3; ++d) {
+      const int64_t L = box_len[d];
+      if (mode[d] == 0)
+        X[d] = box_lo[d] + ((X[d] - box_lo[d]) % L + L) % L;
+      else
+        X[d] = box_lo[d] + L - ((box_lo[d] + L - X[d]) % L + L) % L;
+    }
+    int bi[3];
+    for (int d = 0; d < 3; ++d) {
+      int64_t x = X[d] - box_lo[d] - (mode[d] ? 1 : 0);
+      if (x < 0) x += box_len[d];
+      bi[d] = (int)std::min<int64_t>(x / bsize, nb[d] - 1);
+    }
+    int best = -1;
+    for (int q : bucket[((size_t)bi[2] * nb[1] + bi[1]) * nb[0] + bi[0]]) {
+      bool in = true;
+      for (int d = 0; d < 3 && in; ++d) {
+        const int64_t a = P[q].lo[d], b = P[q].lo[d] + P[q].len;
+        in = mode[d] == 0 ? (X[d] >= a && X[d] < b) : (X[d] > a && X[d] <= b);
+      }
+      if (in && (best < 0 || P[q].dxl < P[best].dxl)) best = q;
+    }
+    return best;
+  }
+
+  // Guard boxes of patch p for guard depth `depth`: per (component, region)
+  // the element boxes and their source patches.
+  int build_boxes(int p, int depth, std::vector<std::vector<GBox>>& per_key, std::set<int>* sources) {
+    const HPatch& H = P[p];
+    const int n = H.n;
+    per_key.assign(108, std::vector<GBox>());
+    int64_t minlen = bsize;
+    for (int comp = -1; comp < 3; ++comp) {
+      for (int rz = 0; rz < 3; ++rz)
+        for (int ry = 0; ry < 3; ++ry)
+          for (int rx = 0; rx < 3; ++rx) {
+            if (rx == 1 && ry == 1 && rz == 1) continue;
+            const int rg[3] = {rx, ry, rz};
+            const int key = (comp + 1) * 27 + (rz * 3 + ry) * 3 + rx;
+            // index ranges, split at the patch centre along a face's own axis
+            std::vector<std::pair<std::array<int, 6>, std::array<int, 3>>> subs;
+            int lo3[3], hi3[3], md[3];
+            for (int d = 0; d < 3; ++d) {
+              const bool fa = (d == comp);
+              if (rg[d] == 0) { lo3[d] = -depth; hi3[d] = -1; }
+              else if (rg[d] == 1) { lo3[d] = 0; hi3[d] = fa ? n : n - 1; }
+              else { lo3[d] = fa ? n + 1 : n; hi3[d] = fa ? n + depth : n + depth - 1; }
+              md[d] = (fa && rg[d] == 2) ? 1 : 0;
+            }
+            if (comp >= 0 && rg[comp] == 1) {
+              std::array<int, 6> a{lo3[0], lo3[1], lo3[2], hi3[0], hi3[1], hi3[2]};
+              std::array<int, 6> b = a;
+              a[3 + comp] = n / 2;
+              b[comp] = n / 2 + 1;
+              std::array<int, 3> ma{md[0], md[1], md[2]}, mb = ma;
+              ma[comp] = 0;
+              mb[comp] = 1;
+              subs.push_back({a, ma});
+              subs.push_back({b, mb});
+            } else {
+              subs.push_back({{lo3[0], lo3[1], lo3[2], hi3[0], hi3[1], hi3[2]}, {md[0], md[1], md[2]}});
+            }
+            for (auto& sb : subs) {
+              const int* blo = sb.first.data();
+              const int* bhi = sb.first.data() + 3;
+              const int* mode = sb.second.data();
+              int64_t base[3];
+              for (int d = 0; d < 3; ++d) base[d] = H.lo[d] + (d == comp ? 0 : H.dxl / 2);
+              // periodic image shift of the whole box
+              int64_t W[3];
+              for (int d = 0; d < 3; ++d) {
+                int64_t x0 = base[d] + (int64_t)blo[d] * H.dxl, x1 = base[d] + (int64_t)bhi[d] * H.dxl;
+                int64_t X0[3] = {0, 0, 0}, X1[3] = {0, 0, 0};
+                X0[d] = x0;
+                X1[d] = x1;
+                const int64_t L = box_len[d];
+                auto wrap = [&](int64_t x) {
+                  return mode[d] == 0 ? box_lo[d] + ((x - box_lo[d]) % L + L) % L
+                                      : box_lo[d] + L - ((box_lo[d] + L - x) % L + L) % L;
+                };
+                W[d] = wrap(x0) - x0;
+                if (wrap(x1) - x1 != W[d]) return fail(DSP_EINVAL, "guard region straddles the periodic boundary");
+              }
+              // discover the source patches by sampling the box
+              std::set<int> qs;
+              int stride[3];
+              for (int d = 0; d < 3; ++d) stride[d] = (int)std::max<int64_t>(1, (minlen / 2) / H.dxl);
+              for (int k = blo[2];; k = std::min(k + stride[2], bhi[2])) {
+                for (int j = blo[1];; j = std::min(j + stride[1], bhi[1])) {
+                  for (int i = blo[0];; i = std::min(i + stride[0], bhi[0])) {
+                    const int id[3] = {i, j, k};
+                    int64_t X[3];
+                    for (int d = 0; d < 3; ++d) X[d] = base[d] + (int64_t)id[d] * H.dxl;
+                    const int q = locate(X, mode);
+                    if (q < 0) return fail(DSP_EINVAL, "a guard zone lies outside every patch");
+                    qs.insert(q);
+                    if (i == bhi[0]) break;
+                  }
+                  if (j == bhi[1]) break;
+                }
+                if (k == bhi[2]) break;
+              }
+              int64_t covered = 0;
+              for (int q : qs) {
+                const HPatch& Q = P[q];
+                GBox g{};
+                g.q = q;
+                bool empty = false;
+                for (int d = 0; d < 3; ++d) {
+                  const int64_t off = base[d] + W[d];
+                  int64_t a, b;
+                  if (mode[d] == 0) {
+                    a = ceildiv(Q.lo[d] - off, H.dxl);
+                    b = floordiv(Q.lo[d] + Q.len - 1 - off, H.dxl);
+                  } else {
+                    a = floordiv(Q.lo[d] - off, H.dxl) + 1;
+                    b = floordiv(Q.lo[d] + Q.len - off, H.dxl);
+                  }
+                  g.lo[d] = (int)std::max<int64_t>(a, blo[d]);
+                  g.hi[d] = (int)std::min<int64_t>(b, bhi[d]);
+                  if (g.lo[d] > g.hi[d]) empty = true;
+                  g.wrap[d] = W[d];
+                }
+                if (empty) continue;
+                bool same = (Q.dxl == H.dxl);
+                for (int d = 0; d < 3 && same; ++d) {
+                  const int64_t rel = base[d] + W[d] + (int64_t)g.lo[d] * H.dxl - Q.lo[d] - (d == comp ? 0 : Q.dxl / 2);
+                  if (rel % Q.dxl != 0) same = false;
+                  else g.shift[d] = (int)(rel / Q.dxl) - g.lo[d];
+                }
+                g.same = same ? 1 : 0;
+                if (same) {  // the shifted box must lie inside the source slice
+                  for (int d = 0; d < 3; ++d) {
+                    const int qhi = Q.n - 1 + (d == comp ? 1 : 0);
+                    if (g.lo[d] + g.shift[d] < 0 || g.hi[d] + g.shift[d] > qhi)
+                      return fail(DSP_EINVAL, "guard box maps outside its source patch");
+                  }
+                }
+                covered += (int64_t)(g.hi[0] - g.lo[0] + 1) * (g.hi[1] - g.lo[1] + 1) * (g.hi[2] - g.lo[2] + 1);
+                per_key[key].push_back(g);
+                if (sources && q != p) sources->insert(q);
+              }
+              const int64_t vol = (int64_t)(bhi[0] - blo[0] + 1) * (bhi[1] - blo[1] + 1) * (bhi[2] - blo[2] + 1);
+              if (covered != vol) return fail(DSP_EINVAL, "guard zone not covered by exactly one patch (overlap?)");
+            }
+          }
+    }
+    return 0;
+  }
+
+  template <class T> WorkPtr<T> work() const {
+    WorkPtr<T> W;
+    W.pad = (T*)work_pad;
+    W.pad_stride = pad_stride;
+    W.w = (T*)work_w;
+    W.h = (T*)work_h;
+    W.w_stride = w_stride;
+    W.s = (T*)work_s;
+    W.s_stride = s_stride;
+    W.f = (T*)work_f;
+    W.f_stride = f_stride;
+    W.fm3 = fm3;
+    W.e = (T*)work_e;
+    W.e_stride = e_stride;
+    W.smax = smax;
+    return W;
+  }
+
+  hipEvent_t next_event(bool first) {
+    if (ev_used >= ev.size()) {
+      hipEvent_t a, b;
+      (void)hipEventCreate(&a);
+      (void)hipEventCreate(&b);
+      ev.push_back({a, b});
+    }
+    return first ? ev[ev_used].first : ev[ev_used].second;
+  }
+
+  // one launch sequence for list[off .. off+count)
+  void update_batch(int off, int count, int dt_kind, double t_end, int clip, const int* list) {
+    hipEvent_t e0 = next_event(true), e1 = next_event(false);
+    ev_used++;
+    StepPtr s2{st.k + off, st.dtk + off, st.dt + off};
+    if (f32)
+      launch_update<float>(D, list + off, count, nmax, (float*)slots, work<float>(), s2, stream, dt_kind, t_end,
+                           clip, e0, e1);
+    else
+      launch_update<double>(D, list + off, count, nmax, (double*)slots, work<double>(), s2, stream, dt_kind, t_end,
+                            clip, e0, e1);
+  }
+
+  int check_err(int bits) {
+    if (bits & ERR_NONFINITE) return fail(DSP_ENONFINITE, "non-finite state or signal speed");
+    if (bits & ERR_NEGATIVE) return fail(DSP_ENEGATIVE, "non-positive density or pressure");
+    if (bits & ERR_KMAX) return fail(DSP_EKMAX, "time-step level exceeds kmax");
+    if (bits & ERR_STATE) return fail(DSP_ESTATE, "guard data not available (internal)");
+    return 0;
+  }
+
+  void begin_timing() {
+    ev_used = 0;
+    kern_ms = 0.0;
+    kern_launches = 0;
+  }
+  void end_timing() {
+    (void)hipStreamSynchronize(stream);
+    for (size_t m = 0; m < ev_used; ++m) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[m].first, ev[m].second) == hipSuccess) kern_ms += ms;
+    }
+    kern_launches = (int64_t)ev_used;
+  }
+};
+
+namespace {
+
+bool tolat(double x, int64_t scale, int64_t& out) {
+  const double y = x * (double)scale;
+  const double r = std::nearbyint(y);
+  if (std::fabs(y - r) > 1e-6) return false;
+  out = (int64_t)r;
+  return true;
+}
+
+int hipck(hipError_t e, const char* what) {
+  if (e != hipSuccess) return fail(DSP_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dsp_last_error(void) { return g_err.c_str(); }
+
+int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, void* hip_stream,
+               const dsp_allocator* alloc, dsp_set** out) {
+  if (!out) return fail(DSP_EINVAL, "null output handle");
+  *out = nullptr;
+  if (!cfg || !pd || npatch <= 0) return fail(DSP_EINVAL, "null argument or no patches");
+  const dsp_config c = *cfg;
+  if (!(c.gamma > 1.0) || !(c.courant > 0.0) || c.nguard < 2 || c.nguard > 3 || c.nslots < 2 ||
+      c.nslots > 8 || c.kmax < 0 || c.kmax > 40 || c.limiter != 0 || c.grace != 0.0 ||
+      (c.prec != DSP_F32 && c.prec != DSP_F64) || c.dt_mode < 0 || c.dt_mode > 3 || c.p_floor < 0.0)
+    return fail(DSP_EINVAL, "invalid configuration");
+  if ((c.dt_mode == DSP_DT_LOCAL || c.dt_mode == DSP_DT_GLOBAL_QUANT) && !(c.dt_base > 0.0))
+    return fail(DSP_EINVAL, "dt_base must be positive");
+  if (c.dt_mode == DSP_DT_FIXED && !(c.dt_fixed > 0.0)) return fail(DSP_EINVAL, "dt_fixed must be positive");
+  for (int d = 0; d < 3; ++d)
+    if (c.periodic[d] != 1) return fail(DSP_EINVAL, "only periodic boxes are supported");
+
+  std::unique_ptr<dsp_set> S(new dsp_set());
+  S->cfg = c;
+  S->np = npatch;
+  S->stream = (hipStream_t)hip_stream;
+  S->f32 = (c.prec == DSP_F32);
+  if (alloc) {
+    if (!alloc->alloc || !alloc->free) return fail(DSP_EINVAL, "allocator without alloc/free");
+    S->use_alloc = true;
+    S->alloc = *alloc;
+  }
+  // lattice: 2 lcm(n/size) points per unit length
+  int64_t F = 1;
+  for (int p = 0; p < npatch; ++p) {
+    const dsp_patch_desc& q = pd[p];
+    if (q.n < 4 || q.n > 64 || !(q.size[0] > 0.0) || q.size[0] != q.size[1] || q.size[0] != q.size[2])
+      return fail(DSP_EINVAL, "patches must be cubic with 4 <= n <= 64");
+    const double cpl = q.n / q.size[0];
+    const int64_t ic = (int64_t)std::llround(cpl);
+    if (ic <= 0 || std::fabs(cpl - (double)ic) > 1e-9 * cpl) return fail(DSP_EINVAL, "n/size must be an integer");
+    F = F / gcd_i64(F, ic) * ic;
+    if (F > ((int64_t)1 << 40)) return fail(DSP_EINVAL, "lattice too fine");
+  }
+  const int64_t scale = 2 * F;
+  for (int d = 0; d < 3; ++d) {
+    int64_t a, b;
+    if (!tolat(c.box_lo[d], scale, a) || !tolat(c.box_hi[d], scale, b) || b <= a)
+      return fail(DSP_EINVAL, "box not on the patch lattice");
+    S->box_lo[d] = a;
+    S->box_len[d] = b - a;
+  }
+  S->P.resize(npatch);
+  int64_t minlen = INT64_MAX, off = 0;
+  S->host_off.assign(npatch + 1, 0);
+  for (int p = 0; p < npatch; ++p) {
+    HPatch& H = S->P[p];
+    H.n = pd[p].n;
+    H.level = pd[p].level;
+    H.dx = pd[p].size[0] / pd[p].n;
+    if (!tolat(pd[p].size[0], scale, H.len)) return fail(DSP_EINVAL, "patch size not on the lattice");
+    H.dxl = H.len / H.n;
+    for (int d = 0; d < 3; ++d) {
+      if (!tolat(pd[p].origin[d], scale, H.lo[d])) return fail(DSP_EINVAL, "origin not on the lattice");
+      if (H.lo[d] < S->box_lo[d] || H.lo[d] + H.len > S->box_lo[d] + S->box_len[d])
+        return fail(DSP_EINVAL, "patch outside the box");
+    }
+    if (c.nguard > H.n) return fail(DSP_EINVAL, "patch smaller than its guard zones");
+    H.V = 5LL * H.n * H.n * H.n + 3LL * H.n * H.n * (H.n + 1);
+    H.slot_off = off;
+    off += H.V * c.nslots;
+    S->host_off[p + 1] = S->host_off[p] + H.V;
+    minlen = std::min(minlen, H.len);
+    S->nmax = std::max(S->nmax, H.n);
+  }
+  S->total_values = S->host_off[npatch];
+  S->bsize = minlen;
+  for (int d = 0; d < 3; ++d) S->nb[d] = (int)((S->box_len[d] + minlen - 1) / minlen);
+  S->bucket.assign((size_t)S->nb[0] * S->nb[1] * S->nb[2], std::vector<int>());
+  for (int p = 0; p < npatch; ++p) {
+    int a[3], b[3];
+    for (int d = 0; d < 3; ++d) {
+      a[d] = (int)((S->P[p].lo[d] - S->box_lo[d]) / minlen);
+      b[d] = (int)((S->P[p].lo[d] + S->P[p].len - 1 - S->box_lo[d]) / minlen);
+    }
+    for (int z = a[2]; z <= b[2]; ++z)
+      for (int y = a[1]; y <= b[1]; ++y)
+        for (int x = a[0]; x <= b[0]; ++x) {
+          auto& bk = S->bucket[((size_t)z * S->nb[1] + y) * S->nb[0] + x];
+          for (int q : bk) {  // patches may not overlap
+            bool ov = true;
+            for (int d = 0; d < 3; ++d)
+              ov = ov && S->P[q].lo[d] < S->P[p].lo[d] + S->P[p].len && S->P[p].lo[d] < S->P[q].lo[d] + S->P[q].len;
+            if (ov) return fail(DSP_EINVAL, "patches overlap");
+          }
+          bk.push_back(p);
+        }
+  }
+  // neighbour relation over the configured guard depth; guard boxes of the
+  // two layers the stencil reads
+  std::vector<std::set<int>> reads(npatch);
+  std::vector<int> rbox_off(1, 0);
+  std::vector<GBox> boxes;
+  std::vector<std::vector<GBox>> keys;
+  for (int p = 0; p < npatch; ++p) {
+    int e = S->build_boxes(p, c.nguard, keys, &reads[p]);
+    if (e) return e;
+    e = S->build_boxes(p, 2, keys, nullptr);
+    if (e) return e;
+    for (int k = 0; k < 108; ++k) {
+      for (const GBox& g : keys[k]) boxes.push_back(g);
+      rbox_off.push_back((int)boxes.size());
+    }
+  }
+  S->nbors.assign(npatch, std::vector<int>());
+  for (int p = 0; p < npatch; ++p)
+    for (int q : reads[p]) {
+      S->nbors[p].push_back(q);
+      S->nbors[q].push_back(p);
+    }
+  std::vector<int> nb_off(1, 0), nb_idx;
+  for (int p = 0; p < npatch; ++p) {
+    auto& v = S->nbors[p];
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    for (int q : v) nb_idx.push_back(q);
+    nb_off.push_back((int)nb_idx.size());
+  }
+
+  // ---- device memory ----------------------------------------------------------
+  dsp_set* s = S.get();
+  const size_t tsz = s->f32 ? 4 : 8;
+  const int ns = c.nslots;
+  auto A = [&](size_t bytes) { return s->dalloc(bytes); };
+  s->slots = A(tsz * (size_t)off);
+  const int N = s->nmax + 4;
+  s->pad_stride = 5LL * N * N * N + 3LL * N * N * (N + 1);
+  s->w_stride = 8LL * N * N * N;
+  s->s_stride = 24LL * N * N * N;
+  s->fm3 = (int64_t)(N + 1) * (N + 1) * (N + 1);
+  s->f_stride = 24LL * s->fm3;
+  s->e_stride = 3LL * s->fm3;
+  const int64_t per_slot = tsz * (s->pad_stride + 2 * s->w_stride + s->s_stride + s->f_stride + s->e_stride);
+  const int64_t budget = (int64_t)16 << 30;  // work memory cap
+  s->B = (int)std::max<int64_t>(1, std::min<int64_t>(npatch, budget / per_slot));
+  if ((c.dt_mode != DSP_DT_LOCAL) && s->B < npatch)
+    return fail(DSP_EINVAL, "global time-step modes need work memory for every patch");
+  s->work_pad = A(tsz * s->pad_stride * s->B);
+  s->work_w = A(tsz * s->w_stride * s->B);
+  s->work_h = A(tsz * s->w_stride * s->B);
+  s->work_s = A(tsz * s->s_stride * s->B);
+  s->work_f = A(tsz * s->f_stride * s->B);
+  s->work_e = A(tsz * s->e_stride * s->B);
+  s->smax = (double*)A(sizeof(double) * s->B);
+  s->d_list = (int*)A(sizeof(int) * npatch);
+  s->d_single = (int*)A(sizeof(int) * 4);
+  s->d_counters = (int*)A(sizeof(int) * 4);
+  s->st.k = (int*)A(sizeof(int) * npatch);
+  s->st.dtk = (int64_t*)A(sizeof(int64_t) * npatch);
+  s->st.dt = (double*)A(sizeof(double) * npatch);
+  s->d_hostbuf = (double*)A(sizeof(double) * (size_t)s->total_values);
+  s->d_host_off = (int64_t*)A(sizeof(int64_t) * (npatch + 1));
+  s->d_stats = (double*)A(sizeof(double) * 9 * npatch);
+  if (s->alloc_failed) return fail(DSP_ENOMEM, "device allocation failed");
+
+  // metadata arrays
+  std::vector<int> hn(npatch);
+  std::vector<double> hdx(npatch);
+  std::vector<int64_t> hlo(3 * npatch), hlen(npatch), hdxl(npatch), hoff(npatch), hV(npatch);
+  for (int p = 0; p < npatch; ++p) {
+    hn[p] = s->P[p].n;
+    hdx[p] = s->P[p].dx;
+    for (int d = 0; d < 3; ++d) hlo[3 * p + d] = s->P[p].lo[d];
+    hlen[p] = s->P[p].len;
+    hdxl[p] = s->P[p].dxl;
+    hoff[p] = s->P[p].slot_off;
+    hV[p] = s->P[p].V;
+  }
+  DevSet& D = s->D;
+  D.npatch = npatch;
+  D.nslots = ns;
+  D.kmax = c.kmax;
+  D.dt_mode = c.dt_mode;
+  D.exact_time = (c.dt_mode == DSP_DT_GLOBAL_EXACT || c.dt_mode == DSP_DT_FIXED) ? 1 : 0;
+  D.klog_cap = s->klog_cap;
+  D.gamma = c.gamma;
+  D.courant = c.courant;
+  D.dt_base = c.dt_base;
+  D.dt_fixed = c.dt_fixed;
+  D.p_floor = c.p_floor;
+  auto up = [&](const void* h, size_t bytes) -> void* {
+    void* d = A(bytes);
+    if (d && bytes) (void)hipMemcpy(d, h, bytes, hipMemcpyHostToDevice);
+    return d;
+  };
+  D.n = (const int*)up(hn.data(), sizeof(int) * npatch);
+  D.dx = (const double*)up(hdx.data(), sizeof(double) * npatch);
+  D.lo = (const int64_t*)up(hlo.data(), sizeof(int64_t) * 3 * npatch);
+  D.len = (const int64_t*)up(hlen.data(), sizeof(int64_t) * npatch);
+  D.dxl = (const int64_t*)up(hdxl.data(), sizeof(int64_t) * npatch);
+  D.slot_off = (const int64_t*)up(hoff.data(), sizeof(int64_t) * npatch);
+  D.slice_len = (const int64_t*)up(hV.data(), sizeof(int64_t) * npatch);
+  D.cur = (int*)A(sizeof(int) * npatch);
+  D.ticks = (int64_t*)A(sizeof(int64_t) * npatch);
+  D.tcur = (double*)A(sizeof(double) * npatch);
+  D.sticks = (int64_t*)A(sizeof(int64_t) * npatch * ns);
+  D.stime = (double*)A(sizeof(double) * npatch * ns);
+  D.svalid = (int8_t*)A((size_t)npatch * ns);
+  D.steps = (int64_t*)A(sizeof(int64_t) * npatch);
+  D.khash = (uint64_t*)A(sizeof(uint64_t) * npatch);
+  D.klog = (int8_t*)A((size_t)npatch * s->klog_cap);
+  D.nb_off = (const int*)up(nb_off.data(), sizeof(int) * nb_off.size());
+  D.nb_idx = (const int*)up(nb_idx.data(), sizeof(int) * std::max<size_t>(1, nb_idx.size()));
+  D.rbox_off = (const int*)up(rbox_off.data(), sizeof(int) * rbox_off.size());
+  D.boxes = (const GBox*)up(boxes.data(), sizeof(GBox) * std::max<size_t>(1, boxes.size()));
+  s->d_err = (int*)A(sizeof(int) * 2);
+  s->d_cnt = (unsigned long long*)A(sizeof(unsigned long long) * 4);
+  D.err = s->d_err;
+  D.floor_hits = s->d_cnt;
+  D.fallback = s->d_cnt + 1;
+  D.updates = s->d_cnt + 2;
+  if (s->alloc_failed) return fail(DSP_ENOMEM, "device allocation failed");
+  int e = hipck(hipMemcpy(s->d_host_off, s->host_off.data(), sizeof(int64_t) * (npatch + 1), hipMemcpyHostToDevice),
+                "hipMemcpy");
+  if (e) return e;
+  e = hipck(hipDeviceSynchronize(), "create");
+  if (e) return e;
+  *out = S.release();
+  return 0;
+}
+
+static int init_common(dsp_set* s, const double* U, const void* U_dev, double t0);
+
+int dsp_init(dsp_set* s, const double* U, size_t n_values, double t0) {
+  if (!s || !U) return fail(DSP_EINVAL, "null argument");
+  if ((int64_t)n_values != s->total_values) return fail(DSP_EINVAL, "wrong number of values");
+  for (size_t m = 0; m < n_values; ++m)
+    if (!std::isfinite(U[m])) return fail(DSP_ENONFINITE, "non-finite initial state");
+  return init_common(s, U, nullptr, t0);
+}
+
+int dsp_init_device(dsp_set* s, const void* U_dev, double t0) {
+  if (!s || !U_dev) return fail(DSP_EINVAL, "null argument");
+  return init_common(s, nullptr, U_dev, t0);
+}
+
+static int init_common(dsp_set* s, const double* U, const void* U_dev, double t0) {
+  const size_t n_values = (size_t)s->total_values;
+  const dsp_config& c = s->cfg;
+  int64_t tk0 = 0;
+  const bool exact = (c.dt_mode == DSP_DT_GLOBAL_EXACT || c.dt_mode == DSP_DT_FIXED);
+  if (!exact) {
+    const double m = t0 / c.dt_base, mr = std::nearbyint(m);
+    if (std::fabs(m - mr) > 1e-9 * std::max(1.0, std::fabs(m))) return fail(DSP_EALIGN, "t0 is not a multiple of dt_base");
+    tk0 = (int64_t)mr << c.kmax;
+  }
+  const int np = s->np, ns = c.nslots;
+  std::vector<int> cur(np, 0);
+  std::vector<int64_t> ticks(np, tk0), sticks((size_t)np * ns, 0), zero64(np, 0);
+  std::vector<double> tc(np, t0), stime((size_t)np * ns, 0.0);
+  std::vector<int8_t> valid((size_t)np * ns, 0), klog((size_t)np * s->klog_cap, -2);
+  std::vector<uint64_t> kh(np, 1469598103934665603ull);
+  for (int p = 0; p < np; ++p) {
+    valid[(size_t)p * ns] = 1;
+    sticks[(size_t)p * ns] = tk0;
+    stime[(size_t)p * ns] = t0;
+  }
+  int e = 0;
+  auto cp = [&](void* d, const void* h, size_t b) {
+    if (!e) e = hipck(hipMemcpyAsync(d, h, b, hipMemcpyHostToDevice, s->stream), "upload");
+  };
+  DevSet& D = s->D;
+  cp(D.cur, cur.data(), sizeof(int) * np);
+  cp(D.ticks, ticks.data(), sizeof(int64_t) * np);
+  cp(D.tcur, tc.data(), sizeof(double) * np);
+  cp(D.sticks, sticks.data(), sizeof(int64_t) * np * ns);
+  cp(D.stime, stime.data(), sizeof(double) * np * ns);
+  cp(D.svalid, valid.data(), (size_t)np * ns);
+  cp(D.steps, zero64.data(), sizeof(int64_t) * np);
+  cp(D.khash, kh.data(), sizeof(uint64_t) * np);
+  cp(D.klog, klog.data(), (size_t)np * s->klog_cap);
+  if (U) cp(s->d_hostbuf, U, sizeof(double) * n_values);
+  if (e) return e;
+  (void)hipMemsetAsync(s->d_err, 0, sizeof(int) * 2, s->stream);
+  (void)hipMemsetAsync(s->d_cnt, 0, sizeof(unsigned long long) * 4, s->stream);
+  if (U) {
+    if (s->f32)
+      launch_scatter<float>(D, (float*)s->slots, s->d_hostbuf, s->d_host_off, s->stream);
+    else
+      launch_scatter<double>(D, (double*)s->slots, s->d_hostbuf, s->d_host_off, s->stream);
+  } else {
+    if (s->f32)
+      launch_unpack<float>(D, (float*)s->slots, (const float*)U_dev, s->d_host_off, s->stream);
+    else
+      launch_unpack<double>(D, (double*)s->slots, (const double*)U_dev, s->d_host_off, s->stream);
+  }
+  e = hipck(hipStreamSynchronize(s->stream), "init");
+  if (e) return e;
+  s->initialised = true;
+  s->rounds = 0;
+  return 0;
+}
+
+static int read_err(dsp_set* s, int* counters_out) {
+  int hbuf[4] = {0, 0, 0, 0};
+  int e = hipck(hipMemcpyAsync(hbuf, s->d_counters, sizeof(int) * 2, hipMemcpyDeviceToHost, s->stream), "readback");
+  if (!e) e = hipck(hipMemcpyAsync(hbuf + 2, s->d_err, sizeof(int), hipMemcpyDeviceToHost, s->stream), "readback");
+  if (!e) e = hipck(hipStreamSynchronize(s->stream), "round");
+  if (e) return e;
+  if (counters_out) {
+    counters_out[0] = hbuf[0];
+    counters_out[1] = hbuf[1];
+  }
+  return s->check_err(hbuf[2]);
+}
+
+static int end_time_ticks(dsp_set* s, double t_end, int64_t& T) {
+  const double m = t_end / s->cfg.dt_base, mr = std::nearbyint(m);
+  if (std::fabs(m - mr) > 1e-9 * std::max(1.0, std::fabs(m))) return fail(DSP_EALIGN, "end time is not a multiple of dt_base");
+  if (mr < 0 || mr * std::ldexp(1.0, s->cfg.kmax) > 9.0e18) return fail(DSP_EINVAL, "end time out of range");
+  T = (int64_t)mr << s->cfg.kmax;
+  return 0;
+}
+
+// GLOBAL modes: every patch steps together; all patches form one batch.
+static int run_global(dsp_set* s, double t_end, int64_t T, int max_steps) {
+  std::vector<int> all(s->np);
+  for (int p = 0; p < s->np; ++p) all[p] = p;
+  int e = hipck(hipMemcpyAsync(s->d_list, all.data(), sizeof(int) * s->np, hipMemcpyHostToDevice, s->stream), "list");
+  if (e) return e;
+  int nstep = 0;
+  while (true) {
+    if (max_steps >= 0 && nstep >= max_steps) return 0;
+    if (max_steps < 0) {
+      if (s->D.exact_time) {
+        double t0;
+        e = hipck(hipMemcpy(&t0, s->D.tcur, sizeof(double), hipMemcpyDeviceToHost), "time");
+        if (e) return e;
+        if (!(t0 < t_end)) return 0;
+      } else {
+        int64_t tk;
+        e = hipck(hipMemcpy(&tk, s->D.ticks, sizeof(int64_t), hipMemcpyDeviceToHost), "time");
+        if (e) return e;
+        if (tk >= T) return 0;
+      }
+    }
+    s->update_batch(0, s->np, 1, t_end, max_steps < 0 ? 1 : 0, s->d_list);
+    launch_publish(s->D, s->d_list, s->np, s->st, s->stream);
+    s->rounds++;
+    nstep++;
+    (void)hipMemsetAsync(s->d_counters, 0, sizeof(int) * 2, s->stream);
+    e = read_err(s, nullptr);
+    if (e) return e;
+  }
+}
+
+int dsp_advance_to(dsp_set* s, double t_end) {
+  if (!s || !s->initialised) return fail(DSP_ESTATE, "set not initialised");
+  auto w0 = std::chrono::steady_clock::now();
+  s->begin_timing();
+  int e;
+  if (s->D.exact_time) {
+    e = run_global(s, t_end, 0, -1);
+  } else {
+    int64_t T;
+    e = end_time_ticks(s, t_end, T);
+    if (e) return e;
+    if (s->cfg.dt_mode == DSP_DT_GLOBAL_QUANT) {
+      e = run_global(s, t_end, T, -1);
+    } else {
+      while (true) {
+        launch_scan(s->D, T, s->d_list, s->d_counters, s->stream);
+        int cnt[2];
+        e = read_err(s, cnt);
+        if (e) break;
+        if (cnt[1] == 0) break;
+        if (cnt[0] == 0) {
+          e = fail(DSP_ESTATE, "no ready patch but not done");
+          break;
+        }
+        for (int off = 0; off < cnt[0]; off += s->B)
+          s->update_batch(off, std::min(s->B, cnt[0] - off), 0, t_end, 0, s->d_list);
+        launch_publish(s->D, s->d_list, cnt[0], s->st, s->stream);
+        s->rounds++;
+      }
+    }
+  }
+  s->end_timing();
+  s->last_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - w0).count();
+  return e;
+}
+
+int dsp_advance_to_plain(dsp_set* s, double t_end) {
+  if (!s || !s->initialised) return fail(DSP_ESTATE, "set not initialised");
+  if (s->cfg.dt_mode != DSP_DT_LOCAL) return dsp_advance_to(s, t_end);
+  int64_t T;
+  int e = end_time_ticks(s, t_end, T);
+  if (e) return e;
+  auto w0 = std::chrono::steady_clock::now();
+  s->begin_timing();
+  const int np = s->np;
+  std::vector<int64_t> ticks(np);
+  e = hipck(hipMemcpy(ticks.data(), s->D.ticks, sizeof(int64_t) * np, hipMemcpyDeviceToHost), "ticks");
+  while (!e) {
+    // oldest ready patch, ties by id (Sec. 3B mode (i))
+    int best = -1;
+    bool done = true;
+    for (int p = 0; p < np; ++p) {
+      if (ticks[p] >= T) continue;
+      done = false;
+      bool ready = true;
+      for (int q : s->nbors[p])
+        if (ticks[q] < ticks[p]) { ready = false; break; }
+      if (ready && (best < 0 || ticks[p] < ticks[best])) best = p;
+    }
+    if (done) break;
+    if (best < 0) { e = fail(DSP_ESTATE, "no ready patch but not done"); break; }
+    e = hipck(hipMemcpyAsync(s->d_single, &best, sizeof(int), hipMemcpyHostToDevice, s->stream), "list");
+    if (e) break;
+    s->update_batch(0, 1, 0, t_end, 0, s->d_single);
+    launch_publish(s->D, s->d_single, 1, s->st, s->stream);
+    s->rounds++;
+    int64_t dtk = 0;
+    e = hipck(hipMemcpyAsync(&dtk, s->st.dtk, sizeof(int64_t), hipMemcpyDeviceToHost, s->stream), "dt");
+    if (e) break;
+    e = read_err(s, nullptr);
+    if (e) break;
+    ticks[best] += dtk;
+  }
+  s->end_timing();
+  s->last_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - w0).count();
+  return e;
+}
+
+int dsp_read_state(const dsp_set* cs, double* U, size_t n_values, double* t_out) {
+  dsp_set* s = const_cast<dsp_set*>(cs);
+  if (!s || !U || !s->initialised) return fail(DSP_EINVAL, "bad argument");
+  if ((int64_t)n_values < s->total_values) return fail(DSP_EINVAL, "output buffer too small");
+  if (s->f32)
+    launch_gather<float>(s->D, (const float*)s->slots, s->d_hostbuf, s->d_host_off, s->stream);
+  else
+    launch_gather<double>(s->D, (const double*)s->slots, s->d_hostbuf, s->d_host_off, s->stream);
+  int e = hipck(hipMemcpyAsync(U, s->d_hostbuf, sizeof(double) * s->total_values, hipMemcpyDeviceToHost, s->stream),
+                "download");
+  if (!e) e = hipck(hipStreamSynchronize(s->stream), "download");
+  if (e) return e;
+  if (t_out) {
+    std::vector<double> tc(s->np);
+    e = hipck(hipMemcpy(tc.data(), s->D.tcur, sizeof(double) * s->np, hipMemcpyDeviceToHost), "time");
+    if (e) return e;
+    *t_out = *std::min_element(tc.begin(), tc.end());
+  }
+  return 0;
+}
+
+int dsp_read_schedule(const dsp_set* s, int64_t* steps, uint64_t* khash, int32_t* klog, size_t klog_cap) {
+  if (!s) return fail(DSP_EINVAL, "null handle");
+  const int np = s->np;
+  int e = 0;
+  if (steps) e = hipck(hipMemcpy(steps, s->D.steps, sizeof(int64_t) * np, hipMemcpyDeviceToHost), "steps");
+  if (!e && khash) e = hipck(hipMemcpy(khash, s->D.khash, sizeof(uint64_t) * np, hipMemcpyDeviceToHost), "khash");
+  if (!e && klog) {
+    std::vector<int8_t> kl((size_t)np * s->klog_cap);
+    e = hipck(hipMemcpy(kl.data(), s->D.klog, kl.size(), hipMemcpyDeviceToHost), "klog");
+    for (int p = 0; p < np && !e; ++p)
+      for (size_t m = 0; m < klog_cap; ++m)
+        klog[(size_t)p * klog_cap + m] = m < (size_t)s->klog_cap ? kl[(size_t)p * s->klog_cap + m] : -2;
+  }
+  return e;
+}
+
+int dsp_stats(const dsp_set* cs, double out[16]) {
+  dsp_set* s = const_cast<dsp_set*>(cs);
+  if (!s || !out) return fail(DSP_EINVAL, "null argument");
+  for (int m = 0; m < 16; ++m) out[m] = 0.0;
+  if (!s->initialised) return fail(DSP_ESTATE, "set not initialised");
+  if (s->f32)
+    launch_stats<float>(s->D, (const float*)s->slots, s->d_stats, s->stream);
+  else
+    launch_stats<double>(s->D, (const double*)s->slots, s->d_stats, s->stream);
+  std::vector<double> ps((size_t)9 * s->np), tc(s->np);
+  unsigned long long cnt[3];
+  int e = hipck(hipMemcpyAsync(ps.data(), s->d_stats, sizeof(double) * ps.size(), hipMemcpyDeviceToHost, s->stream), "stats");
+  if (!e) e = hipck(hipMemcpyAsync(cnt, s->d_cnt, sizeof(cnt), hipMemcpyDeviceToHost, s->stream), "stats");
+  if (!e) e = hipck(hipMemcpyAsync(tc.data(), s->D.tcur, sizeof(double) * s->np, hipMemcpyDeviceToHost, s->stream), "stats");
+  if (!e) e = hipck(hipStreamSynchronize(s->stream), "stats");
+  if (e) return e;
+  double dmax = 0.0;
+  for (int p = 0; p < s->np; ++p) {
+    for (int q = 0; q < 8; ++q) out[1 + q] += ps[(size_t)p * 9 + q];
+    dmax = std::max(dmax, ps[(size_t)p * 9 + 8]);
+  }
+  out[0] = (double)cnt[2];
+  out[9] = dmax;
+  out[10] = (double)cnt[0];
+  out[11] = (double)cnt[1];
+  out[12] = s->last_ms;
+  out[13] = (double)s->rounds;
+  out[14] = *std::min_element(tc.begin(), tc.end());
+  out[15] = *std::max_element(tc.begin(), tc.end());
+  return 0;
+}
+
+int dsp_kernel_time(const dsp_set* s, double* ms, int64_t* launches) {
+  if (!s) return fail(DSP_EINVAL, "null handle");
+  if (ms) *ms = s->kern_ms;
+  if (launches) *launches = s->kern_launches;
+  return 0;
+}
+
+int dsp_fixed_steps_fwd(dsp_set* s, const void* U0_dev, void* UT_dev, int32_t nsteps, void* ckpt_dev) {
+  if (!s || !U0_dev || !UT_dev || nsteps < 0) return fail(DSP_EINVAL, "bad argument");
+  if (s->cfg.dt_mode != DSP_DT_FIXED) return fail(DSP_EINVAL, "fixed steps need the FIXED dt mode");
+  // reset the time bookkeeping to t = 0 with the given state in slot 0
+  const int np = s->np, ns = s->cfg.nslots;
+  std::vector<int> cur(np, 0);
+  std::vector<double> tc(np, 0.0), stime((size_t)np * ns, 0.0);
+  std::vector<int8_t> valid((size_t)np * ns, 0);
+  for (int p = 0; p < np; ++p) valid[(size_t)p * ns] = 1;
+  int e = hipck(hipMemcpyAsync(s->D.cur, cur.data(), sizeof(int) * np, hipMemcpyHostToDevice, s->stream), "reset");
+  if (!e) e = hipck(hipMemcpyAsync(s->D.tcur, tc.data(), sizeof(double) * np, hipMemcpyHostToDevice, s->stream), "reset");
+  if (!e) e = hipck(hipMemcpyAsync(s->D.stime, stime.data(), sizeof(double) * np * ns, hipMemcpyHostToDevice, s->stream), "reset");
+  if (!e) e = hipck(hipMemcpyAsync(s->D.svalid, valid.data(), (size_t)np * ns, hipMemcpyHostToDevice, s->stream), "reset");
+  if (e) return e;
+  if (s->f32)
+    launch_unpack<float>(s->D, (float*)s->slots, (const float*)U0_dev, s->d_host_off, s->stream);
+  else
+    launch_unpack<double>(s->D, (double*)s->slots, (const double*)U0_dev, s->d_host_off, s->stream);
+  s->initialised = true;
+  const size_t tsz = s->f32 ? 4 : 8;
+  s->begin_timing();
+  for (int m = 0; m < nsteps && !e; m += 8) {
+    if (ckpt_dev) {
+      char* dst = (char*)ckpt_dev + (size_t)(m / 8) * s->total_values * tsz;
+      if (s->f32)
+        launch_pack<float>(s->D, (const float*)s->slots, (float*)dst, s->d_host_off, s->stream);
+      else
+        launch_pack<double>(s->D, (const double*)s->slots, (double*)dst, s->d_host_off, s->stream);
+    }
+    e = run_global(s, 0.0, 0, std::min(8, nsteps - m));
+  }
+  if (e) return e;
+  if (ckpt_dev && nsteps % 8 == 0) {
+    char* dst = (char*)ckpt_dev + (size_t)(nsteps / 8) * s->total_values * tsz;
+    if (s->f32)
+      launch_pack<float>(s->D, (const float*)s->slots, (float*)dst, s->d_host_off, s->stream);
+    else
+      launch_pack<double>(s->D, (const double*)s->slots, (double*)dst, s->d_host_off, s->stream);
+  }
+  if (s->f32)
+    launch_pack<float>(s->D, (const float*)s->slots, (float*)UT_dev, s->d_host_off, s->stream);
+  else
+    launch_pack<double>(s->D, (const double*)s->slots, (double*)UT_dev, s->d_host_off, s->stream);
+  s->end_timing();
+  return hipck(hipStreamSynchronize(s->stream), "fixed steps");
+}
+
+int dsp_fixed_steps_adj(dsp_set* s, const void* ckpt_dev, const void* lamT_dev, void* lam0_dev, int32_t nsteps,
+                        int32_t seg) {
+  (void)ckpt_dev;
+  (void)lamT_dev;
+  (void)lam0_dev;
+  (void)nsteps;
+  (void)seg;
+  if (!s) return fail(DSP_EINVAL, "null handle");
+  return fail(DSP_EINVAL, "adjoint not available in this build");
+}
+
+void dsp_destroy(dsp_set* s) { delete s; }
+
+}  // extern "C"

@@ -1,0 +1,241 @@
+"""Thin ctypes binding of libdsp.so (include/dsp.h): argument marshalling only.
+
+Every function keeps the C name (dsp_create, dsp_init, dsp_advance_to, ...);
+`PatchSet` wraps a handle.  Every step of the patch update runs in the HIP
+kernels of libdsp.so; if the library is missing or cannot be loaded the
+import of this module's functions raises.  PyTorch only provides the HIP
+stream the set runs on and the device tensors of the fixed-step entries.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdsp.so")
+_lib = None
+
+DSP_OK, DSP_EINVAL, DSP_ENOMEM, DSP_EHIP, DSP_EKMAX, DSP_EALIGN, DSP_ENONFINITE, DSP_ENEGATIVE, DSP_ESTATE = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8)
+DSP_F32, DSP_F64 = 1, 2
+DSP_DT_LOCAL, DSP_DT_GLOBAL_QUANT, DSP_DT_GLOBAL_EXACT, DSP_DT_FIXED = 0, 1, 2, 3
+
+# every entry point declared in include/dsp.h
+EXPORTS = ["dsp_create", "dsp_init", "dsp_init_device", "dsp_advance_to", "dsp_advance_to_plain", "dsp_read_state",
+           "dsp_read_schedule", "dsp_stats", "dsp_kernel_time", "dsp_fixed_steps_fwd",
+           "dsp_fixed_steps_adj", "dsp_destroy", "dsp_last_error"]
+
+
+class dsp_config(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("courant", C.c_double), ("dt_base", C.c_double),
+                ("dt_fixed", C.c_double), ("grace", C.c_double), ("p_floor", C.c_double),
+                ("kmax", C.c_int32), ("nslots", C.c_int32), ("nguard", C.c_int32),
+                ("limiter", C.c_int32), ("prec", C.c_int32), ("dt_mode", C.c_int32),
+                ("periodic", C.c_int32 * 3), ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3)]
+
+
+class dsp_patch_desc(C.Structure):
+    _fields_ = [("origin", C.c_double * 3), ("size", C.c_double * 3), ("n", C.c_int32),
+                ("level", C.c_int32)]
+
+
+class DspError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libdsp error {code}: {msg}")
+        self.code = code
+
+
+def load():
+    """Load libdsp.so (built in place by csrc/build.py if it is absent)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        from .csrc import build as _b
+        _b.build()
+    L = C.CDLL(LIB_PATH)
+    vp, dp, sz = C.c_void_p, C.POINTER(C.c_double), C.c_size_t
+    L.dsp_create.argtypes = [C.POINTER(dsp_config), C.POINTER(dsp_patch_desc), C.c_int32, vp, vp,
+                             C.POINTER(vp)]
+    L.dsp_init.argtypes = [vp, dp, sz, C.c_double]
+    L.dsp_init_device.argtypes = [vp, vp, C.c_double]
+    L.dsp_advance_to.argtypes = [vp, C.c_double]
+    L.dsp_advance_to_plain.argtypes = [vp, C.c_double]
+    L.dsp_read_state.argtypes = [vp, dp, sz, dp]
+    L.dsp_read_schedule.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_uint64),
+                                    C.POINTER(C.c_int32), sz]
+    L.dsp_stats.argtypes = [vp, dp]
+    L.dsp_kernel_time.argtypes = [vp, dp, C.POINTER(C.c_int64)]
+    L.dsp_fixed_steps_fwd.argtypes = [vp, vp, vp, C.c_int32, vp]
+    L.dsp_fixed_steps_adj.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32]
+    L.dsp_destroy.argtypes = [vp]
+    L.dsp_destroy.restype = None
+    L.dsp_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != 0:
+        raise DspError(rc, load().dsp_last_error().decode())
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def make_config(cfg) -> dsp_config:
+    c = dsp_config()
+    for f in ("gamma", "courant", "dt_base", "dt_fixed", "grace", "p_floor", "kmax", "nslots",
+              "nguard", "limiter", "prec", "dt_mode"):
+        setattr(c, f, getattr(cfg, f))
+    for d in range(3):
+        c.periodic[d] = int(cfg.periodic[d])
+        c.box_lo[d] = cfg.box_lo[d]
+        c.box_hi[d] = cfg.box_hi[d]
+    return c
+
+
+def make_descs(patches):
+    arr = (dsp_patch_desc * len(patches))()
+    for i, p in enumerate(patches):
+        for d in range(3):
+            arr[i].origin[d] = p.origin[d]
+            arr[i].size[d] = p.size
+        arr[i].n = p.n
+        arr[i].level = p.level
+    return arr
+
+
+def _torch_stream():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:  # pragma: no cover - no torch / no GPU
+        pass
+    return None
+
+
+# --- functions with the C names ------------------------------------------------
+
+def dsp_create(cfg, patches, stream=None):
+    c = make_config(cfg)
+    d = make_descs(patches)
+    h = C.c_void_p()
+    _check(load().dsp_create(C.byref(c), d, len(patches), stream, None, C.byref(h)))
+    return h
+
+
+def dsp_init(h, U, t0=0.0):
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    _check(load().dsp_init(h, _dp(U), U.size, float(t0)))
+
+
+def dsp_init_device(h, U_dev, t0=0.0):
+    _check(load().dsp_init_device(h, C.c_void_p(U_dev), float(t0)))
+
+
+def dsp_advance_to(h, t_end):
+    _check(load().dsp_advance_to(h, float(t_end)))
+
+
+def dsp_advance_to_plain(h, t_end):
+    _check(load().dsp_advance_to_plain(h, float(t_end)))
+
+
+def dsp_read_state(h, nvals):
+    U = np.empty(nvals)
+    t = C.c_double()
+    _check(load().dsp_read_state(h, _dp(U), U.size, C.byref(t)))
+    return U, t.value
+
+
+def dsp_read_schedule(h, npatch, klog_cap=0):
+    steps = np.zeros(npatch, dtype=np.int64)
+    kh = np.zeros(npatch, dtype=np.uint64)
+    kl = np.zeros(npatch * max(klog_cap, 1), dtype=np.int32)
+    _check(load().dsp_read_schedule(h, steps.ctypes.data_as(C.POINTER(C.c_int64)),
+                                    kh.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                    kl.ctypes.data_as(C.POINTER(C.c_int32)) if klog_cap else None,
+                                    klog_cap))
+    return (steps, kh, kl.reshape(npatch, klog_cap)) if klog_cap else (steps, kh)
+
+
+def dsp_stats(h):
+    out = np.zeros(16)
+    _check(load().dsp_stats(h, _dp(out)))
+    return out
+
+
+def dsp_kernel_time(h):
+    ms = C.c_double()
+    n = C.c_int64()
+    _check(load().dsp_kernel_time(h, C.byref(ms), C.byref(n)))
+    return ms.value, n.value
+
+
+def dsp_fixed_steps_fwd(h, U0_dev, UT_dev, nsteps, ckpt_dev=None):
+    _check(load().dsp_fixed_steps_fwd(h, C.c_void_p(U0_dev), C.c_void_p(UT_dev), int(nsteps),
+                                      C.c_void_p(ckpt_dev) if ckpt_dev else None))
+
+
+def dsp_fixed_steps_adj(h, ckpt_dev, lamT_dev, lam0_dev, nsteps, seg=8):
+    _check(load().dsp_fixed_steps_adj(h, C.c_void_p(ckpt_dev), C.c_void_p(lamT_dev),
+                                      C.c_void_p(lam0_dev), int(nsteps), int(seg)))
+
+
+def dsp_destroy(h):
+    if h:
+        load().dsp_destroy(h)
+
+
+class PatchSet:
+    """A patch set on the GPU (owns a dsp_set handle)."""
+
+    def __init__(self, cfg, patches, stream="torch"):
+        self.cfg, self.patches = cfg, list(patches)
+        self.nvals = int(sum(5 * p.n ** 3 + 3 * p.n * p.n * (p.n + 1) for p in self.patches))
+        s = _torch_stream() if stream == "torch" else stream
+        self.h = dsp_create(cfg, self.patches, s)
+
+    @classmethod
+    def from_problem(cls, prob, **over):
+        import dataclasses
+        cfg = dataclasses.replace(prob.cfg, **over) if over else prob.cfg
+        s = cls(cfg, prob.patches)
+        s.init(prob.U0)
+        return s
+
+    def close(self):
+        if getattr(self, "h", None):
+            dsp_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def init(self, U, t0=0.0):
+        dsp_init(self.h, U, t0)
+
+    def init_device(self, U_dev, t0=0.0):
+        dsp_init_device(self.h, U_dev, t0)
+
+    def advance_to(self, t):
+        dsp_advance_to(self.h, t)
+
+    def advance_to_plain(self, t):
+        dsp_advance_to_plain(self.h, t)
+
+    def read_state(self):
+        return dsp_read_state(self.h, self.nvals)[0]
+
+    def read_schedule(self, klog_cap=0):
+        return dsp_read_schedule(self.h, len(self.patches), klog_cap)
+
+    def stats(self):
+        return dsp_stats(self.h)
+
+    def kernel_time(self):
+        return dsp_kernel_time(self.h)

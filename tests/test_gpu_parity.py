@@ -1,0 +1,191 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU FP64 oracle on
+the same seeded inputs.
+
+Bars: the update schedule (steps and level hash per patch) bit-exact; FP64
+state within 1e-10 and FP32 within 1e-4, as the largest per-variable relative
+L1 difference max_v |U_gpu - U_orc|_1 / |U_orc|_1; uniform states bitwise."""
+import dataclasses
+import os
+
+import numpy as np
+import pytest
+
+from paper_1705_10774_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+NT = max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def _dsp():
+    from paper_1705_10774_amd import dsp
+    dsp.load()
+    return dsp
+
+
+def rel_l1(Ug, Uo, patches):
+    """max over the 8 variables of |dU|_1 / |U|_1."""
+    worst = 0.0
+    Vg, Vo = I.patch_views(Ug, patches), I.patch_views(Uo, patches)
+    for v in range(8):
+        num = sum(np.abs(a[v] - b[v]).sum() for a, b in zip(Vg, Vo))
+        den = sum(np.abs(b[v]).sum() for b in Vo)
+        if den > 0:
+            worst = max(worst, num / den)
+        else:
+            worst = max(worst, num)
+    return worst
+
+
+def gpu_run(prob, t_end=None, plain=False, **over):
+    dsp = _dsp()
+    s = dsp.PatchSet.from_problem(prob, **over)
+    t = prob.t_end if t_end is None else t_end
+    (s.advance_to_plain if plain else s.advance_to)(t)
+    U = s.read_state()
+    steps, kh = s.read_schedule()
+    st = s.stats()
+    s.close()
+    return U, steps, kh, st
+
+
+def orc_run(orc, prob, t_end=None, **over):
+    s = orc.OracleSet.from_problem(prob, **over)
+    s.set_order(2, 1, NT)
+    s.advance_to(prob.t_end if t_end is None else t_end)
+    U = s.read_state()
+    steps, kh = s.read_schedule()
+    st = s.stats()
+    s.close()
+    return U, steps, kh, st
+
+
+def spread(n=8):
+    # 27 patches with genuinely different local steps (10 at k = 0, 17 at k = 1)
+    return I.turbulence(npd=3, n=n, mach=5.0, seed=5, dt_base=0.02 / 32)
+
+
+# ---------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("prec", [I.F64, I.F32])
+@pytest.mark.parametrize("mode", [I.DT_LOCAL, I.DT_GLOBAL_EXACT])
+def test_uniform_state_bitwise(prec, mode):
+    pr = I.uniform(npd=2, n=8, v=(0.3, -0.2, 0.1), B=(0.7, 0.4, -0.3), mode=mode,
+                   dt_base=1.0 / 64, prec=prec)
+    t = 4.0 / 64 if mode == I.DT_LOCAL else 0.1
+    U, steps, kh, st = gpu_run(pr, t_end=t)
+    U0 = pr.U0 if prec == I.F64 else pr.U0.astype(np.float32).astype(np.float64)
+    assert st[13] >= 8
+    assert np.array_equal(U, U0)
+
+
+def test_cfg1_alfven_fp64_full(orc):
+    """Configuration 1 at full size: 2x2x2 patches of 16^3, global exact dt to t = 1."""
+    pr = I.cfg1_alfven()
+    Ug, sg, kg, stg = gpu_run(pr)
+    Uo, so, ko, sto = orc_run(orc, pr)
+    assert stg[13] == sto[13] > 250  # same number of global steps
+    assert np.array_equal(sg, so) and np.array_equal(kg, ko)
+    assert rel_l1(Ug, Uo, pr.patches) <= 1e-10
+    # the wave itself (By is pure perturbation): relative to its own size
+    Vg, Vo = I.patch_views(Ug, pr.patches), I.patch_views(Uo, pr.patches)
+    num = sum(np.abs(a[6] - b[6]).sum() for a, b in zip(Vg, Vo))
+    den = sum(np.abs(b[6]).sum() for b in Vo)
+    assert num / den <= 1e-8
+    assert stg[9] <= 1e-13 * 16  # div B at rounding (per unit length, |B| ~ 1)
+
+
+@pytest.mark.parametrize("n", [8, 16])
+def test_local_dt_fp64_schedule_and_state(orc, n):
+    pr = spread(n)
+    T = 4 * pr.cfg.dt_base
+    Ug, sg, kg, stg = gpu_run(pr, t_end=T)
+    Uo, so, ko, sto = orc_run(orc, pr, t_end=T)
+    assert len(set(so.tolist())) > 1
+    assert np.array_equal(sg, so)
+    assert np.array_equal(kg, ko)
+    assert stg[0] == sto[0]
+    assert rel_l1(Ug, Uo, pr.patches) <= 1e-10
+    assert stg[11] == sto[11]  # first-order fallback faces
+
+
+def test_local_dt_fp32(orc):
+    pr = spread(16)
+    T = 4 * pr.cfg.dt_base
+    Ug, sg, kg, stg = gpu_run(pr, t_end=T, prec=I.F32)
+    Uo, so, ko, sto = orc_run(orc, pr, t_end=T)
+    assert np.array_equal(sg, so) and np.array_equal(kg, ko)
+    err = rel_l1(Ug, Uo, pr.patches)
+    print("fp32 rel L1", err)
+    assert err <= 1e-4
+
+
+def test_plain_equals_batched_fp64():
+    pr = spread(8)
+    T = 4 * pr.cfg.dt_base
+    a = gpu_run(pr, t_end=T)
+    b = gpu_run(pr, t_end=T, plain=True)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    assert b[3][13] > a[3][13]  # one launch sequence per update vs per round
+
+
+@pytest.mark.parametrize("prec", [I.F64, I.F32])
+def test_repeatable_bitwise(prec):
+    pr = spread(8)
+    T = 4 * pr.cfg.dt_base
+    a = gpu_run(pr, t_end=T, prec=prec)
+    b = gpu_run(pr, t_end=T, prec=prec)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2])
+
+
+@pytest.mark.parametrize("prec", [I.F64, I.F32])
+def test_cfg2_full_size_first_base_step(orc, prec):
+    """Configuration 2 at full size (512 patches of 16^3, local steps), in the
+    benchmark's launch configuration, up to the first dt_base: every patch
+    takes one or two steps, all outputs compared."""
+    pr = I.cfg2_turb(prec=prec)
+    T = pr.cfg.dt_base
+    Ug, sg, kg, stg = gpu_run(pr, t_end=T)
+    Uo, so, ko, sto = orc_run(orc, pr, t_end=T)
+    assert set(so.tolist()) == {1, 2}
+    assert np.array_equal(sg, so) and np.array_equal(kg, ko)
+    err = rel_l1(Ug, Uo, pr.patches)
+    print("cfg2 first dt_base rel L1", prec, err)
+    assert err <= (1e-10 if prec == I.F64 else 1e-4)
+
+
+def test_gpu_error_codes():
+    dsp = _dsp()
+    pr = spread(8)
+    # kmax too small for the levels this set needs
+    s = dsp.PatchSet.from_problem(pr, kmax=0)
+    with pytest.raises(dsp.DspError) as e:
+        s.advance_to(pr.cfg.dt_base)
+    assert e.value.code == dsp.DSP_EKMAX
+    s.close()
+    # end time not on the dt_base grid
+    s = dsp.PatchSet.from_problem(pr)
+    with pytest.raises(dsp.DspError) as e:
+        s.advance_to(pr.cfg.dt_base * 0.5)
+    assert e.value.code == dsp.DSP_EALIGN
+    # the handle stays usable after an error
+    s.advance_to(pr.cfg.dt_base)
+    assert s.stats()[14] == pytest.approx(pr.cfg.dt_base)
+    s.close()
+    # negative pressure without a floor
+    U = pr.U0.copy()
+    I.patch_views(U, pr.patches)[3][4][2, 2, 2] = 0.0
+    s = dsp.PatchSet(pr.cfg, pr.patches)
+    s.init(U)
+    with pytest.raises(dsp.DspError) as e:
+        s.advance_to(pr.cfg.dt_base)
+    assert e.value.code == dsp.DSP_ENEGATIVE
+    s.close()
+    # non-finite initial state
+    U = pr.U0.copy()
+    U[7] = np.inf
+    s = dsp.PatchSet(pr.cfg, pr.patches)
+    with pytest.raises(dsp.DspError) as e:
+        s.init(U)
+    assert e.value.code == dsp.DSP_ENONFINITE
+    s.close()
