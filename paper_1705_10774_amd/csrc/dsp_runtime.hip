@@ -106,13 +106,19 @@ struct dsp_set {
   ~dsp_set() { release(); }
 
   bool alloc_failed = false;
+  std::string alloc_msg;
   void* dalloc(size_t bytes) {
     if (bytes == 0) bytes = 16;
     void* p = nullptr;
     if (use_alloc) {
       p = alloc.alloc(alloc.ctx, bytes);
-    } else if (hipMalloc(&p, bytes) != hipSuccess) {
-      p = nullptr;
+    } else {
+      const hipError_t e = hipMalloc(&p, bytes);
+      if (e != hipSuccess) {
+        p = nullptr;
+        if (alloc_msg.empty())
+          alloc_msg = std::string(hipGetErrorString(e)) + " (" + std::to_string(bytes) + " bytes)";
+      }
     }
     if (p)
       allocs.push_back(p);
@@ -529,7 +535,7 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
   s->d_hostbuf = (double*)A(sizeof(double) * (size_t)s->total_values);
   s->d_host_off = (int64_t*)A(sizeof(int64_t) * (npatch + 1));
   s->d_stats = (double*)A(sizeof(double) * 9 * npatch);
-  if (s->alloc_failed) return fail(DSP_ENOMEM, "device allocation failed");
+  if (s->alloc_failed) return fail(DSP_ENOMEM, "device allocation failed: " + s->alloc_msg);
 
   // metadata arrays
   std::vector<int> hn(npatch);
@@ -587,7 +593,7 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
   D.floor_hits = s->d_cnt;
   D.fallback = s->d_cnt + 1;
   D.updates = s->d_cnt + 2;
-  if (s->alloc_failed) return fail(DSP_ENOMEM, "device allocation failed");
+  if (s->alloc_failed) return fail(DSP_ENOMEM, "device allocation failed: " + s->alloc_msg);
   int e = hipck(hipMemcpy(s->d_host_off, s->host_off.data(), sizeof(int64_t) * (npatch + 1), hipMemcpyHostToDevice),
                 "hipMemcpy");
   if (e) return e;

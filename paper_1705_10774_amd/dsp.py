@@ -52,6 +52,13 @@ def load():
     global _lib
     if _lib is not None:
         return _lib
+    # One HIP runtime per process: torch ships its own libamdhip64.so.7; when it
+    # is imported first, the dynamic loader binds libdsp.so to that copy (same
+    # soname) instead of loading a second runtime from /opt/rocm.
+    try:
+        import torch  # noqa: F401
+    except Exception:  # pragma: no cover - torch absent: system runtime
+        pass
     if not os.path.exists(LIB_PATH):
         from .csrc import build as _b
         _b.build()

@@ -22,17 +22,25 @@ def _dsp():
     return dsp
 
 
-def rel_l1(Ug, Uo, patches):
-    """max over the 8 variables of |dU|_1 / |U|_1."""
+NAMES = ["rho", "mx", "my", "mz", "E", "Bx", "By", "Bz"]
+
+
+def rel_l1(Ug, Uo, patches, floor=1e-4, verbose=True):
+    """max over the 8 variables of |dU|_1 / max(|U|_1, floor * count).  The
+    floor (a signal of `floor` per value) keeps variables that are zero up to
+    rounding noise (e.g. m_z and B_z of a y-polarised wave) from comparing
+    two noise fields."""
     worst = 0.0
     Vg, Vo = I.patch_views(Ug, patches), I.patch_views(Uo, patches)
+    per = []
     for v in range(8):
         num = sum(np.abs(a[v] - b[v]).sum() for a, b in zip(Vg, Vo))
-        den = sum(np.abs(b[v]).sum() for b in Vo)
-        if den > 0:
-            worst = max(worst, num / den)
-        else:
-            worst = max(worst, num)
+        cnt = sum(b[v].size for b in Vo)
+        den = max(sum(np.abs(b[v]).sum() for b in Vo), floor * cnt)
+        per.append(num / den)
+        worst = max(worst, num / den)
+    if verbose:
+        print("rel L1 per variable:", " ".join(f"{n}={e:.2e}" for n, e in zip(NAMES, per)))
     return worst
 
 
@@ -84,14 +92,19 @@ def test_cfg1_alfven_fp64_full(orc):
     pr = I.cfg1_alfven()
     Ug, sg, kg, stg = gpu_run(pr)
     Uo, so, ko, sto = orc_run(orc, pr)
+    err = rel_l1(Ug, Uo, pr.patches)
+    # the wave itself (vy and By are pure perturbation): relative to their size
+    Vg, Vo = I.patch_views(Ug, pr.patches), I.patch_views(Uo, pr.patches)
+    pert = []
+    for v in (2, 6):
+        num = sum(np.abs(a[v] - b[v]).sum() for a, b in zip(Vg, Vo))
+        den = sum(np.abs(b[v]).sum() for b in Vo)
+        pert.append(num / den)
+    print("perturbation-relative L1 (my, By):", pert, "steps", stg[13], sto[13])
     assert stg[13] == sto[13] > 250  # same number of global steps
     assert np.array_equal(sg, so) and np.array_equal(kg, ko)
-    assert rel_l1(Ug, Uo, pr.patches) <= 1e-10
-    # the wave itself (By is pure perturbation): relative to its own size
-    Vg, Vo = I.patch_views(Ug, pr.patches), I.patch_views(Uo, pr.patches)
-    num = sum(np.abs(a[6] - b[6]).sum() for a, b in zip(Vg, Vo))
-    den = sum(np.abs(b[6]).sum() for b in Vo)
-    assert num / den <= 1e-8
+    assert err <= 1e-10
+    assert max(pert) <= 1e-8
     assert stg[9] <= 1e-13 * 16  # div B at rounding (per unit length, |B| ~ 1)
 
 
