@@ -84,6 +84,12 @@ template <class T>
 void launch_update(const DevSet& S, const int* list, int count, int nmax, T* slots, const WorkPtr<T>& W,
                    const StepPtr& st, hipStream_t s, int dt_kind, double t_end, int clip,
                    hipEvent_t ev0, hipEvent_t ev1);
+template <class T>
+void launch_fused(const DevSet& S, const int* list, int count, int nmax, T* slots, double* smax,
+                  const StepPtr& st, hipStream_t s, int dt_kind, double t_end, int clip, hipEvent_t ev0,
+                  hipEvent_t ev1);
+void launch_dt(const DevSet& S, const int* list, int count, const StepPtr& st, const double* smax, hipStream_t s,
+               int dt_kind, double t_end, int clip);
 void launch_publish(const DevSet& S, const int* list, int count, const StepPtr& st, hipStream_t s);
 void launch_scan(const DevSet& S, int64_t T_end, int* list, int* counters, hipStream_t s);
 template <class T> void launch_stats(const DevSet& S, const T* slots, double* out, hipStream_t s);

@@ -1,0 +1,573 @@
+// dsp_fused.hip -- fused patch update for gfx950.
+//
+// One round of the dispatcher (Sec. 3B) updates every ready patch with two
+// kernels:
+//   k_courant   the Courant rate of each patch over its interior and the two
+//               guard layers the stencil reads, guard values fetched on the
+//               fly (time interpolation, resampling), wavefront + workgroup
+//               maxima; pressure-floor and error accounting;
+//   k_step      the whole MUSCL-Hancock + HLLD + constrained-transport step of
+//               one patch tile, fused: the workgroup owns a tile of at most
+//               16 x 16 columns (plus a 2-cell halo) and marches through the
+//               patch along z.  Each (x, y) column is one thread; a plane of
+//               primitives, half-step states, interface fluxes and edge EMFs
+//               lives in LDS, the three planes of primitives the z-slopes need
+//               and the carried z-face state live in registers.  Guard values
+//               are read straight from the neighbours' ring slots, so nothing
+//               but the new slice is written to HBM.
+// Tiles of one patch are given workgroup ids that are equal modulo 8, so they
+// run on the same XCD and share its L2 for the halo and guard reads.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dsp_dev.h"
+#include "dsp_guard.h"
+#include "mhd_dev.h"
+
+namespace dsp {
+
+constexpr int MT = 16;                   // largest tile edge (output cells)
+constexpr int MCX = MT + 4;              // columns per edge incl. 2-cell halo
+constexpr int MCOL = MCX * MCX;          // 400 column threads at most
+constexpr int MPX = MT + 2;              // predictor cells per edge
+constexpr int MPRED = MPX * MPX;         // 324
+constexpr int MXF = (MT + 1) * (MT + 2); // x-faces (or y-faces) per plane: 306
+constexpr int NTHR = 512;
+constexpr int MAXBOX = 256;              // guard boxes per patch (checked on the host)
+
+template <class T> struct StepSmem {
+  // region A: primitives of plane z (load -> predictor), then the plane's
+  // x- and y-face fluxes (fluxes -> edges -> updates)
+  union A {
+    T w[8][MCOL];
+    struct {
+      T fx[8][MXF];
+      T fy[8][MXF];
+    } f;
+  } a;
+  // region B: half-step state, slopes and normal-field increments
+  // (predictor -> fluxes), then the edge EMFs (edges -> updates)
+  union B {
+    struct {
+      T h[8][MPRED];
+      T sx[8][MPRED];
+      T sy[8][MPRED];
+      T db[2][MPRED];
+    } p;
+    struct {
+      T ez[(MT + 1) * (MT + 1)];
+      T ex[MT * (MT + 1)];
+      T ey[(MT + 1) * MT];
+    } e;
+  } b;
+  T bf[2][MCOL];        // Bx on the low x-face and By on the low y-face of each column (t^n)
+  T px[2][MXF];         // previous plane: x-face mass flux and Bz induction flux
+  T py[2][MXF];         // previous plane: y-face mass flux and Bz induction flux
+  T fz[3][MPRED];       // z-face fluxes of the current face: mass, Bx and By induction
+  T ecc[2][3][MPRED];   // cell-centred EMF -v x B of the half-step state, two planes
+  Bracket br[MAXBOX];   // time brackets of this patch's guard boxes
+};
+
+// primitives of one cell from guard-filled values
+template <class T>
+__device__ __forceinline__ void prim_of(T rho, T m0, T m1, T m2, T en, T bx, T by, T bz, T gamma,
+                                        T pfloor, T* w) {
+  const T ir = T(1) / rho;
+  w[0] = rho;
+  w[1] = m0 * ir;
+  w[2] = m1 * ir;
+  w[3] = m2 * ir;
+  T p = (gamma - T(1)) * (en - T(0.5) * (m0 * m0 + m1 * m1 + m2 * m2) * ir - T(0.5) * (bx * bx + by * by + bz * bz));
+  if (pfloor > T(0) && p < pfloor) p = pfloor;
+  w[4] = p;
+  w[5] = bx;
+  w[6] = by;
+  w[7] = bz;
+}
+
+struct PatchCtx {
+  int p, n, box0;
+  int64_t own, out;
+};
+
+template <class T>
+__device__ __forceinline__ T fetch(const DevSet& S, const T* slots, const PatchCtx& c, const Bracket* br,
+                                   int comp, int var, int i, int j, int k) {
+  return fetch_elem(S, slots, c.p, c.n, c.own, c.box0, br, comp, var, i, j, k);
+}
+
+// guard-filled primitives of cell (i, j, k); the fields on its three low
+// faces are returned too (outputs are written last, so they may alias)
+template <class T>
+__device__ void load_cell(const DevSet& S, const T* slots, const PatchCtx& c, const Bracket* br, int i, int j,
+                          int k, T gamma, T pfloor, T* w, T& bxl, T& byl, T& bzl) {
+  const T rho = fetch(S, slots, c, br, -1, 0, i, j, k);
+  const T m0 = fetch(S, slots, c, br, -1, 1, i, j, k);
+  const T m1 = fetch(S, slots, c, br, -1, 2, i, j, k);
+  const T m2 = fetch(S, slots, c, br, -1, 3, i, j, k);
+  const T en = fetch(S, slots, c, br, -1, 4, i, j, k);
+  const T xl = fetch(S, slots, c, br, 0, 0, i, j, k);
+  const T xr = fetch(S, slots, c, br, 0, 0, i + 1, j, k);
+  const T yl = fetch(S, slots, c, br, 1, 0, i, j, k);
+  const T yr = fetch(S, slots, c, br, 1, 0, i, j + 1, k);
+  const T zl = fetch(S, slots, c, br, 2, 0, i, j, k);
+  const T zr = fetch(S, slots, c, br, 2, 0, i, j, k + 1);
+  prim_of(rho, m0, m1, m2, en, T(0.5) * (xl + xr), T(0.5) * (yl + yr), T(0.5) * (zl + zr), gamma, pfloor, w);
+  bxl = xl;
+  byl = yl;
+  bzl = zl;
+}
+
+// ---------------------------------------------------------------------------
+// Courant rate and pressure accounting over the padded cells [-2, n+1]^3
+
+template <class T>
+__global__ __launch_bounds__(256) void k_courant(DevSet S, const int* __restrict__ list, int count,
+                                                 const T* __restrict__ slots, double* __restrict__ smax) {
+  __shared__ Bracket br[MAXBOX];
+  const int b = blockIdx.y;
+  if (b >= count) return;
+  PatchCtx c;
+  c.p = list[b];
+  c.n = S.n[c.p];
+  c.box0 = S.rbox_off[c.p * 108];
+  const int nbox = S.rbox_off[c.p * 108 + 108] - c.box0;
+  c.own = S.slot_off[c.p] + (int64_t)S.cur[c.p] * S.slice_len[c.p];
+  c.out = 0;
+  for (int m = threadIdx.x; m < nbox; m += blockDim.x)
+    br[m] = bracket(S, S.boxes[c.box0 + m].q, S.ticks[c.p], S.tcur[c.p]);
+  __syncthreads();
+  const int N = c.n + 4;
+  const int64_t cid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double s = 0.0;
+  if (cid < (int64_t)N * N * N) {
+    const int i = (int)(cid % N) - 2, j = (int)((cid / N) % N) - 2, k = (int)(cid / ((int64_t)N * N)) - 2;
+    T w[8], bxl, byl, bzl;
+    load_cell(S, slots, c, br, i, j, k, T(S.gamma), T(0), w, bxl, byl, bzl);
+    T pr = w[4];
+    if (!isfinite(w[0]) || !isfinite(pr)) {
+      atomicOr(S.err, ERR_NONFINITE);
+    } else if (!(w[0] > T(0))) {
+      atomicOr(S.err, ERR_NEGATIVE);
+    } else {
+      if (S.p_floor > 0.0) {
+        if (pr < T(S.p_floor)) {
+          pr = T(S.p_floor);
+          atomicAdd(S.floor_hits, 1ULL);
+        }
+      } else if (!(pr > T(0))) {
+        atomicOr(S.err, ERR_NEGATIVE);
+      }
+      if (pr > T(0)) {
+        const T ir = T(1) / w[0];
+        const T a2 = T(S.gamma) * pr * ir;
+        const T bb = (w[5] * w[5] + w[6] * w[6] + w[7] * w[7]) * ir;
+        T sum = fabs(w[1]) + fast_speed(a2, bb, (w[6] * w[6] + w[7] * w[7]) * ir);
+        sum = sum + (fabs(w[2]) + fast_speed(a2, bb, (w[7] * w[7] + w[5] * w[5]) * ir));
+        sum = sum + (fabs(w[3]) + fast_speed(a2, bb, (w[5] * w[5] + w[6] * w[6]) * ir));
+        s = (double)sum / S.dx[c.p];
+        if (!isfinite(s)) atomicOr(S.err, ERR_NONFINITE);
+      }
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_xor(s, off, 64);
+    s = o > s ? o : s;
+  }
+  __shared__ double wmax[4];
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) m = wmax[q] > m ? wmax[q] : m;
+    if (m > 0.0) atomicMax((unsigned long long*)(smax + b), (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// the fused step
+
+// x-face flux of plane z with face index f (left cell f-1) and row j, from the
+// predictor buffers; rotated order (rho, un, ut1, ut2, p, bt1, bt2)
+template <class T>
+__device__ __forceinline__ void face_states(const StepSmem<T>& sm, int d, int pa, int pb, T* l, T* r) {
+  const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+  const T(*sl)[MPRED] = (d == 0) ? sm.b.p.sx : sm.b.p.sy;
+  const int ord[7] = {0, 1 + d, 1 + t1, 1 + t2, 4, 5 + t1, 5 + t2};
+#pragma unroll
+  for (int m = 0; m < 7; ++m) {
+    const int v = ord[m];
+    l[m] = sm.b.p.h[v][pa] + T(0.5) * sl[v][pa];
+    r[m] = sm.b.p.h[v][pb] - T(0.5) * sl[v][pb];
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__ list, int count,
+                                               T* __restrict__ slots, StepPtr st, int tpa) {
+  __shared__ StepSmem<T> sm;
+  const int tid = threadIdx.x;
+  const int T2 = tpa * tpa;  // tile slots per patch
+  const int w = blockIdx.x;
+  const int bidx = (w / (8 * T2)) * 8 + (w % 8);
+  const int tile = (w / 8) % T2;
+  if (bidx >= count) return;
+  PatchCtx c;
+  c.p = list[bidx];
+  const int n = c.n = S.n[c.p];
+  const int nt = (n + MT - 1) / MT;
+  const int tx = tile % tpa, ty = tile / tpa;
+  if (tx >= nt || ty >= nt) return;
+  const int x0 = tx * n / nt, x1 = (tx + 1) * n / nt;
+  const int y0 = ty * n / nt, y1 = (ty + 1) * n / nt;
+  const int TX = x1 - x0, TY = y1 - y0;
+  const int CX = TX + 4, CY = TY + 4, PX = TX + 2;
+  const bool lastx = (x1 == n), lasty = (y1 == n), firstx = (x0 == 0), firsty = (y0 == 0);
+  c.box0 = S.rbox_off[c.p * 108];
+  const int nbox = S.rbox_off[c.p * 108 + 108] - c.box0;
+  const int64_t V = S.slice_len[c.p];
+  c.own = S.slot_off[c.p] + (int64_t)S.cur[c.p] * V;
+  c.out = S.slot_off[c.p] + (int64_t)((S.cur[c.p] + 1) % S.nslots) * V;
+  for (int m = tid; m < nbox; m += NTHR) sm.br[m] = bracket(S, S.boxes[c.box0 + m].q, S.ticks[c.p], S.tcur[c.p]);
+  const T gamma = T(S.gamma), pfloor = T(S.p_floor);
+  const T dtdx = T(st.dt[bidx] / S.dx[c.p]);
+  const T hdtdx = T(0.5) * dtdx;
+  __syncthreads();
+
+  // column of this thread
+  const bool col = tid < CX * CY;
+  const int ca = tid % CX, cb = tid / CX;
+  const int ci = x0 - 2 + ca, cj = y0 - 2 + cb;
+  const bool pred = col && ca >= 1 && ca <= CX - 2 && cb >= 1 && cb <= CY - 2;
+  const int pc = (ca - 1) + (cb - 1) * PX;  // predictor index (valid if pred)
+  const bool own_cell = col && ci >= x0 && ci < x1 && cj >= y0 && cj < y1;
+  const bool own_bx = col && cj >= y0 && cj < y1 && ((ci >= x0 && ci < x1) || (lastx && ci == n));
+  const bool own_by = col && ci >= x0 && ci < x1 && ((cj >= y0 && cj < y1) || (lasty && cj == n));
+  // halo faces are computed by several tiles; each counts only its own
+  auto own_c = [&](int v, int lo, int hi, bool first, bool last) {
+    return (v >= lo && v < hi) || (first && v < 0) || (last && v >= n);
+  };
+
+  T Wm[8], W0[8], Wp[8];
+  T bx0 = 0, by0 = 0, bz0 = 0, bxp = 0, byp = 0, bzp = 0, dummy;
+  if (col) {
+    load_cell(S, slots, c, sm.br, ci, cj, -2, gamma, pfloor, Wm, dummy, dummy, dummy);
+    load_cell(S, slots, c, sm.br, ci, cj, -1, gamma, pfloor, W0, bx0, by0, bz0);
+  }
+  T tl[7];     // top state of the previous plane's z-face (rotated z, x, y)
+  T dzl = 0;   // normal-field increment of the previous plane
+  T fzl[5], fzc[5], duxy[5], dnew[5];
+  T pbx = 0, pby = 0;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) fzl[q] = fzc[q] = duxy[q] = dnew[q] = T(0);
+#pragma unroll
+  for (int q = 0; q < 7; ++q) tl[q] = T(0);
+  const int nxf = (TX + 1) * (TY + 2), nyf = (TX + 2) * (TY + 1);
+
+  for (int z = -1; z <= n; ++z) {
+    // ---- P1: load plane z+1; publish plane z primitives and lo-face fields
+    if (col) {
+      load_cell(S, slots, c, sm.br, ci, cj, z + 1, gamma, pfloor, Wp, bxp, byp, bzp);
+#pragma unroll
+      for (int v = 0; v < 8; ++v) sm.a.w[v][tid] = W0[v];
+      sm.bf[0][tid] = bx0;
+      sm.bf[1][tid] = by0;
+    }
+    __syncthreads();
+    // ---- P2: slopes, Hancock predictor, z-face flux at face z, cell EMF
+    if (pred) {
+      T sl[3][8];
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const T c0 = W0[v];
+        sl[0][v] = van_leer(c0 - sm.a.w[v][tid - 1], sm.a.w[v][tid + 1] - c0);
+        sl[1][v] = van_leer(c0 - sm.a.w[v][tid - CX], sm.a.w[v][tid + CX] - c0);
+        sl[2][v] = van_leer(c0 - Wm[v], Wp[v] - c0);
+      }
+      sl[0][5] = T(0);
+      sl[1][6] = T(0);
+      sl[2][7] = T(0);
+      const T ir = T(1) / W0[0];
+      T sum[8];
+#pragma unroll
+      for (int v = 0; v < 8; ++v) sum[v] = T(0);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+        const T un = W0[1 + d], bn = W0[5 + d], b1 = W0[5 + t1], b2 = W0[5 + t2];
+        const T* s = sl[d];
+        sum[0] = sum[0] + (un * s[0] + W0[0] * s[1 + d]);
+        sum[1 + d] = sum[1 + d] + (un * s[1 + d] + (s[4] + b1 * s[5 + t1] + b2 * s[5 + t2]) * ir);
+        sum[1 + t1] = sum[1 + t1] + (un * s[1 + t1] - bn * s[5 + t1] * ir);
+        sum[1 + t2] = sum[1 + t2] + (un * s[1 + t2] - bn * s[5 + t2] * ir);
+        sum[4] = sum[4] + (un * s[4] + gamma * W0[4] * s[1 + d]);
+        sum[5 + t1] = sum[5 + t1] + (un * s[5 + t1] + b1 * s[1 + d] - bn * s[1 + t1]);
+        sum[5 + t2] = sum[5 + t2] + (un * s[5 + t2] + b2 * s[1 + d] - bn * s[1 + t2]);
+      }
+      T H[8];
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        H[v] = W0[v] - hdtdx * sum[v];
+        sm.b.p.h[v][pc] = H[v];
+        sm.b.p.sx[v][pc] = sl[0][v];
+        sm.b.p.sy[v][pc] = sl[1][v];
+      }
+      sm.b.p.db[0][pc] = H[5] - W0[5];
+      sm.b.p.db[1][pc] = H[6] - W0[6];
+      const T dz = H[7] - W0[7];
+      // rotated (z, x, y): rho, vz, vx, vy, p, bx, by
+      const int ord[7] = {0, 3, 1, 2, 4, 5, 6};
+      T rb[7];
+#pragma unroll
+      for (int m = 0; m < 7; ++m) rb[m] = H[ord[m]] - T(0.5) * sl[2][ord[m]];
+      if (z >= 0) {
+        T l[7], r[7];
+#pragma unroll
+        for (int m = 0; m < 7; ++m) {
+          l[m] = tl[m];
+          r[m] = rb[m];
+        }
+        T bn = bz0 + T(0.5) * (dzl + dz);
+        if (!(l[0] > T(0)) || !(l[4] > T(0)) || !(r[0] > T(0)) || !(r[4] > T(0))) {
+#pragma unroll
+          for (int m = 0; m < 7; ++m) {
+            l[m] = Wm[ord[m]];
+            r[m] = W0[ord[m]];
+          }
+          bn = bz0;
+          if (own_c(ci, x0, x1, firstx, lastx) && own_c(cj, y0, y1, firsty, lasty))
+            atomicAdd(S.fallback, 1ULL);
+        }
+        T f[7];
+        hlld_flux(l, r, bn, gamma, f);
+        // unrotated: mass, mx, my, mz, energy; induction fluxes of Bx, By
+        fzc[0] = f[0];
+        fzc[1] = f[2];
+        fzc[2] = f[3];
+        fzc[3] = f[1];
+        fzc[4] = f[4];
+        sm.fz[0][pc] = f[0];
+        sm.fz[1][pc] = f[5];
+        sm.fz[2][pc] = f[6];
+      }
+#pragma unroll
+      for (int m = 0; m < 7; ++m) tl[m] = H[ord[m]] + T(0.5) * sl[2][ord[m]];
+      dzl = dz;
+      // E = -v x B of the half-step state
+      sm.ecc[z & 1][0][pc] = H[3] * H[6] - H[2] * H[7];
+      sm.ecc[z & 1][1][pc] = H[1] * H[7] - H[3] * H[5];
+      sm.ecc[z & 1][2][pc] = H[2] * H[5] - H[1] * H[6];
+    }
+    __syncthreads();
+    // ---- P3: x- and y-face fluxes of plane z
+    for (int m = tid; m < nxf + nyf; m += NTHR) {
+      const int d = (m < nxf) ? 0 : 1;
+      int pa, pb, fa, fb, e;
+      T bface;
+      int cix, cjx;  // cell (i, j) right/upper of the face
+      if (d == 0) {
+        e = m;
+        const int fl = e % (TX + 1), jr = e / (TX + 1);
+        pa = fl + jr * PX;
+        pb = pa + 1;
+        cix = x0 + fl;
+        cjx = y0 - 1 + jr;
+        fa = (cix - (x0 - 2)) + (cjx - (y0 - 2)) * CX;
+        fb = fa;
+        bface = sm.bf[0][fa];
+      } else {
+        e = m - nxf;
+        const int ir = e % (TX + 2), gl = e / (TX + 2);
+        pa = ir + gl * PX;
+        pb = pa + PX;
+        cix = x0 - 1 + ir;
+        cjx = y0 + gl;
+        fa = (cix - (x0 - 2)) + (cjx - (y0 - 2)) * CX;
+        fb = fa;
+        bface = sm.bf[1][fa];
+      }
+      (void)fb;
+      T l[7], r[7];
+      face_states(sm, d, pa, pb, l, r);
+      T bn = bface + T(0.5) * (sm.b.p.db[d][pa] + sm.b.p.db[d][pb]);
+      if (!(l[0] > T(0)) || !(l[4] > T(0)) || !(r[0] > T(0)) || !(r[4] > T(0))) {
+        // first-order fallback: primitives of the two cells at t^n
+        T wa[8], wb[8], dmy;
+        if (d == 0) {
+          load_cell(S, slots, c, sm.br, cix - 1, cjx, z, gamma, pfloor, wa, dmy, dmy, dmy);
+          load_cell(S, slots, c, sm.br, cix, cjx, z, gamma, pfloor, wb, dmy, dmy, dmy);
+        } else {
+          load_cell(S, slots, c, sm.br, cix, cjx - 1, z, gamma, pfloor, wa, dmy, dmy, dmy);
+          load_cell(S, slots, c, sm.br, cix, cjx, z, gamma, pfloor, wb, dmy, dmy, dmy);
+        }
+        const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+        const int ord[7] = {0, 1 + d, 1 + t1, 1 + t2, 4, 5 + t1, 5 + t2};
+        for (int q = 0; q < 7; ++q) {
+          l[q] = wa[ord[q]];
+          r[q] = wb[ord[q]];
+        }
+        bn = bface;
+        const bool owned = (d == 0) ? (own_c(cix, x0, x1, firstx, false) || (lastx && cix == n)) &&
+                                          own_c(cjx, y0, y1, firsty, lasty)
+                                    : own_c(cix, x0, x1, firstx, lastx) &&
+                                          (own_c(cjx, y0, y1, firsty, false) || (lasty && cjx == n));
+        if (owned) atomicAdd(S.fallback, 1ULL);
+      }
+      T f[7];
+      hlld_flux(l, r, bn, gamma, f);
+      T(*F)[MXF] = (d == 0) ? sm.a.f.fx : sm.a.f.fy;
+      const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+      F[0][e] = f[0];
+      F[1 + d][e] = f[1];
+      F[1 + t1][e] = f[2];
+      F[1 + t2][e] = f[3];
+      F[4][e] = f[4];
+      F[5 + d][e] = T(0);
+      F[5 + t1][e] = f[5];
+      F[5 + t2][e] = f[6];
+    }
+    __syncthreads();
+    // ---- P4: edge EMFs (upwinded by the mass-flux sign) and x/y flux sums
+    {
+      auto up = [](T mflux, T a, T b) -> T {
+        if (mflux > T(0)) return a;
+        if (mflux < T(0)) return b;
+        return T(0.5) * (a + b);
+      };
+      auto edge = [&](T A, T B, T C, T D, T mA, T mB, T mC, T mD, T c00, T c10, T c01, T c11) -> T {
+        const T dc14 = up(mA, c01 - D, c11 - C);
+        const T dc34 = up(mB, D - c00, C - c10);
+        const T db14 = up(mC, c10 - B, c11 - A);
+        const T db34 = up(mD, B - c00, A - c01);
+        return T(0.25) * (A + B + C + D) + T(0.25) * ((dc34 - dc14) + (db34 - db14));
+      };
+      const int pz = z & 1, pzm = (z - 1) & 1;
+      auto P = [&](int i, int j) { return (i - (x0 - 1)) + (j - (y0 - 1)) * PX; };
+      auto XF = [&](int f, int j) { return (f - x0) + (j - (y0 - 1)) * (TX + 1); };
+      auto YF = [&](int i, int g) { return (i - (x0 - 1)) + (g - y0) * (TX + 2); };
+      const int nez = (z >= 0 && z < n) ? (TX + 1) * (TY + 1) : 0;
+      const int nex = (z >= 0) ? TX * (TY + 1) : 0;
+      const int ney = (z >= 0) ? (TX + 1) * TY : 0;
+      for (int m = tid; m < nez + nex + ney; m += NTHR) {
+        if (m < nez) {  // E_z in plane z at (x-face f, y-face g)
+          const int f = x0 + m % (TX + 1), g = y0 + m / (TX + 1);
+          const T A = -sm.a.f.fx[6][XF(f, g)], B = -sm.a.f.fx[6][XF(f, g - 1)];
+          const T C = sm.a.f.fy[5][YF(f, g)], D = sm.a.f.fy[5][YF(f - 1, g)];
+          const T v = edge(A, B, C, D, sm.a.f.fx[0][XF(f, g)], sm.a.f.fx[0][XF(f, g - 1)],
+                           sm.a.f.fy[0][YF(f, g)], sm.a.f.fy[0][YF(f - 1, g)], sm.ecc[pz][2][P(f - 1, g - 1)],
+                           sm.ecc[pz][2][P(f, g - 1)], sm.ecc[pz][2][P(f - 1, g)], sm.ecc[pz][2][P(f, g)]);
+          sm.b.e.ez[m] = v;
+        } else if (m < nez + nex) {  // E_x at z-face z, (x-cell i, y-face g)
+          const int e = m - nez;
+          const int i = x0 + e % TX, g = y0 + e / TX;
+          const T A = -sm.a.f.fy[7][YF(i, g)], B = -sm.py[1][YF(i, g)];
+          const T C = sm.fz[2][P(i, g)], D = sm.fz[2][P(i, g - 1)];
+          const T v = edge(A, B, C, D, sm.a.f.fy[0][YF(i, g)], sm.py[0][YF(i, g)], sm.fz[0][P(i, g)],
+                           sm.fz[0][P(i, g - 1)], sm.ecc[pzm][0][P(i, g - 1)], sm.ecc[pzm][0][P(i, g)],
+                           sm.ecc[pz][0][P(i, g - 1)], sm.ecc[pz][0][P(i, g)]);
+          sm.b.e.ex[e] = v;
+        } else {  // E_y at z-face z, (x-face f, y-cell j)
+          const int e = m - nez - nex;
+          const int f = x0 + e % (TX + 1), j = y0 + e / (TX + 1);
+          const T A = -sm.fz[1][P(f, j)], B = -sm.fz[1][P(f - 1, j)];
+          const T C = sm.a.f.fx[7][XF(f, j)], D = sm.px[1][XF(f, j)];
+          const T v = edge(A, B, C, D, sm.fz[0][P(f, j)], sm.fz[0][P(f - 1, j)], sm.a.f.fx[0][XF(f, j)],
+                           sm.px[0][XF(f, j)], sm.ecc[pzm][1][P(f - 1, j)], sm.ecc[pz][1][P(f - 1, j)],
+                           sm.ecc[pzm][1][P(f, j)], sm.ecc[pz][1][P(f, j)]);
+          sm.b.e.ey[e] = v;
+        }
+      }
+      if (own_cell && z >= 0 && z < n) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q)
+          dnew[q] = (sm.a.f.fx[q][XF(ci + 1, cj)] - sm.a.f.fx[q][XF(ci, cj)]) +
+                    (sm.a.f.fy[q][YF(ci, cj + 1)] - sm.a.f.fy[q][YF(ci, cj)]);
+      }
+    }
+    __syncthreads();
+    // ---- P5: write plane z-1 (cells, Bx, By) and face z (Bz); carry partials
+    {
+      const int n3 = n * n * n;
+      (void)n3;
+      auto EZ = [&](int f, int g) { return sm.b.e.ez[(f - x0) + (g - y0) * (TX + 1)]; };
+      auto EX = [&](int i, int g) { return sm.b.e.ex[(i - x0) + (g - y0) * TX]; };
+      auto EY = [&](int f, int j) { return sm.b.e.ey[(f - x0) + (j - y0) * (TX + 1)]; };
+      if (z >= 1) {
+        const int zc = z - 1;
+        if (own_cell) {
+#pragma unroll
+          for (int q = 0; q < 5; ++q) {
+            const T du = duxy[q] + (fzc[q] - fzl[q]);
+            const int64_t e = scell(n, q, ci, cj, zc);
+            slots[c.out + e] = slots[c.own + e] - dtdx * du;
+          }
+        }
+        if (own_bx) {
+          const int64_t e = sface(n, 0, ci, cj, zc);
+          slots[c.out + e] = slots[c.own + e] - dtdx * (pbx - EY(ci, cj));
+        }
+        if (own_by) {
+          const int64_t e = sface(n, 1, ci, cj, zc);
+          slots[c.out + e] = slots[c.own + e] - dtdx * (pby + EX(ci, cj));
+        }
+      }
+      if (z >= 0 && z < n) {
+        if (own_bx) pbx = (EZ(ci, cj + 1) - EZ(ci, cj)) + EY(ci, cj);
+        if (own_by) pby = -EX(ci, cj) - (EZ(ci + 1, cj) - EZ(ci, cj));
+      }
+      if (z >= 0 && own_cell) {
+        const T curl = (EY(ci + 1, cj) - EY(ci, cj)) - (EX(ci, cj + 1) - EX(ci, cj));
+        const int64_t e = sface(n, 2, ci, cj, z);
+        slots[c.out + e] = slots[c.own + e] - dtdx * curl;
+      }
+      for (int m = tid; m < nxf; m += NTHR) {
+        sm.px[0][m] = sm.a.f.fx[0][m];
+        sm.px[1][m] = sm.a.f.fx[7][m];
+      }
+      for (int m = tid; m < nyf; m += NTHR) {
+        sm.py[0][m] = sm.a.f.fy[0][m];
+        sm.py[1][m] = sm.a.f.fy[7][m];
+      }
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        duxy[q] = dnew[q];
+        fzl[q] = fzc[q];
+      }
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        Wm[v] = W0[v];
+        W0[v] = Wp[v];
+      }
+      bx0 = bxp;
+      by0 = byp;
+      bz0 = bzp;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+
+template <class T>
+void launch_fused(const DevSet& S, const int* list, int count, int nmax, T* slots, double* smax,
+                  const StepPtr& st, hipStream_t s, int dt_kind, double t_end, int clip, hipEvent_t ev0,
+                  hipEvent_t ev1) {
+  const int N = nmax + 4;
+  (void)hipMemsetAsync(smax, 0, sizeof(double) * count, s);
+  hipLaunchKernelGGL(k_courant<T>, dim3((unsigned)(((int64_t)N * N * N + 255) / 256), count), dim3(256), 0, s, S,
+                     list, count, (const T*)slots, smax);
+  launch_dt(S, list, count, st, smax, s, dt_kind, t_end, clip);
+  const int tpa = (nmax + MT - 1) / MT;
+  const int T2 = tpa * tpa;
+  const int groups = ((count + 7) / 8) * 8 * T2;
+  if (ev0) (void)hipEventRecord(ev0, s);
+  hipLaunchKernelGGL(k_step<T>, dim3(groups), dim3(NTHR), 0, s, S, list, count, slots, st, tpa);
+  if (ev1) (void)hipEventRecord(ev1, s);
+}
+
+template void launch_fused<float>(const DevSet&, const int*, int, int, float*, double*, const StepPtr&, hipStream_t,
+                                  int, double, int, hipEvent_t, hipEvent_t);
+template void launch_fused<double>(const DevSet&, const int*, int, int, double*, double*, const StepPtr&,
+                                   hipStream_t, int, double, int, hipEvent_t, hipEvent_t);
+
+}  // namespace dsp

@@ -23,217 +23,10 @@
 #include <stdint.h>
 
 #include "dsp_dev.h"
+#include "dsp_guard.h"
 #include "mhd_dev.h"
 
 namespace dsp {
-
-// ---------------------------------------------------------------------------
-// small helpers
-
-__device__ __forceinline__ int64_t pcell(int N, int v, int i, int j, int k) {
-  return (int64_t)v * N * N * N + ((int64_t)(k + 2) * N + (j + 2)) * N + (i + 2);
-}
-// padded face array of component d inside the padded patch buffer
-__device__ __forceinline__ int64_t pface(int N, int d, int i, int j, int k) {
-  const int sx = N + (d == 0), sy = N + (d == 1);
-  return 5LL * N * N * N + (int64_t)d * N * N * (N + 1) + ((int64_t)(k + 2) * sy + (j + 2)) * sx + (i + 2);
-}
-// slice (interior) layout
-__device__ __forceinline__ int64_t scell(int n, int v, int i, int j, int k) {
-  return (int64_t)v * n * n * n + ((int64_t)k * n + j) * n + i;
-}
-__device__ __forceinline__ int64_t sface(int n, int d, int i, int j, int k) {
-  const int sx = n + (d == 0), sy = n + (d == 1);
-  return 5LL * n * n * n + (int64_t)d * n * n * (n + 1) + ((int64_t)k * sy + j) * sx + i;
-}
-// work arrays indexed by padded cell coordinates [-2, n+1]^3 (stride N^3 per
-// component) and face/edge arrays over [-2, n+2]^3 (stride (N+1)^3)
-__device__ __forceinline__ int64_t wcell(int N, int v, int i, int j, int k) {
-  return (int64_t)v * N * N * N + ((int64_t)(k + 2) * N + (j + 2)) * N + (i + 2);
-}
-__device__ __forceinline__ int64_t wface(int N, int v, int i, int j, int k) {
-  const int M = N + 1;
-  return (int64_t)v * M * M * M + ((int64_t)(k + 2) * M + (j + 2)) * M + (i + 2);
-}
-
-// ordered bit patterns of non-negative floating-point numbers
-__device__ __forceinline__ void atomic_max_pos(double* a, double v) {
-  atomicMax((unsigned long long*)a, (unsigned long long)__double_as_longlong(v));
-}
-
-// time-slice bracket of patch q for time (tk, tt): exact slice or a < t < b
-struct Bracket {
-  int64_t oa, ob;  // element offsets of the two slices
-  double w;        // weight of b (0 for an exact copy)
-};
-__device__ Bracket bracket(const DevSet& S, int q, int64_t tk, double tt) {
-  Bracket br;
-  const int ns = S.nslots;
-  int ia = -1, ib = -1, ie = -1;
-  for (int s = 0; s < ns; ++s) {
-    const int64_t e = (int64_t)q * ns + s;
-    if (!S.svalid[e]) continue;
-    const bool eq = S.exact_time ? (S.stime[e] == tt) : (S.sticks[e] == tk);
-    if (eq) ie = s;
-    if (S.exact_time) {
-      if (S.stime[e] < tt && (ia < 0 || S.stime[e] > S.stime[(int64_t)q * ns + ia])) ia = s;
-      if (S.stime[e] > tt && (ib < 0 || S.stime[e] < S.stime[(int64_t)q * ns + ib])) ib = s;
-    } else {
-      if (S.sticks[e] < tk && (ia < 0 || S.sticks[e] > S.sticks[(int64_t)q * ns + ia])) ia = s;
-      if (S.sticks[e] > tk && (ib < 0 || S.sticks[e] < S.sticks[(int64_t)q * ns + ib])) ib = s;
-    }
-  }
-  const int64_t base = S.slot_off[q];
-  const int64_t V = S.slice_len[q];
-  if (ie >= 0) {
-    br.oa = br.ob = base + ie * V;
-    br.w = 0.0;
-    return br;
-  }
-  if (ia < 0 || ib < 0) {
-    atomicOr(S.err, ERR_STATE);
-    br.oa = br.ob = base;
-    br.w = 0.0;
-    return br;
-  }
-  br.oa = base + ia * V;
-  br.ob = base + ib * V;
-  const int64_t e_a = (int64_t)q * ns + ia, e_b = (int64_t)q * ns + ib;
-  if (S.exact_time)
-    br.w = (tt - S.stime[e_a]) / (S.stime[e_b] - S.stime[e_a]);
-  else
-    br.w = (double)(tk - S.sticks[e_a]) / (double)(S.sticks[e_b] - S.sticks[e_a]);
-  return br;
-}
-
-template <class T>
-__device__ __forceinline__ T tlerp(const T* slots, const Bracket& br, int64_t e) {
-  const T a = slots[br.oa + e];
-  if (br.oa == br.ob) return a;
-  const T b = slots[br.ob + e];
-  return a + (T)br.w * (b - a);
-}
-
-// Cross-resolution guard value: mean over the target box of the source's
-// piecewise-linear, minmod-limited reconstruction (source-interior slopes,
-// one-sided in the source's edge cells).  comp < 0: cell variable var over
-// the target cell [X - h, X + h] per axis; comp = d: face field d over the
-// target face (the source field is linear along d between its faces).
-template <class T>
-__device__ T cross_value(const DevSet& S, const T* slots, const Bracket& br, int q, int comp,
-                         int var, const int64_t* X, int64_t tdx) {
-  const int n = S.n[q];
-  const int64_t sdx = S.dxl[q];
-  const int64_t* lo = S.lo + 3 * q;
-  const int64_t len = S.len[q];
-  int64_t a[3], b[3];
-  for (int d = 0; d < 3; ++d) {
-    int64_t A = (d == comp) ? X[d] : X[d] - tdx / 2;
-    int64_t B = (d == comp) ? X[d] : X[d] + tdx / 2;
-    A -= lo[d];
-    B -= lo[d];
-    a[d] = A < 0 ? 0 : (A > len ? len : A);
-    b[d] = B < 0 ? 0 : (B > len ? len : B);
-  }
-  auto get = [&](int i, int j, int k) -> T {
-    const int64_t e = (comp < 0) ? scell(n, var, i, j, k) : sface(n, comp, i, j, k);
-    return tlerp(slots, br, e);
-  };
-  auto minmod = [](T x, T y) -> T {
-    if (x * y <= T(0)) return T(0);
-    return (fabs(x) < fabs(y)) ? x : y;
-  };
-  // slope of the (cell or face) sample at idx along axis d, in source cells
-  auto slope = [&](int* idx, int d, int hi, T v0) -> T {
-    const int c = idx[d];
-    T s = T(0);
-    if (c - 1 >= 0 && c + 1 <= hi) {
-      idx[d] = c - 1; T vm = get(idx[0], idx[1], idx[2]);
-      idx[d] = c + 1; T vp = get(idx[0], idx[1], idx[2]);
-      s = minmod(v0 - vm, vp - v0);
-    } else if (c + 1 <= hi) {
-      idx[d] = c + 1; s = get(idx[0], idx[1], idx[2]) - v0;
-    } else if (c - 1 >= 0) {
-      idx[d] = c - 1; s = v0 - get(idx[0], idx[1], idx[2]);
-    }
-    idx[d] = c;
-    return s;
-  };
-  if (comp < 0) {
-    int i0[3], i1[3];
-    for (int d = 0; d < 3; ++d) {
-      i0[d] = (int)(a[d] / sdx);
-      i1[d] = (int)((b[d] - 1) / sdx);
-      i0[d] = i0[d] < 0 ? 0 : (i0[d] > n - 1 ? n - 1 : i0[d]);
-      i1[d] = i1[d] < 0 ? 0 : (i1[d] > n - 1 ? n - 1 : i1[d]);
-    }
-    T acc = T(0);
-    double vol = 0.0;
-    for (int k = i0[2]; k <= i1[2]; ++k)
-      for (int j = i0[1]; j <= i1[1]; ++j)
-        for (int i = i0[0]; i <= i1[0]; ++i) {
-          int ci[3] = {i, j, k};
-          double ov = 1.0, off[3];
-          for (int d = 0; d < 3; ++d) {
-            int64_t x0 = a[d] > (int64_t)ci[d] * sdx ? a[d] : (int64_t)ci[d] * sdx;
-            int64_t x1 = b[d] < (int64_t)(ci[d] + 1) * sdx ? b[d] : (int64_t)(ci[d] + 1) * sdx;
-            ov *= (double)(x1 - x0);
-            off[d] = (0.5 * (double)(x0 + x1) - ((double)ci[d] + 0.5) * (double)sdx) / (double)sdx;
-          }
-          if (ov <= 0.0) continue;
-          const T v0 = get(i, j, k);
-          T vv = v0;
-          for (int d = 0; d < 3; ++d) vv = vv + (T)off[d] * slope(ci, d, n - 1, v0);
-          acc = acc + (T)ov * vv;
-          vol += ov;
-        }
-    return acc / (T)vol;
-  }
-  // face field
-  const int d = comp, t1 = (d + 1) % 3, t2 = (d + 2) % 3;
-  int f0 = (int)(a[d] / sdx);
-  int64_t rem = a[d] - (int64_t)f0 * sdx;
-  if (f0 >= n) { f0 = n; rem = 0; }
-  const double wn = (double)rem / (double)sdx;
-  int u0 = (int)(a[t1] / sdx), u1 = (int)((b[t1] - 1) / sdx);
-  int v0_ = (int)(a[t2] / sdx), v1 = (int)((b[t2] - 1) / sdx);
-  u0 = u0 < 0 ? 0 : (u0 > n - 1 ? n - 1 : u0);
-  u1 = u1 < 0 ? 0 : (u1 > n - 1 ? n - 1 : u1);
-  v0_ = v0_ < 0 ? 0 : (v0_ > n - 1 ? n - 1 : v0_);
-  v1 = v1 < 0 ? 0 : (v1 > n - 1 ? n - 1 : v1);
-  T acc = T(0);
-  double area = 0.0;
-  for (int u = u0; u <= u1; ++u)
-    for (int v = v0_; v <= v1; ++v) {
-      const int ti[2] = {u, v};
-      const int ax[2] = {t1, t2};
-      double ov = 1.0, off[2];
-      for (int m = 0; m < 2; ++m) {
-        const int dd = ax[m];
-        int64_t x0 = a[dd] > (int64_t)ti[m] * sdx ? a[dd] : (int64_t)ti[m] * sdx;
-        int64_t x1 = b[dd] < (int64_t)(ti[m] + 1) * sdx ? b[dd] : (int64_t)(ti[m] + 1) * sdx;
-        ov *= (double)(x1 - x0);
-        off[m] = (0.5 * (double)(x0 + x1) - ((double)ti[m] + 0.5) * (double)sdx) / (double)sdx;
-      }
-      if (ov <= 0.0) continue;
-      T vv = T(0);
-      for (int side = 0; side < 2; ++side) {
-        const double ws = side == 0 ? 1.0 - wn : wn;
-        if (ws == 0.0) continue;
-        int idx[3];
-        idx[d] = f0 + side;
-        idx[t1] = u;
-        idx[t2] = v;
-        const T c0 = get(idx[0], idx[1], idx[2]);
-        T lin = c0;
-        for (int m = 0; m < 2; ++m) lin = lin + (T)off[m] * slope(idx, ax[m], n - 1, c0);
-        vv = vv + (T)ws * lin;
-      }
-      acc = acc + (T)ov * vv;
-      area += ov;
-    }
-  return acc / (T)area;
-}
 
 // ---------------------------------------------------------------------------
 // k_fill: one thread per padded element (5 N^3 cell values, then 3 face
@@ -834,10 +627,7 @@ void launch_update(const DevSet& S, const int* list, int count, int nmax, T* slo
   const int64_t fill_elems = 5LL * N * N * N + 3LL * N * N * (N + 1);
   hipLaunchKernelGGL(k_fill<T>, dim3(blocks(fill_elems), count), dim3(TPB), 0, s, S, list, count, slots, W);
   hipLaunchKernelGGL(k_prim<T>, dim3(blocks((int64_t)N * N * N), count), dim3(TPB), 0, s, S, list, count, W);
-  if (dt_kind == 0)
-    hipLaunchKernelGGL(k_dt_local, dim3((count + 255) / 256), dim3(256), 0, s, S, list, count, st, W.smax);
-  else
-    hipLaunchKernelGGL(k_dt_global, dim3(1), dim3(256), 0, s, S, list, count, st, W.smax, t_end, clip);
+  launch_dt(S, list, count, st, W.smax, s, dt_kind, t_end, clip);
   hipLaunchKernelGGL(k_pred<T>, dim3(blocks((int64_t)M * M * M), count), dim3(TPB), 0, s, S, list, count, W, st);
   if (ev0) (void)hipEventRecord(ev0, s);
   hipLaunchKernelGGL(k_flux<T>, dim3(blocks(3LL * (nmax + 1) * M * M), count), dim3(TPB), 0, s, S, list, count, W);
@@ -846,6 +636,14 @@ void launch_update(const DevSet& S, const int* list, int count, int nmax, T* slo
                      count, W);
   hipLaunchKernelGGL(k_update<T>, dim3(blocks((int64_t)nmax * nmax * nmax + 3LL * nmax * nmax * (nmax + 1)), count),
                      dim3(TPB), 0, s, S, list, count, slots, W, st);
+}
+
+void launch_dt(const DevSet& S, const int* list, int count, const StepPtr& st, const double* smax, hipStream_t s,
+               int dt_kind, double t_end, int clip) {
+  if (dt_kind == 0)
+    hipLaunchKernelGGL(k_dt_local, dim3((count + 255) / 256), dim3(256), 0, s, S, list, count, st, smax);
+  else
+    hipLaunchKernelGGL(k_dt_global, dim3(1), dim3(256), 0, s, S, list, count, st, smax, t_end, clip);
 }
 
 void launch_publish(const DevSet& S, const int* list, int count, const StepPtr& st, hipStream_t s) {

@@ -16,6 +16,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <set>
@@ -322,10 +323,19 @@ struct dsp_set {
   }
 
   // one launch sequence for list[off .. off+count)
+  bool fused = true;  // fused marching kernel (false: staged kernels)
   void update_batch(int off, int count, int dt_kind, double t_end, int clip, const int* list) {
     hipEvent_t e0 = next_event(true), e1 = next_event(false);
     ev_used++;
     StepPtr s2{st.k + off, st.dtk + off, st.dt + off};
+    if (fused) {
+      if (f32)
+        launch_fused<float>(D, list + off, count, nmax, (float*)slots, smax, s2, stream, dt_kind, t_end, clip, e0, e1);
+      else
+        launch_fused<double>(D, list + off, count, nmax, (double*)slots, smax, s2, stream, dt_kind, t_end, clip, e0,
+                             e1);
+      return;
+    }
     if (f32)
       launch_update<float>(D, list + off, count, nmax, (float*)slots, work<float>(), s2, stream, dt_kind, t_end,
                            clip, e0, e1);
@@ -485,6 +495,16 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
       for (const GBox& g : keys[k]) boxes.push_back(g);
       rbox_off.push_back((int)boxes.size());
     }
+  }
+  {
+    // the fused kernel keeps the time brackets of a patch's guard boxes in LDS
+    int maxbox = 0;
+    for (int p = 0; p < npatch; ++p) maxbox = std::max(maxbox, rbox_off[(p + 1) * 108] - rbox_off[p * 108]);
+    const char* path = getenv("DSP_PATH");
+    S->fused = !(path && std::string(path) == "staged") && maxbox <= 256;
+    if (getenv("DSP_DEBUG"))
+      fprintf(stderr, "dsp_create: %d patches, nmax %d, max guard boxes per patch %d, %s path\n", npatch,
+              S->nmax, maxbox, S->fused ? "fused" : "staged");
   }
   S->nbors.assign(npatch, std::vector<int>());
   for (int p = 0; p < npatch; ++p)
