@@ -158,6 +158,15 @@ int dsp_stats(const dsp_set* set, double out[16]);
  * summed over the last advance, and the number of its launches. */
 int dsp_kernel_time(const dsp_set* set, double* ms, int64_t* launches);
 
+/* Dominant-kernel record of the last advance (or fixed-step run):
+ *  [0] GPU time (ms, HIP events) summed over the patch-step launches
+ *  [1] number of those launches
+ *  [2] their algorithmic HBM bytes: per patch update the own slice read and
+ *      written plus every value of the two guard layers the stencil reads,
+ *      from one time slice (exact time) or two (interpolated)
+ *  [3] 1 if the fused step kernel ran (the byte count is only kept for it) */
+int dsp_kernel_stats(const dsp_set* set, double out[4]);
+
 /* Fixed-dt forward run for differentiation (all patches step together with
  * dt_fixed, nsteps steps).  U0_dev, UT_dev: device arrays in the host layout
  * and the set's precision (caller-owned).  ckpt_dev (nullable): device array of

@@ -54,6 +54,7 @@ struct DevSet {
   unsigned long long* floor_hits;
   unsigned long long* fallback;
   unsigned long long* updates;
+  unsigned long long* algo_bytes;  // algorithmic HBM bytes of the step launches
 };
 
 // Work buffers of a batch of patch slots (stride = values per slot).

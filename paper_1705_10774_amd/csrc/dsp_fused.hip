@@ -66,6 +66,7 @@ template <class T> struct StepSmem {
   T fz[3][MPRED];       // z-face fluxes of the current face: mass, Bx and By induction
   T ecc[2][3][MPRED];   // cell-centred EMF -v x B of the half-step state, two planes
   Bracket br[MAXBOX];   // time brackets of this patch's guard boxes
+  RegionTab<T> rt;      // direct addressing of single-box guard regions
 };
 
 // primitives of one cell from guard-filled values
@@ -92,26 +93,27 @@ struct PatchCtx {
 
 template <class T>
 __device__ __forceinline__ T fetch(const DevSet& S, const T* slots, const PatchCtx& c, const Bracket* br,
-                                   int comp, int var, int i, int j, int k) {
-  return fetch_elem(S, slots, c.p, c.n, c.own, c.box0, br, comp, var, i, j, k);
+                                   const RegionTab<T>& rt, int comp, int var, int i, int j, int k) {
+  return fetch_fast(S, slots, c.p, c.n, c.own, c.box0, br, rt, comp, var, i, j, k);
 }
 
 // guard-filled primitives of cell (i, j, k); the fields on its three low
 // faces are returned too (outputs are written last, so they may alias)
 template <class T>
-__device__ void load_cell(const DevSet& S, const T* slots, const PatchCtx& c, const Bracket* br, int i, int j,
-                          int k, T gamma, T pfloor, T* w, T& bxl, T& byl, T& bzl) {
-  const T rho = fetch(S, slots, c, br, -1, 0, i, j, k);
-  const T m0 = fetch(S, slots, c, br, -1, 1, i, j, k);
-  const T m1 = fetch(S, slots, c, br, -1, 2, i, j, k);
-  const T m2 = fetch(S, slots, c, br, -1, 3, i, j, k);
-  const T en = fetch(S, slots, c, br, -1, 4, i, j, k);
-  const T xl = fetch(S, slots, c, br, 0, 0, i, j, k);
-  const T xr = fetch(S, slots, c, br, 0, 0, i + 1, j, k);
-  const T yl = fetch(S, slots, c, br, 1, 0, i, j, k);
-  const T yr = fetch(S, slots, c, br, 1, 0, i, j + 1, k);
-  const T zl = fetch(S, slots, c, br, 2, 0, i, j, k);
-  const T zr = fetch(S, slots, c, br, 2, 0, i, j, k + 1);
+__device__ __forceinline__ void load_cell(const DevSet& S, const T* slots, const PatchCtx& c, const Bracket* br,
+                                          const RegionTab<T>& rt, int i, int j, int k, T gamma, T pfloor, T* w,
+                                          T& bxl, T& byl, T& bzl) {
+  const T rho = fetch(S, slots, c, br, rt, -1, 0, i, j, k);
+  const T m0 = fetch(S, slots, c, br, rt, -1, 1, i, j, k);
+  const T m1 = fetch(S, slots, c, br, rt, -1, 2, i, j, k);
+  const T m2 = fetch(S, slots, c, br, rt, -1, 3, i, j, k);
+  const T en = fetch(S, slots, c, br, rt, -1, 4, i, j, k);
+  const T xl = fetch(S, slots, c, br, rt, 0, 0, i, j, k);
+  const T xr = fetch(S, slots, c, br, rt, 0, 0, i + 1, j, k);
+  const T yl = fetch(S, slots, c, br, rt, 1, 0, i, j, k);
+  const T yr = fetch(S, slots, c, br, rt, 1, 0, i, j + 1, k);
+  const T zl = fetch(S, slots, c, br, rt, 2, 0, i, j, k);
+  const T zr = fetch(S, slots, c, br, rt, 2, 0, i, j, k + 1);
   prim_of(rho, m0, m1, m2, en, T(0.5) * (xl + xr), T(0.5) * (yl + yr), T(0.5) * (zl + zr), gamma, pfloor, w);
   bxl = xl;
   byl = yl;
@@ -125,6 +127,7 @@ template <class T>
 __global__ __launch_bounds__(256) void k_courant(DevSet S, const int* __restrict__ list, int count,
                                                  const T* __restrict__ slots, double* __restrict__ smax) {
   __shared__ Bracket br[MAXBOX];
+  __shared__ RegionTab<T> rt;
   const int b = blockIdx.y;
   if (b >= count) return;
   PatchCtx c;
@@ -136,6 +139,7 @@ __global__ __launch_bounds__(256) void k_courant(DevSet S, const int* __restrict
   c.out = 0;
   for (int m = threadIdx.x; m < nbox; m += blockDim.x)
     br[m] = bracket(S, S.boxes[c.box0 + m].q, S.ticks[c.p], S.tcur[c.p]);
+  for (int m = threadIdx.x; m < 108; m += blockDim.x) region_tab_init(S, c.p, rt, m);
   __syncthreads();
   const int N = c.n + 4;
   const int64_t cid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -143,7 +147,7 @@ __global__ __launch_bounds__(256) void k_courant(DevSet S, const int* __restrict
   if (cid < (int64_t)N * N * N) {
     const int i = (int)(cid % N) - 2, j = (int)((cid / N) % N) - 2, k = (int)(cid / ((int64_t)N * N)) - 2;
     T w[8], bxl, byl, bzl;
-    load_cell(S, slots, c, br, i, j, k, T(S.gamma), T(0), w, bxl, byl, bzl);
+    load_cell(S, slots, c, br, rt, i, j, k, T(S.gamma), T(0), w, bxl, byl, bzl);
     T pr = w[4];
     if (!isfinite(w[0]) || !isfinite(pr)) {
       atomicOr(S.err, ERR_NONFINITE);
@@ -229,7 +233,22 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
   c.own = S.slot_off[c.p] + (int64_t)S.cur[c.p] * V;
   c.out = S.slot_off[c.p] + (int64_t)((S.cur[c.p] + 1) % S.nslots) * V;
   for (int m = tid; m < nbox; m += NTHR) sm.br[m] = bracket(S, S.boxes[c.box0 + m].q, S.ticks[c.p], S.tcur[c.p]);
+  for (int m = tid; m < 108; m += NTHR) region_tab_init(S, c.p, sm.rt, m);
   const T gamma = T(S.gamma), pfloor = T(S.p_floor);
+  if (tile == 0 && tid == 0) {
+    // algorithmic traffic of this patch update: own slice read and written,
+    // every guard value of the two stencil layers read from one slice (exact
+    // time) or two (interpolated)
+    unsigned long long vals = 2ULL * (unsigned long long)V;
+    for (int m = 0; m < nbox; ++m) {
+      const GBox& G = S.boxes[c.box0 + m];
+      const Bracket b = bracket(S, G.q, S.ticks[c.p], S.tcur[c.p]);
+      const unsigned long long cnt =
+          (unsigned long long)(G.hi[0] - G.lo[0] + 1) * (G.hi[1] - G.lo[1] + 1) * (G.hi[2] - G.lo[2] + 1);
+      vals += cnt * (b.oa == b.ob ? 1ULL : 2ULL);
+    }
+    atomicAdd(S.algo_bytes, vals * (unsigned long long)sizeof(T));
+  }
   const T dtdx = T(st.dt[bidx] / S.dx[c.p]);
   const T hdtdx = T(0.5) * dtdx;
   __syncthreads();
@@ -251,8 +270,8 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
   T Wm[8], W0[8], Wp[8];
   T bx0 = 0, by0 = 0, bz0 = 0, bxp = 0, byp = 0, bzp = 0, dummy;
   if (col) {
-    load_cell(S, slots, c, sm.br, ci, cj, -2, gamma, pfloor, Wm, dummy, dummy, dummy);
-    load_cell(S, slots, c, sm.br, ci, cj, -1, gamma, pfloor, W0, bx0, by0, bz0);
+    load_cell(S, slots, c, sm.br, sm.rt, ci, cj, -2, gamma, pfloor, Wm, dummy, dummy, dummy);
+    load_cell(S, slots, c, sm.br, sm.rt, ci, cj, -1, gamma, pfloor, W0, bx0, by0, bz0);
   }
   T tl[7];     // top state of the previous plane's z-face (rotated z, x, y)
   T dzl = 0;   // normal-field increment of the previous plane
@@ -267,7 +286,7 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
   for (int z = -1; z <= n; ++z) {
     // ---- P1: load plane z+1; publish plane z primitives and lo-face fields
     if (col) {
-      load_cell(S, slots, c, sm.br, ci, cj, z + 1, gamma, pfloor, Wp, bxp, byp, bzp);
+      load_cell(S, slots, c, sm.br, sm.rt, ci, cj, z + 1, gamma, pfloor, Wp, bxp, byp, bzp);
 #pragma unroll
       for (int v = 0; v < 8; ++v) sm.a.w[v][tid] = W0[v];
       sm.bf[0][tid] = bx0;
@@ -394,11 +413,11 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
         // first-order fallback: primitives of the two cells at t^n
         T wa[8], wb[8], dmy;
         if (d == 0) {
-          load_cell(S, slots, c, sm.br, cix - 1, cjx, z, gamma, pfloor, wa, dmy, dmy, dmy);
-          load_cell(S, slots, c, sm.br, cix, cjx, z, gamma, pfloor, wb, dmy, dmy, dmy);
+          load_cell(S, slots, c, sm.br, sm.rt, cix - 1, cjx, z, gamma, pfloor, wa, dmy, dmy, dmy);
+          load_cell(S, slots, c, sm.br, sm.rt, cix, cjx, z, gamma, pfloor, wb, dmy, dmy, dmy);
         } else {
-          load_cell(S, slots, c, sm.br, cix, cjx - 1, z, gamma, pfloor, wa, dmy, dmy, dmy);
-          load_cell(S, slots, c, sm.br, cix, cjx, z, gamma, pfloor, wb, dmy, dmy, dmy);
+          load_cell(S, slots, c, sm.br, sm.rt, cix, cjx - 1, z, gamma, pfloor, wa, dmy, dmy, dmy);
+          load_cell(S, slots, c, sm.br, sm.rt, cix, cjx, z, gamma, pfloor, wb, dmy, dmy, dmy);
         }
         const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
         const int ord[7] = {0, 1 + d, 1 + t1, 1 + t2, 4, 5 + t1, 5 + t2};

@@ -220,6 +220,37 @@ __device__ T cross_value(const DevSet& S, const T* slots, const Bracket& br, int
 }
 
 
+// Per-workgroup table of the guard regions of one patch: for each of the 108
+// (component, region) keys, either a single same-resolution box with the
+// element offsets of its source's two bracketing slices at the source index
+// (0, 0, 0) of the box's shift (direct addressing), or a pointer back to the
+// generic box list.
+template <class T> struct RegionTab {
+  int64_t base_a[108], base_b[108];
+  T w[108];
+  int nq[108];  // source interior size, or -1: use the generic box list
+};
+
+// Fill the region table (one thread per key).
+template <class T>
+__device__ inline void region_tab_init(const DevSet& S, int p, RegionTab<T>& R, int key) {
+  const int m0 = S.rbox_off[p * 108 + key], m1 = S.rbox_off[p * 108 + key + 1];
+  R.nq[key] = -1;
+  if (m1 - m0 != 1) return;
+  const GBox& G = S.boxes[m0];
+  if (!G.same) return;
+  const Bracket b = bracket(S, G.q, S.ticks[p], S.tcur[p]);
+  const int nq = S.n[G.q];
+  const int comp = key / 27 - 1;
+  // offset of source index (shift) in the slice, for variable 0 of the component
+  const int64_t e0 = (comp < 0) ? scell(nq, 0, G.shift[0], G.shift[1], G.shift[2])
+                                : sface(nq, comp, G.shift[0], G.shift[1], G.shift[2]);
+  R.base_a[key] = b.oa + e0;
+  R.base_b[key] = b.ob + e0;
+  R.w[key] = (T)b.w;
+  R.nq[key] = nq;
+}
+
 // Value of element (comp, var, i, j, k) of patch p's padded view: the
 // interior from the patch's own current slice, guard elements from the box
 // table (source patch, shift or resampling) with brackets br[m - box0].
@@ -258,6 +289,37 @@ __device__ T fetch_elem(const DevSet& S, const T* slots, int p, int n, int64_t o
   }
   atomicOr(S.err, ERR_STATE);
   return T(0);
+}
+
+// Same as fetch_elem, with the single-box regions served from the table.
+template <class T>
+__device__ __forceinline__ T fetch_fast(const DevSet& S, const T* slots, int p, int n, int64_t own, int box0,
+                                        const Bracket* br, const RegionTab<T>& R, int comp, int var, int i, int j,
+                                        int k) {
+  const int hx = n + (comp == 0 ? 1 : 0), hy = n + (comp == 1 ? 1 : 0), hz = n + (comp == 2 ? 1 : 0);
+  const int rx = i < 0 ? 0 : (i < hx ? 1 : 2);
+  const int ry = j < 0 ? 0 : (j < hy ? 1 : 2);
+  const int rz = k < 0 ? 0 : (k < hz ? 1 : 2);
+  if (rx == 1 && ry == 1 && rz == 1) {
+    const int64_t se = (comp < 0) ? scell(n, var, i, j, k) : sface(n, comp, i, j, k);
+    return slots[own + se];
+  }
+  const int key = (comp + 1) * 27 + (rz * 3 + ry) * 3 + rx;
+  const int nq = R.nq[key];
+  if (nq < 0) return fetch_elem(S, slots, p, n, own, box0, br, comp, var, i, j, k);
+  // direct addressing: same index arithmetic as the slice layout, relative to
+  // the box's shifted origin
+  int64_t e;
+  if (comp < 0) {
+    e = (int64_t)var * nq * nq * nq + ((int64_t)k * nq + j) * nq + i;
+  } else {
+    const int sx = nq + (comp == 0), sy = nq + (comp == 1);
+    e = ((int64_t)k * sy + j) * sx + i;
+  }
+  const T a = slots[R.base_a[key] + e];
+  if (R.base_a[key] == R.base_b[key]) return a;
+  const T b = slots[R.base_b[key] + e];
+  return a + R.w[key] * (b - a);
 }
 
 }  // namespace dsp

@@ -353,6 +353,7 @@ struct dsp_set {
   }
 
   void begin_timing() {
+    (void)hipMemsetAsync(d_cnt + 3, 0, sizeof(unsigned long long), stream);
     ev_used = 0;
     kern_ms = 0.0;
     kern_launches = 0;
@@ -608,11 +609,12 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
   D.rbox_off = (const int*)up(rbox_off.data(), sizeof(int) * rbox_off.size());
   D.boxes = (const GBox*)up(boxes.data(), sizeof(GBox) * std::max<size_t>(1, boxes.size()));
   s->d_err = (int*)A(sizeof(int) * 2);
-  s->d_cnt = (unsigned long long*)A(sizeof(unsigned long long) * 4);
+  s->d_cnt = (unsigned long long*)A(sizeof(unsigned long long) * 4);  // floor, fallback, updates, bytes
   D.err = s->d_err;
   D.floor_hits = s->d_cnt;
   D.fallback = s->d_cnt + 1;
   D.updates = s->d_cnt + 2;
+  D.algo_bytes = s->d_cnt + 3;
   if (s->alloc_failed) return fail(DSP_ENOMEM, "device allocation failed: " + s->alloc_msg);
   int e = hipck(hipMemcpy(s->d_host_off, s->host_off.data(), sizeof(int64_t) * (npatch + 1), hipMemcpyHostToDevice),
                 "hipMemcpy");
@@ -892,6 +894,19 @@ int dsp_stats(const dsp_set* cs, double out[16]) {
   out[13] = (double)s->rounds;
   out[14] = *std::min_element(tc.begin(), tc.end());
   out[15] = *std::max_element(tc.begin(), tc.end());
+  return 0;
+}
+
+int dsp_kernel_stats(const dsp_set* cs, double out[4]) {
+  dsp_set* s = const_cast<dsp_set*>(cs);
+  if (!s || !out) return fail(DSP_EINVAL, "null argument");
+  unsigned long long cnt[4];
+  int e = hipck(hipMemcpy(cnt, s->d_cnt, sizeof(cnt), hipMemcpyDeviceToHost), "stats");
+  if (e) return e;
+  out[0] = s->kern_ms;
+  out[1] = (double)s->kern_launches;
+  out[2] = s->fused ? (double)cnt[3] : 0.0;
+  out[3] = s->fused ? 1.0 : 0.0;
   return 0;
 }
 

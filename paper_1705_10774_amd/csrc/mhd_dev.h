@@ -31,7 +31,7 @@ __device__ __forceinline__ T fast_speed(T a2, T b2, T bt2) {
 // F*_R if S_R >= 0, else F_R.  Degenerate star states (vanishing
 // rho (S - u)(S - S_M) - bn^2) keep the transverse velocity and field.
 template <class T>
-__device__ void hlld_flux(const T* l, const T* r, T bn, T gamma, T* f) {
+__device__ __forceinline__ void hlld_flux(const T* l, const T* r, T bn, T gamma, T* f) {
   const T gm1 = gamma - T(1);
   const T bn2 = bn * bn;
   // left

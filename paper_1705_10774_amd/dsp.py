@@ -24,7 +24,7 @@ DSP_DT_LOCAL, DSP_DT_GLOBAL_QUANT, DSP_DT_GLOBAL_EXACT, DSP_DT_FIXED = 0, 1, 2, 
 
 # every entry point declared in include/dsp.h
 EXPORTS = ["dsp_create", "dsp_init", "dsp_init_device", "dsp_advance_to", "dsp_advance_to_plain", "dsp_read_state",
-           "dsp_read_schedule", "dsp_stats", "dsp_kernel_time", "dsp_fixed_steps_fwd",
+           "dsp_read_schedule", "dsp_stats", "dsp_kernel_time", "dsp_kernel_stats", "dsp_fixed_steps_fwd",
            "dsp_fixed_steps_adj", "dsp_destroy", "dsp_last_error"]
 
 
@@ -75,6 +75,7 @@ def load():
                                     C.POINTER(C.c_int32), sz]
     L.dsp_stats.argtypes = [vp, dp]
     L.dsp_kernel_time.argtypes = [vp, dp, C.POINTER(C.c_int64)]
+    L.dsp_kernel_stats.argtypes = [vp, dp]
     L.dsp_fixed_steps_fwd.argtypes = [vp, vp, vp, C.c_int32, vp]
     L.dsp_fixed_steps_adj.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32]
     L.dsp_destroy.argtypes = [vp]
@@ -184,6 +185,12 @@ def dsp_kernel_time(h):
     return ms.value, n.value
 
 
+def dsp_kernel_stats(h):
+    out = np.zeros(4)
+    _check(load().dsp_kernel_stats(h, _dp(out)))
+    return out
+
+
 def dsp_fixed_steps_fwd(h, U0_dev, UT_dev, nsteps, ckpt_dev=None):
     _check(load().dsp_fixed_steps_fwd(h, C.c_void_p(U0_dev), C.c_void_p(UT_dev), int(nsteps),
                                       C.c_void_p(ckpt_dev) if ckpt_dev else None))
@@ -246,3 +253,6 @@ class PatchSet:
 
     def kernel_time(self):
         return dsp_kernel_time(self.h)
+
+    def kernel_stats(self):
+        return dsp_kernel_stats(self.h)
