@@ -86,9 +86,9 @@ void launch_update(const DevSet& S, const int* list, int count, int nmax, T* slo
                    const StepPtr& st, hipStream_t s, int dt_kind, double t_end, int clip,
                    hipEvent_t ev0, hipEvent_t ev1);
 template <class T>
-void launch_fused(const DevSet& S, const int* list, int count, int nmax, T* slots, double* smax,
-                  const StepPtr& st, hipStream_t s, int dt_kind, double t_end, int clip, hipEvent_t ev0,
-                  hipEvent_t ev1);
+void launch_fused(const DevSet& S, const int* list, int count, int nmax, T* slots, T* pad, int64_t pad_stride,
+                  bool gfill, double* smax, const StepPtr& st, hipStream_t s, int dt_kind, double t_end, int clip,
+                  hipEvent_t ev0, hipEvent_t ev1);
 void launch_dt(const DevSet& S, const int* list, int count, const StepPtr& st, const double* smax, hipStream_t s,
                int dt_kind, double t_end, int clip);
 void launch_publish(const DevSet& S, const int* list, int count, const StepPtr& st, hipStream_t s);

@@ -65,8 +65,7 @@ template <class T> struct StepSmem {
   T py[2][MXF];         // previous plane: y-face mass flux and Bz induction flux
   T fz[3][MPRED];       // z-face fluxes of the current face: mass, Bx and By induction
   T ecc[2][3][MPRED];   // cell-centred EMF -v x B of the half-step state, two planes
-  Bracket br[MAXBOX];   // time brackets of this patch's guard boxes
-  RegionTab<T> rt;      // direct addressing of single-box guard regions
+  RegionTab<T> rt;      // addressing of the guard regions
 };
 
 // primitives of one cell from guard-filled values
@@ -86,38 +85,96 @@ __device__ __forceinline__ void prim_of(T rho, T m0, T m1, T m2, T en, T bx, T b
   w[7] = bz;
 }
 
-struct PatchCtx {
-  int p, n, box0;
-  int64_t own, out;
+template <class T> struct PatchCtx {
+  int p, n;
+  const T* ownp;  // current slice of the patch
 };
-
-template <class T>
-__device__ __forceinline__ T fetch(const DevSet& S, const T* slots, const PatchCtx& c, const Bracket* br,
-                                   const RegionTab<T>& rt, int comp, int var, int i, int j, int k) {
-  return fetch_fast(S, slots, c.p, c.n, c.own, c.box0, br, rt, comp, var, i, j, k);
-}
 
 // guard-filled primitives of cell (i, j, k); the fields on its three low
 // faces are returned too (outputs are written last, so they may alias)
 template <class T>
-__device__ __forceinline__ void load_cell(const DevSet& S, const T* slots, const PatchCtx& c, const Bracket* br,
-                                          const RegionTab<T>& rt, int i, int j, int k, T gamma, T pfloor, T* w,
-                                          T& bxl, T& byl, T& bzl) {
-  const T rho = fetch(S, slots, c, br, rt, -1, 0, i, j, k);
-  const T m0 = fetch(S, slots, c, br, rt, -1, 1, i, j, k);
-  const T m1 = fetch(S, slots, c, br, rt, -1, 2, i, j, k);
-  const T m2 = fetch(S, slots, c, br, rt, -1, 3, i, j, k);
-  const T en = fetch(S, slots, c, br, rt, -1, 4, i, j, k);
-  const T xl = fetch(S, slots, c, br, rt, 0, 0, i, j, k);
-  const T xr = fetch(S, slots, c, br, rt, 0, 0, i + 1, j, k);
-  const T yl = fetch(S, slots, c, br, rt, 1, 0, i, j, k);
-  const T yr = fetch(S, slots, c, br, rt, 1, 0, i, j + 1, k);
-  const T zl = fetch(S, slots, c, br, rt, 2, 0, i, j, k);
-  const T zr = fetch(S, slots, c, br, rt, 2, 0, i, j, k + 1);
+__device__ __forceinline__ void load_cell(const PatchCtx<T>& c, const RegionTab<T>& rt, int i, int j, int k,
+                                          T gamma, T pfloor, T* w, T& bxl, T& byl, T& bzl) {
+  const T rho = fetch_fast(c.ownp, c.n, rt, -1, 0, i, j, k);
+  const T m0 = fetch_fast(c.ownp, c.n, rt, -1, 1, i, j, k);
+  const T m1 = fetch_fast(c.ownp, c.n, rt, -1, 2, i, j, k);
+  const T m2 = fetch_fast(c.ownp, c.n, rt, -1, 3, i, j, k);
+  const T en = fetch_fast(c.ownp, c.n, rt, -1, 4, i, j, k);
+  const T xl = fetch_fast(c.ownp, c.n, rt, 0, 0, i, j, k);
+  const T xr = fetch_fast(c.ownp, c.n, rt, 0, 0, i + 1, j, k);
+  const T yl = fetch_fast(c.ownp, c.n, rt, 1, 0, i, j, k);
+  const T yr = fetch_fast(c.ownp, c.n, rt, 1, 0, i, j + 1, k);
+  const T zl = fetch_fast(c.ownp, c.n, rt, 2, 0, i, j, k);
+  const T zr = fetch_fast(c.ownp, c.n, rt, 2, 0, i, j, k + 1);
   prim_of(rho, m0, m1, m2, en, T(0.5) * (xl + xr), T(0.5) * (yl + yr), T(0.5) * (zl + zr), gamma, pfloor, w);
   bxl = xl;
   byl = yl;
   bzl = zl;
+}
+
+// first-order fallback states of an x- (d = 0) or y-face (d = 1) of plane z:
+// the primitives at t^n of the two cells beside the face (cell (i, j) right
+// of or above the face), rotated to the face normal.  Rare; kept out of line.
+template <class T>
+__device__ __attribute__((noinline)) void fallback_states(const PatchCtx<T>& c, const RegionTab<T>& rt, int d,
+                                                          int i, int j, int z, T gamma, T pfloor, T* l, T* r) {
+  T wa[8], wb[8], dmy;
+  load_cell(c, rt, d == 0 ? i - 1 : i, d == 0 ? j : j - 1, z, gamma, pfloor, wa, dmy, dmy, dmy);
+  load_cell(c, rt, i, j, z, gamma, pfloor, wb, dmy, dmy, dmy);
+  const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+  const int ord[7] = {0, 1 + d, 1 + t1, 1 + t2, 4, 5 + t1, 5 + t2};
+  for (int q = 0; q < 7; ++q) {
+    l[q] = wa[ord[q]];
+    r[q] = wb[ord[q]];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Guard regions that are not a single same-resolution box (several sources,
+// or another resolution): values written into the entry's padded buffer with
+// the generic box search, so the marching kernel reads every guard region
+// with one addressing rule.
+
+template <class T>
+__global__ __launch_bounds__(256) void k_gfill(DevSet S, const int* __restrict__ list, int count,
+                                               const T* __restrict__ slots, T* __restrict__ pad,
+                                               int64_t pad_stride) {
+  __shared__ Bracket br[MAXBOX];
+  const int b = blockIdx.y;
+  if (b >= count) return;
+  const int p = list[b];
+  const int n = S.n[p], N = n + 4;
+  const int box0 = S.rbox_off[p * 108];
+  const int nbox = S.rbox_off[p * 108 + 108] - box0;
+  const int64_t own = S.slot_off[p] + (int64_t)S.cur[p] * S.slice_len[p];
+  for (int m = threadIdx.x; m < nbox; m += blockDim.x)
+    br[m] = bracket(S, S.boxes[box0 + m].q, S.ticks[p], S.tcur[p]);
+  __syncthreads();
+  T* dst = pad + (int64_t)b * pad_stride;
+  for (int key = 0; key < 108; ++key) {
+    const int comp = key / 27 - 1, reg = key % 27;
+    if (reg == 13 || region_direct(S, p, key)) continue;
+    int lo[3], ext[3];
+    const int rr[3] = {reg % 3, (reg / 3) % 3, reg / 9};
+    for (int d = 0; d < 3; ++d) {
+      const int h = n + (comp == d ? 1 : 0);
+      lo[d] = rr[d] == 0 ? -2 : (rr[d] == 1 ? 0 : h);
+      ext[d] = rr[d] == 1 ? h : 2;
+    }
+    const int nvar = comp < 0 ? 5 : 1;
+    const int cnt = ext[0] * ext[1] * ext[2] * nvar;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += gridDim.x * blockDim.x) {
+      int r = e;
+      const int i = lo[0] + r % ext[0];
+      r /= ext[0];
+      const int j = lo[1] + r % ext[1];
+      r /= ext[1];
+      const int k = lo[2] + r % ext[2];
+      const int var = r / ext[2];
+      const T v = fetch_elem(S, slots, p, n, own, box0, br, comp, var, i, j, k);
+      dst[(comp < 0) ? pcell(N, var, i, j, k) : pface(N, comp, i, j, k)] = v;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -125,21 +182,17 @@ __device__ __forceinline__ void load_cell(const DevSet& S, const T* slots, const
 
 template <class T>
 __global__ __launch_bounds__(256) void k_courant(DevSet S, const int* __restrict__ list, int count,
-                                                 const T* __restrict__ slots, double* __restrict__ smax) {
-  __shared__ Bracket br[MAXBOX];
+                                                 const T* __restrict__ slots, const T* __restrict__ pad,
+                                                 int64_t pad_stride, double* __restrict__ smax) {
   __shared__ RegionTab<T> rt;
   const int b = blockIdx.y;
   if (b >= count) return;
-  PatchCtx c;
+  PatchCtx<T> c;
   c.p = list[b];
   c.n = S.n[c.p];
-  c.box0 = S.rbox_off[c.p * 108];
-  const int nbox = S.rbox_off[c.p * 108 + 108] - c.box0;
-  c.own = S.slot_off[c.p] + (int64_t)S.cur[c.p] * S.slice_len[c.p];
-  c.out = 0;
-  for (int m = threadIdx.x; m < nbox; m += blockDim.x)
-    br[m] = bracket(S, S.boxes[c.box0 + m].q, S.ticks[c.p], S.tcur[c.p]);
-  for (int m = threadIdx.x; m < 108; m += blockDim.x) region_tab_init(S, c.p, rt, m);
+  c.ownp = slots + S.slot_off[c.p] + (int64_t)S.cur[c.p] * S.slice_len[c.p];
+  for (int m = threadIdx.x; m < 108; m += blockDim.x)
+    region_tab_init(S, slots, pad + (int64_t)b * pad_stride, c.n + 4, c.p, rt, m);
   __syncthreads();
   const int N = c.n + 4;
   const int64_t cid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -147,7 +200,7 @@ __global__ __launch_bounds__(256) void k_courant(DevSet S, const int* __restrict
   if (cid < (int64_t)N * N * N) {
     const int i = (int)(cid % N) - 2, j = (int)((cid / N) % N) - 2, k = (int)(cid / ((int64_t)N * N)) - 2;
     T w[8], bxl, byl, bzl;
-    load_cell(S, slots, c, br, rt, i, j, k, T(S.gamma), T(0), w, bxl, byl, bzl);
+    load_cell(c, rt, i, j, k, T(S.gamma), T(0), w, bxl, byl, bzl);
     T pr = w[4];
     if (!isfinite(w[0]) || !isfinite(pr)) {
       atomicOr(S.err, ERR_NONFINITE);
@@ -208,7 +261,8 @@ __device__ __forceinline__ void face_states(const StepSmem<T>& sm, int d, int pa
 
 template <class T>
 __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__ list, int count,
-                                               T* __restrict__ slots, StepPtr st, int tpa) {
+                                               T* __restrict__ slots, const T* __restrict__ pad,
+                                               int64_t pad_stride, StepPtr st, int tpa) {
   __shared__ StepSmem<T> sm;
   const int tid = threadIdx.x;
   const int T2 = tpa * tpa;  // tile slots per patch
@@ -216,7 +270,7 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
   const int bidx = (w / (8 * T2)) * 8 + (w % 8);
   const int tile = (w / 8) % T2;
   if (bidx >= count) return;
-  PatchCtx c;
+  PatchCtx<T> c;
   c.p = list[bidx];
   const int n = c.n = S.n[c.p];
   const int nt = (n + MT - 1) / MT;
@@ -227,13 +281,14 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
   const int TX = x1 - x0, TY = y1 - y0;
   const int CX = TX + 4, CY = TY + 4, PX = TX + 2;
   const bool lastx = (x1 == n), lasty = (y1 == n), firstx = (x0 == 0), firsty = (y0 == 0);
-  c.box0 = S.rbox_off[c.p * 108];
-  const int nbox = S.rbox_off[c.p * 108 + 108] - c.box0;
+  const int box0 = S.rbox_off[c.p * 108];
+  const int nbox = S.rbox_off[c.p * 108 + 108] - box0;
   const int64_t V = S.slice_len[c.p];
-  c.own = S.slot_off[c.p] + (int64_t)S.cur[c.p] * V;
-  c.out = S.slot_off[c.p] + (int64_t)((S.cur[c.p] + 1) % S.nslots) * V;
-  for (int m = tid; m < nbox; m += NTHR) sm.br[m] = bracket(S, S.boxes[c.box0 + m].q, S.ticks[c.p], S.tcur[c.p]);
-  for (int m = tid; m < 108; m += NTHR) region_tab_init(S, c.p, sm.rt, m);
+  const int64_t own = S.slot_off[c.p] + (int64_t)S.cur[c.p] * V;
+  T* const outp = slots + S.slot_off[c.p] + (int64_t)((S.cur[c.p] + 1) % S.nslots) * V;
+  c.ownp = slots + own;
+  for (int m = tid; m < 108; m += NTHR)
+    region_tab_init(S, (const T*)slots, pad + (int64_t)bidx * pad_stride, n + 4, c.p, sm.rt, m);
   const T gamma = T(S.gamma), pfloor = T(S.p_floor);
   if (tile == 0 && tid == 0) {
     // algorithmic traffic of this patch update: own slice read and written,
@@ -241,7 +296,7 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
     // time) or two (interpolated)
     unsigned long long vals = 2ULL * (unsigned long long)V;
     for (int m = 0; m < nbox; ++m) {
-      const GBox& G = S.boxes[c.box0 + m];
+      const GBox& G = S.boxes[box0 + m];
       const Bracket b = bracket(S, G.q, S.ticks[c.p], S.tcur[c.p]);
       const unsigned long long cnt =
           (unsigned long long)(G.hi[0] - G.lo[0] + 1) * (G.hi[1] - G.lo[1] + 1) * (G.hi[2] - G.lo[2] + 1);
@@ -270,8 +325,8 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
   T Wm[8], W0[8], Wp[8];
   T bx0 = 0, by0 = 0, bz0 = 0, bxp = 0, byp = 0, bzp = 0, dummy;
   if (col) {
-    load_cell(S, slots, c, sm.br, sm.rt, ci, cj, -2, gamma, pfloor, Wm, dummy, dummy, dummy);
-    load_cell(S, slots, c, sm.br, sm.rt, ci, cj, -1, gamma, pfloor, W0, bx0, by0, bz0);
+    load_cell(c, sm.rt, ci, cj, -2, gamma, pfloor, Wm, dummy, dummy, dummy);
+    load_cell(c, sm.rt, ci, cj, -1, gamma, pfloor, W0, bx0, by0, bz0);
   }
   T tl[7];     // top state of the previous plane's z-face (rotated z, x, y)
   T dzl = 0;   // normal-field increment of the previous plane
@@ -286,7 +341,7 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
   for (int z = -1; z <= n; ++z) {
     // ---- P1: load plane z+1; publish plane z primitives and lo-face fields
     if (col) {
-      load_cell(S, slots, c, sm.br, sm.rt, ci, cj, z + 1, gamma, pfloor, Wp, bxp, byp, bzp);
+      load_cell(c, sm.rt, ci, cj, z + 1, gamma, pfloor, Wp, bxp, byp, bzp);
 #pragma unroll
       for (int v = 0; v < 8; ++v) sm.a.w[v][tid] = W0[v];
       sm.bf[0][tid] = bx0;
@@ -411,20 +466,7 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
       T bn = bface + T(0.5) * (sm.b.p.db[d][pa] + sm.b.p.db[d][pb]);
       if (!(l[0] > T(0)) || !(l[4] > T(0)) || !(r[0] > T(0)) || !(r[4] > T(0))) {
         // first-order fallback: primitives of the two cells at t^n
-        T wa[8], wb[8], dmy;
-        if (d == 0) {
-          load_cell(S, slots, c, sm.br, sm.rt, cix - 1, cjx, z, gamma, pfloor, wa, dmy, dmy, dmy);
-          load_cell(S, slots, c, sm.br, sm.rt, cix, cjx, z, gamma, pfloor, wb, dmy, dmy, dmy);
-        } else {
-          load_cell(S, slots, c, sm.br, sm.rt, cix, cjx - 1, z, gamma, pfloor, wa, dmy, dmy, dmy);
-          load_cell(S, slots, c, sm.br, sm.rt, cix, cjx, z, gamma, pfloor, wb, dmy, dmy, dmy);
-        }
-        const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
-        const int ord[7] = {0, 1 + d, 1 + t1, 1 + t2, 4, 5 + t1, 5 + t2};
-        for (int q = 0; q < 7; ++q) {
-          l[q] = wa[ord[q]];
-          r[q] = wb[ord[q]];
-        }
+        fallback_states(c, sm.rt, d, cix, cjx, z, gamma, pfloor, l, r);
         bn = bface;
         const bool owned = (d == 0) ? (own_c(cix, x0, x1, firstx, false) || (lastx && cix == n)) &&
                                           own_c(cjx, y0, y1, firsty, lasty)
@@ -518,16 +560,16 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
           for (int q = 0; q < 5; ++q) {
             const T du = duxy[q] + (fzc[q] - fzl[q]);
             const int64_t e = scell(n, q, ci, cj, zc);
-            slots[c.out + e] = slots[c.own + e] - dtdx * du;
+            outp[e] = c.ownp[e] - dtdx * du;
           }
         }
         if (own_bx) {
           const int64_t e = sface(n, 0, ci, cj, zc);
-          slots[c.out + e] = slots[c.own + e] - dtdx * (pbx - EY(ci, cj));
+          outp[e] = c.ownp[e] - dtdx * (pbx - EY(ci, cj));
         }
         if (own_by) {
           const int64_t e = sface(n, 1, ci, cj, zc);
-          slots[c.out + e] = slots[c.own + e] - dtdx * (pby + EX(ci, cj));
+          outp[e] = c.ownp[e] - dtdx * (pby + EX(ci, cj));
         }
       }
       if (z >= 0 && z < n) {
@@ -537,7 +579,7 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
       if (z >= 0 && own_cell) {
         const T curl = (EY(ci + 1, cj) - EY(ci, cj)) - (EX(ci, cj + 1) - EX(ci, cj));
         const int64_t e = sface(n, 2, ci, cj, z);
-        slots[c.out + e] = slots[c.own + e] - dtdx * curl;
+        outp[e] = c.ownp[e] - dtdx * curl;
       }
       for (int m = tid; m < nxf; m += NTHR) {
         sm.px[0][m] = sm.a.f.fx[0][m];
@@ -568,25 +610,29 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
 // ---------------------------------------------------------------------------
 
 template <class T>
-void launch_fused(const DevSet& S, const int* list, int count, int nmax, T* slots, double* smax,
-                  const StepPtr& st, hipStream_t s, int dt_kind, double t_end, int clip, hipEvent_t ev0,
-                  hipEvent_t ev1) {
+void launch_fused(const DevSet& S, const int* list, int count, int nmax, T* slots, T* pad, int64_t pad_stride,
+                  bool gfill, double* smax, const StepPtr& st, hipStream_t s, int dt_kind, double t_end, int clip,
+                  hipEvent_t ev0, hipEvent_t ev1) {
   const int N = nmax + 4;
+  if (gfill)
+    hipLaunchKernelGGL(k_gfill<T>, dim3(4, count), dim3(256), 0, s, S, list, count, (const T*)slots, pad,
+                       pad_stride);
   (void)hipMemsetAsync(smax, 0, sizeof(double) * count, s);
   hipLaunchKernelGGL(k_courant<T>, dim3((unsigned)(((int64_t)N * N * N + 255) / 256), count), dim3(256), 0, s, S,
-                     list, count, (const T*)slots, smax);
+                     list, count, (const T*)slots, (const T*)pad, pad_stride, smax);
   launch_dt(S, list, count, st, smax, s, dt_kind, t_end, clip);
   const int tpa = (nmax + MT - 1) / MT;
   const int T2 = tpa * tpa;
   const int groups = ((count + 7) / 8) * 8 * T2;
   if (ev0) (void)hipEventRecord(ev0, s);
-  hipLaunchKernelGGL(k_step<T>, dim3(groups), dim3(NTHR), 0, s, S, list, count, slots, st, tpa);
+  hipLaunchKernelGGL(k_step<T>, dim3(groups), dim3(NTHR), 0, s, S, list, count, slots, (const T*)pad, pad_stride,
+                     st, tpa);
   if (ev1) (void)hipEventRecord(ev1, s);
 }
 
-template void launch_fused<float>(const DevSet&, const int*, int, int, float*, double*, const StepPtr&, hipStream_t,
-                                  int, double, int, hipEvent_t, hipEvent_t);
-template void launch_fused<double>(const DevSet&, const int*, int, int, double*, double*, const StepPtr&,
-                                   hipStream_t, int, double, int, hipEvent_t, hipEvent_t);
+template void launch_fused<float>(const DevSet&, const int*, int, int, float*, float*, int64_t, bool, double*,
+                                  const StepPtr&, hipStream_t, int, double, int, hipEvent_t, hipEvent_t);
+template void launch_fused<double>(const DevSet&, const int*, int, int, double*, double*, int64_t, bool, double*,
+                                   const StepPtr&, hipStream_t, int, double, int, hipEvent_t, hipEvent_t);
 
 }  // namespace dsp

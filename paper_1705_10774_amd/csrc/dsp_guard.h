@@ -220,37 +220,6 @@ __device__ T cross_value(const DevSet& S, const T* slots, const Bracket& br, int
 }
 
 
-// Per-workgroup table of the guard regions of one patch: for each of the 108
-// (component, region) keys, either a single same-resolution box with the
-// element offsets of its source's two bracketing slices at the source index
-// (0, 0, 0) of the box's shift (direct addressing), or a pointer back to the
-// generic box list.
-template <class T> struct RegionTab {
-  int64_t base_a[108], base_b[108];
-  T w[108];
-  int nq[108];  // source interior size, or -1: use the generic box list
-};
-
-// Fill the region table (one thread per key).
-template <class T>
-__device__ inline void region_tab_init(const DevSet& S, int p, RegionTab<T>& R, int key) {
-  const int m0 = S.rbox_off[p * 108 + key], m1 = S.rbox_off[p * 108 + key + 1];
-  R.nq[key] = -1;
-  if (m1 - m0 != 1) return;
-  const GBox& G = S.boxes[m0];
-  if (!G.same) return;
-  const Bracket b = bracket(S, G.q, S.ticks[p], S.tcur[p]);
-  const int nq = S.n[G.q];
-  const int comp = key / 27 - 1;
-  // offset of source index (shift) in the slice, for variable 0 of the component
-  const int64_t e0 = (comp < 0) ? scell(nq, 0, G.shift[0], G.shift[1], G.shift[2])
-                                : sface(nq, comp, G.shift[0], G.shift[1], G.shift[2]);
-  R.base_a[key] = b.oa + e0;
-  R.base_b[key] = b.ob + e0;
-  R.w[key] = (T)b.w;
-  R.nq[key] = nq;
-}
-
 // Value of element (comp, var, i, j, k) of patch p's padded view: the
 // interior from the patch's own current slice, guard elements from the box
 // table (source patch, shift or resampling) with brackets br[m - box0].
@@ -291,34 +260,85 @@ __device__ T fetch_elem(const DevSet& S, const T* slots, int p, int n, int64_t o
   return T(0);
 }
 
-// Same as fetch_elem, with the single-box regions served from the table.
+// A guard region (key = (component + 1) * 27 + region, region = (rz * 3 + ry)
+// * 3 + rx, r = 0 / 1 / 2 below / inside / above the interior along an axis)
+// is "direct" when one same-resolution box covers it: its values are then
+// read straight from the source's two bracketing slices.  Every other region
+// is first written into a padded per-entry buffer (k_gfill) and read there.
+__device__ __forceinline__ bool region_direct(const DevSet& S, int p, int key) {
+  const int m0 = S.rbox_off[p * 108 + key], m1 = S.rbox_off[p * 108 + key + 1];
+  return m1 - m0 == 1 && S.boxes[m0].same;
+}
+
+// Per-workgroup table of the 108 regions of one patch: element (var, i, j, k)
+// of region `key` is pa[e] + w (pb[e] - pa[e]), e the slice-layout offset of
+// (var, i, j, k) for a patch of nq cells per edge (pa == pb: exact copy).
+template <class T> struct RegionTab {
+  const T* pa[108];
+  const T* pb[108];
+  T w[108];
+  int nq[108];
+};
+
+// Fill entry `key`.  pad: this entry's padded buffer (layout pcell / pface,
+// N cells per edge including the guard layers).
 template <class T>
-__device__ __forceinline__ T fetch_fast(const DevSet& S, const T* slots, int p, int n, int64_t own, int box0,
-                                        const Bracket* br, const RegionTab<T>& R, int comp, int var, int i, int j,
-                                        int k) {
+__device__ inline void region_tab_init(const DevSet& S, const T* slots, const T* pad, int N, int p,
+                                       RegionTab<T>& R, int key) {
+  const int comp = key / 27 - 1;
+  if (region_direct(S, p, key)) {
+    const GBox& G = S.boxes[S.rbox_off[p * 108 + key]];
+    const Bracket b = bracket(S, G.q, S.ticks[p], S.tcur[p]);
+    const int nq = S.n[G.q];
+    const int64_t e0 = (comp < 0) ? scell(nq, 0, G.shift[0], G.shift[1], G.shift[2])
+                                  : sface(nq, comp, G.shift[0], G.shift[1], G.shift[2]);
+    R.pa[key] = slots + b.oa + e0;
+    R.pb[key] = slots + b.ob + e0;
+    R.w[key] = (T)b.w;
+    R.nq[key] = nq;
+  } else {
+    const T* q = pad + ((comp < 0) ? pcell(N, 0, 0, 0, 0) : pface(N, comp, 0, 0, 0));
+    R.pa[key] = q;
+    R.pb[key] = q;
+    R.w[key] = T(0);
+    R.nq[key] = N;
+  }
+}
+
+// Same value as fetch_elem, through the region table: interior elements from
+// the patch's own slice (ownp), guard elements from the region's source
+// slices or from the padded buffer.  Offsets inside one slice fit in 32 bits.
+template <class T>
+__device__ __forceinline__ T fetch_fast(const T* ownp, int n, const RegionTab<T>& R, int comp, int var, int i,
+                                        int j, int k) {
   const int hx = n + (comp == 0 ? 1 : 0), hy = n + (comp == 1 ? 1 : 0), hz = n + (comp == 2 ? 1 : 0);
   const int rx = i < 0 ? 0 : (i < hx ? 1 : 2);
   const int ry = j < 0 ? 0 : (j < hy ? 1 : 2);
   const int rz = k < 0 ? 0 : (k < hz ? 1 : 2);
   if (rx == 1 && ry == 1 && rz == 1) {
-    const int64_t se = (comp < 0) ? scell(n, var, i, j, k) : sface(n, comp, i, j, k);
-    return slots[own + se];
+    int e;
+    if (comp < 0) {
+      e = ((var * n + k) * n + j) * n + i;
+    } else {
+      const int sx = n + (comp == 0), sy = n + (comp == 1);
+      e = 5 * n * n * n + comp * n * n * (n + 1) + (k * sy + j) * sx + i;
+    }
+    return ownp[e];
   }
   const int key = (comp + 1) * 27 + (rz * 3 + ry) * 3 + rx;
   const int nq = R.nq[key];
-  if (nq < 0) return fetch_elem(S, slots, p, n, own, box0, br, comp, var, i, j, k);
-  // direct addressing: same index arithmetic as the slice layout, relative to
-  // the box's shifted origin
-  int64_t e;
+  int e;
   if (comp < 0) {
-    e = (int64_t)var * nq * nq * nq + ((int64_t)k * nq + j) * nq + i;
+    e = ((var * nq + k) * nq + j) * nq + i;
   } else {
     const int sx = nq + (comp == 0), sy = nq + (comp == 1);
-    e = ((int64_t)k * sy + j) * sx + i;
+    e = (k * sy + j) * sx + i;
   }
-  const T a = slots[R.base_a[key] + e];
-  if (R.base_a[key] == R.base_b[key]) return a;
-  const T b = slots[R.base_b[key] + e];
+  const T* pa = R.pa[key];
+  const T* pb = R.pb[key];
+  const T a = pa[e];
+  if (pa == pb) return a;
+  const T b = pb[e];
   return a + R.w[key] * (b - a);
 }
 

@@ -324,16 +324,18 @@ struct dsp_set {
 
   // one launch sequence for list[off .. off+count)
   bool fused = true;  // fused marching kernel (false: staged kernels)
+  bool any_generic = false;  // some guard region is not one same-resolution box
   void update_batch(int off, int count, int dt_kind, double t_end, int clip, const int* list) {
     hipEvent_t e0 = next_event(true), e1 = next_event(false);
     ev_used++;
     StepPtr s2{st.k + off, st.dtk + off, st.dt + off};
     if (fused) {
       if (f32)
-        launch_fused<float>(D, list + off, count, nmax, (float*)slots, smax, s2, stream, dt_kind, t_end, clip, e0, e1);
+        launch_fused<float>(D, list + off, count, nmax, (float*)slots, (float*)work_pad, pad_stride, any_generic,
+                            smax, s2, stream, dt_kind, t_end, clip, e0, e1);
       else
-        launch_fused<double>(D, list + off, count, nmax, (double*)slots, smax, s2, stream, dt_kind, t_end, clip, e0,
-                             e1);
+        launch_fused<double>(D, list + off, count, nmax, (double*)slots, (double*)work_pad, pad_stride,
+                             any_generic, smax, s2, stream, dt_kind, t_end, clip, e0, e1);
       return;
     }
     if (f32)
@@ -503,6 +505,14 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
     for (int p = 0; p < npatch; ++p) maxbox = std::max(maxbox, rbox_off[(p + 1) * 108] - rbox_off[p * 108]);
     const char* path = getenv("DSP_PATH");
     S->fused = !(path && std::string(path) == "staged") && maxbox <= 256;
+    int ngen = 0;
+    for (int p = 0; p < npatch; ++p)
+      for (int k = 0; k < 108; ++k) {
+        if (k % 27 == 13) continue;
+        const int m0 = rbox_off[p * 108 + k], m1 = rbox_off[p * 108 + k + 1];
+        if (!(m1 - m0 == 1 && boxes[m0].same)) ++ngen;
+      }
+    S->any_generic = ngen > 0;
     if (getenv("DSP_DEBUG"))
       fprintf(stderr, "dsp_create: %d patches, nmax %d, max guard boxes per patch %d, %s path\n", npatch,
               S->nmax, maxbox, S->fused ? "fused" : "staged");
@@ -535,17 +545,25 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
   s->fm3 = (int64_t)(N + 1) * (N + 1) * (N + 1);
   s->f_stride = 24LL * s->fm3;
   s->e_stride = 3LL * s->fm3;
-  const int64_t per_slot = tsz * (s->pad_stride + 2 * s->w_stride + s->s_stride + s->f_stride + s->e_stride);
+  // work memory per batch entry: the staged kernels need every buffer; the
+  // fused kernels only a padded buffer, and only if some guard region is
+  // resampled or has several sources
+  const int64_t pad_vals = (!s->fused || s->any_generic) ? s->pad_stride : 0;
+  const int64_t per_slot =
+      s->fused ? tsz * (pad_vals + 1)
+               : tsz * (s->pad_stride + 2 * s->w_stride + s->s_stride + s->f_stride + s->e_stride);
   const int64_t budget = (int64_t)16 << 30;  // work memory cap
   s->B = (int)std::max<int64_t>(1, std::min<int64_t>(npatch, budget / per_slot));
   if ((c.dt_mode != DSP_DT_LOCAL) && s->B < npatch)
     return fail(DSP_EINVAL, "global time-step modes need work memory for every patch");
-  s->work_pad = A(tsz * s->pad_stride * s->B);
-  s->work_w = A(tsz * s->w_stride * s->B);
-  s->work_h = A(tsz * s->w_stride * s->B);
-  s->work_s = A(tsz * s->s_stride * s->B);
-  s->work_f = A(tsz * s->f_stride * s->B);
-  s->work_e = A(tsz * s->e_stride * s->B);
+  s->work_pad = A(tsz * pad_vals * s->B);
+  if (!s->fused) {
+    s->work_w = A(tsz * s->w_stride * s->B);
+    s->work_h = A(tsz * s->w_stride * s->B);
+    s->work_s = A(tsz * s->s_stride * s->B);
+    s->work_f = A(tsz * s->f_stride * s->B);
+    s->work_e = A(tsz * s->e_stride * s->B);
+  }
   s->smax = (double*)A(sizeof(double) * s->B);
   s->d_list = (int*)A(sizeof(int) * npatch);
   s->d_single = (int*)A(sizeof(int) * 4);

@@ -334,13 +334,13 @@ def cfg2_smooth(prec=F64, npd=8):
 
 
 def uneven(npd=16, seed_sizes=1003, seed_rho=2003, prec=F32, box=1.0, name="cfg3_uneven",
-           dt_base=None, nsteps_base=8):
-    """npd^3 equal-size patches with n drawn uniformly from {16, 24, 32};
+           dt_base=None, nsteps_base=8, sizes=(16, 24, 32)):
+    """npd^3 equal-size patches with n drawn uniformly from `sizes`;
     lognormal density ln rho = 2 G - 2 (G: unit-variance field, E(k) ~ k^-2,
     1 <= |k| <= 4), renormalised to <rho> = 1; p = 0.01 rho; B = (0, 0,
     sqrt 0.02) (beta = 1 at <p>); v = 0.  Runs to nsteps_base * dt_base."""
     rs = np.random.Generator(np.random.PCG64(seed_sizes))
-    ns = rs.choice(np.array([16, 24, 32]), size=npd ** 3)
+    ns = rs.choice(np.array(sizes), size=npd ** 3)
     patches = cartesian(npd, ns, box=box)
     rng = np.random.Generator(np.random.PCG64(seed_rho))
     G = FourierField(rng, 1.0, 4.0, 2.0, box=box)

@@ -202,3 +202,44 @@ def test_gpu_error_codes():
         s.init(U)
     assert e.value.code == dsp.DSP_ENONFINITE
     s.close()
+
+
+def mini_uneven(prec):
+    # configuration 3 in small: 4^3 patches of n in {16, 24, 32} (every
+    # neighbour pair of unequal n is a resolution jump), dt_base = 2^-11
+    return I.uneven(npd=4, seed_sizes=1013, seed_rho=2013, prec=prec, box=0.25, name="cfg3_mini",
+                    dt_base=2.0 ** -11)
+
+
+@pytest.mark.parametrize("prec", [I.F64, I.F32])
+def test_cross_resolution_schedule_and_state(orc, prec):
+    """Uneven patch sizes: guard values resampled across resolutions, local
+    levels k = 1 .. 5 within two dt_base."""
+    pr = mini_uneven(prec)
+    T = 2 * pr.cfg.dt_base
+    Ug, sg, kg, stg = gpu_run(pr, t_end=T)
+    Uo, so, ko, sto = orc_run(orc, pr, t_end=T)
+    assert len(set(so.tolist())) >= 4
+    assert np.array_equal(sg, so) and np.array_equal(kg, ko)
+    err = rel_l1(Ug, Uo, pr.patches)
+    print("cross-resolution rel L1", prec, err)
+    assert err <= (1e-10 if prec == I.F64 else 1e-4)
+
+
+@pytest.mark.parametrize("prec", [I.F64, I.F32])
+def test_smr_blast_first_base_step(orc, prec):
+    """Configuration 4 (three nested levels, blast wave) up to the first
+    dt_base: coarse-fine guard resampling plus levels spanning a factor 64."""
+    pr = I.cfg4_smr()
+    if prec == I.F32:
+        pr = dataclasses.replace(pr, cfg=dataclasses.replace(pr.cfg, prec=I.F32))
+    T = pr.cfg.dt_base
+    Ug, sg, kg, stg = gpu_run(pr, t_end=T)
+    Uo, so, ko, sto = orc_run(orc, pr, t_end=T)
+    assert max(so.tolist()) >= 32
+    assert np.array_equal(sg, so) and np.array_equal(kg, ko)
+    err = rel_l1(Ug, Uo, pr.patches)
+    print("smr rel L1", prec, err)
+    assert err <= (1e-10 if prec == I.F64 else 1e-4)
+    # div B at rounding: |B| ~ 1 over the finest cells (dx = 1/256)
+    assert stg[9] <= (1e-10 if prec == I.F64 else 1e-3)
