@@ -220,9 +220,11 @@ class OracleSet:
 
 
 def hlld_flux(wl, wr, bn, gamma=5.0 / 3.0, eps=1e-12):
+    """(mass, mn, mt1, mt2, energy, bt1, bt2) fluxes and, last, the upwind
+    speed that orients the edge EMFs."""
     wl = np.ascontiguousarray(wl, dtype=np.float64)
     wr = np.ascontiguousarray(wr, dtype=np.float64)
-    f = np.zeros(7)
+    f = np.zeros(8)
     _check(lib().orc_hlld_flux(_dp(wl), _dp(wr), float(bn), gamma, eps, _dp(f)))
     return f
 

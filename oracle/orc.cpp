@@ -989,10 +989,10 @@ int orc_slot(const orc_set* h, int32_t q, int32_t rel, double* out, size_t n_val
 }
 
 int orc_hlld_flux(const double* wl, const double* wr, double bn, double gamma, double eps,
-                  double* flux7) {
-  if (!wl || !wr || !flux7) return fail(ORC_EINVAL, "null argument");
+                  double* flux8) {
+  if (!wl || !wr || !flux8) return fail(ORC_EINVAL, "null argument");
   Phys ph{gamma, eps, 0.0};
-  hlld(wl, wr, bn, ph, flux7);
+  hlld(wl, wr, bn, ph, flux8);
   return 0;
 }
 

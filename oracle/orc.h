@@ -67,9 +67,10 @@ int orc_padded(const orc_set* s, int32_t p, double* out, size_t n_values);
 /* Slice rel = 0 (latest), 1 (previous), ... of patch q with its time. */
 int orc_slot(const orc_set* s, int32_t q, int32_t rel, double* out, size_t n_values,
              int64_t* ticks, double* t);
-/* Single HLLD interface flux: w = (rho, un, ut1, ut2, p, bt1, bt2). */
+/* Single HLLD interface flux: w = (rho, un, ut1, ut2, p, bt1, bt2); flux8 =
+ * (mass, mn, mt1, mt2, energy, bt1, bt2, upwind speed). */
 int orc_hlld_flux(const double* wl, const double* wr, double bn, double gamma, double eps,
-                  double* flux7);
+                  double* flux8);
 /* Forward-mode derivative (exact JVP along the taken branches) of nsteps
  * FIXED steps of the whole set: U0 + eps*dU0 -> UT + eps*dUT. */
 int orc_jvp_fixed(orc_set* s, const double* U0, const double* dU0, int32_t nsteps, double dt,

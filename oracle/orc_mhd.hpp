@@ -103,9 +103,11 @@ template <class R> struct Prim {
   R r, v[3], p, b[3];
 };
 // Unrotated interface flux: mass, momentum, energy, and induction flux of
-// each field component (the normal component's own flux is zero).
+// each field component (the normal component's own flux is zero); u is the
+// upwind speed that orients the edge EMFs (see hlld).
 template <class R> struct Flux {
   R r, m[3], e, b[3];
+  R u;
 };
 
 struct StepCounters {
@@ -194,7 +196,12 @@ template <class R> double courant_rate(const Box3<Prim<R>>& W, int n, double dx,
 // ---------------------------------------------------------------------------
 // HLLD flux (Miyoshi & Kusano 2005) for one interface in the rotated frame.
 // State vectors are (rho, un, ut1, ut2, p, bt1, bt2); bn is the common
-// normal field.  Output flux is (mass, mn, mt1, mt2, energy, bt1, bt2).
+// normal field.  Output flux is (mass, mn, mt1, mt2, energy, bt1, bt2),
+// followed by F[7], the upwind speed: S_L if S_L > 0, S_R if S_R < 0, else
+// the contact speed S_M.  Its sign is the sign of the mass flux in exact
+// arithmetic (S_L < S_M < S_R, rho* > 0), and it is exactly zero when both
+// normal velocities vanish and the total pressures agree, where the computed
+// mass flux is zero only up to rounding.
 template <class R>
 void hlld(const R* wl, const R* wr, R bn, const Phys& ph, R* F) {
   const double g = ph.gamma;
@@ -309,6 +316,7 @@ void hlld(const R* wl, const R* wr, R bn, const Phys& ph, R* F) {
   } else {
     for (int q = 0; q < 7; ++q) F[q] = FR[q];
   }
+  F[7] = (SL > 0.0) ? SL : ((SR < 0.0) ? SR : SM);
 }
 
 // ---------------------------------------------------------------------------
@@ -428,7 +436,7 @@ void step(const Layout& L, const std::vector<R>& P, const Box3<Prim<R>>& W, R dt
             bn = bface;
             cnt.fallback_faces++;
           }
-          R f7[7];
+          R f7[8];
           hlld(wl, wr, bn, ph, f7);
           Flux<R> f;
           f.r = f7[0];
@@ -439,6 +447,7 @@ void step(const Layout& L, const std::vector<R>& P, const Box3<Prim<R>>& W, R dt
           f.b[d] = 0.0;
           f.b[t1] = f7[5];
           f.b[t2] = f7[6];
+          f.u = f7[7];
           Fx[d](i, j, k) = f;
         }
   }
@@ -458,7 +467,8 @@ void step(const Layout& L, const std::vector<R>& P, const Box3<Prim<R>>& W, R dt
         Ecc(i, j, k) = e;
       }
 
-  // Edge EMFs (Gardiner & Stone 2005, upwinded by the sign of the mass flux).
+  // Edge EMFs (Gardiner & Stone 2005), upwinded by the direction of the mass
+  // flux, taken as the sign of the face's upwind speed (Flux::u).
   // E_a lives on edges along a; its a-index is a cell index in [0, n-1] and
   // its b- and c-indices are face indices in [0, n], with (a, b, c) cyclic.
   Box3<R> E[3];
@@ -495,10 +505,10 @@ void step(const Layout& L, const std::vector<R>& P, const Box3<Prim<R>>& W, R dt
             if (m < 0.0) return y;
             return R(0.5 * (x + y));
           };
-          R dc14 = up(FA.r, c01 - D, c11 - C);
-          R dc34 = up(FB.r, D - c00, C - c10);
-          R db14 = up(FC.r, c10 - B, c11 - A);
-          R db34 = up(FD.r, B - c00, A - c01);
+          R dc14 = up(FA.u, c01 - D, c11 - C);
+          R dc34 = up(FB.u, D - c00, C - c10);
+          R db14 = up(FC.u, c10 - B, c11 - A);
+          R db34 = up(FD.u, B - c00, A - c01);
           E[a].at(e0) = 0.25 * (A + B + C + D) + 0.25 * ((dc34 - dc14) + (db34 - db14));
         }
   }

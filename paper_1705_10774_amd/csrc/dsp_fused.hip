@@ -61,9 +61,9 @@ template <class T> struct StepSmem {
     } e;
   } b;
   T bf[2][MCOL];        // Bx on the low x-face and By on the low y-face of each column (t^n)
-  T px[2][MXF];         // previous plane: x-face mass flux and Bz induction flux
-  T py[2][MXF];         // previous plane: y-face mass flux and Bz induction flux
-  T fz[3][MPRED];       // z-face fluxes of the current face: mass, Bx and By induction
+  T px[2][MXF];         // previous plane: x-face upwind speed and Bz induction flux
+  T py[2][MXF];         // previous plane: y-face upwind speed and Bz induction flux
+  T fz[3][MPRED];       // current z-face: upwind speed, Bx and By induction fluxes
   T ecc[2][3][MPRED];   // cell-centred EMF -v x B of the half-step state, two planes
   RegionTab<T> rt;      // addressing of the guard regions
 };
@@ -412,7 +412,7 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
           if (own_c(ci, x0, x1, firstx, lastx) && own_c(cj, y0, y1, firsty, lasty))
             atomicAdd(S.fallback, 1ULL);
         }
-        T f[7];
+        T f[8];
         hlld_flux(l, r, bn, gamma, f);
         // unrotated: mass, mx, my, mz, energy; induction fluxes of Bx, By
         fzc[0] = f[0];
@@ -420,7 +420,7 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
         fzc[2] = f[3];
         fzc[3] = f[1];
         fzc[4] = f[4];
-        sm.fz[0][pc] = f[0];
+        sm.fz[0][pc] = f[7];  // upwind speed (orientation of the edge EMFs)
         sm.fz[1][pc] = f[5];
         sm.fz[2][pc] = f[6];
       }
@@ -474,7 +474,7 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
                                           (own_c(cjx, y0, y1, firsty, false) || (lasty && cjx == n));
         if (owned) atomicAdd(S.fallback, 1ULL);
       }
-      T f[7];
+      T f[8];
       hlld_flux(l, r, bn, gamma, f);
       T(*F)[MXF] = (d == 0) ? sm.a.f.fx : sm.a.f.fy;
       const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
@@ -483,12 +483,12 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
       F[1 + t1][e] = f[2];
       F[1 + t2][e] = f[3];
       F[4][e] = f[4];
-      F[5 + d][e] = T(0);
+      F[5 + d][e] = f[7];  // the normal field has no flux: the slot holds the upwind speed
       F[5 + t1][e] = f[5];
       F[5 + t2][e] = f[6];
     }
     __syncthreads();
-    // ---- P4: edge EMFs (upwinded by the mass-flux sign) and x/y flux sums
+    // ---- P4: edge EMFs (upwinded by the sign of the face upwind speed) and x/y flux sums
     {
       auto up = [](T mflux, T a, T b) -> T {
         if (mflux > T(0)) return a;
@@ -514,8 +514,8 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
           const int f = x0 + m % (TX + 1), g = y0 + m / (TX + 1);
           const T A = -sm.a.f.fx[6][XF(f, g)], B = -sm.a.f.fx[6][XF(f, g - 1)];
           const T C = sm.a.f.fy[5][YF(f, g)], D = sm.a.f.fy[5][YF(f - 1, g)];
-          const T v = edge(A, B, C, D, sm.a.f.fx[0][XF(f, g)], sm.a.f.fx[0][XF(f, g - 1)],
-                           sm.a.f.fy[0][YF(f, g)], sm.a.f.fy[0][YF(f - 1, g)], sm.ecc[pz][2][P(f - 1, g - 1)],
+          const T v = edge(A, B, C, D, sm.a.f.fx[5][XF(f, g)], sm.a.f.fx[5][XF(f, g - 1)],
+                           sm.a.f.fy[6][YF(f, g)], sm.a.f.fy[6][YF(f - 1, g)], sm.ecc[pz][2][P(f - 1, g - 1)],
                            sm.ecc[pz][2][P(f, g - 1)], sm.ecc[pz][2][P(f - 1, g)], sm.ecc[pz][2][P(f, g)]);
           sm.b.e.ez[m] = v;
         } else if (m < nez + nex) {  // E_x at z-face z, (x-cell i, y-face g)
@@ -523,7 +523,7 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
           const int i = x0 + e % TX, g = y0 + e / TX;
           const T A = -sm.a.f.fy[7][YF(i, g)], B = -sm.py[1][YF(i, g)];
           const T C = sm.fz[2][P(i, g)], D = sm.fz[2][P(i, g - 1)];
-          const T v = edge(A, B, C, D, sm.a.f.fy[0][YF(i, g)], sm.py[0][YF(i, g)], sm.fz[0][P(i, g)],
+          const T v = edge(A, B, C, D, sm.a.f.fy[6][YF(i, g)], sm.py[0][YF(i, g)], sm.fz[0][P(i, g)],
                            sm.fz[0][P(i, g - 1)], sm.ecc[pzm][0][P(i, g - 1)], sm.ecc[pzm][0][P(i, g)],
                            sm.ecc[pz][0][P(i, g - 1)], sm.ecc[pz][0][P(i, g)]);
           sm.b.e.ex[e] = v;
@@ -532,7 +532,7 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
           const int f = x0 + e % (TX + 1), j = y0 + e / (TX + 1);
           const T A = -sm.fz[1][P(f, j)], B = -sm.fz[1][P(f - 1, j)];
           const T C = sm.a.f.fx[7][XF(f, j)], D = sm.px[1][XF(f, j)];
-          const T v = edge(A, B, C, D, sm.fz[0][P(f, j)], sm.fz[0][P(f - 1, j)], sm.a.f.fx[0][XF(f, j)],
+          const T v = edge(A, B, C, D, sm.fz[0][P(f, j)], sm.fz[0][P(f - 1, j)], sm.a.f.fx[5][XF(f, j)],
                            sm.px[0][XF(f, j)], sm.ecc[pzm][1][P(f - 1, j)], sm.ecc[pz][1][P(f - 1, j)],
                            sm.ecc[pzm][1][P(f, j)], sm.ecc[pz][1][P(f, j)]);
           sm.b.e.ey[e] = v;
@@ -582,11 +582,11 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
         outp[e] = c.ownp[e] - dtdx * curl;
       }
       for (int m = tid; m < nxf; m += NTHR) {
-        sm.px[0][m] = sm.a.f.fx[0][m];
+        sm.px[0][m] = sm.a.f.fx[5][m];
         sm.px[1][m] = sm.a.f.fx[7][m];
       }
       for (int m = tid; m < nyf; m += NTHR) {
-        sm.py[0][m] = sm.a.f.fy[0][m];
+        sm.py[0][m] = sm.a.f.fy[6][m];
         sm.py[1][m] = sm.a.f.fy[7][m];
       }
 #pragma unroll

@@ -361,7 +361,7 @@ __global__ void k_flux(DevSet S, const int* __restrict__ list, int count, WorkPt
     bn = bface;
     atomicAdd(S.fallback, 1ULL);
   }
-  T f[7];
+  T f[8];
   hlld_flux(l, r, bn, T(S.gamma), f);
   T* Fp = W.f + (int64_t)b * W.f_stride + (int64_t)d * 8 * W.fm3;
   const int64_t o = wface(N, 0, idx[0], idx[1], idx[2]);
@@ -371,7 +371,7 @@ __global__ void k_flux(DevSet S, const int* __restrict__ list, int count, WorkPt
   Fp[(1 + t1) * fs + o] = f[2];
   Fp[(1 + t2) * fs + o] = f[3];
   Fp[4 * fs + o] = f[4];
-  Fp[(5 + d) * fs + o] = T(0);
+  Fp[(5 + d) * fs + o] = f[7];  // the normal field has no flux: the slot holds the upwind speed
   Fp[(5 + t1) * fs + o] = f[5];
   Fp[(5 + t2) * fs + o] = f[6];
 }
@@ -381,7 +381,8 @@ __global__ void k_flux(DevSet S, const int* __restrict__ list, int count, WorkPt
 // other two face indices in [0, n]), (a, b, c) cyclic.  Face EMFs come from
 // the induction fluxes: on b-faces E_a = -F_b[B_c], on c-faces E_a = +F_c[B_b];
 // the cell reference value is E = -v x B of the half-step state; corrections
-// are upwinded by the sign of the mass flux (Gardiner & Stone 2005).
+// are upwinded by the direction of the mass flux (Gardiner & Stone 2005),
+// taken as the sign of the face's upwind speed (HLLD f[7]).
 
 template <class T>
 __global__ void k_emf(DevSet S, const int* __restrict__ list, int count, WorkPtr<T> W) {
@@ -412,7 +413,8 @@ __global__ void k_emf(DevSet S, const int* __restrict__ list, int count, WorkPtr
   const int64_t oC = wface(N, 0, pC[0], pC[1], pC[2]), oD = wface(N, 0, pD[0], pD[1], pD[2]);
   const T A = -Fb[(5 + cax) * fs + oA], B = -Fb[(5 + cax) * fs + oB];
   const T C = Fc[(5 + bax) * fs + oC], D = Fc[(5 + bax) * fs + oD];
-  const T mA = Fb[oA], mB = Fb[oB], mC = Fc[oC], mD = Fc[oD];
+  const T mA = Fb[(5 + bax) * fs + oA], mB = Fb[(5 + bax) * fs + oB];
+  const T mC = Fc[(5 + cax) * fs + oC], mD = Fc[(5 + cax) * fs + oD];
   auto ecc = [&](int db, int dc) -> T {
     int q[3] = {e[0], e[1], e[2]};
     q[bax] += db;

@@ -26,7 +26,11 @@ __device__ __forceinline__ T fast_speed(T a2, T b2, T bt2) {
 
 // HLLD interface flux.  Rotated states (rho, un, ut1, ut2, p, bt1, bt2) on the
 // left (l) and right (r), common normal field bn.  f receives
-// (mass, mn, mt1, mt2, energy, bt1, bt2).  Regions are chosen outermost first:
+// (mass, mn, mt1, mt2, energy, bt1, bt2) and, in f[7], the upwind speed that
+// orients the edge EMFs: S_L if S_L > 0, S_R if S_R < 0, else the contact
+// speed S_M (the mass flux's sign in exact arithmetic, and exactly zero where
+// both normal velocities vanish and the total pressures agree).  Regions are
+// chosen outermost first:
 // F_L if S_L > 0, F*_L if S*_L >= 0, F**_L if S_M >= 0, F**_R if S*_R >= 0,
 // F*_R if S_R >= 0, else F_R.  Degenerate star states (vanishing
 // rho (S - u)(S - S_M) - bn^2) keep the transverse velocity and field.
@@ -64,14 +68,17 @@ __device__ __forceinline__ void hlld_flux(const T* l, const T* r, T bn, T gamma,
   };
   if (SL > T(0)) {
     phys(rl, ul, vl1, vl2, ptl, bl1, bl2, El, f);
+    f[7] = SL;
     return;
   }
   if (SR < T(0)) {
     phys(rr, ur, vr1, vr2, ptr, br1, br2, Er, f);
+    f[7] = SR;
     return;
   }
   const T dl = (SL - ul) * rl, dr = (SR - ur) * rr;
   const T SM = (dr * ur - dl * ul - ptr + ptl) / (dr - dl);
+  f[7] = SM;
   const T pts = (dr * ptl - dl * ptr + dr * dl * (ur - ul)) / (dr - dl);
 
   // single-star state of one side

@@ -148,7 +148,7 @@ def test_hlld_consistency_and_symmetry(orc):
     for _ in range(300):
         w = _rand_state(rng)
         bn = rng.normal(0, 1)
-        f = orc.hlld_flux(w, w, bn, g)
+        f = orc.hlld_flux(w, w, bn, g)[:7]
         ref = _phys_flux(w, bn, g)
         assert np.abs(f - ref).max() <= 1e-12 * (1 + np.abs(ref).max())
     # mirror: reflecting x -> -x swaps the states and flips normal components
@@ -160,8 +160,8 @@ def test_hlld_consistency_and_symmetry(orc):
         fm = orc.hlld_flux(R * flip, L * flip, -bn, g)
         # flux of the mirrored problem: normal flux of scalars changes sign,
         # normal momentum flux keeps its sign; transverse induction fluxes
-        # (b u_n - b_n v) change sign
-        expect = -f * np.array([1, -1, 1, 1, 1, 1, 1.0])
+        # (b u_n - b_n v) change sign; so does the upwind speed
+        expect = -f * np.array([1, -1, 1, 1, 1, 1, 1.0, 1.0])
         assert np.abs(fm - expect).max() <= 1e-11 * (1 + np.abs(f).max())
 
 
@@ -180,6 +180,25 @@ def test_hlld_stationary_contact_zero_mass_flux(orc):
         # A diffusive HLL flux would give ~ S_L S_R (rho_R - rho_L)/(S_R - S_L) = O(1).
         scale = max(L[0], R[0]) * (abs(bn) + math.sqrt(g * p / min(L[0], R[0])) + 3)
         assert abs(f[0]) <= 1e-14 * scale
+        # the upwind speed that orients the edge EMFs is exactly zero here
+        assert f[7] == 0.0
+
+
+def test_hlld_upwind_speed_orients_like_mass_flux(orc):
+    """The upwind speed has the sign of the mass flux wherever the latter is
+    not at rounding level, and lies inside [S_L, S_R]."""
+    rng = np.random.default_rng(14)
+    g = 5.0 / 3.0
+    checked = 0
+    for _ in range(2000):
+        L, R = _rand_state(rng), _rand_state(rng)
+        bn = rng.normal(0, 1)
+        f = orc.hlld_flux(L, R, bn, g)
+        scale = max(L[0], R[0]) * (abs(bn) + 5.0)
+        if abs(f[0]) > 1e-10 * scale:
+            assert np.sign(f[7]) == np.sign(f[0])
+            checked += 1
+    assert checked > 1500
 
 
 # ---------------------------------------------------------------------------
