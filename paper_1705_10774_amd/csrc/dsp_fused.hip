@@ -69,10 +69,10 @@ template <class T> struct StepSmem {
 };
 
 // primitives of one cell from guard-filled values
-template <class T>
+template <class T, class M = Exact<T>>
 __device__ __forceinline__ void prim_of(T rho, T m0, T m1, T m2, T en, T bx, T by, T bz, T gamma,
                                         T pfloor, T* w) {
-  const T ir = T(1) / rho;
+  const T ir = M::rcp(rho);
   w[0] = rho;
   w[1] = m0 * ir;
   w[2] = m1 * ir;
@@ -92,7 +92,7 @@ template <class T> struct PatchCtx {
 
 // guard-filled primitives of cell (i, j, k); the fields on its three low
 // faces are returned too (outputs are written last, so they may alias)
-template <class T>
+template <class T, class M = Exact<T>>
 __device__ __forceinline__ void load_cell(const PatchCtx<T>& c, const RegionTab<T>& rt, int i, int j, int k,
                                           T gamma, T pfloor, T* w, T& bxl, T& byl, T& bzl) {
   const T rho = fetch_fast(c.ownp, c.n, rt, -1, 0, i, j, k);
@@ -106,21 +106,22 @@ __device__ __forceinline__ void load_cell(const PatchCtx<T>& c, const RegionTab<
   const T yr = fetch_fast(c.ownp, c.n, rt, 1, 0, i, j + 1, k);
   const T zl = fetch_fast(c.ownp, c.n, rt, 2, 0, i, j, k);
   const T zr = fetch_fast(c.ownp, c.n, rt, 2, 0, i, j, k + 1);
-  prim_of(rho, m0, m1, m2, en, T(0.5) * (xl + xr), T(0.5) * (yl + yr), T(0.5) * (zl + zr), gamma, pfloor, w);
+  prim_of<T, M>(rho, m0, m1, m2, en, T(0.5) * (xl + xr), T(0.5) * (yl + yr), T(0.5) * (zl + zr), gamma, pfloor,
+                w);
   bxl = xl;
   byl = yl;
   bzl = zl;
 }
 
-// first-order fallback states of an x- (d = 0) or y-face (d = 1) of plane z:
-// the primitives at t^n of the two cells beside the face (cell (i, j) right
-// of or above the face), rotated to the face normal.  Rare; kept out of line.
-template <class T>
+// first-order fallback states of a face along d: the primitives at t^n of
+// the two cells beside it (cell (i, j, z) on its upper side), rotated to the
+// face normal.  Rare; kept out of line.
+template <class T, class M = Exact<T>>
 __device__ __attribute__((noinline)) void fallback_states(const PatchCtx<T>& c, const RegionTab<T>& rt, int d,
                                                           int i, int j, int z, T gamma, T pfloor, T* l, T* r) {
   T wa[8], wb[8], dmy;
-  load_cell(c, rt, d == 0 ? i - 1 : i, d == 0 ? j : j - 1, z, gamma, pfloor, wa, dmy, dmy, dmy);
-  load_cell(c, rt, i, j, z, gamma, pfloor, wb, dmy, dmy, dmy);
+  load_cell<T, M>(c, rt, i - (d == 0), j - (d == 1), z - (d == 2), gamma, pfloor, wa, dmy, dmy, dmy);
+  load_cell<T, M>(c, rt, i, j, z, gamma, pfloor, wb, dmy, dmy, dmy);
   const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
   const int ord[7] = {0, 1 + d, 1 + t1, 1 + t2, 4, 5 + t1, 5 + t2};
   for (int q = 0; q < 7; ++q) {
@@ -244,6 +245,23 @@ __global__ __launch_bounds__(256) void k_courant(DevSet S, const int* __restrict
 // ---------------------------------------------------------------------------
 // the fused step
 
+// Algorithmic HBM traffic of one patch update, added to S.algo_bytes: the own
+// slice read and written once, every guard value of the two stencil layers
+// read from one slice (exact time) or two (interpolated).  Called by every
+// thread of the first tile's workgroup (one box per thread, summed in LDS);
+// the caller synchronises the workgroup before thread 0 publishes the sum.
+__device__ inline void count_traffic(const DevSet& S, int p, int box0, int nbox, int64_t V, int tsz, int tid,
+                                     int nthr, unsigned long long* acc) {
+  if (tid == 0) atomicAdd(acc, 2ULL * (unsigned long long)V * (unsigned long long)tsz);
+  for (int m = tid; m < nbox; m += nthr) {
+    const GBox& G = S.boxes[box0 + m];
+    const Bracket b = bracket(S, G.q, S.ticks[p], S.tcur[p]);
+    const unsigned long long cnt =
+        (unsigned long long)(G.hi[0] - G.lo[0] + 1) * (G.hi[1] - G.lo[1] + 1) * (G.hi[2] - G.lo[2] + 1);
+    atomicAdd(acc, cnt * (b.oa == b.ob ? 1ULL : 2ULL) * (unsigned long long)tsz);
+  }
+}
+
 // x-face flux of plane z with face index f (left cell f-1) and row j, from the
 // predictor buffers; rotated order (rho, un, ut1, ut2, p, bt1, bt2)
 template <class T>
@@ -290,23 +308,14 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
   for (int m = tid; m < 108; m += NTHR)
     region_tab_init(S, (const T*)slots, pad + (int64_t)bidx * pad_stride, n + 4, c.p, sm.rt, m);
   const T gamma = T(S.gamma), pfloor = T(S.p_floor);
-  if (tile == 0 && tid == 0) {
-    // algorithmic traffic of this patch update: own slice read and written,
-    // every guard value of the two stencil layers read from one slice (exact
-    // time) or two (interpolated)
-    unsigned long long vals = 2ULL * (unsigned long long)V;
-    for (int m = 0; m < nbox; ++m) {
-      const GBox& G = S.boxes[box0 + m];
-      const Bracket b = bracket(S, G.q, S.ticks[c.p], S.tcur[c.p]);
-      const unsigned long long cnt =
-          (unsigned long long)(G.hi[0] - G.lo[0] + 1) * (G.hi[1] - G.lo[1] + 1) * (G.hi[2] - G.lo[2] + 1);
-      vals += cnt * (b.oa == b.ob ? 1ULL : 2ULL);
-    }
-    atomicAdd(S.algo_bytes, vals * (unsigned long long)sizeof(T));
-  }
+  __shared__ unsigned long long traffic;
+  if (tid == 0) traffic = 0;
+  __syncthreads();
+  if (tile == 0) count_traffic(S, c.p, box0, nbox, V, (int)sizeof(T), tid, NTHR, &traffic);
   const T dtdx = T(st.dt[bidx] / S.dx[c.p]);
   const T hdtdx = T(0.5) * dtdx;
   __syncthreads();
+  if (tile == 0 && tid == 0) atomicAdd(S.algo_bytes, traffic);
 
   // column of this thread
   const bool col = tid < CX * CY;
@@ -608,6 +617,373 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+// The fused step, wide variant (single precision): 1024 threads per tile.
+// The three planes of primitives the z-slopes need live in an LDS ring instead
+// of registers, and the x-, y- and z-face Riemann problems of a plane are
+// solved in one phase (about one face per thread), so the per-thread state
+// carried through the march is a handful of registers and four waves share
+// each SIMD.
+
+constexpr int NTHR2 = 1024;
+
+template <class T> struct Step2Smem {
+  T w[3][8][MCOL];      // primitives of planes z-1, z, z+1 (slot = plane mod 3)
+  T bfc[2][3][MCOL];    // t^n field on the low x-, y- and z-face of each column (slot = plane mod 2)
+  union B {
+    struct {
+      T h[8][MPRED];    // half-step primitives
+      T sx[8][MPRED];   // x-slopes
+      T sy[8][MPRED];   // y-slopes
+      T db[2][MPRED];   // predictor increments of the cell-centred Bx, By
+    } p;
+    struct {
+      T ez[(MT + 1) * (MT + 1)];
+      T ex[MT * (MT + 1)];
+      T ey[(MT + 1) * MT];
+    } e;
+  } b;
+  T fx[8][MXF];         // x-face fluxes of plane z (slot 5: upwind speed)
+  T fy[8][MXF];         // y-face fluxes of plane z (slot 6: upwind speed)
+  T fz[8][MPRED];       // face z: mass, mx, my, mz, energy, Bx and By induction, upwind speed
+  T zt[2][7][MPRED];    // top face state (z-rotated order) of each cell (slot = plane mod 2)
+  T zb[7][MPRED];       // bottom face state of plane z
+  T dz[2][MPRED];       // predictor increment of the cell-centred Bz (slot = plane mod 2)
+  T px[2][MXF];         // previous plane: x-face upwind speed and Bz induction flux
+  T py[2][MXF];         // previous plane: y-face upwind speed and Bz induction flux
+  T ecc[2][3][MPRED];   // cell-centred EMF -v x B of the half-step state (slot = plane mod 2)
+  RegionTab<T> rt;
+};
+
+__device__ __forceinline__ int mod3(int z) { return (z + 3) % 3; }
+
+template <class T>
+__global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict__ list, int count,
+                                                 T* __restrict__ slots, const T* __restrict__ pad,
+                                                 int64_t pad_stride, StepPtr st, int tpa) {
+  static_assert(sizeof(T) == 4, "the wide step kernel is the single-precision variant");
+  using M = FastF32;
+  __shared__ Step2Smem<T> sm;
+  const int tid = threadIdx.x;
+  const int T2 = tpa * tpa;
+  const int wg = blockIdx.x;
+  const int bidx = (wg / (8 * T2)) * 8 + (wg % 8);
+  const int tile = (wg / 8) % T2;
+  if (bidx >= count) return;
+  PatchCtx<T> c;
+  c.p = list[bidx];
+  const int n = c.n = S.n[c.p];
+  const int nt = (n + MT - 1) / MT;
+  const int tx = tile % tpa, ty = tile / tpa;
+  if (tx >= nt || ty >= nt) return;
+  const int x0 = tx * n / nt, x1 = (tx + 1) * n / nt;
+  const int y0 = ty * n / nt, y1 = (ty + 1) * n / nt;
+  const int TX = x1 - x0, TY = y1 - y0;
+  const int CX = TX + 4, CY = TY + 4, PX = TX + 2, PY = TY + 2;
+  const bool lastx = (x1 == n), lasty = (y1 == n), firstx = (x0 == 0), firsty = (y0 == 0);
+  const int box0 = S.rbox_off[c.p * 108];
+  const int nbox = S.rbox_off[c.p * 108 + 108] - box0;
+  const int64_t V = S.slice_len[c.p];
+  const int64_t own = S.slot_off[c.p] + (int64_t)S.cur[c.p] * V;
+  T* const outp = slots + S.slot_off[c.p] + (int64_t)((S.cur[c.p] + 1) % S.nslots) * V;
+  c.ownp = slots + own;
+  for (int m = tid; m < 108; m += NTHR2)
+    region_tab_init(S, (const T*)slots, pad + (int64_t)bidx * pad_stride, n + 4, c.p, sm.rt, m);
+  const T gamma = T(S.gamma), pfloor = T(S.p_floor);
+  __shared__ unsigned long long traffic;
+  if (tid == 0) traffic = 0;
+  __syncthreads();
+  if (tile == 0) count_traffic(S, c.p, box0, nbox, V, (int)sizeof(T), tid, NTHR2, &traffic);
+  const T dtdx = T(st.dt[bidx] / S.dx[c.p]);
+  const T hdtdx = T(0.5) * dtdx;
+  __syncthreads();
+  if (tile == 0 && tid == 0) atomicAdd(S.algo_bytes, traffic);
+
+  // column of this thread (load phase) and its predictor cell
+  const bool col = tid < CX * CY;
+  const int ca = tid % CX, cb = tid / CX;
+  const int ci = x0 - 2 + ca, cj = y0 - 2 + cb;
+  const bool pred = col && ca >= 1 && ca <= CX - 2 && cb >= 1 && cb <= CY - 2;
+  const int pc = (ca - 1) + (cb - 1) * PX;
+  const bool own_cell = col && ci >= x0 && ci < x1 && cj >= y0 && cj < y1;
+  const bool own_bx = col && cj >= y0 && cj < y1 && ((ci >= x0 && ci < x1) || (lastx && ci == n));
+  const bool own_by = col && ci >= x0 && ci < x1 && ((cj >= y0 && cj < y1) || (lasty && cj == n));
+  auto own_c = [&](int v, int lo, int hi, bool first, bool last) {
+    return (v >= lo && v < hi) || (first && v < 0) || (last && v >= n);
+  };
+  auto load_plane = [&](int z) {  // primitives and low-face fields of plane z into the rings
+    T wv[8], bx, by, bz;
+    load_cell<T, M>(c, sm.rt, ci, cj, z, gamma, pfloor, wv, bx, by, bz);
+    const int s3 = mod3(z), s2 = z & 1;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) sm.w[s3][v][tid] = wv[v];
+    sm.bfc[s2][0][tid] = bx;
+    sm.bfc[s2][1][tid] = by;
+    sm.bfc[s2][2][tid] = bz;
+  };
+  if (col) {
+    load_plane(-2);
+    load_plane(-1);
+  }
+  T acc[5];  // x/y flux differences of the pending cell minus its bottom z-flux
+  T dnew[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) acc[q] = dnew[q] = T(0);
+  T pbx = 0, pby = 0;
+  const int nxf = (TX + 1) * (TY + 2), nyf = (TX + 2) * (TY + 1), nzf = PX * PY;
+
+  for (int z = -1; z <= n; ++z) {
+    // ---- P1: load plane z+1
+    if (col) load_plane(z + 1);
+    __syncthreads();
+    // ---- P2: slopes, Hancock predictor, z-face states and cell EMF of plane z
+    if (pred) {
+      const int sm3 = mod3(z - 1), s0 = mod3(z), sp3 = mod3(z + 1);
+      T W0[8], sl[3][8];
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const T c0 = sm.w[s0][v][tid];
+        W0[v] = c0;
+        sl[0][v] = van_leer<T, M>(c0 - sm.w[s0][v][tid - 1], sm.w[s0][v][tid + 1] - c0);
+        sl[1][v] = van_leer<T, M>(c0 - sm.w[s0][v][tid - CX], sm.w[s0][v][tid + CX] - c0);
+        sl[2][v] = van_leer<T, M>(c0 - sm.w[sm3][v][tid], sm.w[sp3][v][tid] - c0);
+      }
+      sl[0][5] = T(0);
+      sl[1][6] = T(0);
+      sl[2][7] = T(0);
+      const T ir = M::rcp(W0[0]);
+      T sum[8];
+#pragma unroll
+      for (int v = 0; v < 8; ++v) sum[v] = T(0);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+        const T un = W0[1 + d], bn = W0[5 + d], b1 = W0[5 + t1], b2 = W0[5 + t2];
+        const T* s = sl[d];
+        sum[0] = sum[0] + (un * s[0] + W0[0] * s[1 + d]);
+        sum[1 + d] = sum[1 + d] + (un * s[1 + d] + (s[4] + b1 * s[5 + t1] + b2 * s[5 + t2]) * ir);
+        sum[1 + t1] = sum[1 + t1] + (un * s[1 + t1] - bn * s[5 + t1] * ir);
+        sum[1 + t2] = sum[1 + t2] + (un * s[1 + t2] - bn * s[5 + t2] * ir);
+        sum[4] = sum[4] + (un * s[4] + gamma * W0[4] * s[1 + d]);
+        sum[5 + t1] = sum[5 + t1] + (un * s[5 + t1] + b1 * s[1 + d] - bn * s[1 + t1]);
+        sum[5 + t2] = sum[5 + t2] + (un * s[5 + t2] + b2 * s[1 + d] - bn * s[1 + t2]);
+      }
+      T H[8];
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        H[v] = W0[v] - hdtdx * sum[v];
+        sm.b.p.h[v][pc] = H[v];
+        sm.b.p.sx[v][pc] = sl[0][v];
+        sm.b.p.sy[v][pc] = sl[1][v];
+      }
+      sm.b.p.db[0][pc] = H[5] - W0[5];
+      sm.b.p.db[1][pc] = H[6] - W0[6];
+      sm.dz[z & 1][pc] = H[7] - W0[7];
+      const int ord[7] = {0, 3, 1, 2, 4, 5, 6};  // z-rotated: rho, vz, vx, vy, p, bx, by
+#pragma unroll
+      for (int m = 0; m < 7; ++m) {
+        sm.zt[z & 1][m][pc] = H[ord[m]] + T(0.5) * sl[2][ord[m]];
+        sm.zb[m][pc] = H[ord[m]] - T(0.5) * sl[2][ord[m]];
+      }
+      sm.ecc[z & 1][0][pc] = H[3] * H[6] - H[2] * H[7];
+      sm.ecc[z & 1][1][pc] = H[1] * H[7] - H[3] * H[5];
+      sm.ecc[z & 1][2][pc] = H[2] * H[5] - H[1] * H[6];
+    }
+    __syncthreads();
+    // ---- P3: x- and y-face fluxes of plane z, z-face fluxes at face z
+    const int nface = nxf + nyf + (z >= 0 ? nzf : 0);
+    for (int m = tid; m < nface; m += NTHR2) {
+      T l[7], r[7], bn, f[8];
+      if (m < nxf + nyf) {
+        const int d = (m < nxf) ? 0 : 1;
+        int e, pa, pb, cix, cjx;
+        T bface;
+        if (d == 0) {
+          e = m;
+          const int fl = e % (TX + 1), jr = e / (TX + 1);
+          pa = fl + jr * PX;
+          pb = pa + 1;
+          cix = x0 + fl;
+          cjx = y0 - 1 + jr;
+        } else {
+          e = m - nxf;
+          const int ir = e % (TX + 2), gl = e / (TX + 2);
+          pa = ir + gl * PX;
+          pb = pa + PX;
+          cix = x0 - 1 + ir;
+          cjx = y0 + gl;
+        }
+        bface = sm.bfc[z & 1][d][(cix - (x0 - 2)) + (cjx - (y0 - 2)) * CX];
+        const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+        const T(*slp)[MPRED] = (d == 0) ? sm.b.p.sx : sm.b.p.sy;
+        const int ord[7] = {0, 1 + d, 1 + t1, 1 + t2, 4, 5 + t1, 5 + t2};
+#pragma unroll
+        for (int q = 0; q < 7; ++q) {
+          const int v = ord[q];
+          l[q] = sm.b.p.h[v][pa] + T(0.5) * slp[v][pa];
+          r[q] = sm.b.p.h[v][pb] - T(0.5) * slp[v][pb];
+        }
+        bn = bface + T(0.5) * (sm.b.p.db[d][pa] + sm.b.p.db[d][pb]);
+        if (!(l[0] > T(0)) || !(l[4] > T(0)) || !(r[0] > T(0)) || !(r[4] > T(0))) {
+          fallback_states<T, M>(c, sm.rt, d, cix, cjx, z, gamma, pfloor, l, r);
+          bn = bface;
+          const bool owned = (d == 0) ? (own_c(cix, x0, x1, firstx, false) || (lastx && cix == n)) &&
+                                            own_c(cjx, y0, y1, firsty, lasty)
+                                      : own_c(cix, x0, x1, firstx, lastx) &&
+                                            (own_c(cjx, y0, y1, firsty, false) || (lasty && cjx == n));
+          if (owned) atomicAdd(S.fallback, 1ULL);
+        }
+        hlld_flux<T, M>(l, r, bn, gamma, f);
+        T(*F)[MXF] = (d == 0) ? sm.fx : sm.fy;
+        F[0][e] = f[0];
+        F[1 + d][e] = f[1];
+        F[1 + t1][e] = f[2];
+        F[1 + t2][e] = f[3];
+        F[4][e] = f[4];
+        F[5 + d][e] = f[7];  // the normal field has no flux: the slot holds the upwind speed
+        F[5 + t1][e] = f[5];
+        F[5 + t2][e] = f[6];
+      } else {
+        const int q = m - nxf - nyf;  // predictor cell of the face's upper cell
+        const int qa = q % PX, qb = q / PX;
+        const int cix = x0 - 1 + qa, cjx = y0 - 1 + qb;
+        const int cq = (qa + 1) + (qb + 1) * CX;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+          l[k] = sm.zt[(z - 1) & 1][k][q];
+          r[k] = sm.zb[k][q];
+        }
+        const T bface = sm.bfc[z & 1][2][cq];
+        bn = bface + T(0.5) * (sm.dz[(z - 1) & 1][q] + sm.dz[z & 1][q]);
+        if (!(l[0] > T(0)) || !(l[4] > T(0)) || !(r[0] > T(0)) || !(r[4] > T(0))) {
+          fallback_states<T, M>(c, sm.rt, 2, cix, cjx, z, gamma, pfloor, l, r);
+          bn = bface;
+          if (own_c(cix, x0, x1, firstx, lastx) && own_c(cjx, y0, y1, firsty, lasty)) atomicAdd(S.fallback, 1ULL);
+        }
+        hlld_flux<T, M>(l, r, bn, gamma, f);
+        sm.fz[0][q] = f[0];
+        sm.fz[1][q] = f[2];
+        sm.fz[2][q] = f[3];
+        sm.fz[3][q] = f[1];
+        sm.fz[4][q] = f[4];
+        sm.fz[5][q] = f[5];
+        sm.fz[6][q] = f[6];
+        sm.fz[7][q] = f[7];
+      }
+    }
+    __syncthreads();
+    // ---- P4: edge EMFs (upwinded by the sign of the face upwind speed) and x/y flux sums
+    // The t^n values that P5 updates are requested first, so their latency
+    // overlaps the edge work.
+    T old[8];
+    {
+      const int zc = z - 1;
+      if (own_cell && z >= 1) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) old[q] = c.ownp[scell(n, q, ci, cj, zc)];
+      }
+      if (own_bx && z >= 1) old[5] = c.ownp[sface(n, 0, ci, cj, zc)];
+      if (own_by && z >= 1) old[6] = c.ownp[sface(n, 1, ci, cj, zc)];
+      if (own_cell && z >= 0) old[7] = c.ownp[sface(n, 2, ci, cj, z)];
+    }
+    {
+      auto up = [](T u, T a, T b) -> T {
+        if (u > T(0)) return a;
+        if (u < T(0)) return b;
+        return T(0.5) * (a + b);
+      };
+      auto edge = [&](T A, T B, T C, T D, T uA, T uB, T uC, T uD, T c00, T c10, T c01, T c11) -> T {
+        const T dc14 = up(uA, c01 - D, c11 - C);
+        const T dc34 = up(uB, D - c00, C - c10);
+        const T db14 = up(uC, c10 - B, c11 - A);
+        const T db34 = up(uD, B - c00, A - c01);
+        return T(0.25) * (A + B + C + D) + T(0.25) * ((dc34 - dc14) + (db34 - db14));
+      };
+      const int pz = z & 1, pzm = (z - 1) & 1;
+      auto P = [&](int i, int j) { return (i - (x0 - 1)) + (j - (y0 - 1)) * PX; };
+      auto XF = [&](int f, int j) { return (f - x0) + (j - (y0 - 1)) * (TX + 1); };
+      auto YF = [&](int i, int g) { return (i - (x0 - 1)) + (g - y0) * (TX + 2); };
+      const int nez = (z >= 0 && z < n) ? (TX + 1) * (TY + 1) : 0;
+      const int nex = (z >= 0) ? TX * (TY + 1) : 0;
+      const int ney = (z >= 0) ? (TX + 1) * TY : 0;
+      for (int m = tid; m < nez + nex + ney; m += NTHR2) {
+        if (m < nez) {  // E_z in plane z at (x-face f, y-face g)
+          const int f = x0 + m % (TX + 1), g = y0 + m / (TX + 1);
+          const T A = -sm.fx[6][XF(f, g)], B = -sm.fx[6][XF(f, g - 1)];
+          const T C = sm.fy[5][YF(f, g)], D = sm.fy[5][YF(f - 1, g)];
+          sm.b.e.ez[m] = edge(A, B, C, D, sm.fx[5][XF(f, g)], sm.fx[5][XF(f, g - 1)], sm.fy[6][YF(f, g)],
+                              sm.fy[6][YF(f - 1, g)], sm.ecc[pz][2][P(f - 1, g - 1)], sm.ecc[pz][2][P(f, g - 1)],
+                              sm.ecc[pz][2][P(f - 1, g)], sm.ecc[pz][2][P(f, g)]);
+        } else if (m < nez + nex) {  // E_x at z-face z, (x-cell i, y-face g)
+          const int e = m - nez;
+          const int i = x0 + e % TX, g = y0 + e / TX;
+          const T A = -sm.fy[7][YF(i, g)], B = -sm.py[1][YF(i, g)];
+          const T C = sm.fz[6][P(i, g)], D = sm.fz[6][P(i, g - 1)];
+          sm.b.e.ex[e] = edge(A, B, C, D, sm.fy[6][YF(i, g)], sm.py[0][YF(i, g)], sm.fz[7][P(i, g)],
+                              sm.fz[7][P(i, g - 1)], sm.ecc[pzm][0][P(i, g - 1)], sm.ecc[pzm][0][P(i, g)],
+                              sm.ecc[pz][0][P(i, g - 1)], sm.ecc[pz][0][P(i, g)]);
+        } else {  // E_y at z-face z, (x-face f, y-cell j)
+          const int e = m - nez - nex;
+          const int f = x0 + e % (TX + 1), j = y0 + e / (TX + 1);
+          const T A = -sm.fz[5][P(f, j)], B = -sm.fz[5][P(f - 1, j)];
+          const T C = sm.fx[7][XF(f, j)], D = sm.px[1][XF(f, j)];
+          sm.b.e.ey[e] = edge(A, B, C, D, sm.fz[7][P(f, j)], sm.fz[7][P(f - 1, j)], sm.fx[5][XF(f, j)],
+                              sm.px[0][XF(f, j)], sm.ecc[pzm][1][P(f - 1, j)], sm.ecc[pz][1][P(f - 1, j)],
+                              sm.ecc[pzm][1][P(f, j)], sm.ecc[pz][1][P(f, j)]);
+        }
+      }
+      if (own_cell && z >= 0 && z < n) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q)
+          dnew[q] = (sm.fx[q][XF(ci + 1, cj)] - sm.fx[q][XF(ci, cj)]) +
+                    (sm.fy[q][YF(ci, cj + 1)] - sm.fy[q][YF(ci, cj)]);
+      }
+    }
+    __syncthreads();
+    // ---- P5: write plane z-1 (cells, Bx, By) and face z (Bz); carry partials
+    {
+      auto EZ = [&](int f, int g) { return sm.b.e.ez[(f - x0) + (g - y0) * (TX + 1)]; };
+      auto EX = [&](int i, int g) { return sm.b.e.ex[(i - x0) + (g - y0) * TX]; };
+      auto EY = [&](int f, int j) { return sm.b.e.ey[(f - x0) + (j - y0) * (TX + 1)]; };
+      if (own_cell && z >= 0) {
+        T fzc[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) fzc[q] = sm.fz[q][pc];
+        if (z >= 1) {
+#pragma unroll
+          for (int q = 0; q < 5; ++q) {
+            outp[scell(n, q, ci, cj, z - 1)] = old[q] - dtdx * (acc[q] + fzc[q]);
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 5; ++q) acc[q] = dnew[q] - fzc[q];
+      }
+      if (z >= 1) {
+        const int zc = z - 1;
+        if (own_bx) outp[sface(n, 0, ci, cj, zc)] = old[5] - dtdx * (pbx - EY(ci, cj));
+        if (own_by) outp[sface(n, 1, ci, cj, zc)] = old[6] - dtdx * (pby + EX(ci, cj));
+      }
+      if (z >= 0 && z < n) {
+        if (own_bx) pbx = (EZ(ci, cj + 1) - EZ(ci, cj)) + EY(ci, cj);
+        if (own_by) pby = -EX(ci, cj) - (EZ(ci + 1, cj) - EZ(ci, cj));
+      }
+      if (z >= 0 && own_cell) {
+        const T curl = (EY(ci + 1, cj) - EY(ci, cj)) - (EX(ci, cj + 1) - EX(ci, cj));
+        outp[sface(n, 2, ci, cj, z)] = old[7] - dtdx * curl;
+      }
+      for (int m = tid; m < nxf; m += NTHR2) {
+        sm.px[0][m] = sm.fx[5][m];
+        sm.px[1][m] = sm.fx[7][m];
+      }
+      for (int m = tid; m < nyf; m += NTHR2) {
+        sm.py[0][m] = sm.fy[6][m];
+        sm.py[1][m] = sm.fy[7][m];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 
 template <class T>
 void launch_fused(const DevSet& S, const int* list, int count, int nmax, T* slots, T* pad, int64_t pad_stride,
@@ -625,8 +1001,12 @@ void launch_fused(const DevSet& S, const int* list, int count, int nmax, T* slot
   const int T2 = tpa * tpa;
   const int groups = ((count + 7) / 8) * 8 * T2;
   if (ev0) (void)hipEventRecord(ev0, s);
-  hipLaunchKernelGGL(k_step<T>, dim3(groups), dim3(NTHR), 0, s, S, list, count, slots, (const T*)pad, pad_stride,
-                     st, tpa);
+  if constexpr (sizeof(T) == 4)
+    hipLaunchKernelGGL(k_step2<T>, dim3(groups), dim3(NTHR2), 0, s, S, list, count, slots, (const T*)pad,
+                       pad_stride, st, tpa);
+  else
+    hipLaunchKernelGGL(k_step<T>, dim3(groups), dim3(NTHR), 0, s, S, list, count, slots, (const T*)pad, pad_stride,
+                       st, tpa);
   if (ev1) (void)hipEventRecord(ev1, s);
 }
 

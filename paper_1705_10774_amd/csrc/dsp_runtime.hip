@@ -289,9 +289,39 @@ struct dsp_set {
               const int64_t vol = (int64_t)(bhi[0] - blo[0] + 1) * (bhi[1] - blo[1] + 1) * (bhi[2] - blo[2] + 1);
               if (covered != vol) return fail(DSP_EINVAL, "guard zone not covered by exactly one patch (overlap?)");
             }
+            merge_boxes(per_key[key]);
           }
     }
     return 0;
+  }
+
+  // Join boxes of one region that read the same source the same way and
+  // tile a larger box (the split at the patch centre usually leaves two such
+  // halves), so most regions end up as one box.
+  static void merge_boxes(std::vector<GBox>& v) {
+    auto alike = [](const GBox& a, const GBox& b) {
+      if (a.q != b.q || a.same != b.same) return false;
+      for (int d = 0; d < 3; ++d)
+        if (a.shift[d] != b.shift[d] || a.wrap[d] != b.wrap[d]) return false;
+      return true;
+    };
+    for (bool changed = true; changed;) {
+      changed = false;
+      for (size_t x = 0; x < v.size() && !changed; ++x)
+        for (size_t y = 0; y < v.size() && !changed; ++y) {
+          if (x == y || !alike(v[x], v[y])) continue;
+          for (int d = 0; d < 3; ++d) {
+            const int e = (d + 1) % 3, f = (d + 2) % 3;
+            if (v[x].hi[d] + 1 == v[y].lo[d] && v[x].lo[e] == v[y].lo[e] && v[x].hi[e] == v[y].hi[e] &&
+                v[x].lo[f] == v[y].lo[f] && v[x].hi[f] == v[y].hi[f]) {
+              v[x].hi[d] = v[y].hi[d];
+              v.erase(v.begin() + (long)y);
+              changed = true;
+              break;
+            }
+          }
+        }
+    }
   }
 
   template <class T> WorkPtr<T> work() const {
@@ -513,6 +543,7 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
         if (!(m1 - m0 == 1 && boxes[m0].same)) ++ngen;
       }
     S->any_generic = ngen > 0;
+    if (getenv("DSP_DEBUG")) fprintf(stderr, "dsp_create: %d guard regions need the padded buffer\n", ngen);
     if (getenv("DSP_DEBUG"))
       fprintf(stderr, "dsp_create: %d patches, nmax %d, max guard boxes per patch %d, %s path\n", npatch,
               S->nmax, maxbox, S->fused ? "fused" : "staged");

@@ -12,16 +12,31 @@
 
 namespace dsp {
 
+// Arithmetic policy of the stencil.  Exact: IEEE division and square root.
+// FastF32: the hardware reciprocal and square root (about 1 ulp each), for
+// the single-precision step kernel, whose results are held to the
+// single-precision tolerance anyway.
+template <class T> struct Exact {
+  static __device__ __forceinline__ T rcp(T x) { return T(1) / x; }
+  static __device__ __forceinline__ T div(T a, T b) { return a / b; }
+  static __device__ __forceinline__ T root(T x) { return sqrt(x); }
+};
+struct FastF32 {
+  static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+  static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+  static __device__ __forceinline__ float root(float x) { return __builtin_amdgcn_sqrtf(x); }
+};
+
 template <class T> struct Eps;
 template <> struct Eps<float> { static constexpr float deg = 1e-5f; };
 template <> struct Eps<double> { static constexpr double deg = 1e-12; };
 
 // Fast magnetosonic speed from a^2 = gamma p / rho, b^2 = |B|^2 / rho and the
 // transverse part bt^2: cf^2 = (a^2 + b^2 + sqrt((a^2 - b^2)^2 + 4 a^2 bt^2)) / 2.
-template <class T>
+template <class T, class M = Exact<T>>
 __device__ __forceinline__ T fast_speed(T a2, T b2, T bt2) {
   T d = a2 - b2;
-  return sqrt(T(0.5) * (a2 + b2 + sqrt(d * d + T(4) * a2 * bt2)));
+  return M::root(T(0.5) * (a2 + b2 + M::root(d * d + T(4) * a2 * bt2)));
 }
 
 // HLLD interface flux.  Rotated states (rho, un, ut1, ut2, p, bt1, bt2) on the
@@ -34,22 +49,22 @@ __device__ __forceinline__ T fast_speed(T a2, T b2, T bt2) {
 // F_L if S_L > 0, F*_L if S*_L >= 0, F**_L if S_M >= 0, F**_R if S*_R >= 0,
 // F*_R if S_R >= 0, else F_R.  Degenerate star states (vanishing
 // rho (S - u)(S - S_M) - bn^2) keep the transverse velocity and field.
-template <class T>
+template <class T, class M = Exact<T>>
 __device__ __forceinline__ void hlld_flux(const T* l, const T* r, T bn, T gamma, T* f) {
   const T gm1 = gamma - T(1);
   const T bn2 = bn * bn;
   // left
   const T rl = l[0], ul = l[1], vl1 = l[2], vl2 = l[3], pl = l[4], bl1 = l[5], bl2 = l[6];
   const T bbl = bn2 + bl1 * bl1 + bl2 * bl2;
-  const T El = pl / gm1 + T(0.5) * rl * (ul * ul + vl1 * vl1 + vl2 * vl2) + T(0.5) * bbl;
+  const T El = M::div(pl, gm1) + T(0.5) * rl * (ul * ul + vl1 * vl1 + vl2 * vl2) + T(0.5) * bbl;
   const T ptl = pl + T(0.5) * bbl;
-  const T cfl = fast_speed(gamma * pl / rl, bbl / rl, (bl1 * bl1 + bl2 * bl2) / rl);
+  const T cfl = fast_speed<T, M>(M::div(gamma * pl, rl), M::div(bbl, rl), M::div(bl1 * bl1 + bl2 * bl2, rl));
   // right
   const T rr = r[0], ur = r[1], vr1 = r[2], vr2 = r[3], pr = r[4], br1 = r[5], br2 = r[6];
   const T bbr = bn2 + br1 * br1 + br2 * br2;
-  const T Er = pr / gm1 + T(0.5) * rr * (ur * ur + vr1 * vr1 + vr2 * vr2) + T(0.5) * bbr;
+  const T Er = M::div(pr, gm1) + T(0.5) * rr * (ur * ur + vr1 * vr1 + vr2 * vr2) + T(0.5) * bbr;
   const T ptr = pr + T(0.5) * bbr;
-  const T cfr = fast_speed(gamma * pr / rr, bbr / rr, (br1 * br1 + br2 * br2) / rr);
+  const T cfr = fast_speed<T, M>(M::div(gamma * pr, rr), M::div(bbr, rr), M::div(br1 * br1 + br2 * br2, rr));
 
   const T cmax = (cfl < cfr) ? cfr : cfl;
   const T SL = ((ur < ul) ? ur : ul) - cmax;
@@ -77,9 +92,9 @@ __device__ __forceinline__ void hlld_flux(const T* l, const T* r, T bn, T gamma,
     return;
   }
   const T dl = (SL - ul) * rl, dr = (SR - ur) * rr;
-  const T SM = (dr * ur - dl * ul - ptr + ptl) / (dr - dl);
+  const T SM = M::div(dr * ur - dl * ul - ptr + ptl, dr - dl);
   f[7] = SM;
-  const T pts = (dr * ptl - dl * ptr + dr * dl * (ur - ul)) / (dr - dl);
+  const T pts = M::div(dr * ptl - dl * ptr + dr * dl * (ur - ul), dr - dl);
 
   // single-star state of one side
   struct Star {
@@ -87,14 +102,14 @@ __device__ __forceinline__ void hlld_flux(const T* l, const T* r, T bn, T gamma,
   };
   auto star = [&](T rho, T u, T v1, T v2, T pt, T b1, T b2, T E, T S, T d) {
     Star s;
-    s.rho = d / (S - SM);
+    s.rho = M::div(d, S - SM);
     const T den = d * (S - SM) - bn2;
     const T lim = Eps<T>::deg * (d * (S - u) + bn2);
     if (fabs(den) <= lim) {
       s.v1 = v1; s.v2 = v2; s.b1 = b1; s.b2 = b2;
     } else {
-      const T cv = bn * (SM - u) / den;
-      const T cb = (d * (S - u) - bn2) / den;
+      const T cv = M::div(bn * (SM - u), den);
+      const T cb = M::div(d * (S - u) - bn2, den);
       s.v1 = v1 - b1 * cv;
       s.v2 = v2 - b2 * cv;
       s.b1 = b1 * cb;
@@ -102,14 +117,14 @@ __device__ __forceinline__ void hlld_flux(const T* l, const T* r, T bn, T gamma,
     }
     const T vb = u * bn + v1 * b1 + v2 * b2;
     const T vbs = SM * bn + s.v1 * s.b1 + s.v2 * s.b2;
-    s.E = ((S - u) * E - pt * u + pts * SM + bn * (vb - vbs)) / (S - SM);
-    s.sq = sqrt(s.rho);
+    s.E = M::div((S - u) * E - pt * u + pts * SM + bn * (vb - vbs), S - SM);
+    s.sq = M::root(s.rho);
     return s;
   };
   const Star sl = star(rl, ul, vl1, vl2, ptl, bl1, bl2, El, SL, dl);
   const Star sr = star(rr, ur, vr1, vr2, ptr, br1, br2, Er, SR, dr);
-  const T SsL = SM - fabs(bn) / sl.sq;
-  const T SsR = SM + fabs(bn) / sr.sq;
+  const T SsL = SM - M::div(fabs(bn), sl.sq);
+  const T SsR = SM + M::div(fabs(bn), sr.sq);
 
   // choose the side, then F = F_a + S_a (U*_a - U_a) [+ S*_a (U**_a - U*_a)]
   const bool left = SM >= T(0);
@@ -133,7 +148,7 @@ __device__ __forceinline__ void hlld_flux(const T* l, const T* r, T bn, T gamma,
   if (!inner) return;  // single-star region
   // double-star region, s = sign(bn) with sign(0) = +1
   const T sg = (bn >= T(0)) ? T(1) : T(-1);
-  const T isum = T(1) / (sl.sq + sr.sq);
+  const T isum = M::rcp(sl.sq + sr.sq);
   const T w1 = (sl.sq * sl.v1 + sr.sq * sr.v1 + sg * (sr.b1 - sl.b1)) * isum;
   const T w2 = (sl.sq * sl.v2 + sr.sq * sr.v2 + sg * (sr.b2 - sl.b2)) * isum;
   const T c1 = (sl.sq * sr.b1 + sr.sq * sl.b1 + sg * sl.sq * sr.sq * (sr.v1 - sl.v1)) * isum;
@@ -149,10 +164,10 @@ __device__ __forceinline__ void hlld_flux(const T* l, const T* r, T bn, T gamma,
 }
 
 // van Leer limited slope from the two one-sided differences.
-template <class T>
+template <class T, class M = Exact<T>>
 __device__ __forceinline__ T van_leer(T dl, T dr) {
   const T pr = dl * dr;
-  return (pr > T(0)) ? T(2) * pr / (dl + dr) : T(0);
+  return (pr > T(0)) ? M::div(T(2) * pr, dl + dr) : T(0);
 }
 
 }  // namespace dsp
