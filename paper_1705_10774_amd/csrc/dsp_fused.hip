@@ -95,17 +95,17 @@ template <class T> struct PatchCtx {
 template <class T, class M = Exact<T>>
 __device__ __forceinline__ void load_cell(const PatchCtx<T>& c, const RegionTab<T>& rt, int i, int j, int k,
                                           T gamma, T pfloor, T* w, T& bxl, T& byl, T& bzl) {
-  const T rho = fetch_fast(c.ownp, c.n, rt, -1, 0, i, j, k);
-  const T m0 = fetch_fast(c.ownp, c.n, rt, -1, 1, i, j, k);
-  const T m1 = fetch_fast(c.ownp, c.n, rt, -1, 2, i, j, k);
-  const T m2 = fetch_fast(c.ownp, c.n, rt, -1, 3, i, j, k);
-  const T en = fetch_fast(c.ownp, c.n, rt, -1, 4, i, j, k);
-  const T xl = fetch_fast(c.ownp, c.n, rt, 0, 0, i, j, k);
-  const T xr = fetch_fast(c.ownp, c.n, rt, 0, 0, i + 1, j, k);
-  const T yl = fetch_fast(c.ownp, c.n, rt, 1, 0, i, j, k);
-  const T yr = fetch_fast(c.ownp, c.n, rt, 1, 0, i, j + 1, k);
-  const T zl = fetch_fast(c.ownp, c.n, rt, 2, 0, i, j, k);
-  const T zr = fetch_fast(c.ownp, c.n, rt, 2, 0, i, j, k + 1);
+  const T rho = fetch_fast(c.n, rt, -1, 0, i, j, k);
+  const T m0 = fetch_fast(c.n, rt, -1, 1, i, j, k);
+  const T m1 = fetch_fast(c.n, rt, -1, 2, i, j, k);
+  const T m2 = fetch_fast(c.n, rt, -1, 3, i, j, k);
+  const T en = fetch_fast(c.n, rt, -1, 4, i, j, k);
+  const T xl = fetch_fast(c.n, rt, 0, 0, i, j, k);
+  const T xr = fetch_fast(c.n, rt, 0, 0, i + 1, j, k);
+  const T yl = fetch_fast(c.n, rt, 1, 0, i, j, k);
+  const T yr = fetch_fast(c.n, rt, 1, 0, i, j + 1, k);
+  const T zl = fetch_fast(c.n, rt, 2, 0, i, j, k);
+  const T zr = fetch_fast(c.n, rt, 2, 0, i, j, k + 1);
   prim_of<T, M>(rho, m0, m1, m2, en, T(0.5) * (xl + xr), T(0.5) * (yl + yr), T(0.5) * (zl + zr), gamma, pfloor,
                 w);
   bxl = xl;
@@ -193,7 +193,7 @@ __global__ __launch_bounds__(256) void k_courant(DevSet S, const int* __restrict
   c.n = S.n[c.p];
   c.ownp = slots + S.slot_off[c.p] + (int64_t)S.cur[c.p] * S.slice_len[c.p];
   for (int m = threadIdx.x; m < 108; m += blockDim.x)
-    region_tab_init(S, slots, pad + (int64_t)b * pad_stride, c.n + 4, c.p, rt, m);
+    region_tab_init(S, slots, c.ownp, pad + (int64_t)b * pad_stride, c.n + 4, c.p, rt, m);
   __syncthreads();
   const int N = c.n + 4;
   const int64_t cid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -306,7 +306,7 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
   T* const outp = slots + S.slot_off[c.p] + (int64_t)((S.cur[c.p] + 1) % S.nslots) * V;
   c.ownp = slots + own;
   for (int m = tid; m < 108; m += NTHR)
-    region_tab_init(S, (const T*)slots, pad + (int64_t)bidx * pad_stride, n + 4, c.p, sm.rt, m);
+    region_tab_init(S, (const T*)slots, (const T*)c.ownp, pad + (int64_t)bidx * pad_stride, n + 4, c.p, sm.rt, m);
   const T gamma = T(S.gamma), pfloor = T(S.p_floor);
   __shared__ unsigned long long traffic;
   if (tid == 0) traffic = 0;
@@ -687,7 +687,7 @@ __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict
   T* const outp = slots + S.slot_off[c.p] + (int64_t)((S.cur[c.p] + 1) % S.nslots) * V;
   c.ownp = slots + own;
   for (int m = tid; m < 108; m += NTHR2)
-    region_tab_init(S, (const T*)slots, pad + (int64_t)bidx * pad_stride, n + 4, c.p, sm.rt, m);
+    region_tab_init(S, (const T*)slots, (const T*)c.ownp, pad + (int64_t)bidx * pad_stride, n + 4, c.p, sm.rt, m);
   const T gamma = T(S.gamma), pfloor = T(S.p_floor);
   __shared__ unsigned long long traffic;
   if (tid == 0) traffic = 0;

@@ -270,63 +270,64 @@ __device__ __forceinline__ bool region_direct(const DevSet& S, int p, int key) {
   return m1 - m0 == 1 && S.boxes[m0].same;
 }
 
-// Per-workgroup table of the 108 regions of one patch: element (var, i, j, k)
-// of region `key` is pa[e] + w (pb[e] - pa[e]), e the slice-layout offset of
-// (var, i, j, k) for a patch of nq cells per edge (pa == pb: exact copy).
+// Per-workgroup table of the 108 regions of one patch (the four interior
+// regions included): element (var, i, j, k) of region `key` is
+// pa[e] + w (pb[e] - pa[e]), e the slice-layout offset of (var, i, j, k) for a
+// patch of nq cells per edge.  Exact copies and the interior have pa == pb
+// and w = 0, which gives pa[e] exactly.
+template <class T> struct RegionEnt {
+  const T* pa;
+  const T* pb;
+  T w;
+  int nq;
+};
 template <class T> struct RegionTab {
-  const T* pa[108];
-  const T* pb[108];
-  T w[108];
-  int nq[108];
+  RegionEnt<T> r[108];
 };
 
-// Fill entry `key`.  pad: this entry's padded buffer (layout pcell / pface,
-// N cells per edge including the guard layers).
+// Fill entry `key`.  ownp: the patch's current slice; pad: this entry's
+// padded buffer (layout pcell / pface, N cells per edge including the guard
+// layers).
 template <class T>
-__device__ inline void region_tab_init(const DevSet& S, const T* slots, const T* pad, int N, int p,
+__device__ inline void region_tab_init(const DevSet& S, const T* slots, const T* ownp, const T* pad, int N, int p,
                                        RegionTab<T>& R, int key) {
   const int comp = key / 27 - 1;
-  if (region_direct(S, p, key)) {
+  RegionEnt<T> E;
+  if (key % 27 == 13) {  // interior
+    const int n = S.n[p];
+    E.pa = E.pb = ownp + ((comp < 0) ? 0 : sface(n, comp, 0, 0, 0));
+    E.w = T(0);
+    E.nq = n;
+  } else if (region_direct(S, p, key)) {
     const GBox& G = S.boxes[S.rbox_off[p * 108 + key]];
     const Bracket b = bracket(S, G.q, S.ticks[p], S.tcur[p]);
     const int nq = S.n[G.q];
     const int64_t e0 = (comp < 0) ? scell(nq, 0, G.shift[0], G.shift[1], G.shift[2])
                                   : sface(nq, comp, G.shift[0], G.shift[1], G.shift[2]);
-    R.pa[key] = slots + b.oa + e0;
-    R.pb[key] = slots + b.ob + e0;
-    R.w[key] = (T)b.w;
-    R.nq[key] = nq;
+    E.pa = slots + b.oa + e0;
+    E.pb = slots + b.ob + e0;
+    E.w = (T)b.w;
+    E.nq = nq;
   } else {
-    const T* q = pad + ((comp < 0) ? pcell(N, 0, 0, 0, 0) : pface(N, comp, 0, 0, 0));
-    R.pa[key] = q;
-    R.pb[key] = q;
-    R.w[key] = T(0);
-    R.nq[key] = N;
+    E.pa = E.pb = pad + ((comp < 0) ? pcell(N, 0, 0, 0, 0) : pface(N, comp, 0, 0, 0));
+    E.w = T(0);
+    E.nq = N;
   }
+  R.r[key] = E;
 }
 
-// Same value as fetch_elem, through the region table: interior elements from
-// the patch's own slice (ownp), guard elements from the region's source
-// slices or from the padded buffer.  Offsets inside one slice fit in 32 bits.
+// Same value as fetch_elem, through the region table, without branches: the
+// region is selected arithmetically, both slices are read (the same address
+// twice for an exact copy) and blended.  Offsets inside one slice fit in 32
+// bits.  comp is a constant at every call site.
 template <class T>
-__device__ __forceinline__ T fetch_fast(const T* ownp, int n, const RegionTab<T>& R, int comp, int var, int i,
-                                        int j, int k) {
+__device__ __forceinline__ T fetch_fast(int n, const RegionTab<T>& R, int comp, int var, int i, int j, int k) {
   const int hx = n + (comp == 0 ? 1 : 0), hy = n + (comp == 1 ? 1 : 0), hz = n + (comp == 2 ? 1 : 0);
-  const int rx = i < 0 ? 0 : (i < hx ? 1 : 2);
-  const int ry = j < 0 ? 0 : (j < hy ? 1 : 2);
-  const int rz = k < 0 ? 0 : (k < hz ? 1 : 2);
-  if (rx == 1 && ry == 1 && rz == 1) {
-    int e;
-    if (comp < 0) {
-      e = ((var * n + k) * n + j) * n + i;
-    } else {
-      const int sx = n + (comp == 0), sy = n + (comp == 1);
-      e = 5 * n * n * n + comp * n * n * (n + 1) + (k * sy + j) * sx + i;
-    }
-    return ownp[e];
-  }
-  const int key = (comp + 1) * 27 + (rz * 3 + ry) * 3 + rx;
-  const int nq = R.nq[key];
+  const int rx = (i >= 0) + (i >= hx);
+  const int ry = (j >= 0) + (j >= hy);
+  const int rz = (k >= 0) + (k >= hz);
+  const RegionEnt<T> E = R.r[(comp + 1) * 27 + (rz * 3 + ry) * 3 + rx];
+  const int nq = E.nq;
   int e;
   if (comp < 0) {
     e = ((var * nq + k) * nq + j) * nq + i;
@@ -334,12 +335,10 @@ __device__ __forceinline__ T fetch_fast(const T* ownp, int n, const RegionTab<T>
     const int sx = nq + (comp == 0), sy = nq + (comp == 1);
     e = (k * sy + j) * sx + i;
   }
-  const T* pa = R.pa[key];
-  const T* pb = R.pb[key];
-  const T a = pa[e];
-  if (pa == pb) return a;
-  const T b = pb[e];
-  return a + R.w[key] * (b - a);
+  const T a = E.pa[e];
+  const T b = E.pb[e];
+  return a + E.w * (b - a);
 }
+
 
 }  // namespace dsp
