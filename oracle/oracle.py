@@ -68,6 +68,7 @@ def lib():
         L.orc_times.argtypes = [C.c_void_p, C.POINTER(C.c_int64), dp]
         L.orc_hlld_flux.argtypes = [dp, dp, C.c_double, C.c_double, C.c_double, dp]
         L.orc_jvp_fixed.argtypes = [C.c_void_p, dp, dp, C.c_int32, C.c_double, dp, dp]
+        L.orc_count_flops.argtypes = [C.c_void_p, dp, C.c_double, dp]
         _lib = L
     return _lib
 
@@ -217,6 +218,15 @@ class OracleSet:
         dUT = np.empty_like(U0)
         _check(lib().orc_jvp_fixed(self.h, _dp(U0), _dp(dU0), nsteps, dt, _dp(UT), _dp(dUT)))
         return UT, dUT
+
+    def count_flops(self, U0, t_end):
+        """(floating-point operations, cell updates, operations of the
+        Courant rate) of the method from U0 to t_end (+, -, *, / and sqrt
+        count one each)."""
+        U0 = np.ascontiguousarray(U0, dtype=np.float64)
+        out = np.zeros(3)
+        _check(lib().orc_count_flops(self.h, _dp(U0), float(t_end), _dp(out)))
+        return out[0], out[1], out[2]
 
 
 def hlld_flux(wl, wr, bn, gamma=5.0 / 3.0, eps=1e-12):

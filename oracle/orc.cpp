@@ -1026,4 +1026,39 @@ int orc_jvp_fixed(orc_set* h, const double* U0, const double* dU0, int32_t nstep
   return 0;
 }
 
+// Floating-point operations of the method from the given state up to t_end
+// (same configuration and dispatch as the handle, one thread): out[0] =
+// operations (see Flop), out[1] = cell updates, out[2] = the part of out[0]
+// spent in the Courant rate.
+int orc_count_flops(orc_set* h, const double* U0, double t_end, double* out) {
+  if (!h || !U0 || !out) return fail(ORC_EINVAL, "null argument");
+  SetT<Flop> s;
+  int e = make_set(h->s.cfg, h->desc, s);
+  if (e) return e;
+  size_t need = 0;
+  for (size_t q = 0; q < s.p.size(); ++q) need += s.slice_size((int)q);
+  std::vector<Flop> u(need);
+  for (size_t m = 0; m < need; ++m) u[m] = Flop(U0[m]);
+  e = init_set(s, u.data(), need, 0.0);
+  if (e) return e;
+  s.nthreads = 1;
+  flop_tally()[0].store(0);
+  flop_tally()[1].store(0);
+  if (s.exact_time) {
+    e = s.run_global(0, t_end, -1);
+  } else {
+    double m = t_end / s.cfg.dt_base;
+    double mr = std::nearbyint(m);
+    if (std::fabs(m - mr) > 1e-9 * std::max(1.0, std::fabs(m)))
+      return fail(ORC_EALIGN, "end time is not a multiple of dt_base");
+    const int64_t T = (int64_t)mr << s.cfg.kmax;
+    e = (s.cfg.dt_mode == 0) ? s.run_local(T) : s.run_global(T, 0.0, -1);
+  }
+  if (e) return e;
+  out[0] = (double)(flop_tally()[0].load() + flop_tally()[1].load());
+  out[1] = (double)s.updates;
+  out[2] = (double)flop_tally()[1].load();
+  return 0;
+}
+
 }  // extern "C"

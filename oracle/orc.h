@@ -76,6 +76,12 @@ int orc_hlld_flux(const double* wl, const double* wr, double bn, double gamma, d
 int orc_jvp_fixed(orc_set* s, const double* U0, const double* dU0, int32_t nsteps, double dt,
                   double* UT, double* dUT);
 
+/* Arithmetic work of the method: floating-point operations (+, -, *, /,
+ * sqrt, one each) and cell updates from state U0 (slice layout) to t_end,
+ * same configuration, one thread.  out[0] = operations, out[1] = updates,
+ * out[2] = the operations of the Courant rate (included in out[0]). */
+int orc_count_flops(orc_set* s, const double* U0, double t_end, double* out);
+
 #ifdef __cplusplus
 }
 #endif

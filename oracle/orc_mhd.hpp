@@ -11,6 +11,7 @@
 // Everything is written out literally, one quantity at a time, so it can be
 // checked against those methods by eye.  No blocking, fusion or reordering.
 #pragma once
+#include <atomic>
 #include <cmath>
 #include <cstddef>
 #include <cstdint>
@@ -47,8 +48,48 @@ inline Dual sqrt(Dual a) {
   return Dual(s, a.d / (2.0 * s));
 }
 inline Dual fabs(Dual a) { return a.v < 0.0 ? -a : a; }
+// Counting scalar: a double plus a tally of the floating-point operations
+// applied to it (each +, -, *, / and square root counts one; comparisons,
+// signs and absolute values count none).  Used to state the arithmetic work
+// of the method per cell update.
+struct Flop {
+  double v;
+  Flop(double a = 0.0) : v(a) {}
+};
+// Two tallies: [0] everything else, [1] the Courant rate (while a
+// FlopCourant object is alive).
+inline std::atomic<unsigned long long>* flop_tally() {
+  static std::atomic<unsigned long long> t[2] = {{0}, {0}};
+  return t;
+}
+inline std::atomic<int>& flop_bucket() {
+  static std::atomic<int> b{0};
+  return b;
+}
+struct FlopCourant {
+  FlopCourant() { flop_bucket().store(1); }
+  ~FlopCourant() { flop_bucket().store(0); }
+};
+inline Flop flop1(double r) {
+  flop_tally()[flop_bucket().load(std::memory_order_relaxed)].fetch_add(1, std::memory_order_relaxed);
+  return Flop(r);
+}
+inline Flop operator+(Flop a, Flop b) { return flop1(a.v + b.v); }
+inline Flop operator-(Flop a, Flop b) { return flop1(a.v - b.v); }
+inline Flop operator-(Flop a) { return Flop(-a.v); }
+inline Flop operator*(Flop a, Flop b) { return flop1(a.v * b.v); }
+inline Flop operator/(Flop a, Flop b) { return flop1(a.v / b.v); }
+inline Flop& operator+=(Flop& a, Flop b) { a = a + b; return a; }
+inline bool operator<(Flop a, Flop b) { return a.v < b.v; }
+inline bool operator>(Flop a, Flop b) { return a.v > b.v; }
+inline bool operator<=(Flop a, Flop b) { return a.v <= b.v; }
+inline bool operator>=(Flop a, Flop b) { return a.v >= b.v; }
+inline Flop sqrt(Flop a) { return flop1(std::sqrt(a.v)); }
+inline Flop fabs(Flop a) { return Flop(std::fabs(a.v)); }
+
 inline double val(double x) { return x; }
 inline double val(const Dual& x) { return x.v; }
+inline double val(const Flop& x) { return x.v; }
 using std::fabs;
 using std::sqrt;
 
@@ -180,6 +221,7 @@ template <class R> R fast_speed(const Prim<R>& w, int d, double gamma) {
 // (|v_d| + c_f,d) / dx over the interior and the two guard layers the
 // stencil reads.  The largest stable step is courant / smax.
 template <class R> double courant_rate(const Box3<Prim<R>>& W, int n, double dx, double gamma) {
+  FlopCourant tally_as_courant;
   double smax = 0.0;
   for (int k = -2; k <= n + 1; ++k)
     for (int j = -2; j <= n + 1; ++j)

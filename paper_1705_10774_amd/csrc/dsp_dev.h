@@ -5,6 +5,13 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Makes a per-lane value opaque to the optimiser at this point (no code is
+// emitted), so that what is derived from it afterwards is recomputed rather
+// than hoisted and held across long stretches of the kernel.
+#ifndef DSP_OPAQUE
+#define DSP_OPAQUE(x) asm volatile("" : "+v"(x))
+#endif
+
 namespace dsp {
 
 enum : int { ERR_NONFINITE = 1, ERR_NEGATIVE = 2, ERR_KMAX = 4, ERR_STATE = 8 };

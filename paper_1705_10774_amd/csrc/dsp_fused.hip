@@ -115,19 +115,25 @@ __device__ __forceinline__ void load_cell(const PatchCtx<T>& c, const RegionTab<
 
 // first-order fallback states of a face along d: the primitives at t^n of
 // the two cells beside it (cell (i, j, z) on its upper side), rotated to the
-// face normal.  Rare; kept out of line.
+// face normal.  Rare; kept out of line, and returned by value so that the
+// caller's face states never need to live in memory.
+template <class T> struct FaceStates {
+  T l[7], r[7];
+};
 template <class T, class M = Exact<T>>
-__device__ __attribute__((noinline)) void fallback_states(const PatchCtx<T>& c, const RegionTab<T>& rt, int d,
-                                                          int i, int j, int z, T gamma, T pfloor, T* l, T* r) {
+__device__ __attribute__((noinline)) FaceStates<T> fallback_states(const PatchCtx<T>& c, const RegionTab<T>& rt,
+                                                                   int d, int i, int j, int z, T gamma, T pfloor) {
   T wa[8], wb[8], dmy;
   load_cell<T, M>(c, rt, i - (d == 0), j - (d == 1), z - (d == 2), gamma, pfloor, wa, dmy, dmy, dmy);
   load_cell<T, M>(c, rt, i, j, z, gamma, pfloor, wb, dmy, dmy, dmy);
   const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
   const int ord[7] = {0, 1 + d, 1 + t1, 1 + t2, 4, 5 + t1, 5 + t2};
+  FaceStates<T> fs;
   for (int q = 0; q < 7; ++q) {
-    l[q] = wa[ord[q]];
-    r[q] = wb[ord[q]];
+    fs.l[q] = wa[ord[q]];
+    fs.r[q] = wb[ord[q]];
   }
+  return fs;
 }
 
 // ---------------------------------------------------------------------------
@@ -475,7 +481,14 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
       T bn = bface + T(0.5) * (sm.b.p.db[d][pa] + sm.b.p.db[d][pb]);
       if (!(l[0] > T(0)) || !(l[4] > T(0)) || !(r[0] > T(0)) || !(r[4] > T(0))) {
         // first-order fallback: primitives of the two cells at t^n
-        fallback_states(c, sm.rt, d, cix, cjx, z, gamma, pfloor, l, r);
+        {
+          const FaceStates<T> fs = fallback_states(c, sm.rt, d, cix, cjx, z, gamma, pfloor);
+#pragma unroll
+          for (int q = 0; q < 7; ++q) {
+            l[q] = fs.l[q];
+            r[q] = fs.r[q];
+          }
+        }
         bn = bface;
         const bool owned = (d == 0) ? (own_c(cix, x0, x1, firstx, false) || (lastx && cix == n)) &&
                                           own_c(cjx, y0, y1, firsty, lasty)
@@ -698,12 +711,22 @@ __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict
   __syncthreads();
   if (tile == 0 && tid == 0) atomicAdd(S.algo_bytes, traffic);
 
-  // column of this thread (load phase) and its predictor cell
+  // column of this thread (load phase) and its predictor cell.  The lane
+  // indices are re-declared opaque at the start of every phase (reopen), so
+  // the addresses derived from them are recomputed there instead of being
+  // hoisted out of the march and held (or spilled) through the face phase.
   const bool col = tid < CX * CY;
   const int ca = tid % CX, cb = tid / CX;
-  const int ci = x0 - 2 + ca, cj = y0 - 2 + cb;
+  int ci = x0 - 2 + ca, cj = y0 - 2 + cb;
   const bool pred = col && ca >= 1 && ca <= CX - 2 && cb >= 1 && cb <= CY - 2;
-  const int pc = (ca - 1) + (cb - 1) * PX;
+  int pc = (ca - 1) + (cb - 1) * PX;
+  int lane = tid;
+  auto reopen = [&]() {
+    DSP_OPAQUE(lane);
+    DSP_OPAQUE(ci);
+    DSP_OPAQUE(cj);
+    DSP_OPAQUE(pc);
+  };
   const bool own_cell = col && ci >= x0 && ci < x1 && cj >= y0 && cj < y1;
   const bool own_bx = col && cj >= y0 && cj < y1 && ((ci >= x0 && ci < x1) || (lastx && ci == n));
   const bool own_by = col && ci >= x0 && ci < x1 && ((cj >= y0 && cj < y1) || (lasty && cj == n));
@@ -715,10 +738,10 @@ __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict
     load_cell<T, M>(c, sm.rt, ci, cj, z, gamma, pfloor, wv, bx, by, bz);
     const int s3 = mod3(z), s2 = z & 1;
 #pragma unroll
-    for (int v = 0; v < 8; ++v) sm.w[s3][v][tid] = wv[v];
-    sm.bfc[s2][0][tid] = bx;
-    sm.bfc[s2][1][tid] = by;
-    sm.bfc[s2][2][tid] = bz;
+    for (int v = 0; v < 8; ++v) sm.w[s3][v][lane] = wv[v];
+    sm.bfc[s2][0][lane] = bx;
+    sm.bfc[s2][1][lane] = by;
+    sm.bfc[s2][2][lane] = bz;
   };
   if (col) {
     load_plane(-2);
@@ -733,19 +756,21 @@ __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict
 
   for (int z = -1; z <= n; ++z) {
     // ---- P1: load plane z+1
+    reopen();
     if (col) load_plane(z + 1);
     __syncthreads();
     // ---- P2: slopes, Hancock predictor, z-face states and cell EMF of plane z
+    reopen();
     if (pred) {
       const int sm3 = mod3(z - 1), s0 = mod3(z), sp3 = mod3(z + 1);
       T W0[8], sl[3][8];
 #pragma unroll
       for (int v = 0; v < 8; ++v) {
-        const T c0 = sm.w[s0][v][tid];
+        const T c0 = sm.w[s0][v][lane];
         W0[v] = c0;
-        sl[0][v] = van_leer<T, M>(c0 - sm.w[s0][v][tid - 1], sm.w[s0][v][tid + 1] - c0);
-        sl[1][v] = van_leer<T, M>(c0 - sm.w[s0][v][tid - CX], sm.w[s0][v][tid + CX] - c0);
-        sl[2][v] = van_leer<T, M>(c0 - sm.w[sm3][v][tid], sm.w[sp3][v][tid] - c0);
+        sl[0][v] = van_leer<T, M>(c0 - sm.w[s0][v][lane - 1], sm.w[s0][v][lane + 1] - c0);
+        sl[1][v] = van_leer<T, M>(c0 - sm.w[s0][v][lane - CX], sm.w[s0][v][lane + CX] - c0);
+        sl[2][v] = van_leer<T, M>(c0 - sm.w[sm3][v][lane], sm.w[sp3][v][lane] - c0);
       }
       sl[0][5] = T(0);
       sl[1][6] = T(0);
@@ -790,8 +815,9 @@ __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict
     }
     __syncthreads();
     // ---- P3: x- and y-face fluxes of plane z, z-face fluxes at face z
+    reopen();
     const int nface = nxf + nyf + (z >= 0 ? nzf : 0);
-    for (int m = tid; m < nface; m += NTHR2) {
+    for (int m = lane; m < nface; m += NTHR2) {
       T l[7], r[7], bn, f[8];
       if (m < nxf + nyf) {
         const int d = (m < nxf) ? 0 : 1;
@@ -824,7 +850,14 @@ __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict
         }
         bn = bface + T(0.5) * (sm.b.p.db[d][pa] + sm.b.p.db[d][pb]);
         if (!(l[0] > T(0)) || !(l[4] > T(0)) || !(r[0] > T(0)) || !(r[4] > T(0))) {
-          fallback_states<T, M>(c, sm.rt, d, cix, cjx, z, gamma, pfloor, l, r);
+          {
+          const FaceStates<T> fs = fallback_states<T, M>(c, sm.rt, d, cix, cjx, z, gamma, pfloor);
+#pragma unroll
+          for (int q = 0; q < 7; ++q) {
+            l[q] = fs.l[q];
+            r[q] = fs.r[q];
+          }
+        }
           bn = bface;
           const bool owned = (d == 0) ? (own_c(cix, x0, x1, firstx, false) || (lastx && cix == n)) &&
                                             own_c(cjx, y0, y1, firsty, lasty)
@@ -855,7 +888,14 @@ __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict
         const T bface = sm.bfc[z & 1][2][cq];
         bn = bface + T(0.5) * (sm.dz[(z - 1) & 1][q] + sm.dz[z & 1][q]);
         if (!(l[0] > T(0)) || !(l[4] > T(0)) || !(r[0] > T(0)) || !(r[4] > T(0))) {
-          fallback_states<T, M>(c, sm.rt, 2, cix, cjx, z, gamma, pfloor, l, r);
+          {
+          const FaceStates<T> fs = fallback_states<T, M>(c, sm.rt, 2, cix, cjx, z, gamma, pfloor);
+#pragma unroll
+          for (int q = 0; q < 7; ++q) {
+            l[q] = fs.l[q];
+            r[q] = fs.r[q];
+          }
+        }
           bn = bface;
           if (own_c(cix, x0, x1, firstx, lastx) && own_c(cjx, y0, y1, firsty, lasty)) atomicAdd(S.fallback, 1ULL);
         }
@@ -872,6 +912,7 @@ __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict
     }
     __syncthreads();
     // ---- P4: edge EMFs (upwinded by the sign of the face upwind speed) and x/y flux sums
+    reopen();
     // The t^n values that P5 updates are requested first, so their latency
     // overlaps the edge work.
     T old[8];
@@ -905,7 +946,7 @@ __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict
       const int nez = (z >= 0 && z < n) ? (TX + 1) * (TY + 1) : 0;
       const int nex = (z >= 0) ? TX * (TY + 1) : 0;
       const int ney = (z >= 0) ? (TX + 1) * TY : 0;
-      for (int m = tid; m < nez + nex + ney; m += NTHR2) {
+      for (int m = lane; m < nez + nex + ney; m += NTHR2) {
         if (m < nez) {  // E_z in plane z at (x-face f, y-face g)
           const int f = x0 + m % (TX + 1), g = y0 + m / (TX + 1);
           const T A = -sm.fx[6][XF(f, g)], B = -sm.fx[6][XF(f, g - 1)];
@@ -940,6 +981,7 @@ __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict
     }
     __syncthreads();
     // ---- P5: write plane z-1 (cells, Bx, By) and face z (Bz); carry partials
+    reopen();
     {
       auto EZ = [&](int f, int g) { return sm.b.e.ez[(f - x0) + (g - y0) * (TX + 1)]; };
       auto EX = [&](int i, int g) { return sm.b.e.ex[(i - x0) + (g - y0) * TX]; };
@@ -970,11 +1012,11 @@ __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict
         const T curl = (EY(ci + 1, cj) - EY(ci, cj)) - (EX(ci, cj + 1) - EX(ci, cj));
         outp[sface(n, 2, ci, cj, z)] = old[7] - dtdx * curl;
       }
-      for (int m = tid; m < nxf; m += NTHR2) {
+      for (int m = lane; m < nxf; m += NTHR2) {
         sm.px[0][m] = sm.fx[5][m];
         sm.px[1][m] = sm.fx[7][m];
       }
-      for (int m = tid; m < nyf; m += NTHR2) {
+      for (int m = lane; m < nyf; m += NTHR2) {
         sm.py[0][m] = sm.fy[6][m];
         sm.py[1][m] = sm.fy[7][m];
       }
