@@ -121,13 +121,16 @@ def main():
                    "updates_per_step": res32["updates"], "rounds_per_step": res32["rounds"]},
     }
     # dominant kernel: the fused patch step, timed with HIP events on its
-    # stream.  Its arithmetic per cell update is the CPU oracle's tally of the
-    # step (everything but the Courant rate) on this workload; it is bound by
-    # vector ALU work, not by HBM (about 80 algorithmic bytes per update).
+    # stream.  Its arithmetic per cell update is the CPU oracle's tally on this
+    # workload; it is bound by vector ALU work, not by HBM (about 80
+    # algorithmic bytes per update).
     flops = json.load(open(os.path.join(ROOT, "tests", "golden", "flops_per_update.json")))
     kern_s = res32["kern_ms"] / 1e3
     launches = max(res32["kern_launches"], 1)
-    step_flops = flops["step_flops_per_update"] * res32["updates"]
+    # the step kernel also takes the Courant rate when it runs the local
+    # step of single-tile patches (kernel_stats()[3] == 2)
+    per_update = flops["flops_per_update"] if res32["fused"] == 2 else flops["step_flops_per_update"]
+    step_flops = per_update * res32["updates"]
     ach = step_flops / kern_s / 1e12 if kern_s > 0 else 0.0
     hbm = res32["algo_bytes"] / kern_s / 1e9 if kern_s > 0 else 0.0
     out["roofline"] = {"bound": "alu", "achieved": ach, "peak": FP32_VECTOR_PEAK, "unit": "TFLOP/s",
@@ -135,7 +138,7 @@ def main():
                        "traffic": measured_traffic(res32["algo_bytes"] / launches),
                        "kernel": "k_step2<float>", "launches": res32["kern_launches"],
                        "avg_launch_ms": res32["kern_ms"] / launches,
-                       "flops_per_update": flops["step_flops_per_update"],
+                       "flops_per_update": per_update,
                        "algorithmic_bytes_per_update": res32["algo_bytes"] / max(res32["updates"], 1),
                        "algorithmic_hbm_GBs": hbm, "algorithmic_hbm_frac": hbm / HBM_PEAK}
     if not args.no_baselines:

@@ -164,7 +164,9 @@ int dsp_kernel_time(const dsp_set* set, double* ms, int64_t* launches);
  *  [2] their algorithmic HBM bytes: per patch update the own slice read and
  *      written plus every value of the two guard layers the stencil reads,
  *      from one time slice (exact time) or two (interpolated)
- *  [3] 1 if the fused step kernel ran (the byte count is only kept for it) */
+ *  [3] 0: staged kernels (no byte count); 1: fused step kernel; 2: fused step
+ *      kernel that also computed each patch's Courant rate and level (local
+ *      steps of single-tile patches) */
 int dsp_kernel_stats(const dsp_set* set, double out[4]);
 
 /* Fixed-dt forward run for differentiation (all patches step together with

@@ -88,12 +88,33 @@ struct StepPtr {
   double* dt;
 };
 
+// Level k of a local step (dt = dt_base 2^-k) from the patch Courant rate.
+__device__ inline int level_for(const DevSet& S, double smax, int64_t ticks) {
+  // k_c = 0 if r <= 1 else ceil(log2 r) exactly (frexp), r = dt_base smax / C;
+  // raised so that the step keeps the patch time a multiple of the step
+  const double r = S.dt_base * smax / S.courant;
+  int kc = 0;
+  if (r > 1.0) {
+    int e;
+    const double m = frexp(r, &e);
+    kc = (m == 0.5) ? e - 1 : e;
+  }
+  int k = kc;
+  if (ticks != 0) {
+    const int tz = __ffsll((unsigned long long)ticks) - 1;
+    const int al = S.kmax - tz;
+    k = k > al ? k : al;
+  }
+  return k;
+}
+
 template <class T>
 void launch_update(const DevSet& S, const int* list, int count, int nmax, T* slots, const WorkPtr<T>& W,
                    const StepPtr& st, hipStream_t s, int dt_kind, double t_end, int clip,
                    hipEvent_t ev0, hipEvent_t ev1);
+// returns 1 when the Courant rate and level were computed inside the step kernel
 template <class T>
-void launch_fused(const DevSet& S, const int* list, int count, int nmax, T* slots, T* pad, int64_t pad_stride,
+int launch_fused(const DevSet& S, const int* list, int count, int nmax, T* slots, T* pad, int64_t pad_stride,
                   bool gfill, double* smax, const StepPtr& st, hipStream_t s, int dt_kind, double t_end, int clip,
                   hipEvent_t ev0, hipEvent_t ev1);
 void launch_dt(const DevSet& S, const int* list, int count, const StepPtr& st, const double* smax, hipStream_t s,

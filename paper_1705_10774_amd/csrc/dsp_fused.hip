@@ -187,11 +187,62 @@ __global__ __launch_bounds__(256) void k_gfill(DevSet S, const int* __restrict__
 // ---------------------------------------------------------------------------
 // Courant rate and pressure accounting over the padded cells [-2, n+1]^3
 
+// Signal-speed sum of padded cell (i, j, k) divided by dx (0 for a cell that
+// fails the checks); sets the error bits and counts floor hits.  Always IEEE
+// arithmetic: the level of the step follows from it.
+template <class T>
+__device__ __forceinline__ double cell_rate(const DevSet& S, const PatchCtx<T>& c, const RegionTab<T>& rt, int i,
+                                            int j, int k) {
+  T w[8], bxl, byl, bzl;
+  load_cell(c, rt, i, j, k, T(S.gamma), T(0), w, bxl, byl, bzl);
+  T pr = w[4];
+  double s = 0.0;
+  if (!isfinite(w[0]) || !isfinite(pr)) {
+    atomicOr(S.err, ERR_NONFINITE);
+  } else if (!(w[0] > T(0))) {
+    atomicOr(S.err, ERR_NEGATIVE);
+  } else {
+    if (S.p_floor > 0.0) {
+      if (pr < T(S.p_floor)) {
+        pr = T(S.p_floor);
+        atomicAdd(S.floor_hits, 1ULL);
+      }
+    } else if (!(pr > T(0))) {
+      atomicOr(S.err, ERR_NEGATIVE);
+    }
+    if (pr > T(0)) {
+      const T ir = T(1) / w[0];
+      const T a2 = T(S.gamma) * pr * ir;
+      const T bb = (w[5] * w[5] + w[6] * w[6] + w[7] * w[7]) * ir;
+      T sum = fabs(w[1]) + fast_speed(a2, bb, (w[6] * w[6] + w[7] * w[7]) * ir);
+      sum = sum + (fabs(w[2]) + fast_speed(a2, bb, (w[7] * w[7] + w[5] * w[5]) * ir));
+      sum = sum + (fabs(w[3]) + fast_speed(a2, bb, (w[5] * w[5] + w[6] * w[6]) * ir));
+      s = (double)sum / S.dx[c.p];
+      if (!isfinite(s)) atomicOr(S.err, ERR_NONFINITE);
+    }
+  }
+  return s;
+}
+
+// largest value over the workgroup (red: one slot per wavefront)
+__device__ inline double wg_max(double s, double* red, int tid, int nthr) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_xor(s, off, 64);
+    s = o > s ? o : s;
+  }
+  if ((tid & 63) == 0) red[tid >> 6] = s;
+  __syncthreads();
+  double m = 0.0;
+  for (int q = 0; q < nthr / 64; ++q) m = red[q] > m ? red[q] : m;
+  return m;
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void k_courant(DevSet S, const int* __restrict__ list, int count,
                                                  const T* __restrict__ slots, const T* __restrict__ pad,
                                                  int64_t pad_stride, double* __restrict__ smax) {
   __shared__ RegionTab<T> rt;
+  __shared__ double red[4];
   const int b = blockIdx.y;
   if (b >= count) return;
   PatchCtx<T> c;
@@ -204,48 +255,39 @@ __global__ __launch_bounds__(256) void k_courant(DevSet S, const int* __restrict
   const int N = c.n + 4;
   const int64_t cid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double s = 0.0;
-  if (cid < (int64_t)N * N * N) {
-    const int i = (int)(cid % N) - 2, j = (int)((cid / N) % N) - 2, k = (int)(cid / ((int64_t)N * N)) - 2;
-    T w[8], bxl, byl, bzl;
-    load_cell(c, rt, i, j, k, T(S.gamma), T(0), w, bxl, byl, bzl);
-    T pr = w[4];
-    if (!isfinite(w[0]) || !isfinite(pr)) {
-      atomicOr(S.err, ERR_NONFINITE);
-    } else if (!(w[0] > T(0))) {
-      atomicOr(S.err, ERR_NEGATIVE);
-    } else {
-      if (S.p_floor > 0.0) {
-        if (pr < T(S.p_floor)) {
-          pr = T(S.p_floor);
-          atomicAdd(S.floor_hits, 1ULL);
-        }
-      } else if (!(pr > T(0))) {
-        atomicOr(S.err, ERR_NEGATIVE);
-      }
-      if (pr > T(0)) {
-        const T ir = T(1) / w[0];
-        const T a2 = T(S.gamma) * pr * ir;
-        const T bb = (w[5] * w[5] + w[6] * w[6] + w[7] * w[7]) * ir;
-        T sum = fabs(w[1]) + fast_speed(a2, bb, (w[6] * w[6] + w[7] * w[7]) * ir);
-        sum = sum + (fabs(w[2]) + fast_speed(a2, bb, (w[7] * w[7] + w[5] * w[5]) * ir));
-        sum = sum + (fabs(w[3]) + fast_speed(a2, bb, (w[5] * w[5] + w[6] * w[6]) * ir));
-        s = (double)sum / S.dx[c.p];
-        if (!isfinite(s)) atomicOr(S.err, ERR_NONFINITE);
-      }
-    }
+  if (cid < (int64_t)N * N * N)
+    s = cell_rate(S, c, rt, (int)(cid % N) - 2, (int)((cid / N) % N) - 2, (int)(cid / ((int64_t)N * N)) - 2);
+  const double m = wg_max(s, red, threadIdx.x, blockDim.x);
+  if (threadIdx.x == 0 && m > 0.0)
+    atomicMax((unsigned long long*)(smax + b), (unsigned long long)__double_as_longlong(m));
+}
+
+// Local time step of a patch whose whole update is one workgroup (LOCAL
+// mode, one tile per patch): the Courant rate over the padded patch, its
+// level, and the step record the publish kernel reads.  Returns dt to every
+// thread of the workgroup.
+template <class T>
+__device__ double fused_local_dt(const DevSet& S, const PatchCtx<T>& c, const RegionTab<T>& rt, const StepPtr& st,
+                                 int bidx, int tid, int nthr, double* red) {
+  const int N = c.n + 4;
+  double s = 0.0;
+#pragma unroll 4
+  for (int cid = tid; cid < N * N * N; cid += nthr) {
+    const double v = cell_rate(S, c, rt, cid % N - 2, (cid / N) % N - 2, cid / (N * N) - 2);
+    s = v > s ? v : s;
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    const double o = __shfl_xor(s, off, 64);
-    s = o > s ? o : s;
+  const double m = wg_max(s, red, tid, nthr);
+  int k = level_for(S, m, S.ticks[c.p]);
+  if (k > S.kmax) {
+    if (tid == 0) atomicOr(S.err, ERR_KMAX);
+    k = S.kmax;
   }
-  __shared__ double wmax[4];
-  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double m = 0.0;
-    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) m = wmax[q] > m ? wmax[q] : m;
-    if (m > 0.0) atomicMax((unsigned long long*)(smax + b), (unsigned long long)__double_as_longlong(m));
+  if (tid == 0) {
+    st.k[bidx] = k;
+    st.dtk[bidx] = (int64_t)1 << (S.kmax - k);
+    st.dt[bidx] = S.dt_base * ldexp(1.0, -k);
   }
+  return S.dt_base * ldexp(1.0, -k);
 }
 
 // ---------------------------------------------------------------------------
@@ -286,7 +328,7 @@ __device__ __forceinline__ void face_states(const StepSmem<T>& sm, int d, int pa
 template <class T>
 __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__ list, int count,
                                                T* __restrict__ slots, const T* __restrict__ pad,
-                                               int64_t pad_stride, StepPtr st, int tpa) {
+                                               int64_t pad_stride, StepPtr st, int tpa, int fuse_dt) {
   __shared__ StepSmem<T> sm;
   const int tid = threadIdx.x;
   const int T2 = tpa * tpa;  // tile slots per patch
@@ -315,10 +357,12 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
     region_tab_init(S, (const T*)slots, (const T*)c.ownp, pad + (int64_t)bidx * pad_stride, n + 4, c.p, sm.rt, m);
   const T gamma = T(S.gamma), pfloor = T(S.p_floor);
   __shared__ unsigned long long traffic;
+  __shared__ double red[NTHR / 64];
   if (tid == 0) traffic = 0;
   __syncthreads();
   if (tile == 0) count_traffic(S, c.p, box0, nbox, V, (int)sizeof(T), tid, NTHR, &traffic);
-  const T dtdx = T(st.dt[bidx] / S.dx[c.p]);
+  const double dt = fuse_dt ? fused_local_dt(S, c, sm.rt, st, bidx, tid, NTHR, red) : st.dt[bidx];
+  const T dtdx = T(dt / S.dx[c.p]);
   const T hdtdx = T(0.5) * dtdx;
   __syncthreads();
   if (tile == 0 && tid == 0) atomicAdd(S.algo_bytes, traffic);
@@ -672,7 +716,7 @@ __device__ __forceinline__ int mod3(int z) { return (z + 3) % 3; }
 template <class T>
 __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict__ list, int count,
                                                  T* __restrict__ slots, const T* __restrict__ pad,
-                                                 int64_t pad_stride, StepPtr st, int tpa) {
+                                                 int64_t pad_stride, StepPtr st, int tpa, int fuse_dt) {
   static_assert(sizeof(T) == 4, "the wide step kernel is the single-precision variant");
   using M = FastF32;
   __shared__ Step2Smem<T> sm;
@@ -703,10 +747,12 @@ __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict
     region_tab_init(S, (const T*)slots, (const T*)c.ownp, pad + (int64_t)bidx * pad_stride, n + 4, c.p, sm.rt, m);
   const T gamma = T(S.gamma), pfloor = T(S.p_floor);
   __shared__ unsigned long long traffic;
+  __shared__ double red[NTHR2 / 64];
   if (tid == 0) traffic = 0;
   __syncthreads();
   if (tile == 0) count_traffic(S, c.p, box0, nbox, V, (int)sizeof(T), tid, NTHR2, &traffic);
-  const T dtdx = T(st.dt[bidx] / S.dx[c.p]);
+  const double dt = fuse_dt ? fused_local_dt(S, c, sm.rt, st, bidx, tid, NTHR2, red) : st.dt[bidx];
+  const T dtdx = T(dt / S.dx[c.p]);
   const T hdtdx = T(0.5) * dtdx;
   __syncthreads();
   if (tile == 0 && tid == 0) atomicAdd(S.algo_bytes, traffic);
@@ -1028,33 +1074,40 @@ __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict
 // ---------------------------------------------------------------------------
 
 template <class T>
-void launch_fused(const DevSet& S, const int* list, int count, int nmax, T* slots, T* pad, int64_t pad_stride,
+int launch_fused(const DevSet& S, const int* list, int count, int nmax, T* slots, T* pad, int64_t pad_stride,
                   bool gfill, double* smax, const StepPtr& st, hipStream_t s, int dt_kind, double t_end, int clip,
                   hipEvent_t ev0, hipEvent_t ev1) {
   const int N = nmax + 4;
   if (gfill)
     hipLaunchKernelGGL(k_gfill<T>, dim3(4, count), dim3(256), 0, s, S, list, count, (const T*)slots, pad,
                        pad_stride);
-  (void)hipMemsetAsync(smax, 0, sizeof(double) * count, s);
-  hipLaunchKernelGGL(k_courant<T>, dim3((unsigned)(((int64_t)N * N * N + 255) / 256), count), dim3(256), 0, s, S,
-                     list, count, (const T*)slots, (const T*)pad, pad_stride, smax);
-  launch_dt(S, list, count, st, smax, s, dt_kind, t_end, clip);
   const int tpa = (nmax + MT - 1) / MT;
+  // a local step of single-tile patches takes its Courant rate and level
+  // inside the step kernel; otherwise a separate pass (the global modes
+  // need the rate of every patch first)
+  const int fuse_dt = (dt_kind == 0 && tpa == 1) ? 1 : 0;
+  if (!fuse_dt) {
+    (void)hipMemsetAsync(smax, 0, sizeof(double) * count, s);
+    hipLaunchKernelGGL(k_courant<T>, dim3((unsigned)(((int64_t)N * N * N + 255) / 256), count), dim3(256), 0, s, S,
+                       list, count, (const T*)slots, (const T*)pad, pad_stride, smax);
+    launch_dt(S, list, count, st, smax, s, dt_kind, t_end, clip);
+  }
   const int T2 = tpa * tpa;
   const int groups = ((count + 7) / 8) * 8 * T2;
   if (ev0) (void)hipEventRecord(ev0, s);
   if constexpr (sizeof(T) == 4)
     hipLaunchKernelGGL(k_step2<T>, dim3(groups), dim3(NTHR2), 0, s, S, list, count, slots, (const T*)pad,
-                       pad_stride, st, tpa);
+                       pad_stride, st, tpa, fuse_dt);
   else
     hipLaunchKernelGGL(k_step<T>, dim3(groups), dim3(NTHR), 0, s, S, list, count, slots, (const T*)pad, pad_stride,
-                       st, tpa);
+                       st, tpa, fuse_dt);
   if (ev1) (void)hipEventRecord(ev1, s);
+  return fuse_dt;
 }
 
-template void launch_fused<float>(const DevSet&, const int*, int, int, float*, float*, int64_t, bool, double*,
+template int launch_fused<float>(const DevSet&, const int*, int, int, float*, float*, int64_t, bool, double*,
                                   const StepPtr&, hipStream_t, int, double, int, hipEvent_t, hipEvent_t);
-template void launch_fused<double>(const DevSet&, const int*, int, int, double*, double*, int64_t, bool, double*,
+template int launch_fused<double>(const DevSet&, const int*, int, int, double*, double*, int64_t, bool, double*,
                                    const StepPtr&, hipStream_t, int, double, int, hipEvent_t, hipEvent_t);
 
 }  // namespace dsp

@@ -179,25 +179,6 @@ __global__ void k_prim(DevSet S, const int* __restrict__ list, int count, WorkPt
 // ---------------------------------------------------------------------------
 // time-step choice
 
-__device__ int level_for(const DevSet& S, double smax, int64_t ticks) {
-  // k_c = 0 if r <= 1 else ceil(log2 r) exactly (frexp), r = dt_base smax / C;
-  // raised so that the step keeps the patch time a multiple of the step
-  const double r = S.dt_base * smax / S.courant;
-  int kc = 0;
-  if (r > 1.0) {
-    int e;
-    const double m = frexp(r, &e);
-    kc = (m == 0.5) ? e - 1 : e;
-  }
-  int k = kc;
-  if (ticks != 0) {
-    const int tz = __ffsll((unsigned long long)ticks) - 1;
-    const int al = S.kmax - tz;
-    k = k > al ? k : al;
-  }
-  return k;
-}
-
 __global__ void k_dt_local(DevSet S, const int* __restrict__ list, int count, StepPtr st,
                            const double* smax) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;

@@ -355,17 +355,18 @@ struct dsp_set {
   // one launch sequence for list[off .. off+count)
   bool fused = true;  // fused marching kernel (false: staged kernels)
   bool any_generic = false;  // some guard region is not one same-resolution box
+  int dt_fused = 0;          // the last step launch also computed the Courant rate and level
   void update_batch(int off, int count, int dt_kind, double t_end, int clip, const int* list) {
     hipEvent_t e0 = next_event(true), e1 = next_event(false);
     ev_used++;
     StepPtr s2{st.k + off, st.dtk + off, st.dt + off};
     if (fused) {
       if (f32)
-        launch_fused<float>(D, list + off, count, nmax, (float*)slots, (float*)work_pad, pad_stride, any_generic,
-                            smax, s2, stream, dt_kind, t_end, clip, e0, e1);
+        dt_fused = launch_fused<float>(D, list + off, count, nmax, (float*)slots, (float*)work_pad, pad_stride,
+                                       any_generic, smax, s2, stream, dt_kind, t_end, clip, e0, e1);
       else
-        launch_fused<double>(D, list + off, count, nmax, (double*)slots, (double*)work_pad, pad_stride,
-                             any_generic, smax, s2, stream, dt_kind, t_end, clip, e0, e1);
+        dt_fused = launch_fused<double>(D, list + off, count, nmax, (double*)slots, (double*)work_pad, pad_stride,
+                                        any_generic, smax, s2, stream, dt_kind, t_end, clip, e0, e1);
       return;
     }
     if (f32)
@@ -955,7 +956,7 @@ int dsp_kernel_stats(const dsp_set* cs, double out[4]) {
   out[0] = s->kern_ms;
   out[1] = (double)s->kern_launches;
   out[2] = s->fused ? (double)cnt[3] : 0.0;
-  out[3] = s->fused ? 1.0 : 0.0;
+  out[3] = s->fused ? (s->dt_fused ? 2.0 : 1.0) : 0.0;
   return 0;
 }
 

@@ -261,3 +261,24 @@ def test_smr_blast_first_base_step(orc, prec):
     assert err <= (1e-10 if prec == I.F64 else 1e-4)
     # div B at rounding: |B| ~ 1 over the finest cells (dx = 1/256)
     assert stg[9] <= (1e-10 if prec == I.F64 else 1e-3)
+
+
+def test_kernel_record():
+    """The step-kernel record the benchmark reads: timed launches, byte count,
+    and which kernels ran (2: Courant rate and level inside the step kernel
+    for local steps of single-tile patches, 1: separate Courant pass)."""
+    dsp = _dsp()
+    pr = spread(8)
+    s = dsp.PatchSet.from_problem(pr)
+    s.advance_to(4 * pr.cfg.dt_base)
+    ks = s.kernel_stats()
+    rounds = s.stats()[13]
+    s.close()
+    assert ks[0] > 0.0 and ks[1] == rounds and ks[2] > 0.0 and ks[3] == 2
+    pr = I.uniform(npd=2, n=8, v=(0.3, -0.2, 0.1), B=(0.7, 0.4, -0.3), mode=I.DT_GLOBAL_EXACT,
+                   dt_base=1.0 / 64)
+    s = dsp.PatchSet.from_problem(pr)
+    s.advance_to(0.05)
+    ks = s.kernel_stats()
+    s.close()
+    assert ks[0] > 0.0 and ks[1] >= 1 and ks[3] == 1
