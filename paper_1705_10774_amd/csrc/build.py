@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 OUT = os.path.join(PKG, "libdsp.so")
-SOURCES = ["dsp_kernels.hip", "dsp_fused.hip", "dsp_runtime.hip"]
+SOURCES = ["dsp_kernels.hip", "dsp_fused.hip", "dsp_adjoint.hip", "dsp_runtime.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed FP32 instructions (v_pk_*_f32) anywhere in the device code

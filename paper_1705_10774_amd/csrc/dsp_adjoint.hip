@@ -1,0 +1,524 @@
+// dsp_adjoint.hip -- reverse (adjoint) of one fixed-dt step of the whole set.
+//
+// The forward step is the staged one (k_fill, k_prim, k_pred, k_flux, k_emf,
+// k_update), run on the state U^k so that its intermediates sit in the work
+// buffers.  Given lam^{k+1} = dJ/dU^{k+1} (host layout), the kernels below
+// accumulate lam^k = (dU^{k+1}/dU^k)^T lam^{k+1}, walking the stages backwards:
+//
+//   update  -> fluxes, edge EMFs, padded state (identity part)
+//   EMFs    -> induction fluxes, half-step state (cell EMF -v x B)
+//   fluxes  -> half-step state, slopes, primitives, padded face field
+//   Hancock -> primitives, slopes
+//   slopes  -> primitives
+//   prims   -> padded state
+//   fill    -> lam^k of the owning patch (interior) or of the source patch
+//              (guard copy; all patches share the time of a fixed step)
+//
+// The upwind choices of the EMFs, the first-order fallback and the Riemann
+// solver's wave pattern are those of the forward state: the result is the
+// derivative along the branches the forward step takes.  The local Jacobians
+// of the Riemann solver and of the predictor come from running the same device
+// functions on forward-mode numbers (dual_dev.h), one input at a time.
+// Scatters into shared cells and faces use atomic additions.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dsp_dev.h"
+#include "dsp_guard.h"
+#include "dual_dev.h"
+#include "mhd_dev.h"
+
+namespace dsp {
+
+// ---------------------------------------------------------------------------
+// update: out = P - dtdx * sum_d (F_d(+) - F_d(-)) for the cells,
+//         out = P - dtdx * curl(E) for the faces.
+
+template <class T>
+__global__ __launch_bounds__(256) void k_adj_update(DevSet S, const int* __restrict__ list, int count, WorkPtr<T> L, StepPtr st,
+                             const T* __restrict__ lam, const int64_t* __restrict__ host_off) {
+  const int blk = blockIdx.y;
+  if (blk >= count) return;
+  const int p = list[blk];
+  const int n = S.n[p], N = n + 4;
+  const int64_t n3 = (int64_t)n * n * n, nf = (int64_t)n * n * (n + 1);
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n3 + 3 * nf) return;
+  const T* lo = lam + host_off[p];
+  T* LP = L.pad + (int64_t)blk * L.pad_stride;
+  const T dtdx = (T)(st.dt[blk] / S.dx[p]);
+  const int64_t fs = L.fm3;
+  if (c < n3) {
+    const int i = (int)(c % n), j = (int)((c / n) % n), k = (int)(c / ((int64_t)n * n));
+    for (int v = 0; v < 5; ++v) {
+      const T lv = lo[scell(n, v, i, j, k)];
+      LP[pcell(N, v, i, j, k)] += lv;
+      for (int d = 0; d < 3; ++d) {
+        T* LF = L.f + (int64_t)blk * L.f_stride + (int64_t)d * 8 * fs + (int64_t)v * fs;
+        int r[3] = {i, j, k};
+        r[d] += 1;
+        atomicAdd(&LF[wface(N, 0, r[0], r[1], r[2])], -dtdx * lv);
+        atomicAdd(&LF[wface(N, 0, i, j, k)], dtdx * lv);
+      }
+    }
+    return;
+  }
+  c -= n3;
+  const int d = (int)(c / nf);
+  c -= d * nf;
+  const int sx = n + (d == 0), sy = n + (d == 1);
+  const int i = (int)(c % sx), j = (int)((c / sx) % sy), k = (int)(c / ((int64_t)sx * sy));
+  const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+  const T lv = lo[sface(n, d, i, j, k)];
+  LP[pface(N, d, i, j, k)] += lv;
+  T* E1 = L.e + (int64_t)blk * L.e_stride + (int64_t)t1 * fs;
+  T* E2 = L.e + (int64_t)blk * L.e_stride + (int64_t)t2 * fs;
+  int p1[3] = {i, j, k}, p2[3] = {i, j, k};
+  p1[t1] += 1;
+  p2[t2] += 1;
+  const int64_t o0 = wface(N, 0, i, j, k);
+  // curl = (E2(p1) - E2(o)) - (E1(p2) - E1(o)); out = P - dtdx curl
+  atomicAdd(&E2[wface(N, 0, p1[0], p1[1], p1[2])], -dtdx * lv);
+  atomicAdd(&E2[o0], dtdx * lv);
+  atomicAdd(&E1[wface(N, 0, p2[0], p2[1], p2[2])], dtdx * lv);
+  atomicAdd(&E1[o0], -dtdx * lv);
+}
+
+// ---------------------------------------------------------------------------
+// edge EMFs (Gardiner & Stone E^c, upwinded by the face upwind speed)
+
+template <class T> __device__ __forceinline__ void up_adj(T u, T lam, T& la, T& lb) {
+  if (u > T(0)) {
+    la += lam;
+  } else if (u < T(0)) {
+    lb += lam;
+  } else {
+    la += T(0.5) * lam;
+    lb += T(0.5) * lam;
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_adj_emf(DevSet S, const int* __restrict__ list, int count, WorkPtr<T> W, WorkPtr<T> L) {
+  const int blk = blockIdx.y;
+  if (blk >= count) return;
+  const int p = list[blk];
+  const int n = S.n[p], N = n + 4;
+  const int64_t per = (int64_t)n * (n + 1) * (n + 1);
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= 3 * per) return;
+  const int a = (int)(c / per);
+  c -= a * per;
+  const int bax = (a + 1) % 3, cax = (a + 2) % 3;
+  int e[3];
+  e[a] = (int)(c % n);
+  e[bax] = (int)((c / n) % (n + 1));
+  e[cax] = (int)(c / ((int64_t)n * (n + 1)));
+  const int64_t fs = W.fm3;
+  const T lamE = L.e[(int64_t)blk * L.e_stride + (int64_t)a * fs + wface(N, 0, e[0], e[1], e[2])];
+  if (lamE == T(0)) return;
+  const T* Hp = W.h + (int64_t)blk * W.w_stride;
+  const T* Fb = W.f + (int64_t)blk * W.f_stride + (int64_t)bax * 8 * fs;
+  const T* Fc = W.f + (int64_t)blk * W.f_stride + (int64_t)cax * 8 * fs;
+  T* LH = L.h + (int64_t)blk * L.w_stride;
+  T* LFb = L.f + (int64_t)blk * L.f_stride + (int64_t)bax * 8 * fs;
+  T* LFc = L.f + (int64_t)blk * L.f_stride + (int64_t)cax * 8 * fs;
+  const int64_t NC = (int64_t)N * N * N;
+  int pA[3] = {e[0], e[1], e[2]}, pB[3] = {e[0], e[1], e[2]};
+  pB[cax] -= 1;
+  int pC[3] = {e[0], e[1], e[2]}, pD[3] = {e[0], e[1], e[2]};
+  pD[bax] -= 1;
+  const int64_t oA = wface(N, 0, pA[0], pA[1], pA[2]), oB = wface(N, 0, pB[0], pB[1], pB[2]);
+  const int64_t oC = wface(N, 0, pC[0], pC[1], pC[2]), oD = wface(N, 0, pD[0], pD[1], pD[2]);
+  // upwind speeds (the slot of the normal component holds them)
+  const T uA = Fb[(5 + bax) * fs + oA], uB = Fb[(5 + bax) * fs + oB];
+  const T uC = Fc[(5 + cax) * fs + oC], uD = Fc[(5 + cax) * fs + oD];
+  // E = (A + B + C + D)/4 + ((dc34 - dc14) + (db34 - db14))/4 with
+  //   dc14 = up(uA, c01 - D, c11 - C), dc34 = up(uB, D - c00, C - c10),
+  //   db14 = up(uC, c10 - B, c11 - A), db34 = up(uD, B - c00, A - c01)
+  const T q = T(0.25) * lamE;
+  T lA = q, lB = q, lC = q, lD = q, l00 = 0, l10 = 0, l01 = 0, l11 = 0;
+  T x, y;
+  x = y = T(0);  // dc14: weight -q
+  up_adj(uA, -q, x, y);
+  l01 += x; lD -= x; l11 += y; lC -= y;
+  x = y = T(0);  // dc34: weight +q
+  up_adj(uB, q, x, y);
+  lD += x; l00 -= x; lC += y; l10 -= y;
+  x = y = T(0);  // db14: weight -q
+  up_adj(uC, -q, x, y);
+  l10 += x; lB -= x; l11 += y; lA -= y;
+  x = y = T(0);  // db34: weight +q
+  up_adj(uD, q, x, y);
+  lB += x; l00 -= x; lA += y; l01 -= y;
+  // face EMFs: A = -Fb[B_c](oA), B = -Fb[B_c](oB), C = Fc[B_b](oC), D = Fc[B_b](oD)
+  atomicAdd(&LFb[(5 + cax) * fs + oA], -lA);
+  atomicAdd(&LFb[(5 + cax) * fs + oB], -lB);
+  atomicAdd(&LFc[(5 + bax) * fs + oC], lC);
+  atomicAdd(&LFc[(5 + bax) * fs + oD], lD);
+  // cell EMF E_a = v_c B_b - v_b B_c of the half-step state
+  auto cell = [&](int db, int dc, T lc) {
+    if (lc == T(0)) return;
+    int qq[3] = {e[0], e[1], e[2]};
+    qq[bax] += db;
+    qq[cax] += dc;
+    const int64_t o = wcell(N, 0, qq[0], qq[1], qq[2]);
+    const T vc = Hp[(1 + cax) * NC + o], bb = Hp[(5 + bax) * NC + o];
+    const T vb = Hp[(1 + bax) * NC + o], bc = Hp[(5 + cax) * NC + o];
+    atomicAdd(&LH[(1 + cax) * NC + o], lc * bb);
+    atomicAdd(&LH[(5 + bax) * NC + o], lc * vc);
+    atomicAdd(&LH[(1 + bax) * NC + o], -lc * bc);
+    atomicAdd(&LH[(5 + cax) * NC + o], -lc * vb);
+  };
+  cell(-1, -1, l00);
+  cell(0, -1, l10);
+  cell(-1, 0, l01);
+  cell(0, 0, l11);
+}
+
+// ---------------------------------------------------------------------------
+// interface fluxes
+
+template <class T>
+__global__ __launch_bounds__(256) void k_adj_flux(DevSet S, const int* __restrict__ list, int count, WorkPtr<T> W, WorkPtr<T> L) {
+  const int b = blockIdx.y;
+  if (b >= count) return;
+  const int p = list[b];
+  const int n = S.n[p], N = n + 4, M = n + 2;
+  const int64_t per = (int64_t)(n + 1) * M * M;
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= 3 * per) return;
+  const int d = (int)(c / per);
+  c -= d * per;
+  int idx[3];
+  const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+  idx[d] = (int)(c % (n + 1));
+  idx[t1] = (int)((c / (n + 1)) % M) - 1;
+  idx[t2] = (int)(c / ((int64_t)(n + 1) * M)) - 1;
+  int ia[3] = {idx[0], idx[1], idx[2]};
+  ia[d] -= 1;
+  const int64_t fs = W.fm3;
+  const int64_t of = wface(N, 0, idx[0], idx[1], idx[2]);
+  const T* LF = L.f + (int64_t)b * L.f_stride + (int64_t)d * 8 * fs;
+  T lf[7];
+  lf[0] = LF[of];
+  lf[1] = LF[(1 + d) * fs + of];
+  lf[2] = LF[(1 + t1) * fs + of];
+  lf[3] = LF[(1 + t2) * fs + of];
+  lf[4] = LF[4 * fs + of];
+  lf[5] = LF[(5 + t1) * fs + of];
+  lf[6] = LF[(5 + t2) * fs + of];
+  bool any = false;
+  for (int q = 0; q < 7; ++q) any = any || lf[q] != T(0);
+  if (!any) return;
+  const T* Wp = W.w + (int64_t)b * W.w_stride;
+  const T* Hp = W.h + (int64_t)b * W.w_stride;
+  const T* Sp = W.s + (int64_t)b * W.s_stride;
+  const T* Pd = W.pad + (int64_t)b * W.pad_stride;
+  T* LW = L.w + (int64_t)b * L.w_stride;
+  T* LH = L.h + (int64_t)b * L.w_stride;
+  T* LS = L.s + (int64_t)b * L.s_stride;
+  T* LP = L.pad + (int64_t)b * L.pad_stride;
+  const int64_t NC = (int64_t)N * N * N;
+  const int64_t ca = wcell(N, 0, ia[0], ia[1], ia[2]), cb = wcell(N, 0, idx[0], idx[1], idx[2]);
+  const int order[7] = {0, 1 + d, 1 + t1, 1 + t2, 4, 5 + t1, 5 + t2};
+  T l[7], r[7];
+  for (int m = 0; m < 7; ++m) {
+    const int v = order[m];
+    l[m] = Hp[v * NC + ca] + T(0.5) * Sp[(int64_t)(d * 8 + v) * NC + ca];
+    r[m] = Hp[v * NC + cb] - T(0.5) * Sp[(int64_t)(d * 8 + v) * NC + cb];
+  }
+  const int64_t opf = pface(N, d, idx[0], idx[1], idx[2]);
+  const T bface = Pd[opf];
+  T bn = bface + T(0.5) * ((Hp[(5 + d) * NC + ca] - Wp[(5 + d) * NC + ca]) +
+                           (Hp[(5 + d) * NC + cb] - Wp[(5 + d) * NC + cb]));
+  const bool fallback = !(l[0] > T(0)) || !(l[4] > T(0)) || !(r[0] > T(0)) || !(r[4] > T(0));
+  if (fallback) {
+    for (int m = 0; m < 7; ++m) {
+      l[m] = Wp[order[m] * NC + ca];
+      r[m] = Wp[order[m] * NC + cb];
+    }
+    bn = bface;
+  }
+  // lam of the 15 inputs (l, r, bn): one forward-mode pass per input
+  T g[15];
+#pragma unroll 1
+  for (int j = 0; j < 15; ++j) {
+    Dual<T> dl[7], dr[7], df[8];
+    for (int m = 0; m < 7; ++m) {
+      dl[m] = Dual<T>(l[m], j == m ? T(1) : T(0));
+      dr[m] = Dual<T>(r[m], j == 7 + m ? T(1) : T(0));
+    }
+    const Dual<T> dbn(bn, j == 14 ? T(1) : T(0));
+    hlld_flux<Dual<T>, DualExact<T>>(dl, dr, dbn, Dual<T>(T(S.gamma)), df);
+    T acc = T(0);
+    for (int q = 0; q < 7; ++q) acc += lf[q] * df[q].d;
+    g[j] = acc;
+  }
+  if (fallback) {
+    for (int m = 0; m < 7; ++m) {
+      atomicAdd(&LW[order[m] * NC + ca], g[m]);
+      atomicAdd(&LW[order[m] * NC + cb], g[7 + m]);
+    }
+    atomicAdd(&LP[opf], g[14]);
+    return;
+  }
+  for (int m = 0; m < 7; ++m) {
+    const int v = order[m];
+    atomicAdd(&LH[v * NC + ca], g[m]);
+    atomicAdd(&LS[(int64_t)(d * 8 + v) * NC + ca], T(0.5) * g[m]);
+    atomicAdd(&LH[v * NC + cb], g[7 + m]);
+    atomicAdd(&LS[(int64_t)(d * 8 + v) * NC + cb], T(-0.5) * g[7 + m]);
+  }
+  // bn = bface + (H_a - W_a + H_b - W_b)/2 for the normal component
+  const T hb = T(0.5) * g[14];
+  atomicAdd(&LP[opf], g[14]);
+  atomicAdd(&LH[(5 + d) * NC + ca], hb);
+  atomicAdd(&LW[(5 + d) * NC + ca], -hb);
+  atomicAdd(&LH[(5 + d) * NC + cb], hb);
+  atomicAdd(&LW[(5 + d) * NC + cb], -hb);
+}
+
+// ---------------------------------------------------------------------------
+// Hancock predictor on [-1, n]^3 (one thread per cell; no other writer of the
+// cell's entries in this kernel)
+
+template <class T>
+__global__ __launch_bounds__(256) void k_adj_pred(DevSet S, const int* __restrict__ list, int count, WorkPtr<T> W, WorkPtr<T> L,
+                           StepPtr st) {
+  const int b = blockIdx.y;
+  if (b >= count) return;
+  const int p = list[b];
+  const int n = S.n[p], N = n + 4, M = n + 2;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= (int64_t)M * M * M) return;
+  const int i = (int)(c % M) - 1, j = (int)((c / M) % M) - 1, k = (int)(c / ((int64_t)M * M)) - 1;
+  const int64_t NC = (int64_t)N * N * N;
+  const int64_t o = wcell(N, 0, i, j, k);
+  T* LH = L.h + (int64_t)b * L.w_stride;
+  T lh[8];
+  bool any = false;
+  for (int v = 0; v < 8; ++v) {
+    lh[v] = LH[v * NC + o];
+    any = any || lh[v] != T(0);
+  }
+  if (!any) return;
+  const T* Wp = W.w + (int64_t)b * W.w_stride;
+  const T* Sp = W.s + (int64_t)b * W.s_stride;
+  T* LW = L.w + (int64_t)b * L.w_stride;
+  T* LS = L.s + (int64_t)b * L.s_stride;
+  T w[8], sl[3][8];
+  for (int v = 0; v < 8; ++v) w[v] = Wp[v * NC + o];
+  for (int d = 0; d < 3; ++d)
+    for (int v = 0; v < 8; ++v) sl[d][v] = Sp[(int64_t)(d * 8 + v) * NC + o];
+  const T hdtdx = (T)(0.5 * st.dt[b] / S.dx[p]);
+  const Dual<T> g(T(S.gamma)), hd(hdtdx);
+  // inputs 0..7: primitives, 8..31: slopes (d, v); sl[d][5 + d] is not an input
+#pragma unroll 1
+  for (int jdir = 0; jdir < 32; ++jdir) {
+    if (jdir >= 8) {
+      const int d = (jdir - 8) / 8, v = (jdir - 8) % 8;
+      if (v == 5 + d) continue;
+    }
+    Dual<T> dw[8], dsl[3][8], dH[8];
+    for (int v = 0; v < 8; ++v) dw[v] = Dual<T>(w[v], jdir == v ? T(1) : T(0));
+    for (int d = 0; d < 3; ++d)
+      for (int v = 0; v < 8; ++v) dsl[d][v] = Dual<T>(sl[d][v], jdir == 8 + d * 8 + v ? T(1) : T(0));
+    hancock<Dual<T>, DualExact<T>>(dw, dsl, hd, g, dH);
+    T acc = T(0);
+    for (int v = 0; v < 8; ++v) acc += lh[v] * dH[v].d;
+    if (jdir < 8)
+      LW[jdir * NC + o] += acc;
+    else
+      LS[(int64_t)(jdir - 8) * NC + o] += acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// van Leer slopes S_d(c) = vl(W(c) - W(c - e_d), W(c + e_d) - W(c)), c in [-1, n]^3
+
+template <class T>
+__global__ __launch_bounds__(256) void k_adj_slope(DevSet S, const int* __restrict__ list, int count, WorkPtr<T> W, WorkPtr<T> L) {
+  const int b = blockIdx.y;
+  if (b >= count) return;
+  const int p = list[b];
+  const int n = S.n[p], N = n + 4, M = n + 2;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= (int64_t)M * M * M) return;
+  const int i = (int)(c % M) - 1, j = (int)((c / M) % M) - 1, k = (int)(c / ((int64_t)M * M)) - 1;
+  const int64_t NC = (int64_t)N * N * N;
+  const T* Wp = W.w + (int64_t)b * W.w_stride;
+  const T* LS = L.s + (int64_t)b * L.s_stride;
+  T* LW = L.w + (int64_t)b * L.w_stride;
+  const int64_t o = wcell(N, 0, i, j, k);
+  for (int d = 0; d < 3; ++d) {
+    int im = i, jm = j, km = k, ip = i, jp = j, kp = k;
+    if (d == 0) { im--; ip++; } else if (d == 1) { jm--; jp++; } else { km--; kp++; }
+    const int64_t om = wcell(N, 0, im, jm, km), op = wcell(N, 0, ip, jp, kp);
+    for (int v = 0; v < 8; ++v) {
+      if (v == 5 + d) continue;
+      const T ls = LS[(int64_t)(d * 8 + v) * NC + o];
+      if (ls == T(0)) continue;
+      const T w0 = Wp[v * NC + o];
+      const T dl = w0 - Wp[v * NC + om], dr = Wp[v * NC + op] - w0;
+      if (!(dl * dr > T(0))) continue;  // limited to zero: no dependence
+      const T sum = dl + dr;
+      const T gl = T(2) * dr * dr / (sum * sum), gr = T(2) * dl * dl / (sum * sum);
+      atomicAdd(&LW[v * NC + om], -ls * gl);
+      atomicAdd(&LW[v * NC + o], ls * (gl - gr));
+      atomicAdd(&LW[v * NC + op], ls * gr);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// primitives over the padded cells [-2, n+1]^3
+
+template <class T>
+__global__ __launch_bounds__(256) void k_adj_prim(DevSet S, const int* __restrict__ list, int count, WorkPtr<T> W, WorkPtr<T> L) {
+  const int b = blockIdx.y;
+  if (b >= count) return;
+  const int p = list[b];
+  const int n = S.n[p], N = n + 4;
+  const int64_t NC = (int64_t)N * N * N;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= NC) return;
+  const int i = (int)(c % N) - 2, j = (int)((c / N) % N) - 2, k = (int)(c / ((int64_t)N * N)) - 2;
+  const int64_t o = wcell(N, 0, i, j, k);
+  const T* LW = L.w + (int64_t)b * L.w_stride;
+  T lw[8];
+  bool any = false;
+  for (int v = 0; v < 8; ++v) {
+    lw[v] = LW[v * NC + o];
+    any = any || lw[v] != T(0);
+  }
+  if (!any) return;
+  const T* Pd = W.pad + (int64_t)b * W.pad_stride;
+  T* LP = L.pad + (int64_t)b * L.pad_stride;
+  const T rho = Pd[pcell(N, 0, i, j, k)];
+  const T m[3] = {Pd[pcell(N, 1, i, j, k)], Pd[pcell(N, 2, i, j, k)], Pd[pcell(N, 3, i, j, k)]};
+  const T en = Pd[pcell(N, 4, i, j, k)];
+  const int64_t fl[3] = {pface(N, 0, i, j, k), pface(N, 1, i, j, k), pface(N, 2, i, j, k)};
+  const int64_t fr[3] = {pface(N, 0, i + 1, j, k), pface(N, 1, i, j + 1, k), pface(N, 2, i, j, k + 1)};
+  T bc[3];
+  for (int d = 0; d < 3; ++d) bc[d] = T(0.5) * (Pd[fl[d]] + Pd[fr[d]]);
+  const T ir = T(1) / rho;
+  const T ke = T(0.5) * (m[0] * m[0] + m[1] * m[1] + m[2] * m[2]) * ir;
+  const T gm1 = T(S.gamma) - T(1);
+  const T pr = gm1 * (en - ke - T(0.5) * (bc[0] * bc[0] + bc[1] * bc[1] + bc[2] * bc[2]));
+  // a pressure raised to the floor does not depend on the state
+  const T lp = (S.p_floor > 0.0 && pr < T(S.p_floor)) ? T(0) : lw[4];
+  T lrho = lw[0] + lp * gm1 * ke * ir;
+  T lm[3], lb[3];
+  for (int d = 0; d < 3; ++d) {
+    const T vd = m[d] * ir;
+    lrho -= lw[1 + d] * vd * ir;
+    lm[d] = lw[1 + d] * ir - lp * gm1 * vd;
+    lb[d] = lw[5 + d] - lp * gm1 * bc[d];
+  }
+  LP[pcell(N, 0, i, j, k)] += lrho;
+  for (int d = 0; d < 3; ++d) LP[pcell(N, 1 + d, i, j, k)] += lm[d];
+  LP[pcell(N, 4, i, j, k)] += lp * gm1;
+  for (int d = 0; d < 3; ++d) {
+    atomicAdd(&LP[fl[d]], T(0.5) * lb[d]);
+    atomicAdd(&LP[fr[d]], T(0.5) * lb[d]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// guard fill: every padded element is the patch's own value (interior) or a
+// copy of one source element (same resolution, same time in a fixed step)
+
+template <class T>
+__global__ __launch_bounds__(256) void k_adj_fill(DevSet S, const int* __restrict__ list, int count, WorkPtr<T> L,
+                           T* __restrict__ lam, const int64_t* __restrict__ host_off) {
+  const int b = blockIdx.y;
+  if (b >= count) return;
+  const int p = list[b];
+  const int n = S.n[p], N = n + 4;
+  const int64_t ncell = (int64_t)N * N * N, nface = (int64_t)N * N * (N + 1);
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 5 * ncell + 3 * nface) return;
+  const T lv = L.pad[(int64_t)b * L.pad_stride + e];
+  if (lv == T(0)) return;
+  int comp, var, i, j, k;
+  if (e < 5 * ncell) {
+    comp = -1;
+    var = (int)(e / ncell);
+    int64_t r = e - var * ncell;
+    i = (int)(r % N) - 2;
+    r /= N;
+    j = (int)(r % N) - 2;
+    k = (int)(r / N) - 2;
+  } else {
+    int64_t r = e - 5 * ncell;
+    comp = (int)(r / nface);
+    var = 0;
+    r -= comp * nface;
+    const int sx = N + (comp == 0), sy = N + (comp == 1);
+    i = (int)(r % sx) - 2;
+    r /= sx;
+    j = (int)(r % sy) - 2;
+    k = (int)(r / sy) - 2;
+  }
+  const int idx[3] = {i, j, k};
+  int rg[3];
+  bool interior = true;
+  for (int d = 0; d < 3; ++d) {
+    const int hi = n + (d == comp ? 1 : 0);
+    rg[d] = idx[d] < 0 ? 0 : (idx[d] < hi ? 1 : 2);
+    interior = interior && rg[d] == 1;
+  }
+  if (interior) {
+    const int64_t se = (comp < 0) ? scell(n, var, i, j, k) : sface(n, comp, i, j, k);
+    atomicAdd(&lam[host_off[p] + se], lv);
+    return;
+  }
+  const int key = p * 108 + (comp + 1) * 27 + (rg[2] * 3 + rg[1]) * 3 + rg[0];
+  for (int m = S.rbox_off[key]; m < S.rbox_off[key + 1]; ++m) {
+    const GBox& G = S.boxes[m];
+    if (i < G.lo[0] || i > G.hi[0] || j < G.lo[1] || j > G.hi[1] || k < G.lo[2] || k > G.hi[2]) continue;
+    if (!G.same) {
+      atomicOr(S.err, ERR_STATE);  // resampled guards are not differentiated here
+      return;
+    }
+    const int nq = S.n[G.q];
+    const int qi = i + G.shift[0], qj = j + G.shift[1], qk = k + G.shift[2];
+    const int64_t se = (comp < 0) ? scell(nq, var, qi, qj, qk) : sface(nq, comp, qi, qj, qk);
+    atomicAdd(&lam[host_off[G.q] + se], lv);
+    return;
+  }
+  atomicOr(S.err, ERR_STATE);
+}
+
+// ---------------------------------------------------------------------------
+
+template <class T>
+void launch_adjoint_step(const DevSet& S, const int* list, int count, int nmax, const WorkPtr<T>& W,
+                         const WorkPtr<T>& L, const StepPtr& st, const T* lam_next, T* lam_prev,
+                         const int64_t* host_off, hipStream_t s) {
+  const int n = nmax, N = n + 4, M = n + 2;
+  auto blocks = [](int64_t items) { return (unsigned)((items + 255) / 256); };
+  const int64_t n3 = (int64_t)n * n * n, nf = (int64_t)n * n * (n + 1);
+  hipLaunchKernelGGL(k_adj_update<T>, dim3(blocks(n3 + 3 * nf), count), dim3(256), 0, s, S, list, count, L, st,
+                     lam_next, host_off);
+  hipLaunchKernelGGL(k_adj_emf<T>, dim3(blocks(3LL * n * (n + 1) * (n + 1)), count), dim3(256), 0, s, S, list, count,
+                     W, L);
+  hipLaunchKernelGGL(k_adj_flux<T>, dim3(blocks(3LL * (n + 1) * M * M), count), dim3(256), 0, s, S, list, count, W,
+                     L);
+  hipLaunchKernelGGL(k_adj_pred<T>, dim3(blocks((int64_t)M * M * M), count), dim3(256), 0, s, S, list, count, W, L,
+                     st);
+  hipLaunchKernelGGL(k_adj_slope<T>, dim3(blocks((int64_t)M * M * M), count), dim3(256), 0, s, S, list, count, W, L);
+  hipLaunchKernelGGL(k_adj_prim<T>, dim3(blocks((int64_t)N * N * N), count), dim3(256), 0, s, S, list, count, W, L);
+  hipLaunchKernelGGL(k_adj_fill<T>, dim3(blocks(5LL * N * N * N + 3LL * N * N * (N + 1)), count), dim3(256), 0, s,
+                     S, list, count, L, lam_prev, host_off);
+}
+
+template void launch_adjoint_step<float>(const DevSet&, const int*, int, int, const WorkPtr<float>&,
+                                         const WorkPtr<float>&, const StepPtr&, const float*, float*,
+                                         const int64_t*, hipStream_t);
+template void launch_adjoint_step<double>(const DevSet&, const int*, int, int, const WorkPtr<double>&,
+                                          const WorkPtr<double>&, const StepPtr&, const double*, double*,
+                                          const int64_t*, hipStream_t);
+
+}  // namespace dsp

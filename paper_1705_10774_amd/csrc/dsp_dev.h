@@ -117,6 +117,10 @@ template <class T>
 int launch_fused(const DevSet& S, const int* list, int count, int nmax, T* slots, T* pad, int64_t pad_stride,
                   bool gfill, double* smax, const StepPtr& st, hipStream_t s, int dt_kind, double t_end, int clip,
                   hipEvent_t ev0, hipEvent_t ev1);
+template <class T>
+void launch_adjoint_step(const DevSet& S, const int* list, int count, int nmax, const WorkPtr<T>& W,
+                         const WorkPtr<T>& L, const StepPtr& st, const T* lam_next, T* lam_prev,
+                         const int64_t* host_off, hipStream_t s);
 void launch_dt(const DevSet& S, const int* list, int count, const StepPtr& st, const double* smax, hipStream_t s,
                int dt_kind, double t_end, int clip);
 void launch_publish(const DevSet& S, const int* list, int count, const StepPtr& st, hipStream_t s);

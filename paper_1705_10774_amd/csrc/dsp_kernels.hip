@@ -261,38 +261,24 @@ __global__ void k_pred(DevSet S, const int* __restrict__ list, int count, WorkPt
   T* Sp = W.s + (int64_t)b * W.s_stride;
   T* Hp = W.h + (int64_t)b * W.w_stride;
   const int64_t NC = (int64_t)N * N * N;
-  T w[8];
+  T w[8], sl[3][8], H[8];
   for (int v = 0; v < 8; ++v) w[v] = Wp[wcell(N, v, i, j, k)];
-  const T ir = T(1) / w[0];
-  const T g = T(S.gamma);
-  T sum[8] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
   for (int d = 0; d < 3; ++d) {
-    const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
     int im = i, jm = j, km = k, ip = i, jp = j, kp = k;
     if (d == 0) { im--; ip++; } else if (d == 1) { jm--; jp++; } else { km--; kp++; }
-    T sl[8];
     for (int v = 0; v < 8; ++v) {
       if (v == 5 + d) {
-        sl[v] = T(0);
+        sl[d][v] = T(0);
         continue;
       }
       const T a = Wp[wcell(N, v, im, jm, km)], cc = Wp[wcell(N, v, ip, jp, kp)];
-      sl[v] = van_leer(w[v] - a, cc - w[v]);
+      sl[d][v] = van_leer(w[v] - a, cc - w[v]);
     }
-    for (int v = 0; v < 8; ++v) Sp[(int64_t)(d * 8 + v) * NC + wcell(N, 0, i, j, k)] = sl[v];
-    // primitive Jacobian of the 1-D problem along d, normal field constant
-    const T un = w[1 + d];
-    const T bn = w[5 + d], b1 = w[5 + t1], b2 = w[5 + t2];
-    sum[0] = sum[0] + (un * sl[0] + w[0] * sl[1 + d]);
-    sum[1 + d] = sum[1 + d] + (un * sl[1 + d] + (sl[4] + b1 * sl[5 + t1] + b2 * sl[5 + t2]) * ir);
-    sum[1 + t1] = sum[1 + t1] + (un * sl[1 + t1] - bn * sl[5 + t1] * ir);
-    sum[1 + t2] = sum[1 + t2] + (un * sl[1 + t2] - bn * sl[5 + t2] * ir);
-    sum[4] = sum[4] + (un * sl[4] + g * w[4] * sl[1 + d]);
-    sum[5 + t1] = sum[5 + t1] + (un * sl[5 + t1] + b1 * sl[1 + d] - bn * sl[1 + t1]);
-    sum[5 + t2] = sum[5 + t2] + (un * sl[5 + t2] + b2 * sl[1 + d] - bn * sl[1 + t2]);
+    for (int v = 0; v < 8; ++v) Sp[(int64_t)(d * 8 + v) * NC + wcell(N, 0, i, j, k)] = sl[d][v];
   }
   const T hdtdx = (T)(0.5 * st.dt[b] / S.dx[p]);
-  for (int v = 0; v < 8; ++v) Hp[wcell(N, v, i, j, k)] = w[v] - hdtdx * sum[v];
+  hancock(w, sl, hdtdx, T(S.gamma), H);
+  for (int v = 0; v < 8; ++v) Hp[wcell(N, v, i, j, k)] = H[v];
 }
 
 // ---------------------------------------------------------------------------

@@ -355,6 +355,46 @@ struct dsp_set {
   // one launch sequence for list[off .. off+count)
   bool fused = true;  // fused marching kernel (false: staged kernels)
   bool any_generic = false;  // some guard region is not one same-resolution box
+  // adjoint: staged work buffers of the recomputed forward step, their
+  // cotangents, the states of one checkpoint segment and two cotangent
+  // vectors (allocated on first use)
+  bool adj_ready = false;
+  void* adj_w[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  void* adj_l[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  void *adj_states = nullptr, *adj_la = nullptr, *adj_lb = nullptr;
+  int adj_prepare() {
+    if (adj_ready) return 0;
+    const size_t tsz = f32 ? 4 : 8;
+    const int64_t sizes[6] = {pad_stride, w_stride, w_stride, s_stride, f_stride, e_stride};
+    for (int q = 0; q < 6; ++q) {
+      adj_w[q] = dalloc(tsz * (size_t)sizes[q] * np);
+      adj_l[q] = dalloc(tsz * (size_t)sizes[q] * np);
+    }
+    adj_states = dalloc(tsz * (size_t)total_values * 8);
+    adj_la = dalloc(tsz * (size_t)total_values);
+    adj_lb = dalloc(tsz * (size_t)total_values);
+    if (alloc_failed) return DSP_ENOMEM;
+    adj_ready = true;
+    return 0;
+  }
+  template <class T> WorkPtr<T> adj_work(bool cot) const {
+    void* const* b = cot ? adj_l : adj_w;
+    WorkPtr<T> W;
+    W.pad = (T*)b[0];
+    W.pad_stride = pad_stride;
+    W.w = (T*)b[1];
+    W.h = (T*)b[2];
+    W.w_stride = w_stride;
+    W.s = (T*)b[3];
+    W.s_stride = s_stride;
+    W.f = (T*)b[4];
+    W.f_stride = f_stride;
+    W.fm3 = fm3;
+    W.e = (T*)b[5];
+    W.e_stride = e_stride;
+    W.smax = smax;
+    return W;
+  }
   int dt_fused = 0;          // the last step launch also computed the Courant rate and level
   void update_batch(int off, int count, int dt_kind, double t_end, int clip, const int* list) {
     hipEvent_t e0 = next_event(true), e1 = next_event(false);
@@ -967,25 +1007,68 @@ int dsp_kernel_time(const dsp_set* s, double* ms, int64_t* launches) {
   return 0;
 }
 
+// Fixed steps: every patch at t = 0 with the given state (device, host
+// layout) in slot 0, schedule record, counters and error flags cleared.
+static int reset_fixed(dsp_set* s, const void* U_dev) { return init_common(s, nullptr, U_dev, 0.0); }
+
+extern "C++" {
+// One fixed step with the staged kernels from state U_in, leaving every
+// intermediate in the adjoint's work buffers; U_out (nullable) receives the
+// new state.
+template <class T> static int staged_fixed_step(dsp_set* s, const T* U_in, T* U_out) {
+  int e = reset_fixed(s, U_in);
+  if (e) return e;
+  launch_update<T>(s->D, s->d_list, s->np, s->nmax, (T*)s->slots, s->adj_work<T>(false), s->st, s->stream, 1, 0.0,
+                   0, nullptr, nullptr);
+  if (U_out) {
+    launch_publish(s->D, s->d_list, s->np, s->st, s->stream);
+    launch_pack<T>(s->D, (const T*)s->slots, U_out, s->d_host_off, s->stream);
+  }
+  return 0;
+}
+
+template <class T>
+static int adjoint_run(dsp_set* s, const T* ckpt, const T* lamT, T* lam0, int nsteps) {
+  const size_t V = (size_t)s->total_values;
+  std::vector<int> all(s->np);
+  for (int p = 0; p < s->np; ++p) all[p] = p;
+  int e = hipck(hipMemcpyAsync(s->d_list, all.data(), sizeof(int) * s->np, hipMemcpyHostToDevice, s->stream), "list");
+  if (e) return e;
+  T* states = (T*)s->adj_states;
+  T* la = (T*)s->adj_la;
+  T* lb = (T*)s->adj_lb;
+  e = hipck(hipMemcpyAsync(la, lamT, sizeof(T) * V, hipMemcpyDeviceToDevice, s->stream), "adjoint");
+  const WorkPtr<T> W = s->adj_work<T>(false), L = s->adj_work<T>(true);
+  const int nseg = (nsteps + 7) / 8;
+  for (int seg = nseg - 1; seg >= 0 && !e; --seg) {
+    const int len = std::min(8, nsteps - 8 * seg);
+    e = hipck(hipMemcpyAsync(states, ckpt + (size_t)seg * V, sizeof(T) * V, hipMemcpyDeviceToDevice, s->stream),
+              "adjoint");
+    for (int j = 1; j < len && !e; ++j) e = staged_fixed_step<T>(s, states + (size_t)(j - 1) * V, states + (size_t)j * V);
+    for (int j = len - 1; j >= 0 && !e; --j) {
+      e = staged_fixed_step<T>(s, states + (size_t)j * V, (T*)nullptr);
+      if (e) break;
+      for (int q = 0; q < 6; ++q) {
+        const int64_t sizes[6] = {s->pad_stride, s->w_stride, s->w_stride, s->s_stride, s->f_stride, s->e_stride};
+        (void)hipMemsetAsync(s->adj_l[q], 0, sizeof(T) * (size_t)sizes[q] * s->np, s->stream);
+      }
+      (void)hipMemsetAsync(lb, 0, sizeof(T) * V, s->stream);
+      launch_adjoint_step<T>(s->D, s->d_list, s->np, s->nmax, W, L, s->st, la, lb, s->d_host_off, s->stream);
+      e = read_err(s, nullptr);
+      std::swap(la, lb);
+    }
+  }
+  if (!e) e = hipck(hipMemcpyAsync(lam0, la, sizeof(T) * V, hipMemcpyDeviceToDevice, s->stream), "adjoint");
+  if (!e) e = hipck(hipStreamSynchronize(s->stream), "adjoint");
+  return e;
+}
+}  // extern "C++"
+
 int dsp_fixed_steps_fwd(dsp_set* s, const void* U0_dev, void* UT_dev, int32_t nsteps, void* ckpt_dev) {
   if (!s || !U0_dev || !UT_dev || nsteps < 0) return fail(DSP_EINVAL, "bad argument");
   if (s->cfg.dt_mode != DSP_DT_FIXED) return fail(DSP_EINVAL, "fixed steps need the FIXED dt mode");
-  // reset the time bookkeeping to t = 0 with the given state in slot 0
-  const int np = s->np, ns = s->cfg.nslots;
-  std::vector<int> cur(np, 0);
-  std::vector<double> tc(np, 0.0), stime((size_t)np * ns, 0.0);
-  std::vector<int8_t> valid((size_t)np * ns, 0);
-  for (int p = 0; p < np; ++p) valid[(size_t)p * ns] = 1;
-  int e = hipck(hipMemcpyAsync(s->D.cur, cur.data(), sizeof(int) * np, hipMemcpyHostToDevice, s->stream), "reset");
-  if (!e) e = hipck(hipMemcpyAsync(s->D.tcur, tc.data(), sizeof(double) * np, hipMemcpyHostToDevice, s->stream), "reset");
-  if (!e) e = hipck(hipMemcpyAsync(s->D.stime, stime.data(), sizeof(double) * np * ns, hipMemcpyHostToDevice, s->stream), "reset");
-  if (!e) e = hipck(hipMemcpyAsync(s->D.svalid, valid.data(), (size_t)np * ns, hipMemcpyHostToDevice, s->stream), "reset");
+  int e = reset_fixed(s, U0_dev);
   if (e) return e;
-  if (s->f32)
-    launch_unpack<float>(s->D, (float*)s->slots, (const float*)U0_dev, s->d_host_off, s->stream);
-  else
-    launch_unpack<double>(s->D, (double*)s->slots, (const double*)U0_dev, s->d_host_off, s->stream);
-  s->initialised = true;
   const size_t tsz = s->f32 ? 4 : 8;
   s->begin_timing();
   for (int m = 0; m < nsteps && !e; m += 8) {
@@ -1016,13 +1099,18 @@ int dsp_fixed_steps_fwd(dsp_set* s, const void* U0_dev, void* UT_dev, int32_t ns
 
 int dsp_fixed_steps_adj(dsp_set* s, const void* ckpt_dev, const void* lamT_dev, void* lam0_dev, int32_t nsteps,
                         int32_t seg) {
-  (void)ckpt_dev;
-  (void)lamT_dev;
-  (void)lam0_dev;
-  (void)nsteps;
-  (void)seg;
-  if (!s) return fail(DSP_EINVAL, "null handle");
-  return fail(DSP_EINVAL, "adjoint not available in this build");
+  if (!s || !ckpt_dev || !lamT_dev || !lam0_dev || nsteps < 0) return fail(DSP_EINVAL, "bad argument");
+  if (s->cfg.dt_mode != DSP_DT_FIXED) return fail(DSP_EINVAL, "the adjoint needs the FIXED dt mode");
+  if (seg != 8) return fail(DSP_EINVAL, "checkpoint segments are 8 steps");
+  if (s->any_generic)
+    return fail(DSP_EINVAL, "the adjoint covers sets whose guard regions are same-resolution copies");
+  int e = s->adj_prepare();
+  if (e) return fail(DSP_ENOMEM, "device allocation failed: " + s->alloc_msg);
+  if (s->f32)
+    e = adjoint_run<float>(s, (const float*)ckpt_dev, (const float*)lamT_dev, (float*)lam0_dev, nsteps);
+  else
+    e = adjoint_run<double>(s, (const double*)ckpt_dev, (const double*)lamT_dev, (double*)lam0_dev, nsteps);
+  return e;
 }
 
 void dsp_destroy(dsp_set* s) { delete s; }

@@ -163,6 +163,33 @@ __device__ __forceinline__ void hlld_flux(const T* l, const T* r, T bn, T gamma,
   f[6] = f[6] + Ss * (c2 - s.b2);
 }
 
+// Hancock half-step predictor of one cell: W^{n+1/2} = W - (dt/2dx) sum_d
+// A_d(W) sl_d, with A_d the 1-D primitive Jacobian along d (normal field held
+// constant), summed in the order x, y, z.  w = (rho, vx, vy, vz, p, Bx, By,
+// Bz); sl[d] the limited slopes along d (sl[d][5 + d] = 0).
+template <class T, class M = Exact<T>>
+__device__ __forceinline__ void hancock(const T* w, const T (*sl)[8], T hdtdx, T gamma, T* H) {
+  const T ir = M::rcp(w[0]);
+  T sum[8];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) sum[v] = T(0);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+    const T un = w[1 + d], bn = w[5 + d], b1 = w[5 + t1], b2 = w[5 + t2];
+    const T* s = sl[d];
+    sum[0] = sum[0] + (un * s[0] + w[0] * s[1 + d]);
+    sum[1 + d] = sum[1 + d] + (un * s[1 + d] + (s[4] + b1 * s[5 + t1] + b2 * s[5 + t2]) * ir);
+    sum[1 + t1] = sum[1 + t1] + (un * s[1 + t1] - bn * s[5 + t1] * ir);
+    sum[1 + t2] = sum[1 + t2] + (un * s[1 + t2] - bn * s[5 + t2] * ir);
+    sum[4] = sum[4] + (un * s[4] + gamma * w[4] * s[1 + d]);
+    sum[5 + t1] = sum[5 + t1] + (un * s[5 + t1] + b1 * s[1 + d] - bn * s[1 + t1]);
+    sum[5 + t2] = sum[5 + t2] + (un * s[5 + t2] + b2 * s[1 + d] - bn * s[1 + t2]);
+  }
+#pragma unroll
+  for (int v = 0; v < 8; ++v) H[v] = w[v] - hdtdx * sum[v];
+}
+
 // van Leer limited slope from the two one-sided differences.
 template <class T, class M = Exact<T>>
 __device__ __forceinline__ T van_leer(T dl, T dr) {

@@ -256,3 +256,52 @@ class PatchSet:
 
     def kernel_stats(self):
         return dsp_kernel_stats(self.h)
+
+    # ---- fixed-dt steps and their adjoint (device tensors in the host layout)
+
+    def _dtype(self):
+        import torch
+        return torch.float32 if self.cfg.prec == 1 else torch.float64
+
+    def fixed_steps_fwd(self, U0, nsteps, checkpoints=True):
+        """nsteps fixed steps from the device tensor U0 (host layout, the set's
+        precision).  Returns (UT, ckpt): ckpt holds the state every 8 steps
+        (None if checkpoints is False)."""
+        import torch
+        U0 = U0.contiguous()
+        if U0.dtype != self._dtype() or U0.numel() != self.nvals or not U0.is_cuda:
+            raise ValueError("U0 must be a device tensor of the set's precision and size")
+        UT = torch.empty_like(U0)
+        ckpt = torch.empty((nsteps // 8 + 1, self.nvals), dtype=U0.dtype, device=U0.device) if checkpoints else None
+        dsp_fixed_steps_fwd(self.h, U0.data_ptr(), UT.data_ptr(), nsteps,
+                            ckpt.data_ptr() if ckpt is not None else None)
+        return UT, ckpt
+
+    def fixed_steps_adj(self, ckpt, lamT, nsteps):
+        """dJ/dU0 from dJ/dUT (device tensors) through nsteps fixed steps,
+        recomputing forward states from the checkpoints."""
+        import torch
+        lamT = lamT.contiguous().to(self._dtype())
+        lam0 = torch.empty_like(lamT)
+        dsp_fixed_steps_adj(self.h, ckpt.data_ptr(), lamT.data_ptr(), lam0.data_ptr(), nsteps, 8)
+        return lam0
+
+
+def fixed_steps(pset, U0, nsteps):
+    """Differentiable nsteps fixed-dt steps of the patch set: UT = F(U0), with
+    the gradient from the hand-written adjoint (checkpoints every 8 steps)."""
+    import torch
+
+    class _FixedSteps(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, u0):
+            UT, ckpt = pset.fixed_steps_fwd(u0.detach(), nsteps, checkpoints=True)
+            ctx.save_for_backward(ckpt)
+            return UT
+
+        @staticmethod
+        def backward(ctx, gUT):
+            (ckpt,) = ctx.saved_tensors
+            return pset.fixed_steps_adj(ckpt, gUT, nsteps)
+
+    return _FixedSteps.apply(U0)
