@@ -160,6 +160,42 @@ def main():
         out["fp64_plain"] = {"value": plain_rate, "sample": "cfg2, t 0 -> 4 dt_base",
                              "updates": pst[0]}
         out["speedup_batched_fp32_vs_plain_fp64"] = value / plain_rate
+        # local-dt saving: cell updates of the same run with one global
+        # quantised step (the smallest level of the set) over local steps
+        pr_g = I.cfg2_turb(prec=I.F32)
+        s = dsp.PatchSet.from_problem(pr_g, dt_mode=I.DT_GLOBAL_QUANT)
+        s.advance_to(pr_g.t_end)
+        upd_global = s.stats()[0]
+        s.close()
+        out["local_dt_saving"] = upd_global / res32["updates"]
+        # adjoint: 64 patches of 16^3, 32 fixed FP64 steps, checkpoints every 8
+        pr5 = I.cfg5_adjoint(prec=I.F64)
+        s = dsp.PatchSet(pr5.cfg, pr5.patches)
+        U5 = torch.from_numpy(pr5.U0).to(dev)
+        s.fixed_steps_fwd(U5, pr5.nsteps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        UT5, ck5 = s.fixed_steps_fwd(U5, pr5.nsteps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s.fixed_steps_adj(ck5, torch.ones_like(UT5), pr5.nsteps)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        s.close()
+        out["adjoint"] = {"workload": "64 patches of 16^3, 32 fixed FP64 steps, checkpoints every 8",
+                          "forward_ms": (t1 - t0) * 1e3, "adjoint_ms": (t2 - t1) * 1e3,
+                          "adjoint_over_forward": (t2 - t1) / (t1 - t0)}
+        # plain device copy bandwidth on this GPU (256 MiB, read + write)
+        a = torch.ones(64 * 1024 * 1024, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        out["copy_GBs"] = 10 * 2 * a.numel() * 4 / (t1 - t0) / 1e9
         # CPU baseline: the oracle on the host cores, bounded sample
         from oracle import oracle
         cores = len(os.sched_getaffinity(0))
