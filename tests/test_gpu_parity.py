@@ -282,3 +282,37 @@ def test_kernel_record():
     ks = s.kernel_stats()
     s.close()
     assert ks[0] > 0.0 and ks[1] >= 1 and ks[3] == 1
+
+
+@pytest.fixture(scope="module")
+def cfg2_oracle_full(orc):
+    """The oracle's configuration 2 run to t_end (computed once per module)."""
+    pr = I.cfg2_turb(prec=I.F64)
+    return orc_run(orc, pr)
+
+
+@pytest.mark.parametrize("prec", [I.F64, I.F32])
+def test_cfg2_full_run(cfg2_oracle_full, prec):
+    """Configuration 2 at full size over the whole run (t 0 -> 0.02, 256
+    rounds, 4.65e8 cell updates; the benchmark workload), in the benchmark's
+    launch configuration: schedule bit-exact, floor hits equal, state within
+    the tolerance of its precision."""
+    pr = I.cfg2_turb(prec=prec)
+    Ug, sg, kg, stg = gpu_run(pr)
+    Uo, so, ko, sto = cfg2_oracle_full
+    assert np.array_equal(sg, so) and np.array_equal(kg, ko)
+    assert stg[0] == sto[0] and stg[10] == sto[10] and stg[11] == sto[11]
+    err = rel_l1(Ug, Uo, pr.patches)
+    print("cfg2 full run rel L1", prec, err)
+    assert err <= (1e-10 if prec == I.F64 else 1e-4)
+
+
+def test_cfg2_smooth_fp32_full_run(orc):
+    """The smooth variant (rms Mach 0.5) in FP32 over the whole run."""
+    pr = I.cfg2_smooth(prec=I.F32)
+    Ug, sg, kg, stg = gpu_run(pr)
+    Uo, so, ko, sto = orc_run(orc, pr)
+    assert np.array_equal(sg, so) and np.array_equal(kg, ko)
+    err = rel_l1(Ug, Uo, pr.patches)
+    print("cfg2-smooth fp32 rel L1", err)
+    assert err <= 1e-4
