@@ -62,7 +62,20 @@ struct DevSet {
   unsigned long long* fallback;
   unsigned long long* updates;
   unsigned long long* algo_bytes;  // algorithmic HBM bytes of the step launches
+  // device-counted rounds: when set, the ready list's length (written by the
+  // readiness scan) bounds every round kernel, and rounds counts the
+  // non-empty rounds
+  const int* live;
+  int* rounds;
 };
+
+// entries of a round launch: the host's count, or the device-counted length
+// of the ready list when the rounds run without host round trips
+__device__ __forceinline__ int live_count(const DevSet& S, int count) {
+  if (!S.live) return count;
+  const int m = *S.live;
+  return m < count ? m : count;
+}
 
 // Work buffers of a batch of patch slots (stride = values per slot).
 template <class T> struct WorkPtr {

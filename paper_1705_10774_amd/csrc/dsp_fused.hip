@@ -148,7 +148,7 @@ __global__ __launch_bounds__(256) void k_gfill(DevSet S, const int* __restrict__
                                                int64_t pad_stride) {
   __shared__ Bracket br[MAXBOX];
   const int b = blockIdx.y;
-  if (b >= count) return;
+  if (b >= live_count(S, count)) return;
   const int p = list[b];
   const int n = S.n[p], N = n + 4;
   const int box0 = S.rbox_off[p * 108];
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(256) void k_courant(DevSet S, const int* __restrict
   __shared__ RegionTab<T> rt;
   __shared__ double red[4];
   const int b = blockIdx.y;
-  if (b >= count) return;
+  if (b >= live_count(S, count)) return;
   PatchCtx<T> c;
   c.p = list[b];
   c.n = S.n[c.p];
@@ -335,7 +335,7 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
   const int w = blockIdx.x;
   const int bidx = (w / (8 * T2)) * 8 + (w % 8);
   const int tile = (w / 8) % T2;
-  if (bidx >= count) return;
+  if (bidx >= live_count(S, count)) return;
   PatchCtx<T> c;
   c.p = list[bidx];
   const int n = c.n = S.n[c.p];
@@ -725,7 +725,7 @@ __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict
   const int wg = blockIdx.x;
   const int bidx = (wg / (8 * T2)) * 8 + (wg % 8);
   const int tile = (wg / 8) % T2;
-  if (bidx >= count) return;
+  if (bidx >= live_count(S, count)) return;
   PatchCtx<T> c;
   c.p = list[bidx];
   const int n = c.n = S.n[c.p];

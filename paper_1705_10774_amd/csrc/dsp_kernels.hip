@@ -182,7 +182,7 @@ __global__ void k_prim(DevSet S, const int* __restrict__ list, int count, WorkPt
 __global__ void k_dt_local(DevSet S, const int* __restrict__ list, int count, StepPtr st,
                            const double* smax) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= count) return;
+  if (b >= live_count(S, count)) return;
   const int p = list[b];
   const int k = level_for(S, smax[b], S.ticks[p]);
   if (k > S.kmax) {
@@ -459,7 +459,8 @@ __global__ void k_update(DevSet S, const int* __restrict__ list, int count, T* _
 
 __global__ void k_publish(DevSet S, const int* __restrict__ list, int count, StepPtr st) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= count) return;
+  if (b >= live_count(S, count)) return;
+  if (b == 0 && S.rounds) atomicAdd(S.rounds, 1);
   const int p = list[b];
   const int ns = S.nslots;
   const int nxt = (S.cur[p] + 1) % ns;
@@ -492,6 +493,7 @@ __global__ void k_publish(DevSet S, const int* __restrict__ list, int count, Ste
 __global__ void k_scan(DevSet S, int64_t T_end, int* __restrict__ list, int* __restrict__ counters) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= S.npatch) return;
+  if (*S.err) return;  // an error stops the scheduling: later rounds find nothing to do
   const int64_t t = S.ticks[p];
   if (t >= T_end) return;
   atomicAdd(counters + 1, 1);  // not yet done

@@ -431,13 +431,16 @@ struct dsp_set {
     kern_ms = 0.0;
     kern_launches = 0;
   }
-  void end_timing() {
+  // real: how many of the recorded launches did work (rounds counted on the
+  // device also enqueue a few empty rounds at the end); -1 = all
+  void end_timing(int64_t real = -1) {
     (void)hipStreamSynchronize(stream);
-    for (size_t m = 0; m < ev_used; ++m) {
+    const size_t m_end = (real >= 0 && (size_t)real < ev_used) ? (size_t)real : ev_used;
+    for (size_t m = 0; m < m_end; ++m) {
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, ev[m].first, ev[m].second) == hipSuccess) kern_ms += ms;
     }
-    kern_launches = (int64_t)ev_used;
+    kern_launches = (int64_t)m_end;
   }
 };
 
@@ -840,11 +843,44 @@ static int run_global(dsp_set* s, double t_end, int64_t T, int max_steps) {
   }
 }
 
+// LOCAL rounds without a host round trip per round: chunks of rounds (scan,
+// step, publish) are queued on the stream, every round kernel bounded by the
+// ready-list length that the scan writes on the device; the host reads the
+// counters and the error flags once per chunk.  Rounds queued after the last
+// patch reached t_end find an empty ready list and do nothing.
+static int run_local_device(dsp_set* s, double t_end, int64_t T, int64_t& rounds_done) {
+  const int K = 16;
+  int e = hipck(hipMemsetAsync(s->d_counters + 2, 0, sizeof(int), s->stream), "rounds");
+  if (e) return e;
+  s->D.live = s->d_counters;
+  s->D.rounds = s->d_counters + 2;
+  while (!e) {
+    for (int r = 0; r < K; ++r) {
+      launch_scan(s->D, T, s->d_list, s->d_counters, s->stream);
+      s->update_batch(0, s->np, 0, t_end, 0, s->d_list);
+      launch_publish(s->D, s->d_list, s->np, s->st, s->stream);
+    }
+    int cnt[2];
+    e = read_err(s, cnt);
+    if (e) break;
+    if (cnt[1] == 0) break;
+    if (cnt[0] == 0) e = fail(DSP_ESTATE, "no ready patch but not done");
+  }
+  s->D.live = nullptr;
+  s->D.rounds = nullptr;
+  int r = 0;
+  const int e2 = hipck(hipMemcpy(&r, s->d_counters + 2, sizeof(int), hipMemcpyDeviceToHost), "rounds");
+  rounds_done = r;
+  s->rounds += r;
+  return e ? e : e2;
+}
+
 int dsp_advance_to(dsp_set* s, double t_end) {
   if (!s || !s->initialised) return fail(DSP_ESTATE, "set not initialised");
   auto w0 = std::chrono::steady_clock::now();
   s->begin_timing();
   int e;
+  int64_t real_launches = -1;
   if (s->D.exact_time) {
     e = run_global(s, t_end, 0, -1);
   } else {
@@ -853,6 +889,10 @@ int dsp_advance_to(dsp_set* s, double t_end) {
     if (e) return e;
     if (s->cfg.dt_mode == DSP_DT_GLOBAL_QUANT) {
       e = run_global(s, t_end, T, -1);
+    } else if (s->fused && s->B >= s->np && !getenv("DSP_HOST_ROUNDS")) {
+      int64_t done = 0;
+      e = run_local_device(s, t_end, T, done);
+      real_launches = done;
     } else {
       while (true) {
         launch_scan(s->D, T, s->d_list, s->d_counters, s->stream);
@@ -871,7 +911,7 @@ int dsp_advance_to(dsp_set* s, double t_end) {
       }
     }
   }
-  s->end_timing();
+  s->end_timing(real_launches);
   s->last_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - w0).count();
   return e;
 }
