@@ -335,8 +335,11 @@ __device__ __forceinline__ T fetch_fast(int n, const RegionTab<T>& R, int comp, 
     const int sx = nq + (comp == 0), sy = nq + (comp == 1);
     e = (k * sy + j) * sx + i;
   }
-  const T a = E.pa[e];
-  const T b = E.pb[e];
+  // the table's pointers are global memory: say so, so the reads are global
+  // (not flat) loads and do not hold up the workgroup's LDS traffic
+  using gptr = const T __attribute__((address_space(1)))*;
+  const T a = ((gptr)E.pa)[e];
+  const T b = ((gptr)E.pb)[e];
   return a + E.w * (b - a);
 }
 
