@@ -183,6 +183,19 @@ int dsp_fixed_steps_fwd(dsp_set* set, const void* U0_dev, void* UT_dev, int32_t 
 int dsp_fixed_steps_adj(dsp_set* set, const void* ckpt_dev, const void* lamT_dev,
                         void* lam0_dev, int32_t nsteps, int32_t seg);
 
+/* Snapshot files (restart; output of the task list, Sec. 3E).  The file
+ * holds the whole state of the set: for every patch (id order) its size and
+ * level, time (ticks and FP64), current slot, step count, level hash and level
+ * log, and every ring slot with its time, validity flag and values (host
+ * layout, the set's precision).  Little-endian binary: the magic "DSPSNAP1",
+ * int32 npatch, nslots, prec, kmax, log capacity, double dt_base, then the
+ * per-patch records.  A set restored with dsp_load_snapshot (created with the
+ * same patches and configuration) continues exactly as the saved one would
+ * have.  Errors: DSP_EINVAL for file errors or a mismatching set, DSP_ESTATE
+ * when saving an uninitialised set.  The caller owns the path. */
+int dsp_save_snapshot(const dsp_set* set, const char* path);
+int dsp_load_snapshot(dsp_set* set, const char* path);
+
 /* Free every device allocation of the set (NULL is a no-op). */
 void dsp_destroy(dsp_set* set);
 

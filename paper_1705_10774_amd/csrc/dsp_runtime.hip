@@ -1153,6 +1153,159 @@ int dsp_fixed_steps_adj(dsp_set* s, const void* ckpt_dev, const void* lamT_dev, 
   return e;
 }
 
+// ---------------------------------------------------------------------------
+// Snapshot files (restart).  The whole device state of the set: every ring
+// slot with its time, the patch times and the schedule record, so that a run
+// restarted from the file continues exactly as the uninterrupted run.
+
+static const char kSnapMagic[8] = {'D', 'S', 'P', 'S', 'N', 'A', 'P', '1'};
+
+struct SnapHost {
+  std::vector<int> cur;
+  std::vector<int64_t> ticks, sticks, steps;
+  std::vector<double> tcur, stime;
+  std::vector<int8_t> svalid, klog;
+  std::vector<uint64_t> khash;
+  std::vector<char> slots;
+  void size_for(const dsp_set* s) {
+    const size_t np = (size_t)s->np, ns = (size_t)s->cfg.nslots;
+    cur.resize(np);
+    ticks.resize(np);
+    steps.resize(np);
+    tcur.resize(np);
+    khash.resize(np);
+    sticks.resize(np * ns);
+    stime.resize(np * ns);
+    svalid.resize(np * ns);
+    klog.resize(np * (size_t)s->klog_cap);
+    slots.resize((size_t)s->total_values * ns * (s->f32 ? 4 : 8));
+  }
+};
+
+int dsp_save_snapshot(const dsp_set* s, const char* path) {
+  if (!s || !path) return fail(DSP_EINVAL, "null argument");
+  if (!s->initialised) return fail(DSP_ESTATE, "set not initialised");
+  SnapHost h;
+  h.size_for(s);
+  const size_t np = (size_t)s->np, ns = (size_t)s->cfg.nslots;
+  const DevSet& D = s->D;
+  int e = 0;
+  auto get = [&](void* dst, const void* src, size_t b) {
+    if (!e) e = hipck(hipMemcpyAsync(dst, src, b, hipMemcpyDeviceToHost, s->stream), "snapshot");
+  };
+  get(h.cur.data(), D.cur, sizeof(int) * np);
+  get(h.ticks.data(), D.ticks, sizeof(int64_t) * np);
+  get(h.tcur.data(), D.tcur, sizeof(double) * np);
+  get(h.sticks.data(), D.sticks, sizeof(int64_t) * np * ns);
+  get(h.stime.data(), D.stime, sizeof(double) * np * ns);
+  get(h.svalid.data(), D.svalid, np * ns);
+  get(h.steps.data(), D.steps, sizeof(int64_t) * np);
+  get(h.khash.data(), D.khash, sizeof(uint64_t) * np);
+  get(h.klog.data(), D.klog, h.klog.size());
+  get(h.slots.data(), s->slots, h.slots.size());
+  if (!e) e = hipck(hipStreamSynchronize(s->stream), "snapshot");
+  if (e) return e;
+  FILE* f = fopen(path, "wb");
+  if (!f) return fail(DSP_EINVAL, std::string("cannot write ") + path);
+  bool ok = true;
+  auto put = [&](const void* p, size_t b) { ok = ok && fwrite(p, 1, b, f) == b; };
+  const int32_t hdr[5] = {(int32_t)np, (int32_t)ns, (int32_t)s->cfg.prec, s->cfg.kmax, s->klog_cap};
+  put(kSnapMagic, 8);
+  put(hdr, sizeof(hdr));
+  put(&s->cfg.dt_base, sizeof(double));
+  const size_t tsz = s->f32 ? 4 : 8;
+  for (size_t p = 0; p < np && ok; ++p) {
+    const int32_t nl[2] = {s->P[p].n, s->P[p].level};
+    put(nl, sizeof(nl));
+    put(&h.ticks[p], 8);
+    put(&h.tcur[p], 8);
+    put(&h.cur[p], 4);
+    put(&h.steps[p], 8);
+    put(&h.khash[p], 8);
+    for (size_t q = 0; q < ns; ++q) {
+      put(&h.sticks[p * ns + q], 8);
+      put(&h.stime[p * ns + q], 8);
+      put(&h.svalid[p * ns + q], 1);
+    }
+    put(&h.klog[p * (size_t)s->klog_cap], (size_t)s->klog_cap);
+    put(h.slots.data() + (size_t)s->P[p].slot_off * tsz, (size_t)s->P[p].V * ns * tsz);
+  }
+  ok = (fclose(f) == 0) && ok;
+  return ok ? 0 : fail(DSP_EINVAL, std::string("write failed: ") + path);
+}
+
+int dsp_load_snapshot(dsp_set* s, const char* path) {
+  if (!s || !path) return fail(DSP_EINVAL, "null argument");
+  FILE* f = fopen(path, "rb");
+  if (!f) return fail(DSP_EINVAL, std::string("cannot read ") + path);
+  bool ok = true;
+  auto take = [&](void* p, size_t b) { ok = ok && fread(p, 1, b, f) == b; };
+  char magic[8];
+  int32_t hdr[5];
+  double dtb = 0.0;
+  take(magic, 8);
+  take(hdr, sizeof(hdr));
+  take(&dtb, sizeof(double));
+  const size_t np = (size_t)s->np, ns = (size_t)s->cfg.nslots;
+  if (!ok || memcmp(magic, kSnapMagic, 8) != 0) {
+    fclose(f);
+    return fail(DSP_EINVAL, "not a snapshot file");
+  }
+  if (hdr[0] != (int32_t)np || hdr[1] != (int32_t)ns || hdr[2] != (int32_t)s->cfg.prec || hdr[3] != s->cfg.kmax ||
+      hdr[4] != s->klog_cap || dtb != s->cfg.dt_base) {
+    fclose(f);
+    return fail(DSP_EINVAL, "snapshot does not match the set (patches, slots, precision, kmax or dt_base)");
+  }
+  SnapHost h;
+  h.size_for(s);
+  const size_t tsz = s->f32 ? 4 : 8;
+  for (size_t p = 0; p < np && ok; ++p) {
+    int32_t nl[2];
+    take(nl, sizeof(nl));
+    if (ok && (nl[0] != s->P[p].n || nl[1] != s->P[p].level)) {
+      fclose(f);
+      return fail(DSP_EINVAL, "snapshot does not match the set's patches");
+    }
+    take(&h.ticks[p], 8);
+    take(&h.tcur[p], 8);
+    take(&h.cur[p], 4);
+    take(&h.steps[p], 8);
+    take(&h.khash[p], 8);
+    for (size_t q = 0; q < ns; ++q) {
+      take(&h.sticks[p * ns + q], 8);
+      take(&h.stime[p * ns + q], 8);
+      take(&h.svalid[p * ns + q], 1);
+    }
+    take(&h.klog[p * (size_t)s->klog_cap], (size_t)s->klog_cap);
+    take(h.slots.data() + (size_t)s->P[p].slot_off * tsz, (size_t)s->P[p].V * ns * tsz);
+    if (ok && (h.cur[p] < 0 || h.cur[p] >= (int)ns)) ok = false;
+  }
+  fclose(f);
+  if (!ok) return fail(DSP_EINVAL, "truncated or corrupt snapshot");
+  DevSet& D = s->D;
+  int e = 0;
+  auto cp = [&](void* dst, const void* src, size_t b) {
+    if (!e) e = hipck(hipMemcpyAsync(dst, src, b, hipMemcpyHostToDevice, s->stream), "snapshot");
+  };
+  cp(D.cur, h.cur.data(), sizeof(int) * np);
+  cp(D.ticks, h.ticks.data(), sizeof(int64_t) * np);
+  cp(D.tcur, h.tcur.data(), sizeof(double) * np);
+  cp(D.sticks, h.sticks.data(), sizeof(int64_t) * np * ns);
+  cp(D.stime, h.stime.data(), sizeof(double) * np * ns);
+  cp(D.svalid, h.svalid.data(), np * ns);
+  cp(D.steps, h.steps.data(), sizeof(int64_t) * np);
+  cp(D.khash, h.khash.data(), sizeof(uint64_t) * np);
+  cp(D.klog, h.klog.data(), h.klog.size());
+  cp(s->slots, h.slots.data(), h.slots.size());
+  if (!e) e = hipck(hipMemsetAsync(s->d_err, 0, sizeof(int) * 2, s->stream), "snapshot");
+  if (!e) e = hipck(hipMemsetAsync(s->d_cnt, 0, sizeof(unsigned long long) * 4, s->stream), "snapshot");
+  if (!e) e = hipck(hipStreamSynchronize(s->stream), "snapshot");
+  if (e) return e;
+  s->initialised = true;
+  s->rounds = 0;
+  return 0;
+}
+
 void dsp_destroy(dsp_set* s) { delete s; }
 
 }  // extern "C"

@@ -25,7 +25,7 @@ DSP_DT_LOCAL, DSP_DT_GLOBAL_QUANT, DSP_DT_GLOBAL_EXACT, DSP_DT_FIXED = 0, 1, 2, 
 # every entry point declared in include/dsp.h
 EXPORTS = ["dsp_create", "dsp_init", "dsp_init_device", "dsp_advance_to", "dsp_advance_to_plain", "dsp_read_state",
            "dsp_read_schedule", "dsp_stats", "dsp_kernel_time", "dsp_kernel_stats", "dsp_fixed_steps_fwd",
-           "dsp_fixed_steps_adj", "dsp_destroy", "dsp_last_error"]
+           "dsp_fixed_steps_adj", "dsp_save_snapshot", "dsp_load_snapshot", "dsp_destroy", "dsp_last_error"]
 
 
 class dsp_config(C.Structure):
@@ -78,6 +78,8 @@ def load():
     L.dsp_kernel_stats.argtypes = [vp, dp]
     L.dsp_fixed_steps_fwd.argtypes = [vp, vp, vp, C.c_int32, vp]
     L.dsp_fixed_steps_adj.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32]
+    L.dsp_save_snapshot.argtypes = [vp, C.c_char_p]
+    L.dsp_load_snapshot.argtypes = [vp, C.c_char_p]
     L.dsp_destroy.argtypes = [vp]
     L.dsp_destroy.restype = None
     L.dsp_last_error.restype = C.c_char_p
@@ -201,6 +203,14 @@ def dsp_fixed_steps_adj(h, ckpt_dev, lamT_dev, lam0_dev, nsteps, seg=8):
                                       C.c_void_p(lam0_dev), int(nsteps), int(seg)))
 
 
+def dsp_save_snapshot(h, path):
+    _check(load().dsp_save_snapshot(h, str(path).encode()))
+
+
+def dsp_load_snapshot(h, path):
+    _check(load().dsp_load_snapshot(h, str(path).encode()))
+
+
 def dsp_destroy(h):
     if h:
         load().dsp_destroy(h)
@@ -256,6 +266,12 @@ class PatchSet:
 
     def kernel_stats(self):
         return dsp_kernel_stats(self.h)
+
+    def save(self, path):
+        dsp_save_snapshot(self.h, path)
+
+    def load(self, path):
+        dsp_load_snapshot(self.h, path)
 
     # ---- fixed-dt steps and their adjoint (device tensors in the host layout)
 
