@@ -69,6 +69,7 @@ def lib():
         L.orc_hlld_flux.argtypes = [dp, dp, C.c_double, C.c_double, C.c_double, dp]
         L.orc_jvp_fixed.argtypes = [C.c_void_p, dp, dp, C.c_int32, C.c_double, dp, dp]
         L.orc_count_flops.argtypes = [C.c_void_p, dp, C.c_double, dp]
+        L.orc_extrapolated.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
         _lib = L
     return _lib
 
@@ -154,6 +155,11 @@ class OracleSet:
         t = np.zeros(n)
         _check(lib().orc_times(self.h, tk.ctypes.data_as(C.POINTER(C.c_int64)), _dp(t)))
         return tk, t
+
+    def extrapolated(self):
+        c = C.c_int64()
+        _check(lib().orc_extrapolated(self.h, C.byref(c)))
+        return c.value
 
     def read_state(self):
         U = np.empty(self.nvals)

@@ -6,9 +6,12 @@
 //  * a patch task keeps its state in a ring of time slices (Sec. 3A);
 //  * before an update its guard zones are filled from the neighbouring
 //    patches, interpolating linearly in time between the two slices that
-//    bracket the patch time (Sec. 3A, Sec. 3B "Defining task readiness");
-//  * a task is ready when no neighbour lags behind it, Eq. (1) with grace
-//    g = 0 (Sec. 3B);
+//    bracket the patch time (Sec. 3A, Sec. 3B "Defining task readiness"),
+//    or extrapolating linearly from a neighbour's two newest slices when
+//    the grace of Eq. (1) lets the task run ahead of it;
+//  * a task is ready when no neighbour lags behind it by more than the
+//    grace g times the neighbour's step, Eq. (1) (Sec. 3B), and its ring has
+//    a slice that no neighbour still needs;
 //  * the task list executes ready tasks, oldest first, until every task
 //    reaches the final time (Sec. 2.2, Sec. 3B mode (i));
 //  * the new slice overwrites the oldest one and the task waits again.
@@ -90,6 +93,7 @@ template <class R> struct SetT {
   StepCounters cnt;
   int64_t updates = 0;
   int64_t rounds = 0;
+  int64_t extrapolated = 0;  // updates whose guard fill extrapolated in time
   double last_ms = 0.0;
 
   size_t slice_size(int q) const { return Layout(p[q].n, 0).size(); }
@@ -147,7 +151,9 @@ template <class R> struct SetT {
 
   // ---- time interpolation ---------------------------------------------------
   // Pick the slice(s) of patch q for time (ticks or t): an exact copy when a
-  // slice has that time, else the adjacent pair a < t < b with weight w.
+  // slice has that time, else the adjacent pair a < t < b with weight w.  With
+  // a grace g > 0 (LOCAL mode) a time past q's newest slice is extrapolated
+  // from the two newest slices a < b < t (w > 1; Sec. 3B).
   int bracket(int q, int64_t tk, double tt, int& sa, int& sb, double& w) const {
     const PatchT<R>& Q = p[q];
     int ns = (int)Q.slot.size();
@@ -171,6 +177,15 @@ template <class R> struct SetT {
         if (Q.sticks[s] < tk && (ia < 0 || Q.sticks[s] > Q.sticks[ia])) ia = s;
         if (Q.sticks[s] > tk && (ib < 0 || Q.sticks[s] < Q.sticks[ib])) ib = s;
       }
+    }
+    if (ia >= 0 && ib < 0 && cfg.grace > 0.0 && !exact_time) {
+      // every slice is older than tk: ia is the newest; a = the next older one
+      int i2 = -1;
+      for (int s = 0; s < ns; ++s)
+        if (Q.svalid[s] && Q.sticks[s] < Q.sticks[ia] && (i2 < 0 || Q.sticks[s] > Q.sticks[i2])) i2 = s;
+      if (i2 < 0) return -1;
+      ib = ia;
+      ia = i2;
     }
     if (ia < 0 || ib < 0) return -1;
     sa = ia;
@@ -343,7 +358,8 @@ template <class R> struct SetT {
   // Fill the padded array of patch q at its own time: interior from its
   // latest slice, every guard entry of the nguard-deep shell from the patch
   // that holds that point (the finest one), interpolated in time.
-  int fill(int q, std::vector<R>& Pd) const {
+  int fill(int q, std::vector<R>& Pd, bool& extrap) const {
+    extrap = false;
     const PatchT<R>& P = p[q];
     const int n = P.n, ng = cfg.nguard;
     Layout L(n, ng), S(n, 0);
@@ -377,6 +393,7 @@ template <class R> struct SetT {
             double w;
             if (bracket(s, P.ticks, P.t, sa, sb, w) != 0)
               return fail(ORC_ESTATE, "no time slices bracket the guard time");
+            if (w > 1.0) extrap = true;
             const PatchT<R>& Q = p[s];
             bool same = (Q.dxl == P.dxl);
             int li[3];
@@ -482,10 +499,11 @@ template <class R> struct SetT {
     int64_t dtk = 0;
     StepCounters c;
     int err = 0;
+    bool extrap = false;
   };
 
   int prepare(int q, Work& wk) const {
-    int e = fill(q, wk.P);
+    int e = fill(q, wk.P, wk.extrap);
     if (e) return e;
     Layout L(p[q].n, cfg.nguard);
     e = prims(L, wk.P, ph, wk.W, wk.c);
@@ -518,6 +536,7 @@ template <class R> struct SetT {
     }
     P.cur = nxt;
     P.steps++;
+    if (wk.extrap) extrapolated++;
     P.khash = khash_step(P.khash, k);
     if (P.klog.size() < 4096) P.klog.push_back((int8_t)k);
     cnt.floor_hits += wk.c.floor_hits;
@@ -525,10 +544,28 @@ template <class R> struct SetT {
     updates += (int64_t)P.n * P.n * P.n;
   }
 
+  // Eq. (1): t_q <= t_s + g dt_s for every neighbour s, with dt_s the step s
+  // took last (0 before its first update, so no grace then), in ticks
+  // floor(g dt_s).  The new slice overwrites q's oldest slot, so q also waits
+  // until no neighbour can still need that slice: the slice after it must not
+  // be newer than any neighbour's time (implied when g = 0).
+  int64_t last_step(int s) const {
+    const PatchT<R>& S = p[s];
+    const int ns = (int)S.slot.size();
+    const int prev = (S.cur + ns - 1) % ns;
+    if (S.steps == 0 || !S.svalid[prev] || prev == S.cur) return 0;
+    return S.ticks - S.sticks[prev];
+  }
   bool ready(int q, int64_t T) const {
-    if (p[q].ticks >= T) return false;
-    for (int s : p[q].nbors)
-      if (p[s].ticks < p[q].ticks) return false;  // Eq. (1) with g = 0
+    const PatchT<R>& P = p[q];
+    if (P.ticks >= T) return false;
+    const int ns = (int)P.slot.size();
+    const int oldest = (P.cur + 1) % ns, after = (P.cur + 2) % ns;
+    for (int s : P.nbors) {
+      const int64_t g = (int64_t)std::floor(cfg.grace * (double)last_step(s));
+      if (P.ticks > p[s].ticks + g) return false;
+      if (P.svalid[oldest] && P.sticks[after] > p[s].ticks) return false;
+    }
     return true;
   }
 
@@ -655,8 +692,10 @@ static int build_set_common(const orc_config* cfg, const orc_patch_desc* pd, int
   if (!cfg || !pd || npatch <= 0) return fail(ORC_EINVAL, "null argument or no patches");
   c = *cfg;
   if (!(c.gamma > 1.0) || !(c.courant > 0.0) || c.nguard < 2 || c.nslots < 2 || c.kmax < 0 ||
-      c.kmax > 40 || c.limiter != 0 || c.grace != 0.0 || c.dt_mode < 0 || c.dt_mode > 3)
+      c.kmax > 40 || c.limiter != 0 || !(c.grace >= 0.0 && c.grace < 1.0) || c.dt_mode < 0 || c.dt_mode > 3)
     return fail(ORC_EINVAL, "invalid configuration");
+  if (c.grace > 0.0 && (c.dt_mode != 0 || c.nslots < 3))
+    return fail(ORC_EINVAL, "a grace needs LOCAL time steps and at least 3 slots");
   if ((c.dt_mode == 0 || c.dt_mode == 1) && !(c.dt_base > 0.0))
     return fail(ORC_EINVAL, "dt_base must be positive");
   if (c.dt_mode == 3 && !(c.dt_fixed > 0.0)) return fail(ORC_EINVAL, "dt_fixed must be positive");
@@ -779,6 +818,7 @@ template <class R> static int init_set(SetT<R>& s, const R* U, size_t nvals, dou
   s.cnt = StepCounters();
   s.updates = 0;
   s.rounds = 0;
+  s.extrapolated = 0;
   s.initialised = true;
   return 0;
 }
@@ -842,8 +882,8 @@ int orc_advance_to(orc_set* h, double t_end) {
 }
 
 int orc_advance_limited(orc_set* h, double t_end, int64_t max_updates) {
-  if (!h || !h->s.initialised || h->s.cfg.dt_mode != 0 || h->s.order == 2)
-    return fail(ORC_ESTATE, "limited advance needs LOCAL mode and a sequential order");
+  if (!h || !h->s.initialised || h->s.cfg.dt_mode != 0)
+    return fail(ORC_ESTATE, "limited advance needs LOCAL mode");
   SetT<double>& s = h->s;
   double m = t_end / s.cfg.dt_base;
   double mr = std::nearbyint(m);
@@ -961,10 +1001,17 @@ int orc_nbors(const orc_set* h, int32_t* counts, int32_t* ids, size_t cap) {
   return (ids && m > cap) ? fail(ORC_EINVAL, "capacity too small") : 0;
 }
 
+int orc_extrapolated(const orc_set* h, int64_t* count) {
+  if (!h || !count) return fail(ORC_EINVAL, "null argument");
+  *count = h->s.extrapolated;
+  return 0;
+}
+
 int orc_padded(const orc_set* h, int32_t q, double* out, size_t n_values) {
   if (!h || !out || q < 0 || q >= (int32_t)h->s.p.size()) return fail(ORC_EINVAL, "bad argument");
   std::vector<double> P;
-  int e = h->s.fill(q, P);
+  bool extrap;
+  int e = h->s.fill(q, P, extrap);
   if (e) return e;
   if (n_values != P.size()) return fail(ORC_EINVAL, "wrong size");
   std::copy(P.begin(), P.end(), out);

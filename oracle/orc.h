@@ -53,12 +53,16 @@ const char* orc_last_error(void);
 /* order: 0 = oldest-first (ticks, id); 1 = uniformly random ready patch (seeded);
  * 2 = rounds: the whole ready set at once, updated by nthreads threads. */
 int orc_set_order(orc_set* s, int32_t order, uint64_t seed, int32_t nthreads);
-/* LOCAL mode, sequential order: stop after max_updates patch updates. */
+/* LOCAL mode: stop after max_updates patch updates (sequential orders) or
+ * max_updates rounds (order 2). */
 int orc_advance_limited(orc_set* s, double t_end, int64_t max_updates);
 /* Current time of every patch (ticks and/or double). */
 int orc_times(const orc_set* s, int64_t* ticks, double* t);
 /* Number of values per patch slice and per-patch offsets (npatch+1 entries). */
 int orc_layout(const orc_set* s, int64_t* offsets);
+/* Number of updates whose guard fill extrapolated a neighbour in time (a
+ * grace g > 0 let the patch run ahead of that neighbour). */
+int orc_extrapolated(const orc_set* s, int64_t* count);
 /* Symmetric neighbour lists: counts[npatch], then ids (capacity cap). */
 int orc_nbors(const orc_set* s, int32_t* counts, int32_t* ids, size_t cap);
 /* Guard-filled padded array of patch p at its current time: layout of the

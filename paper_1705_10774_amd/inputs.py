@@ -252,15 +252,20 @@ def row(npx: int, n: int, length: float = 1.0):
 
 
 def linear_wave(kind="alfven", npd=2, n=16, amp=1e-6, gamma=5.0 / 3.0, t_end=1.0,
-                mode=DT_GLOBAL_EXACT, prec=F64, courant=0.4, npx_row=0, p0=0.6):
+                mode=DT_GLOBAL_EXACT, prec=F64, courant=0.4, npx_row=0, p0=0.6, row_levels=()):
     """Plane waves along x on rho = 1, p = 0.6, B = (1, 0, 0) (c_s = v_A = 1),
     point-sampled at cell and face centres.
     alfven: right-going, y-polarised, dBy = A sin 2 pi x, dvy = -A sin 2 pi x.
     sound:  right-going sound wave, drho = A sin, dvx = c_s A sin, dp = c_s^2 A sin
             with c_s^2 = gamma p0 (p0 sets the background pressure).
-    npx_row > 0 lays the patches out in a row along x instead of a cube."""
+    npx_row > 0 lays the patches out in a row along x instead of a cube;
+    row_levels = (k_0, k_1, ...) lays out a row whose patch i has n 2^k_i
+    cells per edge."""
     box = (1.0, 1.0, 1.0)
-    if npx_row > 0:
+    if row_levels:
+        patches, box = row(len(row_levels), n)
+        patches = [Patch(q.origin, q.size, n << k) for q, k in zip(patches, row_levels)]
+    elif npx_row > 0:
         patches, box = row(npx_row, n)
     else:
         patches = cartesian(npd, n)
@@ -288,6 +293,22 @@ def linear_wave(kind="alfven", npd=2, n=16, amp=1e-6, gamma=5.0 / 3.0, t_end=1.0
     U = assemble(patches, rho, vel, pres, bf, gamma)
     cfg = Config(gamma=gamma, courant=courant, dt_mode=mode, prec=prec, box_hi=box)
     return Problem(f"{kind}_wave", cfg, patches, U, t_end, extra={"amp": amp})
+
+
+def level_row(levels=(0, 0, 1, 0, 2), n=8, amp=1e-3, prec=F64, dt_base=None, nslots=4, grace=0.0):
+    """A sound wave (A = 1e-3) along a periodic row of equal-size patches with
+    n 2^k cells per edge: LOCAL steps in which patch i keeps level k_i (the
+    Courant rate doubles with the resolution; dt_base puts the coarsest at
+    r ~ 0.75).  A row of mixed levels is where a grace lets patches run ahead
+    of a coarser neighbour even when every ready patch updates at once."""
+    pr = linear_wave("sound", n=n, amp=amp, prec=prec, mode=DT_LOCAL, row_levels=tuple(levels))
+    if dt_base is None:
+        # c_s = v_A = 1 with B along x: fast speed 1 along x, sqrt 2 across
+        rate = (1.0 + 2.0 * math.sqrt(2.0)) / (pr.patches[0].size / n)
+        dt_base = 0.75 * pr.cfg.courant / rate
+    pr.cfg = dataclasses.replace(pr.cfg, dt_base=dt_base, nslots=nslots, grace=grace)
+    pr.name = "level_row"
+    return pr
 
 
 def cfg1_alfven(prec=F64):

@@ -490,6 +490,164 @@ def test_time_interpolation_formula(orc):
 
 
 # ---------------------------------------------------------------------------
+# grace g > 0 in Eq. (1): patches may run ahead of coarser neighbours and then
+# extrapolate them in time
+
+
+def _grace_rounds(levels, g, ns, T):
+    """Brute force of the readiness rule on a periodic row: patch p is ready
+    when t_p <= t_q + floor(g dt_q) for both row neighbours q (dt_q = q's last
+    step, 0 before its first) and, once its ring of ns slices is full, its
+    second-oldest slice is not newer than either neighbour; every round
+    updates the whole ready set.  Times in units of the finest step."""
+    n, kmax = len(levels), max(levels)
+    dt = [1 << (kmax - k) for k in levels]
+    t, last, ring, rounds = [0] * n, [0] * n, [[0] for _ in range(n)], []
+    while any(x < T for x in t):
+        R = []
+        for p in range(n):
+            if t[p] >= T:
+                continue
+            nb = [(p - 1) % n, (p + 1) % n]
+            if all(t[p] <= t[q] + math.floor(g * last[q]) and
+                   not (len(ring[p]) == ns and ring[p][1] > t[q]) for q in nb):
+                R.append(p)
+        assert R
+        rounds.append(R)
+        for p in R:
+            t[p] += dt[p]
+            last[p] = dt[p]
+            ring[p] = (ring[p] + [t[p]])[-ns:]
+    return rounds
+
+
+def _grace_row(levels, g, ns):
+    """Uniform state on a periodic row of equal-size patches with n = 8 2^k:
+    the Courant rate doubles with each level, and dt_base puts the n = 8
+    patches at r = 0.75, so patch i takes level levels[i] at every step."""
+    patches, box = I.row(len(levels), 8)
+    patches = [I.Patch(q.origin, q.size, 8 << k) for q, k in zip(patches, levels)]
+    sh = [(q.n,) * 3 for q in patches]
+    B = (0.6, 0.3, 0.0)
+    bf = [(np.full((q.n, q.n, q.n + 1), B[0]), np.full((q.n, q.n + 1, q.n), B[1]),
+           np.full((q.n + 1, q.n, q.n), B[2])) for q in patches]
+    U = I.assemble(patches, [np.ones(s) for s in sh], [[np.zeros(s)] * 3 for s in sh],
+                   [np.full(s, 0.6) for s in sh], bf, 5.0 / 3.0)
+    gm, rho, p = 5.0 / 3.0, 1.0, 0.6
+    a2, b2 = gm * p / rho, (B[0] ** 2 + B[1] ** 2) / rho
+    s = 0.0
+    for d in range(3):
+        bt2 = (B[0] ** 2 + B[1] ** 2 - B[d] ** 2) / rho
+        s += math.sqrt(0.5 * (a2 + b2 + math.sqrt((a2 - b2) ** 2 + 4 * a2 * bt2)))
+    s /= patches[0].size / 8
+    dt_base = 0.75 * 0.4 / s
+    cfg = I.Config(dt_mode=I.DT_LOCAL, dt_base=dt_base, box_hi=box, grace=g, nslots=ns)
+    return cfg, patches, U
+
+
+@pytest.mark.parametrize("g", [0.0, 0.5, 0.75])
+def test_grace_schedule_bruteforce(orc, g):
+    """Round by round, the set of patches that advance equals the brute-force
+    rule; with a grace the schedule differs from g = 0 and guard fills
+    extrapolate; the uniform state stays uniform (to rounding: restriction
+    over a factor-4 jump sums unequal overlaps)."""
+    levels, ns = (0, 0, 1, 0, 2), 4
+    cfg, patches, U = _grace_row(levels, g, ns)
+    T = 4  # in units of the finest step: one dt_base
+    want = _grace_rounds(levels, g, ns, 4 * T)
+    o = orc.OracleSet(cfg, patches)
+    o.init(U)
+    o.set_order(2, 1, 1)
+    tk_prev = o.times()[0]
+    got = []
+    for _ in range(len(want) + 1):
+        o.advance_limited(4 * cfg.dt_base, 1)  # one round
+        tk = o.times()[0]
+        moved = [p for p in range(len(levels)) if tk[p] != tk_prev[p]]
+        if not moved:
+            break
+        got.append(moved)
+        tk_prev = tk
+    assert got == want
+    assert (o.extrapolated() > 0) == (g > 0)
+    if g > 0:
+        assert want != _grace_rounds(levels, 0.0, ns, 4 * T)
+    assert np.abs(o.read_state() - U).max() <= 1e-13
+    o.close()
+
+
+def test_grace_equal_levels_is_no_grace(orc):
+    """With every patch on the same level a grace g < 1 can never let a patch
+    pass a neighbour (g dt < dt on a common grid of times), so the run is
+    bit-identical to g = 0."""
+    pr = I.linear_wave("alfven", npd=2, n=8, amp=1e-3, mode=I.DT_LOCAL, t_end=0.05)
+    pr = dataclasses.replace(pr, cfg=dataclasses.replace(pr.cfg, dt_base=0.05 / 4))
+    res = []
+    for g in (0.0, 0.9):
+        s = orc.OracleSet.from_problem(pr, grace=g, nslots=4)
+        s.set_order(2, 1, NT)
+        s.advance_to(0.05)
+        st, kh, kl = s.read_schedule(klog_cap=64)
+        res.append((s.read_state(), st, kl))
+        assert s.extrapolated() == 0
+        s.close()
+    assert len(set(res[0][2][:, :res[0][1][0]].ravel().tolist())) == 1
+    assert np.array_equal(res[0][1], res[1][1])
+    assert np.array_equal(res[0][0], res[1][0])
+
+
+def test_time_extrapolation_formula(orc):
+    """Mid-run with a grace, a patch's guard cells taken from a neighbour that
+    lags behind it equal s_a + w (s_b - s_a) of the neighbour's two newest
+    slices with w = (t - t_a) / (t_b - t_a) > 1 (same-level periodic layout,
+    independent index arithmetic)."""
+    pr = _local_spread()
+    npd, n, ng = 3, 8, pr.cfg.nguard
+    Nn = n + 2 * ng
+    T = 0.02 / 8
+    s2 = orc.OracleSet.from_problem(pr, grace=0.75, nslots=4)
+    s2.set_order(2, 1, 1)
+    for _ in range(40):
+        s2.advance_limited(T, 1)  # one round
+        tk, _ = s2.times()
+        nb = s2.nbors()
+        for p in range(len(pr.patches)):
+            behind = [q for q in nb[p] if tk[q] < tk[p]]
+            if not behind:
+                continue
+            q = behind[0]
+            sb, tb, _ = s2.slot(q, 0)
+            sa, ta, _ = s2.slot(q, 1)
+            assert ta < tb < tk[p]
+            w = (tk[p] - ta) / (tb - ta)
+            assert w > 1.0
+            Pd = s2.padded(p)
+            pq = [int(round(pr.patches[q].origin[d] * npd)) for d in range(3)]
+            pp = [int(round(pr.patches[p].origin[d] * npd)) for d in range(3)]
+            checked = 0
+            for var in range(5):
+                Pv = Pd[var * Nn ** 3:(var + 1) * Nn ** 3].reshape(Nn, Nn, Nn)
+                qa = sa[var * n ** 3:(var + 1) * n ** 3].reshape(n, n, n)
+                qb = sb[var * n ** 3:(var + 1) * n ** 3].reshape(n, n, n)
+                for k in range(-ng, n + ng):
+                    for j in range(-ng, n + ng):
+                        for i in range(-ng, n + ng):
+                            gidx = [pp[0] * n + i, pp[1] * n + j, pp[2] * n + k]
+                            owner = [(gidx[d] % (npd * n)) // n for d in range(3)]
+                            if owner != pq:
+                                continue
+                            li = [gidx[d] % n for d in range(3)]
+                            a, b = qa[li[2], li[1], li[0]], qb[li[2], li[1], li[0]]
+                            assert Pv[k + ng, j + ng, i + ng] == a + w * (b - a)
+                            checked += 1
+            assert checked > 0
+            s2.close()
+            return
+    s2.close()
+    pytest.fail("no patch ran ahead of a neighbour")
+
+
+# ---------------------------------------------------------------------------
 # cross-resolution guard values (prolongation / restriction)
 
 
@@ -579,9 +737,10 @@ def test_error_codes(orc):
     with pytest.raises(orc.OracleError) as e:
         s2.advance_to(sp.cfg.dt_base)
     assert e.value.code == -4
-    with pytest.raises(orc.OracleError) as e:
-        orc.OracleSet(dataclasses.replace(pr.cfg, grace=0.1), pr.patches)
-    assert e.value.code == -1
+    for bad in (dict(grace=1.0), dict(grace=-0.1), dict(grace=0.5, nslots=2), dict(grace=0.5, dt_mode=2)):
+        with pytest.raises(orc.OracleError) as e:
+            orc.OracleSet(dataclasses.replace(pr.cfg, **bad), pr.patches)
+        assert e.value.code == -1
     # negative pressure without a floor
     U3 = pr.U0.copy()
     V = I.patch_views(U3, pr.patches)
