@@ -5,13 +5,13 @@
  * A patch set is the paper's task list of patch tasks (Sec. 2.1-2.2): each
  * patch is a cube of n^3 cells whose state is kept as a ring of time slices
  * (Sec. 3A).  Advancing the set to a time repeatedly updates every patch that
- * is ready in the sense of Eq. (1) with grace g = 0 (Sec. 3B), until every
- * patch has reached that time (the task list "execute" of Sec. 2.2).  One
- * patch update
+ * is ready in the sense of Eq. (1) (Sec. 3B), until every patch has reached
+ * that time (the task list "execute" of Sec. 2.2).  One patch update
  *   1. fills the patch's guard zones from its neighbours, interpolating
  *      linearly in time between the two stored slices that bracket the
- *      patch time, and in space (conservative prolongation / restriction)
- *      where the neighbour has another resolution (Sec. 3A);
+ *      patch time (extrapolating from the two newest when a grace g > 0 let
+ *      the patch run ahead), and in space (conservative prolongation /
+ *      restriction) where the neighbour has another resolution (Sec. 3A);
  *   2. takes one second-order MUSCL-Hancock step with HLLD fluxes and
  *      constrained transport of face-centred B (Sec. 4.1, 4.3), with its own
  *      Courant time step quantised to dt_base * 2^-k (local time steps,
@@ -74,7 +74,11 @@ typedef struct {
   double courant;  /* Courant number C of the rate sum_d (|v_d| + c_f,d)/dx */
   double dt_base;  /* coarsest quantised step (LOCAL, GLOBAL_QUANT) */
   double dt_fixed; /* step of the FIXED mode */
-  double grace;    /* g of Eq. (1); must be 0 */
+  double grace;    /* g of Eq. (1), 0 <= g < 1; g > 0 needs LOCAL and nslots >= 3.
+                    * A patch p is ready when t_p <= t_q + floor(g dt_q) (ticks)
+                    * for every neighbour q, dt_q the step q took last (0 before
+                    * its first), and no neighbour still needs p's oldest slice
+                    * (the next slice is not newer than any neighbour) */
   double p_floor;  /* 0: non-positive pressure is DSP_ENEGATIVE; > 0: floor (counted) */
   int32_t kmax;    /* finest level, 0..40; times are integer ticks dt_base 2^-kmax */
   int32_t nslots;  /* time slices kept per patch, >= 2 (3 recommended) */

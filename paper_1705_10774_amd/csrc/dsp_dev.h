@@ -32,6 +32,7 @@ struct GBox {
 struct DevSet {
   int npatch, nslots, kmax, dt_mode, exact_time, klog_cap;
   double gamma, courant, dt_base, dt_fixed, p_floor;
+  double grace;  // g of Eq. (1) (LOCAL mode)
   // geometry
   const int* n;           // interior cells per edge
   const double* dx;       // cell size

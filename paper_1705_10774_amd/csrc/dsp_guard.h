@@ -45,7 +45,9 @@ __device__ __forceinline__ void atomic_max_pos(double* a, double v) {
   atomicMax((unsigned long long*)a, (unsigned long long)__double_as_longlong(v));
 }
 
-// time-slice bracket of patch q for time (tk, tt): exact slice or a < t < b
+// time-slice bracket of patch q for time (tk, tt): exact slice or a < t < b;
+// with a grace (LOCAL mode) a time past q's newest slice is extrapolated from
+// the two newest slices a < b < t (w > 1)
 struct Bracket {
   int64_t oa, ob;  // element offsets of the two slices
   double w;        // weight of b (0 for an exact copy)
@@ -73,6 +75,17 @@ __device__ inline Bracket bracket(const DevSet& S, int q, int64_t tk, double tt)
     br.oa = br.ob = base + ie * V;
     br.w = 0.0;
     return br;
+  }
+  if (ia >= 0 && ib < 0 && S.grace > 0.0 && !S.exact_time) {
+    int i2 = -1;
+    for (int s = 0; s < ns; ++s) {
+      const int64_t e = (int64_t)q * ns + s;
+      if (S.svalid[e] && S.sticks[e] < S.sticks[(int64_t)q * ns + ia] &&
+          (i2 < 0 || S.sticks[e] > S.sticks[(int64_t)q * ns + i2]))
+        i2 = s;
+    }
+    ib = ia;
+    ia = i2;
   }
   if (ia < 0 || ib < 0) {
     atomicOr(S.err, ERR_STATE);

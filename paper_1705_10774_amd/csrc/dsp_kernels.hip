@@ -497,8 +497,24 @@ __global__ void k_scan(DevSet S, int64_t T_end, int* __restrict__ list, int* __r
   const int64_t t = S.ticks[p];
   if (t >= T_end) return;
   atomicAdd(counters + 1, 1);  // not yet done
-  for (int m = S.nb_off[p]; m < S.nb_off[p + 1]; ++m)
-    if (S.ticks[S.nb_idx[m]] < t) return;
+  // Eq. (1): t_p <= t_q + floor(g dt_q) for every neighbour q (dt_q: the step
+  // q took last, 0 before its first); and p's oldest slot, which the update
+  // overwrites, must not be needed by any neighbour any more: the slice after
+  // it is not newer than the neighbour (implied when g = 0)
+  const int ns = S.nslots;
+  const int64_t ob = (int64_t)p * ns;
+  const int oldest = (S.cur[p] + 1) % ns, after = (S.cur[p] + 2) % ns;
+  const int64_t t_after = S.svalid[ob + oldest] ? S.sticks[ob + after] : INT64_MIN;
+  for (int m = S.nb_off[p]; m < S.nb_off[p + 1]; ++m) {
+    const int q = S.nb_idx[m];
+    const int64_t tq = S.ticks[q];
+    int64_t g = 0;
+    if (S.grace > 0.0 && S.steps[q] > 0) {
+      const int prev = (S.cur[q] + ns - 1) % ns;
+      if (S.svalid[(int64_t)q * ns + prev]) g = (int64_t)floor(S.grace * (double)(tq - S.sticks[(int64_t)q * ns + prev]));
+    }
+    if (t > tq + g || t_after > tq) return;
+  }
   const int slot = atomicAdd(counters, 1);
   list[slot] = p;
 }

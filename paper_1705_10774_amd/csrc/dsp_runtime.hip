@@ -472,11 +472,13 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
   if (!cfg || !pd || npatch <= 0) return fail(DSP_EINVAL, "null argument or no patches");
   const dsp_config c = *cfg;
   if (!(c.gamma > 1.0) || !(c.courant > 0.0) || c.nguard < 2 || c.nguard > 3 || c.nslots < 2 ||
-      c.nslots > 8 || c.kmax < 0 || c.kmax > 40 || c.limiter != 0 || c.grace != 0.0 ||
+      c.nslots > 8 || c.kmax < 0 || c.kmax > 40 || c.limiter != 0 || !(c.grace >= 0.0 && c.grace < 1.0) ||
       (c.prec != DSP_F32 && c.prec != DSP_F64) || c.dt_mode < 0 || c.dt_mode > 3 || c.p_floor < 0.0)
     return fail(DSP_EINVAL, "invalid configuration");
   if ((c.dt_mode == DSP_DT_LOCAL || c.dt_mode == DSP_DT_GLOBAL_QUANT) && !(c.dt_base > 0.0))
     return fail(DSP_EINVAL, "dt_base must be positive");
+  if (c.grace > 0.0 && (c.dt_mode != DSP_DT_LOCAL || c.nslots < 3))
+    return fail(DSP_EINVAL, "a grace needs LOCAL time steps and at least 3 slots");
   if (c.dt_mode == DSP_DT_FIXED && !(c.dt_fixed > 0.0)) return fail(DSP_EINVAL, "dt_fixed must be positive");
   for (int d = 0; d < 3; ++d)
     if (c.periodic[d] != 1) return fail(DSP_EINVAL, "only periodic boxes are supported");
@@ -676,6 +678,7 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
   D.dt_base = c.dt_base;
   D.dt_fixed = c.dt_fixed;
   D.p_floor = c.p_floor;
+  D.grace = c.grace;
   auto up = [&](const void* h, size_t bytes) -> void* {
     void* d = A(bytes);
     if (d && bytes) (void)hipMemcpy(d, h, bytes, hipMemcpyHostToDevice);
@@ -924,9 +927,35 @@ int dsp_advance_to_plain(dsp_set* s, double t_end) {
   if (e) return e;
   auto w0 = std::chrono::steady_clock::now();
   s->begin_timing();
-  const int np = s->np;
-  std::vector<int64_t> ticks(np);
-  e = hipck(hipMemcpy(ticks.data(), s->D.ticks, sizeof(int64_t) * np, hipMemcpyDeviceToHost), "ticks");
+  const int np = s->np, ns = s->cfg.nslots;
+  // host copy of the time bookkeeping, kept in step with the publish kernel
+  std::vector<int64_t> ticks(np), sticks((size_t)np * ns), steps(np);
+  std::vector<int> cur(np);
+  std::vector<int8_t> valid((size_t)np * ns);
+  auto get = [&](void* h, const void* d, size_t b) {
+    if (!e) e = hipck(hipMemcpy(h, d, b, hipMemcpyDeviceToHost), "ticks");
+  };
+  get(ticks.data(), s->D.ticks, sizeof(int64_t) * np);
+  get(sticks.data(), s->D.sticks, sizeof(int64_t) * np * ns);
+  get(steps.data(), s->D.steps, sizeof(int64_t) * np);
+  get(cur.data(), s->D.cur, sizeof(int) * np);
+  get(valid.data(), s->D.svalid, (size_t)np * ns);
+  // readiness as in the scan kernel: Eq. (1) with the grace, and a free slot
+  auto ready = [&](int p) {
+    const size_t ob = (size_t)p * ns;
+    const int oldest = (cur[p] + 1) % ns, after = (cur[p] + 2) % ns;
+    const int64_t t_after = valid[ob + oldest] ? sticks[ob + after] : INT64_MIN;
+    for (int q : s->nbors[p]) {
+      int64_t g = 0;
+      if (s->cfg.grace > 0.0 && steps[q] > 0) {
+        const int prev = (cur[q] + ns - 1) % ns;
+        if (valid[(size_t)q * ns + prev])
+          g = (int64_t)std::floor(s->cfg.grace * (double)(ticks[q] - sticks[(size_t)q * ns + prev]));
+      }
+      if (ticks[p] > ticks[q] + g || t_after > ticks[q]) return false;
+    }
+    return true;
+  };
   while (!e) {
     // oldest ready patch, ties by id (Sec. 3B mode (i))
     int best = -1;
@@ -934,10 +963,7 @@ int dsp_advance_to_plain(dsp_set* s, double t_end) {
     for (int p = 0; p < np; ++p) {
       if (ticks[p] >= T) continue;
       done = false;
-      bool ready = true;
-      for (int q : s->nbors[p])
-        if (ticks[q] < ticks[p]) { ready = false; break; }
-      if (ready && (best < 0 || ticks[p] < ticks[best])) best = p;
+      if (ready(p) && (best < 0 || ticks[p] < ticks[best])) best = p;
     }
     if (done) break;
     if (best < 0) { e = fail(DSP_ESTATE, "no ready patch but not done"); break; }
@@ -952,6 +978,10 @@ int dsp_advance_to_plain(dsp_set* s, double t_end) {
     e = read_err(s, nullptr);
     if (e) break;
     ticks[best] += dtk;
+    cur[best] = (cur[best] + 1) % ns;
+    sticks[(size_t)best * ns + cur[best]] = ticks[best];
+    valid[(size_t)best * ns + cur[best]] = 1;
+    steps[best]++;
   }
   s->end_timing();
   s->last_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - w0).count();

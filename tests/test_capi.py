@@ -36,7 +36,8 @@ def test_struct_layout_matches_header():
     assert C.sizeof(dsp.dsp_patch_desc) == 56
 
 
-@pytest.mark.parametrize("bad", [dict(grace=0.1), dict(periodic=(1, 0, 1)), dict(nguard=1),
+@pytest.mark.parametrize("bad", [dict(grace=1.0), dict(grace=-0.1), dict(grace=0.5, nslots=2),
+                                 dict(grace=0.5, dt_mode=2), dict(periodic=(1, 0, 1)), dict(nguard=1),
                                  dict(limiter=1), dict(kmax=41), dict(nslots=1), dict(prec=3),
                                  dict(dt_base=0.0), dict(gamma=1.0)])
 def test_invalid_config_rejected_on_host(bad):
