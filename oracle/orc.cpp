@@ -509,7 +509,7 @@ template <class R> struct SetT {
     e = prims(L, wk.P, ph, wk.W, wk.c);
     if (e == S_ENONFINITE) return fail(ORC_ENONFINITE, "non-finite state");
     if (e == S_ENEGATIVE) return fail(ORC_ENEGATIVE, "non-positive density or pressure");
-    wk.smax = courant_rate(wk.W, p[q].n, p[q].dx, ph.gamma);
+    wk.smax = courant_rate(wk.W, p[q].n, p[q].dx, ph);
     if (!std::isfinite(wk.smax)) return fail(ORC_ENONFINITE, "non-finite signal speed");
     return 0;
   }
@@ -696,6 +696,8 @@ static int build_set_common(const orc_config* cfg, const orc_patch_desc* pd, int
     return fail(ORC_EINVAL, "invalid configuration");
   if (c.grace > 0.0 && (c.dt_mode != 0 || c.nslots < 3))
     return fail(ORC_EINVAL, "a grace needs LOCAL time steps and at least 3 slots");
+  if (!(c.eta >= 0.0) || !(c.gamma_ad >= 0.0) || (c.gamma_ad > 0.0 && !(c.rho_ion > 0.0)))
+    return fail(ORC_EINVAL, "invalid non-ideal parameters");
   if ((c.dt_mode == 0 || c.dt_mode == 1) && !(c.dt_base > 0.0))
     return fail(ORC_EINVAL, "dt_base must be positive");
   if (c.dt_mode == 3 && !(c.dt_fixed > 0.0)) return fail(ORC_EINVAL, "dt_fixed must be positive");
@@ -714,6 +716,10 @@ template <class R> static int make_set(const orc_config& c, const std::vector<or
   s.ph.gamma = c.gamma;
   s.ph.eps_deg = 1e-12;
   s.ph.p_floor = c.p_floor;
+  s.ph.eta = c.eta;
+  s.ph.gamma_ad = c.gamma_ad;
+  s.ph.rho_i = c.rho_ion;
+  s.ph.courant = c.courant;
   s.exact_time = (c.dt_mode == 2 || c.dt_mode == 3);
   // lattice: 2 * lcm(cells per unit length) units per unit length, so every
   // cell centre and face lies on an integer point

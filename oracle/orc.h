@@ -30,6 +30,9 @@ typedef struct {
   int32_t dt_mode; /* 0 LOCAL, 1 GLOBAL_QUANT, 2 GLOBAL_EXACT, 3 FIXED */
   int32_t periodic[3];
   double box_lo[3], box_hi[3];
+  /* non-ideal MHD (Sec. 4.3): Ohmic resistivity eta_Ohm, ambipolar drift
+   * coefficient gamma_AD and ion density rho_i; 0, 0 = ideal */
+  double eta, gamma_ad, rho_ion;
 } orc_config;
 
 typedef struct {

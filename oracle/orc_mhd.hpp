@@ -160,7 +160,16 @@ struct Phys {
   double gamma;
   double eps_deg;  // HLLD degeneracy threshold
   double p_floor;  // 0 = no floor (negative pressure is an error)
+  // non-ideal terms (Sec. 4.3): Ohmic resistivity, ambipolar drift
+  // coefficient and ion density; eta = gamma_ad = 0 is ideal MHD
+  double eta = 0.0, gamma_ad = 0.0, rho_i = 1.0;
+  double courant = 0.4;  // MHD Courant number (converts the non-ideal limits to rates)
+  bool nonideal() const { return eta > 0.0 || gamma_ad > 0.0; }
 };
+
+// Courant-like factor of the Ohmic and ambipolar step limits, C_Ohm = C_AD
+// (Eqs. dtOhm and dtAD).
+constexpr double kCourantNonideal = 0.1;
 
 // Return codes shared with orc.h.
 enum { S_OK = 0, S_ENONFINITE = -6, S_ENEGATIVE = -7 };
@@ -220,8 +229,14 @@ template <class R> R fast_speed(const Prim<R>& w, int d, double gamma) {
 // Courant rate of a patch: the largest sum over directions of
 // (|v_d| + c_f,d) / dx over the interior and the two guard layers the
 // stencil reads.  The largest stable step is courant / smax.
-template <class R> double courant_rate(const Box3<Prim<R>>& W, int n, double dx, double gamma) {
+// With non-ideal terms the step must also satisfy dt <= C_Ohm dx^2 / eta
+// (Eq. dtOhm) and dt <= C_AD gamma_AD rho_i rho dx^2 / B^2 (Eq. dtAD); each
+// limit enters as the rate that gives that step with the MHD Courant number,
+// (C / C_ni) eta / dx^2 and (C / C_ni) B^2 / (gamma_AD rho_i rho dx^2).
+template <class R> double courant_rate(const Box3<Prim<R>>& W, int n, double dx, const Phys& ph) {
   FlopCourant tally_as_courant;
+  const double gamma = ph.gamma;
+  const double f = ph.courant / kCourantNonideal / (dx * dx);
   double smax = 0.0;
   for (int k = -2; k <= n + 1; ++k)
     for (int j = -2; j <= n + 1; ++j)
@@ -230,6 +245,15 @@ template <class R> double courant_rate(const Box3<Prim<R>>& W, int n, double dx,
         double s = 0.0;
         for (int d = 0; d < 3; ++d) s = s + (std::fabs(val(w.v[d])) + val(fast_speed(w, d, gamma)));
         s = s / dx;
+        if (ph.eta > 0.0) {
+          const double so = ph.eta * f;
+          if (so > s) s = so;
+        }
+        if (ph.gamma_ad > 0.0) {
+          const double bb = val(w.b[0] * w.b[0] + w.b[1] * w.b[1] + w.b[2] * w.b[2]);
+          const double sa = bb / (ph.gamma_ad * ph.rho_i * val(w.r)) * f;
+          if (sa > s) s = sa;
+        }
         if (!(s <= smax)) smax = s;  // also propagates NaN
       }
   return smax;
@@ -359,6 +383,141 @@ void hlld(const R* wl, const R* wr, R bn, const Phys& ph, R* F) {
     for (int q = 0; q < 7; ++q) F[q] = FR[q];
   }
   F[7] = (SL > 0.0) ? SL : ((SR < 0.0) ? SR : SM);
+}
+
+// ---------------------------------------------------------------------------
+// Non-ideal electric field (Sec. 4.3) on the edges of constrained transport,
+// from the state at t^n: Ohmic E = eta J (Eq. Ohm) and ambipolar
+// E = -v_D x B with v_D = J x B / (gamma_AD rho rho_i) (Eq. AD), written as
+// (B^2 J - (J.B) B) / (gamma_AD rho rho_i).  J_a = (curl B)_a lives on the
+// a-edges (a-index a cell index, b- and c-indices face indices, (a, b, c)
+// cyclic); on each a-edge the other two components of J are the means of
+// the four nearest b- (c-) edges, B_a the mean of the eight nearest a-faces,
+// B_b and B_c the means of the two b- (c-) faces through the edge, and rho
+// the mean of the four cells around it.  The field is added to the edge
+// EMFs.  The energy flux through each face gains the Poynting flux E x B of
+// this field (the face means of the two E components on its edges and of the
+// two transverse B components on the four faces around it), so that total
+// energy is conserved and the magnetic energy removed appears as heat J.E
+// (Eqs. Ohm_heat and Q_AD) in the internal energy.
+template <class R>
+void nonideal(const Layout& L, const std::vector<R>& P, const Box3<Prim<R>>& W, double dx, const Phys& ph,
+              Box3<R>* E, Box3<Flux<R>>* Fx) {
+  const int n = L.n;
+  auto bf = [&](int d, const int* q) -> R { return P[L.face(d, q[0], q[1], q[2])]; };
+  // J_a on a-edges with a-cell index in [-1, n] and face indices in [0, n]
+  Box3<R> J[3];
+  for (int a = 0; a < 3; ++a) {
+    const int b = (a + 1) % 3, c = (a + 2) % 3;
+    int lo[3] = {0, 0, 0}, hi[3] = {n, n, n};
+    lo[a] = -1;
+    J[a].init(lo[0], hi[0], lo[1], hi[1], lo[2], hi[2]);
+    for (int k = lo[2]; k <= hi[2]; ++k)
+      for (int j = lo[1]; j <= hi[1]; ++j)
+        for (int i = lo[0]; i <= hi[0]; ++i) {
+          const int e[3] = {i, j, k};
+          int eb[3] = {i, j, k}, ec[3] = {i, j, k};
+          eb[b] -= 1;
+          ec[c] -= 1;
+          // dB_c/dx_b - dB_b/dx_c
+          J[a].at(e) = ((bf(c, e) - bf(c, eb)) - (bf(b, e) - bf(b, ec))) / dx;
+        }
+  }
+  // the non-ideal field on the EMF edges: a-cell in [0, n-1], faces in [0, n]
+  Box3<R> En[3];
+  for (int a = 0; a < 3; ++a) {
+    const int b = (a + 1) % 3, c = (a + 2) % 3;
+    int lo[3] = {0, 0, 0}, hi[3] = {n, n, n};
+    hi[a] = n - 1;
+    En[a].init(lo[0], hi[0], lo[1], hi[1], lo[2], hi[2]);
+    for (int k = lo[2]; k <= hi[2]; ++k)
+      for (int j = lo[1]; j <= hi[1]; ++j)
+        for (int i = lo[0]; i <= hi[0]; ++i) {
+          const int e[3] = {i, j, k};
+          const R ja = J[a].at(e);
+          R en = ph.eta * ja;
+          if (ph.gamma_ad > 0.0) {
+            R jb = 0.0, jc = 0.0, ba = 0.0, bb = 0.0, bc = 0.0, rho = 0.0;
+            for (int s = -1; s <= 0; ++s)
+              for (int t = 0; t <= 1; ++t) {
+                int q[3] = {i, j, k};
+                q[b] += s;
+                q[a] += t;
+                jb = jb + J[b].at(q);
+                int r[3] = {i, j, k};
+                r[c] += s;
+                r[a] += t;
+                jc = jc + J[c].at(r);
+              }
+            for (int t = 0; t <= 1; ++t)
+              for (int s = -1; s <= 0; ++s)
+                for (int u = -1; u <= 0; ++u) {
+                  int q[3] = {i, j, k};
+                  q[a] += t;
+                  q[b] += s;
+                  q[c] += u;
+                  ba = ba + bf(a, q);
+                }
+            for (int s = -1; s <= 0; ++s) {
+              int q[3] = {i, j, k}, r[3] = {i, j, k}, w[3] = {i, j, k};
+              q[c] += s;  // b-faces through the edge
+              bb = bb + bf(b, q);
+              r[b] += s;  // c-faces through the edge
+              bc = bc + bf(c, r);
+              for (int u = -1; u <= 0; ++u) {
+                w[b] = e[b] + s;
+                w[c] = e[c] + u;
+                rho = rho + W.at(w).r;
+              }
+            }
+            jb = 0.25 * jb;
+            jc = 0.25 * jc;
+            ba = 0.125 * ba;
+            bb = 0.5 * bb;
+            bc = 0.5 * bc;
+            rho = 0.25 * rho;
+            const R b2 = ba * ba + bb * bb + bc * bc;
+            const R jdotb = ja * ba + jb * bb + jc * bc;
+            en = en + (b2 * ja - jdotb * ba) / (ph.gamma_ad * ph.rho_i * rho);
+          }
+          En[a].at(e) = en;
+          E[a].at(e) = E[a].at(e) + en;
+        }
+  }
+  // Poynting flux (E x B)_d on d-faces with face index in [0, n] and cells in [0, n-1]
+  for (int d = 0; d < 3; ++d) {
+    const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+    int hi[3] = {n - 1, n - 1, n - 1};
+    hi[d] = n;
+    for (int k = 0; k <= hi[2]; ++k)
+      for (int j = 0; j <= hi[1]; ++j)
+        for (int i = 0; i <= hi[0]; ++i) {
+          const int f[3] = {i, j, k};
+          R e1 = 0.0, e2 = 0.0, b1 = 0.0, b2 = 0.0;
+          for (int s = 0; s <= 1; ++s) {
+            int q[3] = {i, j, k}, r[3] = {i, j, k};
+            q[t2] += s;  // t1-edges on the face
+            e1 = e1 + En[t1].at(q);
+            r[t1] += s;  // t2-edges on the face
+            e2 = e2 + En[t2].at(r);
+            for (int u = -1; u <= 0; ++u) {
+              int x[3] = {i, j, k}, y[3] = {i, j, k};
+              x[t2] += s;  // t2-faces around the face
+              x[d] += u;
+              b2 = b2 + bf(t2, x);
+              y[t1] += s;  // t1-faces around the face
+              y[d] += u;
+              b1 = b1 + bf(t1, y);
+            }
+          }
+          e1 = 0.5 * e1;
+          e2 = 0.5 * e2;
+          b1 = 0.25 * b1;
+          b2 = 0.25 * b2;
+          Flux<R>& F = Fx[d].at(f);
+          F.e = F.e + (e1 * b2 - e2 * b1);
+        }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -554,6 +713,8 @@ void step(const Layout& L, const std::vector<R>& P, const Box3<Prim<R>>& W, R dt
           E[a].at(e0) = 0.25 * (A + B + C + D) + 0.25 * ((dc34 - dc14) + (db34 - db14));
         }
   }
+
+  if (ph.nonideal()) nonideal(L, P, W, dx, ph, E, Fx);
 
   // Conservative update of the cell variables, fluxes summed x, y, z.
   Layout O(n, 0);

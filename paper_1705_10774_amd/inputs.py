@@ -45,6 +45,9 @@ class Config:
     periodic: Tuple[int, int, int] = (1, 1, 1)
     box_lo: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     box_hi: Tuple[float, float, float] = (1.0, 1.0, 1.0)
+    eta: float = 0.0       # Ohmic resistivity (Sec. 4.3.1); 0 = none
+    gamma_ad: float = 0.0  # ambipolar drift coefficient (Sec. 4.3.2); 0 = none
+    rho_ion: float = 1.0   # ion density of the ambipolar term
 
 
 @dataclasses.dataclass
@@ -309,6 +312,42 @@ def level_row(levels=(0, 0, 1, 0, 2), n=8, amp=1e-3, prec=F64, dt_base=None, nsl
     pr.cfg = dataclasses.replace(pr.cfg, dt_base=dt_base, nslots=nslots, grace=grace)
     pr.name = "level_row"
     return pr
+
+
+def field_1d(kind="beltrami", npd=2, n=16, B0=1.0, b=0.1, p0=1.0, eta=0.0, gamma_ad=0.0, rho_ion=1.0,
+             mode=DT_FIXED, dt_fixed=1e-3, dt_base=0.0, prec=F64, t_end=0.1):
+    """Fields along x on rho = 1, p = p0, v = 0, sampled at face centres, for
+    the non-ideal terms (Sec. 4.3); k = 2 pi.
+    beltrami:   B = B0 (0, sin kx, cos kx), force free (J = k B), |B| = B0;
+    transverse: B = (0, B0 + b sin kx, 0), J = b k cos kx z (J x B != 0);
+    alfven:     B = (B0, b sin kx, 0), J perpendicular to B, |B|^2 = B0^2 + O(b^2)."""
+    patches = cartesian(npd, n)
+    rho, vel, pres, bf = [], [], [], []
+    for q in patches:
+        x = cell_coords(q)[0]
+        sx = np.sin(2 * np.pi * x)[None, None, :]
+        cx = np.cos(2 * np.pi * x)[None, None, :]
+        bx = np.zeros((q.n, q.n, q.n + 1))
+        by = np.zeros((q.n, q.n + 1, q.n))
+        bz = np.zeros((q.n + 1, q.n, q.n))
+        if kind == "beltrami":
+            by[...] = B0 * sx
+            bz[...] = B0 * cx
+        elif kind == "transverse":
+            by[...] = B0 + b * sx
+        elif kind == "alfven":
+            bx[...] = B0
+            by[...] = b * sx
+        else:
+            raise ValueError(kind)
+        rho.append(np.ones((q.n,) * 3))
+        vel.append([np.zeros((q.n,) * 3) for _ in range(3)])
+        pres.append(np.full((q.n,) * 3, p0))
+        bf.append((bx, by, bz))
+    U = assemble(patches, rho, vel, pres, bf, 5.0 / 3.0)
+    cfg = Config(dt_mode=mode, dt_fixed=dt_fixed, dt_base=dt_base, prec=prec, eta=eta, gamma_ad=gamma_ad,
+                 rho_ion=rho_ion)
+    return Problem(f"{kind}_1d", cfg, patches, U, t_end, extra={"B0": B0, "b": b, "p0": p0})
 
 
 def cfg1_alfven(prec=F64):

@@ -30,10 +30,27 @@ def test_library_exports_every_symbol():
         assert hasattr(L, name), name
 
 
-def test_struct_layout_matches_header():
-    # 6 doubles, 6 int32, 3 int32, 6 doubles -> 48 + 24 + 12 (+4 pad) + 48
-    assert C.sizeof(dsp.dsp_config) == 136
-    assert C.sizeof(dsp.dsp_patch_desc) == 56
+def test_struct_layout_matches_header(tmp_path):
+    """Size and every field offset of the binding's structures against the C
+    compiler's layout of include/dsp.h."""
+    import subprocess
+    lines = []
+    for cname, ct in (("dsp_config", dsp.dsp_config), ("dsp_patch_desc", dsp.dsp_patch_desc)):
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in ct._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "dsp.h"\nint main(void) {\n' +
+                   "\n".join(lines) + "\nreturn 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    want = []
+    for cname, ct in (("dsp_config", dsp.dsp_config), ("dsp_patch_desc", dsp.dsp_patch_desc)):
+        want.append(f"{cname} size {C.sizeof(ct)}")
+        for f, _ in ct._fields_:
+            want.append(f"{cname} {f} {getattr(ct, f).offset}")
+    assert [g for g in got if g] == want
 
 
 @pytest.mark.parametrize("bad", [dict(grace=1.0), dict(grace=-0.1), dict(grace=0.5, nslots=2),

@@ -648,6 +648,141 @@ def test_time_extrapolation_formula(orc):
 
 
 # ---------------------------------------------------------------------------
+# non-ideal MHD (Sec. 4.3): Ohmic and ambipolar electric fields
+
+
+def _pressure(U, pr):
+    out = []
+    for v in I.patch_views(U, pr.patches):
+        m = np.array(v[1:4])
+        bc = [0.5 * (v[5][..., :-1] + v[5][..., 1:]), 0.5 * (v[6][:, :-1, :] + v[6][:, 1:, :]),
+              0.5 * (v[7][:-1] + v[7][1:])]
+        out.append((5.0 / 3.0 - 1.0) * (v[4] - 0.5 * (m ** 2).sum(0) / v[0] - 0.5 * sum(c ** 2 for c in bc)))
+    return out
+
+
+def _fixed_run(orc, pr, nsteps):
+    s = orc.OracleSet.from_problem(pr)
+    s.set_order(2, 1, NT)
+    s.advance_to(nsteps * pr.cfg.dt_fixed)
+    U = s.read_state()
+    st, kh, kl = s.read_schedule(klog_cap=64)
+    s.close()
+    return U, kl
+
+
+@pytest.mark.parametrize("n,tol", [(16, 5e-6), (32, 1e-7)])
+def test_ohmic_decay_of_force_free_field(orc, n, tol):
+    """B = B0 (0, sin kx, cos kx) is force free and has J = k B, so Ohmic
+    diffusion alone changes it: each explicit step multiplies the mode by
+    1 - eta k_d^2 dt, k_d = 2 sin(k dx / 2) / dx the wavenumber of the discrete
+    curl curl.  The Poynting flux of eta J vanishes (|B| uniform), so every
+    cell keeps the magnetic energy it loses as heat: p - p0 = (gamma - 1)
+    (B0^2 - a^2) / 2 for the remaining amplitude a."""
+    eta, dt, N = 0.05, 1e-3, 100
+    pr = I.field_1d("beltrami", n=n, eta=eta, dt_fixed=dt)
+    U, _ = _fixed_run(orc, pr, N)
+    num = den = 0.0
+    for q, v in zip(pr.patches, I.patch_views(U, pr.patches)):
+        sx = np.sin(2 * np.pi * I.cell_coords(q)[0])[None, None, :]
+        by = v[6][:, :-1, :]
+        num += float((by * sx).sum())
+        den += float((np.broadcast_to(sx, by.shape) ** 2).sum())
+    a = num / den
+    dx = pr.patches[0].size / n
+    kd2 = (2.0 * math.sin(math.pi * dx) / dx) ** 2
+    want = (1.0 - eta * kd2 * dt) ** N
+    print("amplitude", a, "discrete decay", want, "continuum", math.exp(-eta * 4 * math.pi ** 2 * N * dt))
+    assert abs(a / want - 1.0) <= tol
+    P = np.concatenate([p.ravel() for p in _pressure(U, pr)])
+    gain = (5.0 / 3.0 - 1.0) * (1.0 - a * a) / 2.0
+    assert abs((P.mean() - 1.0) / gain - 1.0) <= 1e-4
+
+
+def test_ohmic_heating_is_eta_j_squared(orc):
+    """B = (0, B0 + b sin kx, 0): one short step heats every cell by
+    (gamma - 1) eta J^2 dt (Eq. Ohm_heat), J^2 the mean over the cell's two
+    x-faces of J = dBy/dx; the ideal part is removed by a run with eta = 0.
+    Without the Poynting flux of eta J the heating would instead follow
+    -B dB (sign changing)."""
+    eta, dt, b = 0.05, 1e-5, 0.1
+    p1 = I.field_1d("transverse", n=16, eta=eta, dt_fixed=dt, b=b)
+    p0 = I.field_1d("transverse", n=16, dt_fixed=dt, b=b)
+    U1, _ = _fixed_run(orc, p1, 1)
+    U0, _ = _fixed_run(orc, p0, 1)
+    worst = scale = 0.0
+    for q, a, c in zip(p1.patches, _pressure(U1, p1), _pressure(U0, p0)):
+        x = I.cell_coords(q)[0]
+        dx = q.size / q.n
+
+        def J(xf):
+            return b * (np.sin(2 * np.pi * (xf + dx / 2)) - np.sin(2 * np.pi * (xf - dx / 2))) / dx
+
+        want = (5.0 / 3.0 - 1.0) * eta * dt * 0.5 * (J(x - dx / 2) ** 2 + J(x + dx / 2) ** 2)
+        worst = max(worst, float(np.abs((a - c) - want[None, None, :]).max()))
+        scale = max(scale, float(want.max()))
+    print("heating error relative to its peak", worst / scale)
+    assert worst <= 1e-4 * scale
+
+
+def test_ambipolar_equals_ohmic_for_perpendicular_current(orc):
+    """B = (B0, b sin kx, 0) carries J = (0, 0, b k cos kx), perpendicular to
+    B, so E_AD = -v_D x B = B^2 J / (gamma_AD rho rho_i) (Eq. AD): Ohmic
+    diffusion with eta = B0^2 / (gamma_AD rho rho_i) up to O(b^2 / B0^2)."""
+    B0, b, gad, dt, N = 1.0, 1e-3, 20.0, 1e-3, 100
+    pa = I.field_1d("alfven", B0=B0, b=b, gamma_ad=gad, rho_ion=1.0, dt_fixed=dt)
+    po = I.field_1d("alfven", B0=B0, b=b, eta=B0 ** 2 / gad, dt_fixed=dt)
+    pi = I.field_1d("alfven", B0=B0, b=b, dt_fixed=dt)
+    Ua, _ = _fixed_run(orc, pa, N)
+    Uo, _ = _fixed_run(orc, po, N)
+    Ui, _ = _fixed_run(orc, pi, N)
+    effect = np.abs(Uo - Ui).max()
+    print("AD - Ohm", np.abs(Ua - Uo).max(), "effect of the diffusion", effect)
+    assert effect > 1e-5
+    assert np.abs(Ua - Uo).max() <= 1e-5 * effect
+
+
+def test_ambipolar_vanishes_for_force_free_field(orc):
+    """For J parallel to B the drift v_D = J x B / (gamma_AD rho rho_i) is 0: the
+    first step of a force-free field is that of ideal MHD."""
+    pa = I.field_1d("beltrami", gamma_ad=20.0, dt_fixed=1e-3)
+    pi = I.field_1d("beltrami", dt_fixed=1e-3)
+    Ua, _ = _fixed_run(orc, pa, 1)
+    Ui, _ = _fixed_run(orc, pi, 1)
+    assert np.abs(Ui - pi.U0).max() > 1e-5
+    assert np.abs(Ua - Ui).max() <= 1e-15
+
+
+@pytest.mark.parametrize("kind", ["ohm", "ad"])
+def test_nonideal_step_limits(orc, kind):
+    """Uniform state (J = 0) in LOCAL mode: the level is set by
+    dt_Ohm = 0.1 dx^2 / eta (Eq. dtOhm) or dt_AD = 0.1 gamma_AD rho_i rho
+    dx^2 / B^2 (Eq. dtAD) when that is below the MHD Courant step."""
+    dt_base = 1e-3
+    over = dict(eta=0.3) if kind == "ohm" else dict(gamma_ad=0.7, rho_ion=1.3)
+    pr = I.field_1d("alfven", b=0.0, mode=I.DT_LOCAL, dt_base=dt_base, **over)
+    dx = pr.patches[0].size / pr.patches[0].n
+    if kind == "ohm":
+        dt_lim = 0.1 * dx ** 2 / over["eta"]
+    else:
+        dt_lim = 0.1 * over["gamma_ad"] * over["rho_ion"] * 1.0 * dx ** 2 / 1.0 ** 2
+    # MHD: rho = 1, p = 1, B = (1, 0, 0): fast speed 1.29.. along x, (a^2 + b^2)^1/2 across
+    a2 = 5.0 / 3.0
+    dt_mhd = 0.4 / ((math.sqrt(max(a2, 1.0)) + 2 * math.sqrt(a2 + 1.0)) / dx)
+    dt = min(dt_lim, dt_mhd)
+    assert dt_lim < dt_mhd
+    k = math.ceil(math.log2(dt_base / dt))
+    assert abs(math.log2(dt_base / dt) - round(math.log2(dt_base / dt))) > 0.05
+    s = orc.OracleSet.from_problem(pr)
+    s.set_order(2, 1, NT)
+    s.advance_to(dt_base)
+    st, kh, kl = s.read_schedule(klog_cap=64)
+    s.close()
+    assert (st == 2 ** k).all()
+    assert (kl[:, :st[0]] == k).all()
+
+
+# ---------------------------------------------------------------------------
 # cross-resolution guard values (prolongation / restriction)
 
 
@@ -737,7 +872,8 @@ def test_error_codes(orc):
     with pytest.raises(orc.OracleError) as e:
         s2.advance_to(sp.cfg.dt_base)
     assert e.value.code == -4
-    for bad in (dict(grace=1.0), dict(grace=-0.1), dict(grace=0.5, nslots=2), dict(grace=0.5, dt_mode=2)):
+    for bad in (dict(grace=1.0), dict(grace=-0.1), dict(grace=0.5, nslots=2), dict(grace=0.5, dt_mode=2),
+                dict(eta=-1.0), dict(gamma_ad=-1.0), dict(gamma_ad=1.0, rho_ion=0.0)):
         with pytest.raises(orc.OracleError) as e:
             orc.OracleSet(dataclasses.replace(pr.cfg, **bad), pr.patches)
         assert e.value.code == -1
