@@ -88,6 +88,16 @@ typedef struct {
   dsp_dt_mode dt_mode;
   int32_t periodic[3]; /* must be 1, 1, 1 */
   double box_lo[3], box_hi[3];
+  /* Non-ideal MHD (Sec. 4.3), all >= 0; eta = gamma_ad = 0 is ideal MHD.
+   * eta: Ohmic resistivity, E += eta J (Eq. Ohm); gamma_ad > 0: ambipolar
+   * diffusion, E += -v_D x B with v_D = J x B / (gamma_ad rho rho_ion)
+   * (Eq. AD), rho_ion > 0.  J = curl B on the edges of constrained transport,
+   * from the state at the start of the step; the energy flux carries the
+   * Poynting flux of this field, so the removed magnetic energy becomes heat
+   * J.E.  The step also obeys dt <= 0.1 dx^2 / eta (Eq. dtOhm) and
+   * dt <= 0.1 gamma_ad rho_ion rho dx^2 / B^2 (Eq. dtAD) in LOCAL and GLOBAL
+   * modes.  Runs on the staged kernels; no adjoint. */
+  double eta, gamma_ad, rho_ion;
 } dsp_config;
 
 /* One cubic patch: origin, edge length (size[0] == size[1] == size[2]),

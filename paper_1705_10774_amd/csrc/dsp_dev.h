@@ -33,6 +33,10 @@ struct DevSet {
   int npatch, nslots, kmax, dt_mode, exact_time, klog_cap;
   double gamma, courant, dt_base, dt_fixed, p_floor;
   double grace;  // g of Eq. (1) (LOCAL mode)
+  // non-ideal MHD (Sec. 4.3): Ohmic resistivity, ambipolar drift coefficient,
+  // ion density; nonideal = eta > 0 or gamma_ad > 0
+  double eta, gamma_ad, rho_i;
+  int nonideal;
   // geometry
   const int* n;           // interior cells per edge
   const double* dx;       // cell size
@@ -77,6 +81,10 @@ __device__ __forceinline__ int live_count(const DevSet& S, int count) {
   const int m = *S.live;
   return m < count ? m : count;
 }
+
+// Courant-like factor of the Ohmic and ambipolar step limits, C_Ohm = C_AD
+// (Eqs. dtOhm and dtAD).
+constexpr double kCourantNonideal = 0.1;
 
 // Work buffers of a batch of patch slots (stride = values per slot).
 template <class T> struct WorkPtr {

@@ -13,6 +13,8 @@
 //   k_pred     van Leer slopes and the Hancock half-step predictor;
 //   k_flux     HLLD fluxes on every face the update and the edge EMFs need;
 //   k_emf      upwinded edge EMFs (constrained transport);
+//   k_ni_emf   with non-ideal MHD: Ohmic and ambipolar fields added to the
+//              edge EMFs, and k_ni_flux their Poynting flux to the energy flux;
 //   k_update   conservative update of the cell variables and CT update of B,
 //              written into the patch's next ring slot;
 //   k_publish  new slot, ticks, step count and level hash (after the whole
@@ -165,6 +167,18 @@ __global__ void k_prim(DevSet S, const int* __restrict__ list, int count, WorkPt
       sum = sum + (fabs(vy) + fast_speed(a2, b2, (bz * bz + bx * bx) * ir));
       sum = sum + (fabs(vz) + fast_speed(a2, b2, (bx * bx + by * by) * ir));
       s = (double)sum / S.dx[p];
+      if (S.nonideal) {
+        // Ohmic and ambipolar limits as rates (Eqs. dtOhm, dtAD, C = 0.1)
+        const double f = S.courant / kCourantNonideal / (S.dx[p] * S.dx[p]);
+        if (S.eta > 0.0) {
+          const double so = S.eta * f;
+          if (so > s) s = so;
+        }
+        if (S.gamma_ad > 0.0) {
+          const double sa = (double)bb / (S.gamma_ad * S.rho_i * (double)rho) * f;
+          if (sa > s) s = sa;
+        }
+      }
       if (!isfinite(s)) atomicOr(S.err, ERR_NONFINITE);
     }
   }
@@ -406,6 +420,148 @@ __global__ void k_emf(DevSet S, const int* __restrict__ list, int count, WorkPtr
 }
 
 // ---------------------------------------------------------------------------
+// Non-ideal electric field (Sec. 4.3) from the padded state at t^n, on the
+// edges of k_emf: Ohmic E = eta J (Eq. Ohm) plus ambipolar
+// E = -v_D x B = (B^2 J - (J.B) B) / (gamma_AD rho rho_i) (Eq. AD).  J_a is the
+// discrete curl of the face field on the a-edge; on an a-edge the b and c
+// components of J are the means of the four nearest b- (c-) edges, B_a the
+// mean of the eight nearest a-faces, B_b and B_c the means of the two faces
+// through the edge, rho the mean of the four cells around it.  The field is
+// added to the edge EMFs and kept (in the slope buffer, dead after k_flux)
+// for k_ni_flux.
+
+// J_a on the a-edge (a-index a cell index, the others face indices) of the
+// padded patch Pd
+template <class T>
+__device__ __forceinline__ T edge_current(const T* Pd, int N, T dx, int a, int i0, int i1, int i2) {
+  const int b = (a + 1) % 3, c = (a + 2) % 3;
+  int e[3] = {i0, i1, i2}, eb[3] = {i0, i1, i2}, ec[3] = {i0, i1, i2};
+  eb[b] -= 1;
+  ec[c] -= 1;
+  const T dcb = Pd[pface(N, c, e[0], e[1], e[2])] - Pd[pface(N, c, eb[0], eb[1], eb[2])];
+  const T dbc = Pd[pface(N, b, e[0], e[1], e[2])] - Pd[pface(N, b, ec[0], ec[1], ec[2])];
+  return (dcb - dbc) / dx;
+}
+
+template <class T>
+__global__ void k_ni_emf(DevSet S, const int* __restrict__ list, int count, WorkPtr<T> W) {
+  const int blk = blockIdx.y;
+  if (blk >= count) return;
+  const int p = list[blk];
+  const int n = S.n[p], N = n + 4;
+  const int64_t per = (int64_t)n * (n + 1) * (n + 1);
+  int64_t c0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c0 >= 3 * per) return;
+  const int a = (int)(c0 / per);
+  c0 -= a * per;
+  const int bax = (a + 1) % 3, cax = (a + 2) % 3;
+  int e[3];
+  e[a] = (int)(c0 % n);
+  e[bax] = (int)((c0 / n) % (n + 1));
+  e[cax] = (int)(c0 / ((int64_t)n * (n + 1)));
+  const T* Pd = W.pad + (int64_t)blk * W.pad_stride;
+  const T* Wp = W.w + (int64_t)blk * W.w_stride;
+  const T dx = (T)S.dx[p];
+  const T ja = edge_current(Pd, N, dx, a, e[0], e[1], e[2]);
+  T en = T(S.eta) * ja;
+  if (S.gamma_ad > 0.0) {
+    T jb = T(0), jc = T(0), ba = T(0), bb = T(0), bc = T(0), rho = T(0);
+    for (int s = -1; s <= 0; ++s)
+      for (int t = 0; t <= 1; ++t) {
+        int q[3] = {e[0], e[1], e[2]}, r[3] = {e[0], e[1], e[2]};
+        q[bax] += s;
+        q[a] += t;
+        jb = jb + edge_current(Pd, N, dx, bax, q[0], q[1], q[2]);
+        r[cax] += s;
+        r[a] += t;
+        jc = jc + edge_current(Pd, N, dx, cax, r[0], r[1], r[2]);
+      }
+    for (int t = 0; t <= 1; ++t)
+      for (int s = -1; s <= 0; ++s)
+        for (int u = -1; u <= 0; ++u) {
+          int q[3] = {e[0], e[1], e[2]};
+          q[a] += t;
+          q[bax] += s;
+          q[cax] += u;
+          ba = ba + Pd[pface(N, a, q[0], q[1], q[2])];
+        }
+    for (int s = -1; s <= 0; ++s) {
+      int q[3] = {e[0], e[1], e[2]}, r[3] = {e[0], e[1], e[2]}, w[3] = {e[0], e[1], e[2]};
+      q[cax] += s;
+      bb = bb + Pd[pface(N, bax, q[0], q[1], q[2])];
+      r[bax] += s;
+      bc = bc + Pd[pface(N, cax, r[0], r[1], r[2])];
+      for (int u = -1; u <= 0; ++u) {
+        w[bax] = e[bax] + s;
+        w[cax] = e[cax] + u;
+        rho = rho + Wp[wcell(N, 0, w[0], w[1], w[2])];
+      }
+    }
+    jb = T(0.25) * jb;
+    jc = T(0.25) * jc;
+    ba = T(0.125) * ba;
+    bb = T(0.5) * bb;
+    bc = T(0.5) * bc;
+    rho = T(0.25) * rho;
+    const T b2 = ba * ba + bb * bb + bc * bc;
+    const T jdotb = ja * ba + jb * bb + jc * bc;
+    en = en + (b2 * ja - jdotb * ba) / (T(S.gamma_ad * S.rho_i) * rho);
+  }
+  const int64_t o = (int64_t)a * W.fm3 + wface(N, 0, e[0], e[1], e[2]);
+  W.s[(int64_t)blk * W.s_stride + o] = en;
+  W.e[(int64_t)blk * W.e_stride + o] += en;
+}
+
+// Poynting flux (E x B)_d of the non-ideal field through the d-faces of the
+// update (face index [0, n] along d, cells [0, n-1] across): the means of E_t1
+// and E_t2 over the two edges of each kind on the face, and of B_t1 and B_t2
+// over the four faces around it, added to the energy flux.  Total energy
+// stays conserved; the magnetic energy removed becomes the heat J.E (Eqs.
+// Ohm_heat and Q_AD).
+template <class T>
+__global__ void k_ni_flux(DevSet S, const int* __restrict__ list, int count, WorkPtr<T> W) {
+  const int blk = blockIdx.y;
+  if (blk >= count) return;
+  const int p = list[blk];
+  const int n = S.n[p], N = n + 4;
+  const int64_t per = (int64_t)(n + 1) * n * n;
+  int64_t c0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c0 >= 3 * per) return;
+  const int d = (int)(c0 / per);
+  c0 -= d * per;
+  const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+  int f[3];
+  f[d] = (int)(c0 % (n + 1));
+  f[t1] = (int)((c0 / (n + 1)) % n);
+  f[t2] = (int)(c0 / ((int64_t)(n + 1) * n));
+  const T* Pd = W.pad + (int64_t)blk * W.pad_stride;
+  const T* En = W.s + (int64_t)blk * W.s_stride;
+  T e1 = T(0), e2 = T(0), b1 = T(0), b2 = T(0);
+  for (int s = 0; s <= 1; ++s) {
+    int q[3] = {f[0], f[1], f[2]}, r[3] = {f[0], f[1], f[2]};
+    q[t2] += s;
+    e1 = e1 + En[(int64_t)t1 * W.fm3 + wface(N, 0, q[0], q[1], q[2])];
+    r[t1] += s;
+    e2 = e2 + En[(int64_t)t2 * W.fm3 + wface(N, 0, r[0], r[1], r[2])];
+    for (int u = -1; u <= 0; ++u) {
+      int x[3] = {f[0], f[1], f[2]}, y[3] = {f[0], f[1], f[2]};
+      x[t2] += s;
+      x[d] += u;
+      b2 = b2 + Pd[pface(N, t2, x[0], x[1], x[2])];
+      y[t1] += s;
+      y[d] += u;
+      b1 = b1 + Pd[pface(N, t1, y[0], y[1], y[2])];
+    }
+  }
+  e1 = T(0.5) * e1;
+  e2 = T(0.5) * e2;
+  b1 = T(0.25) * b1;
+  b2 = T(0.25) * b2;
+  T* Fd = W.f + (int64_t)blk * W.f_stride + (int64_t)d * 8 * W.fm3;
+  Fd[4 * W.fm3 + wface(N, 0, f[0], f[1], f[2])] += e1 * b2 - e2 * b1;
+}
+
+// ---------------------------------------------------------------------------
 // k_update: new slice = conservative update of the cells + CT update of the
 // faces, written into the patch's next ring slot.
 
@@ -621,6 +777,12 @@ void launch_update(const DevSet& S, const int* list, int count, int nmax, T* slo
   if (ev1) (void)hipEventRecord(ev1, s);
   hipLaunchKernelGGL(k_emf<T>, dim3(blocks(3LL * nmax * (nmax + 1) * (nmax + 1)), count), dim3(TPB), 0, s, S, list,
                      count, W);
+  if (S.nonideal) {
+    hipLaunchKernelGGL(k_ni_emf<T>, dim3(blocks(3LL * nmax * (nmax + 1) * (nmax + 1)), count), dim3(TPB), 0, s, S,
+                       list, count, W);
+    hipLaunchKernelGGL(k_ni_flux<T>, dim3(blocks(3LL * (nmax + 1) * nmax * nmax), count), dim3(TPB), 0, s, S, list,
+                       count, W);
+  }
   hipLaunchKernelGGL(k_update<T>, dim3(blocks((int64_t)nmax * nmax * nmax + 3LL * nmax * nmax * (nmax + 1)), count),
                      dim3(TPB), 0, s, S, list, count, slots, W, st);
 }

@@ -479,6 +479,8 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
     return fail(DSP_EINVAL, "dt_base must be positive");
   if (c.grace > 0.0 && (c.dt_mode != DSP_DT_LOCAL || c.nslots < 3))
     return fail(DSP_EINVAL, "a grace needs LOCAL time steps and at least 3 slots");
+  if (!(c.eta >= 0.0) || !(c.gamma_ad >= 0.0) || (c.gamma_ad > 0.0 && !(c.rho_ion > 0.0)))
+    return fail(DSP_EINVAL, "invalid non-ideal parameters");
   if (c.dt_mode == DSP_DT_FIXED && !(c.dt_fixed > 0.0)) return fail(DSP_EINVAL, "dt_fixed must be positive");
   for (int d = 0; d < 3; ++d)
     if (c.periodic[d] != 1) return fail(DSP_EINVAL, "only periodic boxes are supported");
@@ -580,7 +582,8 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
     int maxbox = 0;
     for (int p = 0; p < npatch; ++p) maxbox = std::max(maxbox, rbox_off[(p + 1) * 108] - rbox_off[p * 108]);
     const char* path = getenv("DSP_PATH");
-    S->fused = !(path && std::string(path) == "staged") && maxbox <= 256;
+    // the non-ideal terms run on the staged kernels only
+    S->fused = !(path && std::string(path) == "staged") && maxbox <= 256 && !(cfg->eta > 0.0 || cfg->gamma_ad > 0.0);
     int ngen = 0;
     for (int p = 0; p < npatch; ++p)
       for (int k = 0; k < 108; ++k) {
@@ -679,6 +682,10 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
   D.dt_fixed = c.dt_fixed;
   D.p_floor = c.p_floor;
   D.grace = c.grace;
+  D.eta = c.eta;
+  D.gamma_ad = c.gamma_ad;
+  D.rho_i = c.rho_ion;
+  D.nonideal = (c.eta > 0.0 || c.gamma_ad > 0.0) ? 1 : 0;
   auto up = [&](const void* h, size_t bytes) -> void* {
     void* d = A(bytes);
     if (d && bytes) (void)hipMemcpy(d, h, bytes, hipMemcpyHostToDevice);
@@ -1171,6 +1178,7 @@ int dsp_fixed_steps_adj(dsp_set* s, const void* ckpt_dev, const void* lamT_dev, 
                         int32_t seg) {
   if (!s || !ckpt_dev || !lamT_dev || !lam0_dev || nsteps < 0) return fail(DSP_EINVAL, "bad argument");
   if (s->cfg.dt_mode != DSP_DT_FIXED) return fail(DSP_EINVAL, "the adjoint needs the FIXED dt mode");
+  if (s->D.nonideal) return fail(DSP_EINVAL, "the adjoint covers ideal MHD only");
   if (seg != 8) return fail(DSP_EINVAL, "checkpoint segments are 8 steps");
   if (s->any_generic)
     return fail(DSP_EINVAL, "the adjoint covers sets whose guard regions are same-resolution copies");

@@ -33,7 +33,8 @@ class dsp_config(C.Structure):
                 ("dt_fixed", C.c_double), ("grace", C.c_double), ("p_floor", C.c_double),
                 ("kmax", C.c_int32), ("nslots", C.c_int32), ("nguard", C.c_int32),
                 ("limiter", C.c_int32), ("prec", C.c_int32), ("dt_mode", C.c_int32),
-                ("periodic", C.c_int32 * 3), ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3)]
+                ("periodic", C.c_int32 * 3), ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3),
+                ("eta", C.c_double), ("gamma_ad", C.c_double), ("rho_ion", C.c_double)]
 
 
 class dsp_patch_desc(C.Structure):
@@ -99,7 +100,7 @@ def _dp(a):
 def make_config(cfg) -> dsp_config:
     c = dsp_config()
     for f in ("gamma", "courant", "dt_base", "dt_fixed", "grace", "p_floor", "kmax", "nslots",
-              "nguard", "limiter", "prec", "dt_mode"):
+              "nguard", "limiter", "prec", "dt_mode", "eta", "gamma_ad", "rho_ion"):
         setattr(c, f, getattr(cfg, f))
     for d in range(3):
         c.periodic[d] = int(cfg.periodic[d])
