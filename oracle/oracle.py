@@ -35,7 +35,7 @@ class _Cfg(C.Structure):
                 ("limiter", C.c_int32), ("prec", C.c_int32), ("dt_mode", C.c_int32),
                 ("periodic", C.c_int32 * 3), ("box_lo", C.c_double * 3),
                 ("box_hi", C.c_double * 3), ("eta", C.c_double), ("gamma_ad", C.c_double),
-                ("rho_ion", C.c_double)]
+                ("rho_ion", C.c_double), ("torder", C.c_int32)]
 
 
 class _Desc(C.Structure):
@@ -93,7 +93,7 @@ def _dp(a):
 def make_cfg(cfg) -> _Cfg:
     c = _Cfg()
     for f in ("gamma", "courant", "dt_base", "dt_fixed", "grace", "p_floor", "kmax", "nslots",
-              "nguard", "limiter", "prec", "dt_mode", "eta", "gamma_ad", "rho_ion"):
+              "nguard", "limiter", "prec", "dt_mode", "eta", "gamma_ad", "rho_ion", "torder"):
         setattr(c, f, getattr(cfg, f))
     for d in range(3):
         c.periodic[d] = int(cfg.periodic[d])

@@ -153,8 +153,36 @@ template <class R> struct SetT {
   // Pick the slice(s) of patch q for time (ticks or t): an exact copy when a
   // slice has that time, else the adjacent pair a < t < b with weight w.  With
   // a grace g > 0 (LOCAL mode) a time past q's newest slice is extrapolated
-  // from the two newest slices a < b < t (w > 1; Sec. 3B).
-  int bracket(int q, int64_t tk, double tt, int& sa, int& sb, double& w) const {
+  // from the two newest slices a < b < t (w > 1; Sec. 3B).  With time order 2
+  // (ticks modes) a third slice c joins (the next older than a, else the next
+  // newer than b) and the value is the quadratic through the three:
+  // s_a + L_b (s_b - s_a) + L_c (s_c - s_a), L the Lagrange weights.
+  struct TB {
+    int sa = -1, sb = -1, sc = -1;  // sc < 0: linear (or a copy when sa == sb)
+    double w = 0.0, wc = 0.0;       // weights of b and c
+  };
+  int bracket(int q, int64_t tk, double tt, TB& tb) const {
+    int e = bracket2(q, tk, tt, tb.sa, tb.sb, tb.w);
+    tb.sc = -1;
+    tb.wc = 0.0;
+    if (e || tb.sa == tb.sb || cfg.torder < 2 || exact_time) return e;
+    const PatchT<R>& Q = p[q];
+    const int ns = (int)Q.slot.size();
+    const int64_t ta = Q.sticks[tb.sa], tbk = Q.sticks[tb.sb];
+    int c = -1;
+    for (int s = 0; s < ns; ++s)  // the next older than a
+      if (Q.svalid[s] && Q.sticks[s] < ta && (c < 0 || Q.sticks[s] > Q.sticks[c])) c = s;
+    if (c < 0)
+      for (int s = 0; s < ns; ++s)  // else the next newer than b
+        if (Q.svalid[s] && Q.sticks[s] > tbk && (c < 0 || Q.sticks[s] < Q.sticks[c])) c = s;
+    if (c < 0) return 0;
+    const double x = (double)(tk - ta), xb = (double)(tbk - ta), xc = (double)(Q.sticks[c] - ta);
+    tb.sc = c;
+    tb.w = x * (x - xc) / (xb * (xb - xc));
+    tb.wc = x * (x - xb) / (xc * (xc - xb));
+    return 0;
+  }
+  int bracket2(int q, int64_t tk, double tt, int& sa, int& sb, double& w) const {
     const PatchT<R>& Q = p[q];
     int ns = (int)Q.slot.size();
     sa = sb = -1;
@@ -197,12 +225,15 @@ template <class R> struct SetT {
     return 0;
   }
 
-  // value of slice entry e of patch q at the bracket (sa, sb, w): s_a + w (s_b - s_a)
-  R tval(int q, size_t e, int sa, int sb, double w) const {
-    const R& a = p[q].slot[sa][e];
-    if (sa == sb) return a;
-    const R& b = p[q].slot[sb][e];
-    return a + w * (b - a);
+  // value of slice entry e of patch q at the bracket: s_a + w (s_b - s_a)
+  // [+ w_c (s_c - s_a)]
+  R tval(int q, size_t e, const TB& tb) const {
+    const R& a = p[q].slot[tb.sa][e];
+    if (tb.sa == tb.sb) return a;
+    const R& b = p[q].slot[tb.sb][e];
+    if (tb.sc < 0) return a + tb.w * (b - a);
+    const R& c = p[q].slot[tb.sc][e];
+    return a + tb.w * (b - a) + tb.wc * (c - a);
   }
 
   // ---- cross-resolution guard value --------------------------------------
@@ -212,14 +243,13 @@ template <class R> struct SetT {
   // cell variable the box is the target cell; for a face field it is the
   // face area (and the source field is linear in the normal direction
   // between the two bracketing source faces).
-  R cross_value(int q, int c, int var, const int64_t X[3], int64_t tdx, int sa, int sb,
-                double w) const {
+  R cross_value(int q, int c, int var, const int64_t X[3], int64_t tdx, const TB& tb) const {
     const PatchT<R>& Q = p[q];
     const int n = Q.n;
     Layout SL(n, 0);
     auto get = [&](int v, int cc, int i, int j, int k) -> R {
       size_t e = (cc < 0) ? SL.cell(v, i, j, k) : SL.face(cc, i, j, k);
-      return tval(q, e, sa, sb, w);
+      return tval(q, e, tb);
     };
     auto minmod = [](R a, R b) -> R {
       if (val(a) * val(b) <= 0.0) return R(0.0);
@@ -389,11 +419,10 @@ template <class R> struct SetT {
             int64_t Xw[3] = {X[0], X[1], X[2]};
             int s = locate(Xw, mode);
             if (s < 0) return fail(ORC_ESTATE, "guard point outside every patch");
-            int sa, sb;
-            double w;
-            if (bracket(s, P.ticks, P.t, sa, sb, w) != 0)
+            TB tb;
+            if (bracket(s, P.ticks, P.t, tb) != 0)
               return fail(ORC_ESTATE, "no time slices bracket the guard time");
-            if (w > 1.0) extrap = true;
+            if (tb.sa != tb.sb && !exact_time && P.ticks > p[s].sticks[tb.sb]) extrap = true;
             const PatchT<R>& Q = p[s];
             bool same = (Q.dxl == P.dxl);
             int li[3];
@@ -410,9 +439,9 @@ template <class R> struct SetT {
               if (same) {
                 Layout QS(Q.n, 0);
                 size_t eq = (c < 0) ? QS.cell(v, li[0], li[1], li[2]) : QS.face(c, li[0], li[1], li[2]);
-                val_ = tval(s, eq, sa, sb, w);
+                val_ = tval(s, eq, tb);
               } else {
-                val_ = cross_value(s, c, v, Xw, P.dxl, sa, sb, w);
+                val_ = cross_value(s, c, v, Xw, P.dxl, tb);
               }
               if (c < 0)
                 Pd[L.cell(v, i, j, k)] = val_;
@@ -560,7 +589,8 @@ template <class R> struct SetT {
     const PatchT<R>& P = p[q];
     if (P.ticks >= T) return false;
     const int ns = (int)P.slot.size();
-    const int oldest = (P.cur + 1) % ns, after = (P.cur + 2) % ns;
+    // with time order 2 the slice before a bracket is read too: keep two
+    const int oldest = (P.cur + 1) % ns, after = (P.cur + 1 + std::max(1, cfg.torder)) % ns;
     for (int s : P.nbors) {
       const int64_t g = (int64_t)std::floor(cfg.grace * (double)last_step(s));
       if (P.ticks > p[s].ticks + g) return false;
@@ -698,6 +728,8 @@ static int build_set_common(const orc_config* cfg, const orc_patch_desc* pd, int
     return fail(ORC_EINVAL, "a grace needs LOCAL time steps and at least 3 slots");
   if (!(c.eta >= 0.0) || !(c.gamma_ad >= 0.0) || (c.gamma_ad > 0.0 && !(c.rho_ion > 0.0)))
     return fail(ORC_EINVAL, "invalid non-ideal parameters");
+  if (c.torder < 0 || c.torder > 2 || (c.torder == 2 && c.nslots < 3))
+    return fail(ORC_EINVAL, "time order must be 1 or 2 (2 needs at least 3 slots)");
   if ((c.dt_mode == 0 || c.dt_mode == 1) && !(c.dt_base > 0.0))
     return fail(ORC_EINVAL, "dt_base must be positive");
   if (c.dt_mode == 3 && !(c.dt_fixed > 0.0)) return fail(ORC_EINVAL, "dt_fixed must be positive");

@@ -33,6 +33,9 @@ typedef struct {
   /* non-ideal MHD (Sec. 4.3): Ohmic resistivity eta_Ohm, ambipolar drift
    * coefficient gamma_AD and ion density rho_i; 0, 0 = ideal */
   double eta, gamma_ad, rho_ion;
+  /* order of the guard-zone time interpolation: 0 or 1 linear, 2 quadratic
+   * through three slices (Sec. 3B) */
+  int32_t torder;
 } orc_config;
 
 typedef struct {

@@ -48,6 +48,7 @@ class Config:
     eta: float = 0.0       # Ohmic resistivity (Sec. 4.3.1); 0 = none
     gamma_ad: float = 0.0  # ambipolar drift coefficient (Sec. 4.3.2); 0 = none
     rho_ion: float = 1.0   # ion density of the ambipolar term
+    torder: int = 1        # guard time interpolation: 1 linear, 2 quadratic (three slices)
 
 
 @dataclasses.dataclass

@@ -648,6 +648,104 @@ def test_time_extrapolation_formula(orc):
 
 
 # ---------------------------------------------------------------------------
+# quadratic time interpolation from three slices (time order 2)
+
+
+def test_time_quadratic_formula(orc):
+    """Mid-run with time order 2, a patch's guard cells taken from a
+    neighbour that is ahead equal the quadratic through three of the
+    neighbour's slices: the bracketing pair a < t < b and the next older
+    slice c, with Lagrange weights (independent index arithmetic)."""
+    pr = _local_spread()
+    npd, n, ng = 3, 8, pr.cfg.nguard
+    Nn = n + 2 * ng
+    T = 0.02 / 8
+    s2 = orc.OracleSet.from_problem(pr, torder=2, nslots=4)
+    s2.set_order(0, 1, 1)
+    for _ in range(400):
+        s2.advance_limited(T, 1)
+        tk, _ = s2.times()
+        nb = s2.nbors()
+        for p in range(len(pr.patches)):
+            if any(tk[q] < tk[p] for q in nb[p]):
+                continue  # a neighbour behind: no guard fill at this time
+            for q in nb[p]:
+                if tk[q] <= tk[p]:
+                    continue
+                sl = []
+                for rel in range(4):
+                    try:
+                        sl.append(s2.slot(q, rel))
+                    except orc.OracleError:
+                        break
+                times = [x[1] for x in sl]
+                if tk[p] in times:
+                    continue  # a slice at that time: an exact copy
+                older = [m for m, t in enumerate(times) if t < tk[p]]
+                newer = [m for m, t in enumerate(times) if t > tk[p]]
+                if not older or not newer or len(older) < 2:
+                    continue
+                ia = max(older, key=lambda m: times[m])
+                ib = min(newer, key=lambda m: times[m])
+                ic = max([m for m in older if m != ia], key=lambda m: times[m])
+                ta, tb, tc = times[ia], times[ib], times[ic]
+                t = tk[p]
+                La = (t - tb) * (t - tc) / ((ta - tb) * (ta - tc))
+                Lb = (t - ta) * (t - tc) / ((tb - ta) * (tb - tc))
+                Lc = (t - ta) * (t - tb) / ((tc - ta) * (tc - tb))
+                assert abs(La + Lb + Lc - 1.0) < 1e-12
+                Pd = s2.padded(p)
+                pq = [int(round(pr.patches[q].origin[d] * npd)) for d in range(3)]
+                pp = [int(round(pr.patches[p].origin[d] * npd)) for d in range(3)]
+                checked = 0
+                for var in range(5):
+                    Pv = Pd[var * Nn ** 3:(var + 1) * Nn ** 3].reshape(Nn, Nn, Nn)
+                    sv = [sl[m][0][var * n ** 3:(var + 1) * n ** 3].reshape(n, n, n) for m in (ia, ib, ic)]
+                    for k in range(-ng, n + ng):
+                        for j in range(-ng, n + ng):
+                            for i in range(-ng, n + ng):
+                                gidx = [pp[0] * n + i, pp[1] * n + j, pp[2] * n + k]
+                                owner = [(gidx[d] % (npd * n)) // n for d in range(3)]
+                                if owner != pq:
+                                    continue
+                                li = [gidx[d] % n for d in range(3)]
+                                va, vb, vc = (x[li[2], li[1], li[0]] for x in sv)
+                                want = La * va + Lb * vb + Lc * vc
+                                assert abs(Pv[k + ng, j + ng, i + ng] - want) <= 1e-13 * max(1.0, abs(want))
+                                checked += 1
+                assert checked > 0
+                s2.close()
+                return
+    s2.close()
+    pytest.fail("no guard read three slices")
+
+
+def test_time_order2_keeps_copies_and_constants(orc):
+    """Time order 2 changes nothing where no interpolation happens (every
+    patch on one level) and keeps a uniform state uniform across a
+    resolution jump, where the fine patch interpolates the coarse one."""
+    pr = I.linear_wave("alfven", npd=2, n=8, amp=1e-3, mode=I.DT_LOCAL, t_end=0.05)
+    pr = dataclasses.replace(pr, cfg=dataclasses.replace(pr.cfg, dt_base=0.05 / 4))
+    res = []
+    for order in (1, 2):
+        s = orc.OracleSet.from_problem(pr, torder=order, nslots=4)
+        s.set_order(2, 1, NT)
+        s.advance_to(0.05)
+        res.append(s.read_state())
+        s.close()
+    assert np.array_equal(res[0], res[1])
+    cfg, patches, U = _grace_row((0, 1, 0, 1), 0.0, 4)
+    o = orc.OracleSet(dataclasses.replace(cfg, torder=2), patches)
+    o.init(U)
+    o.set_order(2, 1, 1)
+    o.advance_to(4 * cfg.dt_base)
+    st, _ = o.read_schedule()
+    assert st.tolist() == [4, 8, 4, 8]
+    assert np.array_equal(o.read_state(), U)
+    o.close()
+
+
+# ---------------------------------------------------------------------------
 # non-ideal MHD (Sec. 4.3): Ohmic and ambipolar electric fields
 
 
@@ -873,7 +971,8 @@ def test_error_codes(orc):
         s2.advance_to(sp.cfg.dt_base)
     assert e.value.code == -4
     for bad in (dict(grace=1.0), dict(grace=-0.1), dict(grace=0.5, nslots=2), dict(grace=0.5, dt_mode=2),
-                dict(eta=-1.0), dict(gamma_ad=-1.0), dict(gamma_ad=1.0, rho_ion=0.0)):
+                dict(eta=-1.0), dict(gamma_ad=-1.0), dict(gamma_ad=1.0, rho_ion=0.0), dict(torder=3),
+                dict(torder=2, nslots=2)):
         with pytest.raises(orc.OracleError) as e:
             orc.OracleSet(dataclasses.replace(pr.cfg, **bad), pr.patches)
         assert e.value.code == -1
