@@ -98,6 +98,12 @@ typedef struct {
    * dt <= 0.1 gamma_ad rho_ion rho dx^2 / B^2 (Eq. dtAD) in LOCAL and GLOBAL
    * modes.  Runs on the staged kernels; no adjoint. */
   double eta, gamma_ad, rho_ion;
+  /* Order of the guard time interpolation (Sec. 3B): 0 or 1 linear between
+   * the two bracketing slices; 2 quadratic through three slices (the pair and
+   * the next older slice, else the next newer), Lagrange weights; needs
+   * nslots >= 3, and a patch then also keeps the slice before any
+   * neighbour's time.  Exact slice times are still plain copies. */
+  int32_t torder;
 } dsp_config;
 
 /* One cubic patch: origin, edge length (size[0] == size[1] == size[2]),

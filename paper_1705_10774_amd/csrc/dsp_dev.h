@@ -37,6 +37,7 @@ struct DevSet {
   // ion density; nonideal = eta > 0 or gamma_ad > 0
   double eta, gamma_ad, rho_i;
   int nonideal;
+  int torder;  // guard time interpolation: 1 linear, 2 quadratic (three slices)
   // geometry
   const int* n;           // interior cells per edge
   const double* dx;       // cell size

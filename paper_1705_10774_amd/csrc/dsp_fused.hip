@@ -306,7 +306,7 @@ __device__ inline void count_traffic(const DevSet& S, int p, int box0, int nbox,
     const Bracket b = bracket(S, G.q, S.ticks[p], S.tcur[p]);
     const unsigned long long cnt =
         (unsigned long long)(G.hi[0] - G.lo[0] + 1) * (G.hi[1] - G.lo[1] + 1) * (G.hi[2] - G.lo[2] + 1);
-    atomicAdd(acc, cnt * (b.oa == b.ob ? 1ULL : 2ULL) * (unsigned long long)tsz);
+    atomicAdd(acc, cnt * (b.oa == b.ob ? 1ULL : (b.oc < 0 ? 2ULL : 3ULL)) * (unsigned long long)tsz);
   }
 }
 

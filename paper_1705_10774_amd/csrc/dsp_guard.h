@@ -47,10 +47,13 @@ __device__ __forceinline__ void atomic_max_pos(double* a, double v) {
 
 // time-slice bracket of patch q for time (tk, tt): exact slice or a < t < b;
 // with a grace (LOCAL mode) a time past q's newest slice is extrapolated from
-// the two newest slices a < b < t (w > 1)
+// the two newest slices a < b < t (w > 1).  With time order 2 (ticks modes)
+// a third slice c joins, the next older than a, else the next newer than b,
+// and the value is the quadratic s_a + w (s_b - s_a) + wc (s_c - s_a) with
+// the Lagrange weights.
 struct Bracket {
-  int64_t oa, ob;  // element offsets of the two slices
-  double w;        // weight of b (0 for an exact copy)
+  int64_t oa, ob, oc;  // element offsets of the slices (oc < 0: no third)
+  double w, wc;        // weights of b and c (0 for an exact copy)
 };
 __device__ inline Bracket bracket(const DevSet& S, int q, int64_t tk, double tt) {
   Bracket br;
@@ -71,6 +74,8 @@ __device__ inline Bracket bracket(const DevSet& S, int q, int64_t tk, double tt)
   }
   const int64_t base = S.slot_off[q];
   const int64_t V = S.slice_len[q];
+  br.oc = -1;
+  br.wc = 0.0;
   if (ie >= 0) {
     br.oa = br.ob = base + ie * V;
     br.w = 0.0;
@@ -100,6 +105,25 @@ __device__ inline Bracket bracket(const DevSet& S, int q, int64_t tk, double tt)
     br.w = (tt - S.stime[e_a]) / (S.stime[e_b] - S.stime[e_a]);
   else
     br.w = (double)(tk - S.sticks[e_a]) / (double)(S.sticks[e_b] - S.sticks[e_a]);
+  if (S.torder >= 2 && !S.exact_time) {
+    const int64_t ta = S.sticks[e_a], tb = S.sticks[e_b];
+    int ic = -1;
+    for (int s = 0; s < ns; ++s) {  // the next older than a
+      const int64_t e = (int64_t)q * ns + s;
+      if (S.svalid[e] && S.sticks[e] < ta && (ic < 0 || S.sticks[e] > S.sticks[(int64_t)q * ns + ic])) ic = s;
+    }
+    if (ic < 0)
+      for (int s = 0; s < ns; ++s) {  // else the next newer than b
+        const int64_t e = (int64_t)q * ns + s;
+        if (S.svalid[e] && S.sticks[e] > tb && (ic < 0 || S.sticks[e] < S.sticks[(int64_t)q * ns + ic])) ic = s;
+      }
+    if (ic >= 0) {
+      const double x = (double)(tk - ta), xb = (double)(tb - ta), xc = (double)(S.sticks[(int64_t)q * ns + ic] - ta);
+      br.oc = base + ic * V;
+      br.w = x * (x - xc) / (xb * (xb - xc));
+      br.wc = x * (x - xb) / (xc * (xc - xb));
+    }
+  }
   return br;
 }
 
@@ -108,7 +132,9 @@ __device__ __forceinline__ T tlerp(const T* slots, const Bracket& br, int64_t e)
   const T a = slots[br.oa + e];
   if (br.oa == br.ob) return a;
   const T b = slots[br.ob + e];
-  return a + (T)br.w * (b - a);
+  if (br.oc < 0) return a + (T)br.w * (b - a);
+  const T c = slots[br.oc + e];
+  return a + (T)br.w * (b - a) + (T)br.wc * (c - a);
 }
 
 // Cross-resolution guard value: mean over the target box of the source's
@@ -280,7 +306,7 @@ __device__ T fetch_elem(const DevSet& S, const T* slots, int p, int n, int64_t o
 // is first written into a padded per-entry buffer (k_gfill) and read there.
 __device__ __forceinline__ bool region_direct(const DevSet& S, int p, int key) {
   const int m0 = S.rbox_off[p * 108 + key], m1 = S.rbox_off[p * 108 + key + 1];
-  return m1 - m0 == 1 && S.boxes[m0].same;
+  return m1 - m0 == 1 && S.boxes[m0].same && S.torder < 2;  // the table blends two slices
 }
 
 // Per-workgroup table of the 108 regions of one patch (the four interior

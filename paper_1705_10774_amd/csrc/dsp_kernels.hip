@@ -659,7 +659,8 @@ __global__ void k_scan(DevSet S, int64_t T_end, int* __restrict__ list, int* __r
   // it is not newer than the neighbour (implied when g = 0)
   const int ns = S.nslots;
   const int64_t ob = (int64_t)p * ns;
-  const int oldest = (S.cur[p] + 1) % ns, after = (S.cur[p] + 2) % ns;
+  // (with time order 2 the slice before a bracket is read too: two are kept)
+  const int oldest = (S.cur[p] + 1) % ns, after = (S.cur[p] + 1 + (S.torder > 1 ? 2 : 1)) % ns;
   const int64_t t_after = S.svalid[ob + oldest] ? S.sticks[ob + after] : INT64_MIN;
   for (int m = S.nb_off[p]; m < S.nb_off[p + 1]; ++m) {
     const int q = S.nb_idx[m];

@@ -481,6 +481,8 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
     return fail(DSP_EINVAL, "a grace needs LOCAL time steps and at least 3 slots");
   if (!(c.eta >= 0.0) || !(c.gamma_ad >= 0.0) || (c.gamma_ad > 0.0 && !(c.rho_ion > 0.0)))
     return fail(DSP_EINVAL, "invalid non-ideal parameters");
+  if (c.torder < 0 || c.torder > 2 || (c.torder == 2 && c.nslots < 3))
+    return fail(DSP_EINVAL, "time order must be 1 or 2 (2 needs at least 3 slots)");
   if (c.dt_mode == DSP_DT_FIXED && !(c.dt_fixed > 0.0)) return fail(DSP_EINVAL, "dt_fixed must be positive");
   for (int d = 0; d < 3; ++d)
     if (c.periodic[d] != 1) return fail(DSP_EINVAL, "only periodic boxes are supported");
@@ -589,7 +591,7 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
       for (int k = 0; k < 108; ++k) {
         if (k % 27 == 13) continue;
         const int m0 = rbox_off[p * 108 + k], m1 = rbox_off[p * 108 + k + 1];
-        if (!(m1 - m0 == 1 && boxes[m0].same)) ++ngen;
+        if (!(m1 - m0 == 1 && boxes[m0].same) || cfg->torder >= 2) ++ngen;
       }
     S->any_generic = ngen > 0;
     if (getenv("DSP_DEBUG")) fprintf(stderr, "dsp_create: %d guard regions need the padded buffer\n", ngen);
@@ -686,6 +688,7 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
   D.gamma_ad = c.gamma_ad;
   D.rho_i = c.rho_ion;
   D.nonideal = (c.eta > 0.0 || c.gamma_ad > 0.0) ? 1 : 0;
+  D.torder = c.torder;
   auto up = [&](const void* h, size_t bytes) -> void* {
     void* d = A(bytes);
     if (d && bytes) (void)hipMemcpy(d, h, bytes, hipMemcpyHostToDevice);
@@ -950,7 +953,7 @@ int dsp_advance_to_plain(dsp_set* s, double t_end) {
   // readiness as in the scan kernel: Eq. (1) with the grace, and a free slot
   auto ready = [&](int p) {
     const size_t ob = (size_t)p * ns;
-    const int oldest = (cur[p] + 1) % ns, after = (cur[p] + 2) % ns;
+    const int oldest = (cur[p] + 1) % ns, after = (cur[p] + 1 + (s->cfg.torder > 1 ? 2 : 1)) % ns;
     const int64_t t_after = valid[ob + oldest] ? sticks[ob + after] : INT64_MIN;
     for (int q : s->nbors[p]) {
       int64_t g = 0;

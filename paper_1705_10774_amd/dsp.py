@@ -34,7 +34,7 @@ class dsp_config(C.Structure):
                 ("kmax", C.c_int32), ("nslots", C.c_int32), ("nguard", C.c_int32),
                 ("limiter", C.c_int32), ("prec", C.c_int32), ("dt_mode", C.c_int32),
                 ("periodic", C.c_int32 * 3), ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3),
-                ("eta", C.c_double), ("gamma_ad", C.c_double), ("rho_ion", C.c_double)]
+                ("eta", C.c_double), ("gamma_ad", C.c_double), ("rho_ion", C.c_double), ("torder", C.c_int32)]
 
 
 class dsp_patch_desc(C.Structure):
@@ -100,7 +100,7 @@ def _dp(a):
 def make_config(cfg) -> dsp_config:
     c = dsp_config()
     for f in ("gamma", "courant", "dt_base", "dt_fixed", "grace", "p_floor", "kmax", "nslots",
-              "nguard", "limiter", "prec", "dt_mode", "eta", "gamma_ad", "rho_ion"):
+              "nguard", "limiter", "prec", "dt_mode", "eta", "gamma_ad", "rho_ion", "torder"):
         setattr(c, f, getattr(cfg, f))
     for d in range(3):
         c.periodic[d] = int(cfg.periodic[d])
