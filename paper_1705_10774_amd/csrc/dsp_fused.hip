@@ -187,16 +187,14 @@ __global__ __launch_bounds__(256) void k_gfill(DevSet S, const int* __restrict__
 // ---------------------------------------------------------------------------
 // Courant rate and pressure accounting over the padded cells [-2, n+1]^3
 
-// Signal-speed sum of padded cell (i, j, k) divided by dx (0 for a cell that
-// fails the checks); sets the error bits and counts floor hits.  Always IEEE
-// arithmetic: the level of the step follows from it.
+// Signal-speed sum over the three directions, sum_d (|v_d| + c_f,d), of a
+// cell with primitives w (0 for a cell that fails the checks); sets the error
+// bits and counts floor hits.  Always IEEE arithmetic: the level of the step
+// follows from it.  The Courant rate is the sum divided by dx.
 template <class T>
-__device__ __forceinline__ double cell_rate(const DevSet& S, const PatchCtx<T>& c, const RegionTab<T>& rt, int i,
-                                            int j, int k) {
-  T w[8], bxl, byl, bzl;
-  load_cell(c, rt, i, j, k, T(S.gamma), T(0), w, bxl, byl, bzl);
+__device__ __forceinline__ T cell_sum(const DevSet& S, const T* w) {
   T pr = w[4];
-  double s = 0.0;
+  T sum = T(0);
   if (!isfinite(w[0]) || !isfinite(pr)) {
     atomicOr(S.err, ERR_NONFINITE);
   } else if (!(w[0] > T(0))) {
@@ -214,14 +212,72 @@ __device__ __forceinline__ double cell_rate(const DevSet& S, const PatchCtx<T>& 
       const T ir = T(1) / w[0];
       const T a2 = T(S.gamma) * pr * ir;
       const T bb = (w[5] * w[5] + w[6] * w[6] + w[7] * w[7]) * ir;
-      T sum = fabs(w[1]) + fast_speed(a2, bb, (w[6] * w[6] + w[7] * w[7]) * ir);
+      sum = fabs(w[1]) + fast_speed(a2, bb, (w[6] * w[6] + w[7] * w[7]) * ir);
       sum = sum + (fabs(w[2]) + fast_speed(a2, bb, (w[7] * w[7] + w[5] * w[5]) * ir));
       sum = sum + (fabs(w[3]) + fast_speed(a2, bb, (w[5] * w[5] + w[6] * w[6]) * ir));
-      s = (double)sum / S.dx[c.p];
-      if (!isfinite(s)) atomicOr(S.err, ERR_NONFINITE);
+      if (!isfinite(sum)) atomicOr(S.err, ERR_NONFINITE);
     }
   }
+  return sum;
+}
+
+// Courant rate of padded cell (i, j, k) through the region table
+template <class T>
+__device__ __forceinline__ double cell_rate(const DevSet& S, const PatchCtx<T>& c, const RegionTab<T>& rt, int i,
+                                            int j, int k) {
+  T w[8], bxl, byl, bzl;
+  load_cell(c, rt, i, j, k, T(S.gamma), T(0), w, bxl, byl, bzl);
+  const double s = (double)cell_sum(S, w) / S.dx[c.p];
+  if (!isfinite(s)) atomicOr(S.err, ERR_NONFINITE);
   return s;
+}
+
+// Signal-speed sum of interior cell (i, j, k), read straight from the patch's
+// own slice
+template <class T>
+__device__ __forceinline__ T interior_sum(const DevSet& S, const PatchCtx<T>& c, int i, int j, int k) {
+  using gptr = const T __attribute__((address_space(1)))*;
+  const gptr u = (gptr)c.ownp;
+  const int n = c.n;
+  const int64_t e = ((int64_t)k * n + j) * n + i, n3 = (int64_t)n * n * n, nf = (int64_t)n * n * (n + 1);
+  const int64_t fx = 5 * n3 + ((int64_t)k * n + j) * (n + 1) + i;
+  const int64_t fy = 5 * n3 + nf + ((int64_t)k * (n + 1) + j) * n + i;
+  const int64_t fz = 5 * n3 + 2 * nf + ((int64_t)k * n + j) * n + i;
+  T w[8];
+  prim_of<T>(u[e], u[n3 + e], u[2 * n3 + e], u[3 * n3 + e], u[4 * n3 + e], T(0.5) * (u[fx] + u[fx + 1]),
+             T(0.5) * (u[fy] + u[fy + n]), T(0.5) * (u[fz] + u[fz + (int64_t)n * n]), T(S.gamma), T(0), w);
+  return cell_sum(S, w);
+}
+
+// Padded coordinates of entry r of the two-layer guard shell around an n^3
+// interior (N = n + 4): the two full planes below, the rings of the n
+// interior planes, the two full planes above.
+__device__ __forceinline__ void shell_cell(int r, int n, int& i, int& j, int& k) {
+  const int N = n + 4, N2 = N * N, ring = N2 - n * n;
+  if (r < 2 * N2 || r >= 2 * N2 + n * ring) {
+    const int q = r < 2 * N2 ? r : r - n * ring;  // planes -2, -1 | n, n + 1
+    k = q / N2 - 2 + (r < 2 * N2 ? 0 : n);
+    const int m = q % N2;
+    j = m / N - 2;
+    i = m % N - 2;
+    return;
+  }
+  const int q = r - 2 * N2;
+  k = q / ring;
+  int m = q % ring;
+  if (m < 2 * N) {  // rows -2, -1
+    j = m / N - 2;
+    i = m % N - 2;
+  } else if (m < 2 * N + 4 * n) {  // rows 0 .. n-1: two cells on each side
+    m -= 2 * N;
+    j = m / 4;
+    const int s = m % 4;
+    i = s < 2 ? s - 2 : n + s - 2;
+  } else {  // rows n, n + 1
+    m -= 2 * N + 4 * n;
+    j = n + m / N;
+    i = m % N - 2;
+  }
 }
 
 // largest value over the workgroup (red: one slot per wavefront)
@@ -269,14 +325,27 @@ __global__ __launch_bounds__(256) void k_courant(DevSet S, const int* __restrict
 template <class T>
 __device__ double fused_local_dt(const DevSet& S, const PatchCtx<T>& c, const RegionTab<T>& rt, const StepPtr& st,
                                  int bidx, int tid, int nthr, double* red) {
-  const int N = c.n + 4;
-  double s = 0.0;
+  // The largest signal-speed sum, divided by dx once: division by a positive
+  // number is monotonic, so this is the largest of the per-cell rates.
+  const int n = c.n, N = n + 4;
+  T ms = T(0);
 #pragma unroll 4
-  for (int cid = tid; cid < N * N * N; cid += nthr) {
-    const double v = cell_rate(S, c, rt, cid % N - 2, (cid / N) % N - 2, cid / (N * N) - 2);
-    s = v > s ? v : s;
+  for (int cid = tid; cid < n * n * n; cid += nthr) {
+    const T v = interior_sum(S, c, cid % n, (cid / n) % n, cid / (n * n));
+    ms = v > ms ? v : ms;
   }
-  const double m = wg_max(s, red, tid, nthr);
+  const int nshell = N * N * N - n * n * n;
+#pragma unroll 2
+  for (int r = tid; r < nshell; r += nthr) {
+    int i, j, k;
+    shell_cell(r, n, i, j, k);
+    T w[8], bxl, byl, bzl;
+    load_cell(c, rt, i, j, k, T(S.gamma), T(0), w, bxl, byl, bzl);
+    const T v = cell_sum(S, w);
+    ms = v > ms ? v : ms;
+  }
+  const double m = wg_max((double)ms, red, tid, nthr) / S.dx[c.p];
+  if (tid == 0 && !isfinite(m)) atomicOr(S.err, ERR_NONFINITE);
   int k = level_for(S, m, S.ticks[c.p]);
   if (k > S.kmax) {
     if (tid == 0) atomicOr(S.err, ERR_KMAX);
