@@ -40,7 +40,7 @@ class _Cfg(C.Structure):
 
 class _Desc(C.Structure):
     _fields_ = [("origin", C.c_double * 3), ("size", C.c_double * 3), ("n", C.c_int32),
-                ("level", C.c_int32)]
+                ("level", C.c_int32), ("flags", C.c_int32)]
 
 
 def lib():
@@ -110,6 +110,7 @@ def make_descs(patches):
             arr[i].size[d] = p.size
         arr[i].n = p.n
         arr[i].level = p.level
+        arr[i].flags = 1 if p.frozen else 0
     return arr
 
 

@@ -73,6 +73,7 @@ template <class R> struct PatchT {
   uint64_t khash = KHASH0;
   std::vector<int8_t> klog;
   std::vector<int> nbors;
+  bool frozen = false;  // boundary patch: never updated, its slice holds at every time
 };
 
 template <class R> struct SetT {
@@ -185,6 +186,11 @@ template <class R> struct SetT {
   int bracket2(int q, int64_t tk, double tt, int& sa, int& sb, double& w) const {
     const PatchT<R>& Q = p[q];
     int ns = (int)Q.slot.size();
+    if (Q.frozen) {  // a boundary value: the same at every time
+      sa = sb = Q.cur;
+      w = 0.0;
+      return 0;
+    }
     sa = sb = -1;
     for (int s = 0; s < ns; ++s) {
       if (!Q.svalid[s]) continue;
@@ -587,11 +593,12 @@ template <class R> struct SetT {
   }
   bool ready(int q, int64_t T) const {
     const PatchT<R>& P = p[q];
-    if (P.ticks >= T) return false;
+    if (P.frozen || P.ticks >= T) return false;
     const int ns = (int)P.slot.size();
     // with time order 2 the slice before a bracket is read too: keep two
     const int oldest = (P.cur + 1) % ns, after = (P.cur + 1 + std::max(1, cfg.torder)) % ns;
     for (int s : P.nbors) {
+      if (p[s].frozen) continue;  // boundary patches never lag
       const int64_t g = (int64_t)std::floor(cfg.grace * (double)last_step(s));
       if (P.ticks > p[s].ticks + g) return false;
       if (P.svalid[oldest] && P.sticks[after] > p[s].ticks) return false;
@@ -611,7 +618,7 @@ template <class R> struct SetT {
       R_.clear();
       bool done = true;
       for (int q = 0; q < np_; ++q) {
-        if (p[q].ticks < T) done = false;
+        if (!p[q].frozen && p[q].ticks < T) done = false;
         if (ready(q, T)) R_.push_back(q);
       }
       if (done) return 0;
@@ -736,6 +743,10 @@ static int build_set_common(const orc_config* cfg, const orc_patch_desc* pd, int
   for (int dd = 0; dd < 3; ++dd)
     if (!c.periodic[dd]) return fail(ORC_EINVAL, "only periodic boxes are supported");
   d.assign(pd, pd + npatch);
+  int nactive = 0;
+  for (auto& q : d) nactive += (q.flags & 1) ? 0 : 1;
+  if (nactive == 0) return fail(ORC_EINVAL, "every patch is a boundary patch");
+  if (nactive < npatch && c.dt_mode != 0) return fail(ORC_EINVAL, "boundary patches need LOCAL time steps");
   for (auto& q : d)
     if (q.n < 4 || !(q.size[0] > 0.0) || q.size[0] != q.size[1] || q.size[0] != q.size[2])
       return fail(ORC_EINVAL, "patches must be cubic with n >= 4");
@@ -785,6 +796,7 @@ template <class R> static int make_set(const orc_config& c, const std::vector<or
     PatchT<R>& P = s.p[q];
     P.n = d[q].n;
     P.level = d[q].level;
+    P.frozen = (d[q].flags & 1) != 0;
     P.dx = d[q].size[0] / d[q].n;
     if (!tolat(d[q].size[0], P.len)) return fail(ORC_EINVAL, "patch size not on the lattice");
     P.dxl = P.len / P.n;
@@ -983,8 +995,10 @@ int orc_stats(const orc_set* h, double out[16]) {
                        (u[S.face(2, i, j, k + 1)] - u[S.face(2, i, j, k)]);
           divmax = std::max(divmax, std::fabs(div) / P.dx);
         }
-    tmin = std::min(tmin, P.t);
-    tmax = std::max(tmax, P.t);
+    if (!P.frozen) {
+      tmin = std::min(tmin, P.t);
+      tmax = std::max(tmax, P.t);
+    }
   }
   out[9] = divmax;
   out[10] = (double)s.cnt.floor_hits;

@@ -38,9 +38,12 @@ typedef struct {
   int32_t torder;
 } orc_config;
 
+/* flags: bit 0 = boundary patch (never updated; its one slice is the value
+ * at every time, and readiness ignores it; LOCAL mode only) */
 typedef struct {
   double origin[3], size[3];
   int32_t n, level;
+  int32_t flags;
 } orc_patch_desc;
 
 typedef struct orc_set orc_set;

@@ -57,6 +57,7 @@ class Patch:
     size: float
     n: int
     level: int = 0
+    frozen: bool = False  # boundary patch: never updated, its state holds at every time
 
 
 @dataclasses.dataclass
@@ -349,6 +350,35 @@ def field_1d(kind="beltrami", npd=2, n=16, B0=1.0, b=0.1, p0=1.0, eta=0.0, gamma
     cfg = Config(dt_mode=mode, dt_fixed=dt_fixed, dt_base=dt_base, prec=prec, eta=eta, gamma_ad=gamma_ad,
                  rho_ion=rho_ion)
     return Problem(f"{kind}_1d", cfg, patches, U, t_end, extra={"B0": B0, "b": b, "p0": p0})
+
+
+def cshock(pre, post, gamma, eta=0.0, gamma_ad=0.0, rho_ion=1.0, n=16, npatch=5, size=0.2, dt_base=2.5e-4,
+           t_end=1.0, prec=F64):
+    """A stationary shock along x between two states (rho, vx, vy, Bx, By, P)
+    of the shock frame: a row of npatch patches of size `size` (n^3 cells,
+    uniform in y and z) with the upstream state left of the middle of the
+    row and the downstream state right of it, between two boundary patches
+    that hold the upstream (left) and downstream (right) state."""
+    patches, box = row(npatch + 2, n, length=size * (npatch + 2))
+    patches = [Patch(q.origin, q.size, q.n, frozen=(m == 0 or m == npatch + 1)) for m, q in enumerate(patches)]
+    xm = size * (1 + npatch / 2.0)
+    rho, vel, pres, bf = [], [], [], []
+    for q in patches:
+        x = cell_coords(q)[0]
+        xf = face_coords(q, 0)[0]
+        up = (x < xm)[None, None, :]
+        sel = lambda a, b: np.broadcast_to(np.where(up, a, b), (q.n,) * 3).copy()
+        rho.append(sel(pre[0], post[0]))
+        vel.append([sel(pre[1], post[1]), sel(pre[2], post[2]), np.zeros((q.n,) * 3)])
+        pres.append(sel(pre[5], post[5]))
+        bx = np.broadcast_to(np.where(xf < xm, pre[3], post[3])[None, None, :], (q.n, q.n, q.n + 1)).copy()
+        by = np.broadcast_to(np.where(up, pre[4], post[4]), (q.n, q.n + 1, q.n)).copy()
+        bz = np.zeros((q.n + 1, q.n, q.n))
+        bf.append((bx, by, bz))
+    U = assemble(patches, rho, vel, pres, bf, gamma)
+    cfg = Config(gamma=gamma, dt_mode=DT_LOCAL, dt_base=dt_base, prec=prec, eta=eta, gamma_ad=gamma_ad,
+                 rho_ion=rho_ion, box_hi=box)
+    return Problem("cshock", cfg, patches, U, t_end, extra={"pre": pre, "post": post, "xm": xm})
 
 
 def cfg1_alfven(prec=F64):
