@@ -185,6 +185,27 @@ def main():
         out["adjoint"] = {"workload": "64 patches of 16^3, 32 fixed FP64 steps, checkpoints every 8",
                           "forward_ms": (t1 - t0) * 1e3, "adjoint_ms": (t2 - t1) * 1e3,
                           "adjoint_over_forward": (t2 - t1) / (t1 - t0)}
+        # uneven patches at full size (4096 patches of 16^3, 24^3 or 32^3,
+        # levels 0..7; two-by-two tiles and a separate Courant pass for the
+        # larger patches): FP32, the first dt_base, after a warm-up pass
+        pr3 = I.cfg3_uneven(prec=I.F32)
+        U3 = torch.from_numpy(pr3.U0).to(dev).float()
+        s = dsp.PatchSet(pr3.cfg, pr3.patches)
+        del pr3.U0
+        s.init_device(U3.data_ptr())
+        s.advance_to(pr3.cfg.dt_base)
+        s.init_device(U3.data_ptr())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.advance_to(pr3.cfg.dt_base)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        upd3 = s.stats()[0]
+        s.close()
+        del U3
+        out["cfg3_fp32"] = {"workload": "cfg3: 4096 patches of 16^3/24^3/32^3, t 0 -> dt_base",
+                            "value": upd3 / (t1 - t0), "unit": "cell-updates/s", "updates": upd3,
+                            "ms": (t1 - t0) * 1e3}
         # plain device copy bandwidth on this GPU (256 MiB, read + write)
         a = torch.ones(64 * 1024 * 1024, device=dev)
         b = torch.empty_like(a)

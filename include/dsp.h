@@ -109,10 +109,16 @@ typedef struct {
 /* One cubic patch: origin, edge length (size[0] == size[1] == size[2]),
  * interior cells n per edge (n >= 4), refinement level (informational).
  * Origins and sizes must lie on a common lattice: n/size integral and every
- * origin a multiple of 1/(2 lcm(n/size)). */
+ * origin a multiple of 1/(2 lcm(n/size)).
+ * flags: DSP_PATCH_FROZEN marks a boundary patch (the boundary tasks of
+ * Sec. 3C, as a fixed state): it is never updated, its one slice is the
+ * guard value at every time, and readiness ignores it.  LOCAL mode only;
+ * at least one patch must be updated. */
+enum { DSP_PATCH_FROZEN = 1 };
 typedef struct {
   double origin[3], size[3];
   int32_t n, level;
+  int32_t flags;
 } dsp_patch_desc;
 
 /* Optional device allocator (e.g. a framework's caching allocator).

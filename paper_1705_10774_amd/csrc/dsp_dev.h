@@ -46,6 +46,7 @@ struct DevSet {
   const int64_t* dxl;     // lattice cell size
   const int64_t* slot_off;   // element offset of slot 0 of each patch
   const int64_t* slice_len;  // values per slice
+  const int8_t* frozen;      // boundary patch: never updated, its slice holds at every time
   // time bookkeeping (FP64 + integer ticks)
   int* cur;
   int64_t* ticks;

@@ -58,6 +58,12 @@ struct Bracket {
 __device__ inline Bracket bracket(const DevSet& S, int q, int64_t tk, double tt) {
   Bracket br;
   const int ns = S.nslots;
+  if (S.frozen[q]) {  // a boundary value: the same at every time
+    br.oa = br.ob = S.slot_off[q] + (int64_t)S.cur[q] * S.slice_len[q];
+    br.oc = -1;
+    br.w = br.wc = 0.0;
+    return br;
+  }
   int ia = -1, ib = -1, ie = -1;
   for (int s = 0; s < ns; ++s) {
     const int64_t e = (int64_t)q * ns + s;

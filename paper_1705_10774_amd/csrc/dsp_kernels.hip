@@ -650,6 +650,7 @@ __global__ void k_scan(DevSet S, int64_t T_end, int* __restrict__ list, int* __r
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= S.npatch) return;
   if (*S.err) return;  // an error stops the scheduling: later rounds find nothing to do
+  if (S.frozen[p]) return;  // boundary patches never update
   const int64_t t = S.ticks[p];
   if (t >= T_end) return;
   atomicAdd(counters + 1, 1);  // not yet done
@@ -664,6 +665,7 @@ __global__ void k_scan(DevSet S, int64_t T_end, int* __restrict__ list, int* __r
   const int64_t t_after = S.svalid[ob + oldest] ? S.sticks[ob + after] : INT64_MIN;
   for (int m = S.nb_off[p]; m < S.nb_off[p + 1]; ++m) {
     const int q = S.nb_idx[m];
+    if (S.frozen[q]) continue;  // and never lag
     const int64_t tq = S.ticks[q];
     int64_t g = 0;
     if (S.grace > 0.0 && S.steps[q] > 0) {

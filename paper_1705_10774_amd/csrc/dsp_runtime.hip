@@ -53,6 +53,7 @@ int64_t ceildiv(int64_t a, int64_t b) { return -floordiv(-a, b); }
 
 struct HPatch {
   int n, level;
+  bool frozen;
   double dx;
   int64_t lo[3], len, dxl;
   int64_t V, slot_off;
@@ -470,6 +471,13 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
   if (!out) return fail(DSP_EINVAL, "null output handle");
   *out = nullptr;
   if (!cfg || !pd || npatch <= 0) return fail(DSP_EINVAL, "null argument or no patches");
+  {
+    int nactive = 0;
+    for (int p = 0; p < npatch; ++p) nactive += (pd[p].flags & DSP_PATCH_FROZEN) ? 0 : 1;
+    if (nactive == 0) return fail(DSP_EINVAL, "every patch is a boundary patch");
+    if (nactive < npatch && cfg->dt_mode != DSP_DT_LOCAL)
+      return fail(DSP_EINVAL, "boundary patches need LOCAL time steps");
+  }
   const dsp_config c = *cfg;
   if (!(c.gamma > 1.0) || !(c.courant > 0.0) || c.nguard < 2 || c.nguard > 3 || c.nslots < 2 ||
       c.nslots > 8 || c.kmax < 0 || c.kmax > 40 || c.limiter != 0 || !(c.grace >= 0.0 && c.grace < 1.0) ||
@@ -524,6 +532,7 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
     HPatch& H = S->P[p];
     H.n = pd[p].n;
     H.level = pd[p].level;
+    H.frozen = (pd[p].flags & DSP_PATCH_FROZEN) != 0;
     H.dx = pd[p].size[0] / pd[p].n;
     if (!tolat(pd[p].size[0], scale, H.len)) return fail(DSP_EINVAL, "patch size not on the lattice");
     H.dxl = H.len / H.n;
@@ -660,10 +669,12 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
 
   // metadata arrays
   std::vector<int> hn(npatch);
+  std::vector<int8_t> hfz(npatch);
   std::vector<double> hdx(npatch);
   std::vector<int64_t> hlo(3 * npatch), hlen(npatch), hdxl(npatch), hoff(npatch), hV(npatch);
   for (int p = 0; p < npatch; ++p) {
     hn[p] = s->P[p].n;
+    hfz[p] = s->P[p].frozen ? 1 : 0;
     hdx[p] = s->P[p].dx;
     for (int d = 0; d < 3; ++d) hlo[3 * p + d] = s->P[p].lo[d];
     hlen[p] = s->P[p].len;
@@ -695,6 +706,7 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
     return d;
   };
   D.n = (const int*)up(hn.data(), sizeof(int) * npatch);
+  D.frozen = (const int8_t*)up(hfz.data(), (size_t)npatch);
   D.dx = (const double*)up(hdx.data(), sizeof(double) * npatch);
   D.lo = (const int64_t*)up(hlo.data(), sizeof(int64_t) * 3 * npatch);
   D.len = (const int64_t*)up(hlen.data(), sizeof(int64_t) * npatch);
@@ -952,10 +964,12 @@ int dsp_advance_to_plain(dsp_set* s, double t_end) {
   get(valid.data(), s->D.svalid, (size_t)np * ns);
   // readiness as in the scan kernel: Eq. (1) with the grace, and a free slot
   auto ready = [&](int p) {
+    if (s->P[p].frozen) return false;
     const size_t ob = (size_t)p * ns;
     const int oldest = (cur[p] + 1) % ns, after = (cur[p] + 1 + (s->cfg.torder > 1 ? 2 : 1)) % ns;
     const int64_t t_after = valid[ob + oldest] ? sticks[ob + after] : INT64_MIN;
     for (int q : s->nbors[p]) {
+      if (s->P[q].frozen) continue;
       int64_t g = 0;
       if (s->cfg.grace > 0.0 && steps[q] > 0) {
         const int prev = (cur[q] + ns - 1) % ns;
@@ -971,7 +985,7 @@ int dsp_advance_to_plain(dsp_set* s, double t_end) {
     int best = -1;
     bool done = true;
     for (int p = 0; p < np; ++p) {
-      if (ticks[p] >= T) continue;
+      if (s->P[p].frozen || ticks[p] >= T) continue;
       done = false;
       if (ready(p) && (best < 0 || ticks[p] < ticks[best])) best = p;
     }
@@ -1062,8 +1076,15 @@ int dsp_stats(const dsp_set* cs, double out[16]) {
   out[11] = (double)cnt[1];
   out[12] = s->last_ms;
   out[13] = (double)s->rounds;
-  out[14] = *std::min_element(tc.begin(), tc.end());
-  out[15] = *std::max_element(tc.begin(), tc.end());
+  // times of the updated patches (boundary patches stay at t0)
+  double tmin = INFINITY, tmax = -INFINITY;
+  for (int p = 0; p < s->np; ++p)
+    if (!s->P[p].frozen) {
+      tmin = std::min(tmin, tc[p]);
+      tmax = std::max(tmax, tc[p]);
+    }
+  out[14] = tmin;
+  out[15] = tmax;
   return 0;
 }
 

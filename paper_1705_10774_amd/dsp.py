@@ -39,7 +39,7 @@ class dsp_config(C.Structure):
 
 class dsp_patch_desc(C.Structure):
     _fields_ = [("origin", C.c_double * 3), ("size", C.c_double * 3), ("n", C.c_int32),
-                ("level", C.c_int32)]
+                ("level", C.c_int32), ("flags", C.c_int32)]
 
 
 class DspError(RuntimeError):
@@ -117,6 +117,7 @@ def make_descs(patches):
             arr[i].size[d] = p.size
         arr[i].n = p.n
         arr[i].level = p.level
+        arr[i].flags = 1 if p.frozen else 0
     return arr
 
 

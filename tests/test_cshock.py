@@ -82,3 +82,47 @@ def test_cshock_levels_and_boundary_patches(orc, case):
         assert len(set(k)) == 1
     else:
         assert k[0] == k[1] and k[2] == k[3] == k[4] == k[0] + 1
+
+
+def steady_isothermal_cshock(case="ad_iso", x_end=1.0):
+    """Steady isothermal C-shock with ambipolar diffusion, from the upstream
+    state of the table: with j = rho u, the x- and y-momentum fluxes and the
+    z electric field uniform (B_x fixed, B_z = v_z = 0, sound speed
+    c^2 = P / rho), u, v and rho follow from B_y algebraically, and
+    dB_y/dx = (u B_y - v B_x - E_0) / eta_AD with eta_AD = B^2 / (gamma_AD rho
+    rho_i) (Eq. AD for a current along z).  Returns x and B_y along the
+    solution, started a hair above the upstream state."""
+    from scipy.integrate import solve_ivp
+    c = TABLE[case]
+    rho0, u0, v0, bx, by0, p0 = c["pre"]
+    c2 = p0 / rho0
+    j = rho0 * u0
+    px = rho0 * u0 * u0 + p0 + 0.5 * by0 * by0
+    py = rho0 * u0 * v0 - bx * by0
+    e0 = u0 * by0 - v0 * bx
+
+    def state(by):
+        v = (py + bx * by) / j
+        a = px - 0.5 * by * by
+        u = (a + math.sqrt(max(a * a - 4.0 * j * j * c2, 0.0))) / (2.0 * j)  # the supersonic branch
+        return u, v, j / u
+
+    def rhs(x, y):
+        u, v, rho = state(y[0])
+        eta = (bx * bx + y[0] * y[0]) / (c["gamma_ad"] * rho * c["rho_ion"])
+        return [(u * y[0] - v * bx - e0) / eta]
+
+    sol = solve_ivp(rhs, [0.0, x_end], [by0 + 1e-6], max_step=1e-3, rtol=1e-10, atol=1e-12)
+    return sol.t, sol.y[0], state
+
+
+def test_steady_cshock_ends_in_the_table_state():
+    """The steady isothermal C-shock, integrated from the table's upstream
+    state, ends in the table's downstream state (to its printed digits)."""
+    x, by, state = steady_isothermal_cshock()
+    u, v, rho = state(by[-1])
+    post = TABLE["ad_iso"]["post"]
+    got = [rho, u, v, by[-1]]
+    want = [post[0], post[1], post[2], post[4]]
+    print("downstream of the steady C-shock", got, "table", want)
+    assert all(abs(a - b) <= 1e-4 * max(1.0, abs(b)) for a, b in zip(got, want))
