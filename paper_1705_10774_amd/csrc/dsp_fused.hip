@@ -138,48 +138,99 @@ __device__ __attribute__((noinline)) FaceStates<T> fallback_states(const PatchCt
 
 // ---------------------------------------------------------------------------
 // Guard regions that are not a single same-resolution box (several sources,
-// or another resolution): values written into the entry's padded buffer with
-// the generic box search, so the marching kernel reads every guard region
-// with one addressing rule.
+// or another resolution): values written into the entry's padded buffer, so
+// the marching kernel reads every guard region with one addressing rule.
+// One workgroup per (region, patch).  A box from a patch of another
+// resolution first interpolates the block of source values it reads (slope
+// neighbours included) in time into LDS, once per variable; every target
+// value then resamples from there, with the arithmetic of cross_value.
+
+constexpr int GSTAGE = 8192;  // staged source values per workgroup
 
 template <class T>
 __global__ __launch_bounds__(256) void k_gfill(DevSet S, const int* __restrict__ list, int count,
                                                const T* __restrict__ slots, T* __restrict__ pad,
                                                int64_t pad_stride) {
-  __shared__ Bracket br[MAXBOX];
+  __shared__ T stage[GSTAGE];
+  const int key = blockIdx.x;
   const int b = blockIdx.y;
   if (b >= live_count(S, count)) return;
   const int p = list[b];
+  const int comp = key / 27 - 1, reg = key % 27;
+  if (reg == 13 || region_direct(S, p, key)) return;
+  const int tid = threadIdx.x, nthr = blockDim.x;
   const int n = S.n[p], N = n + 4;
-  const int box0 = S.rbox_off[p * 108];
-  const int nbox = S.rbox_off[p * 108 + 108] - box0;
-  const int64_t own = S.slot_off[p] + (int64_t)S.cur[p] * S.slice_len[p];
-  for (int m = threadIdx.x; m < nbox; m += blockDim.x)
-    br[m] = bracket(S, S.boxes[box0 + m].q, S.ticks[p], S.tcur[p]);
-  __syncthreads();
+  const int nvar = comp < 0 ? 5 : 1;
+  const int m0 = S.rbox_off[p * 108 + key], m1 = S.rbox_off[p * 108 + key + 1];
+  const int64_t dxl = S.dxl[p];
   T* dst = pad + (int64_t)b * pad_stride;
-  for (int key = 0; key < 108; ++key) {
-    const int comp = key / 27 - 1, reg = key % 27;
-    if (reg == 13 || region_direct(S, p, key)) continue;
-    int lo[3], ext[3];
-    const int rr[3] = {reg % 3, (reg / 3) % 3, reg / 9};
-    for (int d = 0; d < 3; ++d) {
-      const int h = n + (comp == d ? 1 : 0);
-      lo[d] = rr[d] == 0 ? -2 : (rr[d] == 1 ? 0 : h);
-      ext[d] = rr[d] == 1 ? h : 2;
+  // lattice position of target element (i, j, k), in the source's periodic image
+  auto lattice = [&](const GBox& G, int i, int j, int k, int64_t* X) {
+    const int idx[3] = {i, j, k};
+    for (int d = 0; d < 3; ++d)
+      X[d] = S.lo[3 * p + d] + (int64_t)idx[d] * dxl + (d == comp ? 0 : dxl / 2) + G.wrap[d];
+  };
+  // an element of an earlier box of the region belongs to that box
+  auto earlier = [&](int m, int i, int j, int k) {
+    for (int mm = m0; mm < m; ++mm) {
+      const GBox& H = S.boxes[mm];
+      if (i >= H.lo[0] && i <= H.hi[0] && j >= H.lo[1] && j <= H.hi[1] && k >= H.lo[2] && k <= H.hi[2]) return true;
     }
-    const int nvar = comp < 0 ? 5 : 1;
-    const int cnt = ext[0] * ext[1] * ext[2] * nvar;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += gridDim.x * blockDim.x) {
-      int r = e;
-      const int i = lo[0] + r % ext[0];
-      r /= ext[0];
-      const int j = lo[1] + r % ext[1];
-      r /= ext[1];
-      const int k = lo[2] + r % ext[2];
-      const int var = r / ext[2];
-      const T v = fetch_elem(S, slots, p, n, own, box0, br, comp, var, i, j, k);
-      dst[(comp < 0) ? pcell(N, var, i, j, k) : pface(N, comp, i, j, k)] = v;
+    return false;
+  };
+  for (int m = m0; m < m1; ++m) {
+    const GBox G = S.boxes[m];
+    const Bracket br = bracket(S, G.q, S.ticks[p], S.tcur[p]);
+    const int ex = G.hi[0] - G.lo[0] + 1, ey = G.hi[1] - G.lo[1] + 1, ez = G.hi[2] - G.lo[2] + 1;
+    const int cnt = ex * ey * ez;
+    const int nq = S.n[G.q];
+    if (G.same) {
+      for (int e = tid; e < cnt * nvar; e += nthr) {
+        int r = e;
+        const int i = G.lo[0] + r % ex;
+        r /= ex;
+        const int j = G.lo[1] + r % ey;
+        r /= ey;
+        const int k = G.lo[2] + r % ez;
+        const int var = r / ez;
+        if (earlier(m, i, j, k)) continue;
+        const int qi = i + G.shift[0], qj = j + G.shift[1], qk = k + G.shift[2];
+        const int64_t se = (comp < 0) ? scell(nq, var, qi, qj, qk) : sface(nq, comp, qi, qj, qk);
+        dst[(comp < 0) ? pcell(N, var, i, j, k) : pface(N, comp, i, j, k)] = tlerp(slots, br, se);
+      }
+      continue;
+    }
+    int64_t Xlo[3], Xhi[3];
+    lattice(G, G.lo[0], G.lo[1], G.lo[2], Xlo);
+    lattice(G, G.hi[0], G.hi[1], G.hi[2], Xhi);
+    int r0[3], r1[3];
+    cross_source_range(S, G.q, comp, Xlo, Xhi, dxl, r0, r1);
+    const int sx = r1[0] - r0[0] + 1, sy = r1[1] - r0[1] + 1, sz = r1[2] - r0[2] + 1;
+    const bool staged = (int64_t)sx * sy * sz <= GSTAGE;
+    for (int var = 0; var < nvar; ++var) {
+      if (staged) {
+        __syncthreads();  // the previous variable's readers are done
+        for (int e = tid; e < sx * sy * sz; e += nthr) {
+          const int ii = r0[0] + e % sx, jj = r0[1] + (e / sx) % sy, kk = r0[2] + e / (sx * sy);
+          const int64_t se = (comp < 0) ? scell(nq, var, ii, jj, kk) : sface(nq, comp, ii, jj, kk);
+          stage[e] = tlerp(slots, br, se);
+        }
+        __syncthreads();
+      }
+      for (int e = tid; e < cnt; e += nthr) {
+        const int i = G.lo[0] + e % ex, j = G.lo[1] + (e / ex) % ey, k = G.lo[2] + e / (ex * ey);
+        if (earlier(m, i, j, k)) continue;
+        int64_t X[3];
+        lattice(G, i, j, k, X);
+        T v;
+        if (staged)
+          v = cross_value_from<T>(S, G.q, comp, X, dxl, [&](int a, int c, int d) -> T {
+            return stage[((d - r0[2]) * sy + (c - r0[1])) * sx + (a - r0[0])];
+          });
+        else
+          v = cross_value(S, slots, br, G.q, comp, var, X, dxl);
+        dst[(comp < 0) ? pcell(N, var, i, j, k) : pface(N, comp, i, j, k)] = v;
+      }
     }
   }
 }
@@ -1148,7 +1199,7 @@ int launch_fused(const DevSet& S, const int* list, int count, int nmax, T* slots
                   hipEvent_t ev0, hipEvent_t ev1) {
   const int N = nmax + 4;
   if (gfill)
-    hipLaunchKernelGGL(k_gfill<T>, dim3(4, count), dim3(256), 0, s, S, list, count, (const T*)slots, pad,
+    hipLaunchKernelGGL(k_gfill<T>, dim3(108, count), dim3(256), 0, s, S, list, count, (const T*)slots, pad,
                        pad_stride);
   const int tpa = (nmax + MT - 1) / MT;
   // a local step of single-tile patches takes its Courant rate and level
