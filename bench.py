@@ -52,6 +52,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-baselines", action="store_true", help="skip FP64, plain and CPU legs")
     ap.add_argument("--cpu-sample", type=int, default=64, help="dt_base units of the CPU sample")
+    ap.add_argument("--cfg3", action="store_true",
+                    help="only the full-size uneven configuration (FP32, t 0 -> dt_base per step)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 3 plain device copies of 256 MiB (scale for the FETCH_SIZE / "
                          "WRITE_SIZE counters)")
@@ -76,6 +78,36 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration": {"copies": 3, "bytes_each": a.numel() * 4}}), flush=True)
+        return
+
+    def run_cfg3(steps, warmup):
+        # uneven patches at full size (4096 patches of 16^3, 24^3 or 32^3,
+        # levels 0..7; two-by-two tiles and a separate Courant pass for the
+        # larger patches): FP32, each step t 0 -> dt_base from the
+        # device-resident initial state
+        pr3 = I.cfg3_uneven(prec=I.F32)
+        U3 = torch.from_numpy(pr3.U0).to(dev).float()
+        s = dsp.PatchSet(pr3.cfg, pr3.patches)
+        del pr3.U0
+        for _ in range(warmup):
+            s.init_device(U3.data_ptr())
+            s.advance_to(pr3.cfg.dt_base)
+        ms, upd3 = 0.0, 0.0
+        for _ in range(steps):
+            s.init_device(U3.data_ptr())
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.advance_to(pr3.cfg.dt_base)
+            torch.cuda.synchronize()
+            ms += (time.perf_counter() - t0) * 1e3
+            upd3 += s.stats()[0]
+        s.close()
+        return {"workload": "cfg3: 4096 patches of 16^3/24^3/32^3, t 0 -> dt_base",
+                "value": upd3 / (ms * 1e-3), "unit": "cell-updates/s", "updates_per_step": upd3 / steps,
+                "ms_per_step": ms / steps}
+
+    if args.cfg3:
+        print(json.dumps({"cfg3_fp32": run_cfg3(args.steps, args.warmup)}), flush=True)
         return
 
     def run_batched(prec, steps, warmup):
@@ -185,27 +217,7 @@ def main():
         out["adjoint"] = {"workload": "64 patches of 16^3, 32 fixed FP64 steps, checkpoints every 8",
                           "forward_ms": (t1 - t0) * 1e3, "adjoint_ms": (t2 - t1) * 1e3,
                           "adjoint_over_forward": (t2 - t1) / (t1 - t0)}
-        # uneven patches at full size (4096 patches of 16^3, 24^3 or 32^3,
-        # levels 0..7; two-by-two tiles and a separate Courant pass for the
-        # larger patches): FP32, the first dt_base, after a warm-up pass
-        pr3 = I.cfg3_uneven(prec=I.F32)
-        U3 = torch.from_numpy(pr3.U0).to(dev).float()
-        s = dsp.PatchSet(pr3.cfg, pr3.patches)
-        del pr3.U0
-        s.init_device(U3.data_ptr())
-        s.advance_to(pr3.cfg.dt_base)
-        s.init_device(U3.data_ptr())
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s.advance_to(pr3.cfg.dt_base)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        upd3 = s.stats()[0]
-        s.close()
-        del U3
-        out["cfg3_fp32"] = {"workload": "cfg3: 4096 patches of 16^3/24^3/32^3, t 0 -> dt_base",
-                            "value": upd3 / (t1 - t0), "unit": "cell-updates/s", "updates": upd3,
-                            "ms": (t1 - t0) * 1e3}
+        out["cfg3_fp32"] = run_cfg3(1, 1)
         # plain device copy bandwidth on this GPU (256 MiB, read + write)
         a = torch.ones(64 * 1024 * 1024, device=dev)
         b = torch.empty_like(a)
