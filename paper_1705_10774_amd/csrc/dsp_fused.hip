@@ -359,14 +359,29 @@ __global__ __launch_bounds__(256) void k_courant(DevSet S, const int* __restrict
   for (int m = threadIdx.x; m < 108; m += blockDim.x)
     region_tab_init(S, slots, c.ownp, pad + (int64_t)b * pad_stride, c.n + 4, c.p, rt, m);
   __syncthreads();
-  const int N = c.n + 4;
-  const int64_t cid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double s = 0.0;
-  if (cid < (int64_t)N * N * N)
-    s = cell_rate(S, c, rt, (int)(cid % N) - 2, (int)((cid / N) % N) - 2, (int)(cid / ((int64_t)N * N)) - 2);
-  const double m = wg_max(s, red, threadIdx.x, blockDim.x);
-  if (threadIdx.x == 0 && m > 0.0)
-    atomicMax((unsigned long long*)(smax + b), (unsigned long long)__double_as_longlong(m));
+  // several cells per thread (one table per workgroup): interior cells from
+  // the own slice, the guard shell through the table; the largest signal-speed
+  // sum, divided by dx once (monotonic: the largest per-cell rate)
+  const int n = c.n, N = n + 4;
+  const int first = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+  T ms = T(0);
+  for (int cid = first; cid < n * n * n; cid += stride) {
+    const T v = interior_sum(S, c, cid % n, (cid / n) % n, cid / (n * n));
+    ms = v > ms ? v : ms;
+  }
+  for (int r = first; r < N * N * N - n * n * n; r += stride) {
+    int i, j, k;
+    shell_cell(r, n, i, j, k);
+    T w[8], bxl, byl, bzl;
+    load_cell(c, rt, i, j, k, T(S.gamma), T(0), w, bxl, byl, bzl);
+    const T v = cell_sum(S, w);
+    ms = v > ms ? v : ms;
+  }
+  const double m = wg_max((double)ms, red, threadIdx.x, blockDim.x) / S.dx[c.p];
+  if (threadIdx.x == 0) {
+    if (!isfinite(m)) atomicOr(S.err, ERR_NONFINITE);
+    if (m > 0.0) atomicMax((unsigned long long*)(smax + b), (unsigned long long)__double_as_longlong(m));
+  }
 }
 
 // Local time step of a patch whose whole update is one workgroup (LOCAL
@@ -1208,7 +1223,8 @@ int launch_fused(const DevSet& S, const int* list, int count, int nmax, T* slots
   const int fuse_dt = (dt_kind == 0 && tpa == 1) ? 1 : 0;
   if (!fuse_dt) {
     (void)hipMemsetAsync(smax, 0, sizeof(double) * count, s);
-    hipLaunchKernelGGL(k_courant<T>, dim3((unsigned)(((int64_t)N * N * N + 255) / 256), count), dim3(256), 0, s, S,
+    const unsigned gx = (unsigned)std::max<int64_t>(1, ((int64_t)N * N * N + 2047) / 2048);  // ~8 cells per thread
+    hipLaunchKernelGGL(k_courant<T>, dim3(gx, count), dim3(256), 0, s, S,
                        list, count, (const T*)slots, (const T*)pad, pad_stride, smax);
     launch_dt(S, list, count, st, smax, s, dt_kind, t_end, clip);
   }
