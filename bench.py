@@ -52,6 +52,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-baselines", action="store_true", help="skip FP64, plain and CPU legs")
     ap.add_argument("--cpu-sample", type=int, default=64, help="dt_base units of the CPU sample")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="only the adjoint leg (64 patches of 16^3, 32 fixed FP64 steps)")
     ap.add_argument("--cfg3", action="store_true",
                     help="only the full-size uneven configuration (FP32, t 0 -> dt_base per step)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -105,6 +107,29 @@ def main():
         return {"workload": "cfg3: 4096 patches of 16^3/24^3/32^3, t 0 -> dt_base",
                 "value": upd3 / (ms * 1e-3), "unit": "cell-updates/s", "updates_per_step": upd3 / steps,
                 "ms_per_step": ms / steps}
+
+    def run_adjoint():
+        # adjoint: 64 patches of 16^3, 32 fixed FP64 steps, checkpoints every 8
+        pr5 = I.cfg5_adjoint(prec=I.F64)
+        s = dsp.PatchSet(pr5.cfg, pr5.patches)
+        U5 = torch.from_numpy(pr5.U0).to(dev)
+        s.fixed_steps_fwd(U5, pr5.nsteps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        UT5, ck5 = s.fixed_steps_fwd(U5, pr5.nsteps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s.fixed_steps_adj(ck5, torch.ones_like(UT5), pr5.nsteps)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        s.close()
+        return {"workload": "64 patches of 16^3, 32 fixed FP64 steps, checkpoints every 8",
+                "forward_ms": (t1 - t0) * 1e3, "adjoint_ms": (t2 - t1) * 1e3,
+                "adjoint_over_forward": (t2 - t1) / (t1 - t0)}
+
+    if args.adjoint:
+        print(json.dumps({"adjoint": run_adjoint()}), flush=True)
+        return
 
     if args.cfg3:
         print(json.dumps({"cfg3_fp32": run_cfg3(args.steps, args.warmup)}), flush=True)
@@ -200,23 +225,7 @@ def main():
         upd_global = s.stats()[0]
         s.close()
         out["local_dt_saving"] = upd_global / res32["updates"]
-        # adjoint: 64 patches of 16^3, 32 fixed FP64 steps, checkpoints every 8
-        pr5 = I.cfg5_adjoint(prec=I.F64)
-        s = dsp.PatchSet(pr5.cfg, pr5.patches)
-        U5 = torch.from_numpy(pr5.U0).to(dev)
-        s.fixed_steps_fwd(U5, pr5.nsteps)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        UT5, ck5 = s.fixed_steps_fwd(U5, pr5.nsteps)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        s.fixed_steps_adj(ck5, torch.ones_like(UT5), pr5.nsteps)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        s.close()
-        out["adjoint"] = {"workload": "64 patches of 16^3, 32 fixed FP64 steps, checkpoints every 8",
-                          "forward_ms": (t1 - t0) * 1e3, "adjoint_ms": (t2 - t1) * 1e3,
-                          "adjoint_over_forward": (t2 - t1) / (t1 - t0)}
+        out["adjoint"] = run_adjoint()
         out["cfg3_fp32"] = run_cfg3(1, 1)
         # plain device copy bandwidth on this GPU (256 MiB, read + write)
         a = torch.ones(64 * 1024 * 1024, device=dev)
