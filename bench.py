@@ -249,10 +249,28 @@ def main():
         t1 = time.perf_counter()
         ost = o.stats()
         o.close()
-        out["cpu_baseline"] = {"value": ost[0] / (t1 - t0), "unit": "cell-updates/s", "cores": cores,
+        # the same oracle on one thread, over the first 4 dt_base
+        o1 = oracle.OracleSet.from_problem(pr)
+        o1.set_order(2, 1, 1)
+        t2 = time.perf_counter()
+        o1.advance_to(4 * pr.cfg.dt_base)
+        t3 = time.perf_counter()
+        one = o1.stats()[0] / (t3 - t2)
+        o1.close()
+        model = ""
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+        rate = ost[0] / (t1 - t0)
+        out["cpu_baseline"] = {"value": rate, "unit": "cell-updates/s", "cores": cores,
                                "kind": "oracle",
                                "sample": f"cfg2 t 0 -> {args.cpu_sample} dt_base ({int(ost[0])} updates, "
-                                         f"{t1 - t0:.1f} s)"}
+                                         f"{t1 - t0:.1f} s)",
+                               "per_core": rate / cores, "one_thread": one, "cpu_model": model}
     print(json.dumps(out), flush=True)
 
 

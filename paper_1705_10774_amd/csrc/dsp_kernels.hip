@@ -644,7 +644,7 @@ __global__ void k_publish(DevSet S, const int* __restrict__ list, int count, Ste
 }
 
 // ---------------------------------------------------------------------------
-// k_scan: readiness of every patch (Eq. (1), g = 0) and the ready list.
+// k_scan: readiness of every patch (Eq. (1), with the grace) and the ready list.
 
 __global__ void k_scan(DevSet S, int64_t T_end, int* __restrict__ list, int* __restrict__ counters) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;

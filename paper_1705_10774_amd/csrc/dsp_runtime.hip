@@ -2,11 +2,12 @@
 // on an exact integer lattice, neighbour and guard-box tables, device memory,
 // the round driver of the dispatcher, and the C ABI declared in dsp.h.
 //
-// Dispatcher (Sec. 3B): a round scans every patch for readiness (Eq. (1)
-// with g = 0: no neighbour lags behind it), then updates the whole ready set
-// in one launch sequence and publishes it.  With g = 0 the updates of one
-// round never read a slot that another update of the round writes, so the
-// result does not depend on how the ready set is split or ordered.
+// Dispatcher (Sec. 3B): a round scans every patch for readiness (Eq. (1):
+// no neighbour lags behind it by more than the grace, and the slot the update
+// overwrites is no longer needed), then updates the whole ready set in one
+// launch sequence and publishes it.  The updates of one round never read a
+// slot that another update of the round writes, so the result does not
+// depend on how the ready set is split or ordered.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
