@@ -56,7 +56,8 @@ def test_struct_layout_matches_header(tmp_path):
 @pytest.mark.parametrize("bad", [dict(grace=1.0), dict(grace=-0.1), dict(grace=0.5, nslots=2),
                                  dict(grace=0.5, dt_mode=2), dict(periodic=(1, 0, 1)), dict(nguard=1),
                                  dict(limiter=1), dict(kmax=41), dict(nslots=1), dict(prec=3),
-                                 dict(dt_base=0.0), dict(gamma=1.0)])
+                                 dict(dt_base=0.0), dict(gamma=1.0), dict(eta=-1.0), dict(gamma_ad=-1.0),
+                                 dict(gamma_ad=1.0, rho_ion=0.0), dict(torder=3), dict(torder=2, nslots=2)])
 def test_invalid_config_rejected_on_host(bad):
     pr = I.cfg2_turb(npd=2)
     cfg = dataclasses.replace(pr.cfg, **bad)
@@ -77,3 +78,23 @@ def test_invalid_geometry_rejected_on_host():
     q[0] = I.Patch((0.1, 0.0, 0.0), q[0].size, q[0].n)  # off the lattice / gap
     with pytest.raises(dsp.DspError):
         dsp.dsp_create(pr.cfg, q)
+
+
+def test_boundary_patches_rejected_on_host():
+    """Boundary patches need LOCAL steps, and at least one patch must update."""
+    pr = I.cfg2_turb(npd=2)
+    p = [I.Patch(q.origin, q.size, q.n, frozen=(m == 0)) for m, q in enumerate(pr.patches)]
+    with pytest.raises(dsp.DspError) as e:
+        dsp.dsp_create(dataclasses.replace(pr.cfg, dt_mode=I.DT_GLOBAL_EXACT), p)
+    assert e.value.code == dsp.DSP_EINVAL
+    allf = [I.Patch(q.origin, q.size, q.n, frozen=True) for q in pr.patches]
+    with pytest.raises(dsp.DspError) as e:
+        dsp.dsp_create(pr.cfg, allf)
+    assert e.value.code == dsp.DSP_EINVAL
+
+
+def test_snapshot_rejects_bad_path_on_host(tmp_path):
+    """A missing file is refused before any device work (null set handles too)."""
+    L = dsp.load()
+    assert L.dsp_load_snapshot(None, str(tmp_path / "absent.bin").encode()) == dsp.DSP_EINVAL
+    assert L.dsp_save_snapshot(None, str(tmp_path / "x.bin").encode()) == dsp.DSP_EINVAL
