@@ -663,16 +663,32 @@ __global__ void k_scan(DevSet S, int64_t T_end, int* __restrict__ list, int* __r
   // (with time order 2 the slice before a bracket is read too: two are kept)
   const int oldest = (S.cur[p] + 1) % ns, after = (S.cur[p] + 1 + (S.torder > 1 ? 2 : 1)) % ns;
   const int64_t t_after = S.svalid[ob + oldest] ? S.sticks[ob + after] : INT64_MIN;
-  for (int m = S.nb_off[p]; m < S.nb_off[p + 1]; ++m) {
-    const int q = S.nb_idx[m];
-    if (S.frozen[q]) continue;  // and never lag
-    const int64_t tq = S.ticks[q];
-    int64_t g = 0;
-    if (S.grace > 0.0 && S.steps[q] > 0) {
-      const int prev = (S.cur[q] + ns - 1) % ns;
-      if (S.svalid[(int64_t)q * ns + prev]) g = (int64_t)floor(S.grace * (double)(tq - S.sticks[(int64_t)q * ns + prev]));
+  // the neighbours' times are fetched eight at a time before any is tested,
+  // so their loads overlap instead of waiting on each other
+  const int m0 = S.nb_off[p], m1 = S.nb_off[p + 1];
+  for (int mb = m0; mb < m1; mb += 8) {
+    int qs[8];
+    int64_t tqs[8];
+    bool fz[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) qs[u] = mb + u < m1 ? S.nb_idx[mb + u] : -1;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      tqs[u] = qs[u] >= 0 ? S.ticks[qs[u]] : INT64_MAX;
+      fz[u] = qs[u] < 0 || S.frozen[qs[u]];  // boundary patches never lag
     }
-    if (t > tq + g || t_after > tq) return;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (fz[u]) continue;
+      const int q = qs[u];
+      const int64_t tq = tqs[u];
+      int64_t g = 0;
+      if (S.grace > 0.0 && S.steps[q] > 0) {
+        const int prev = (S.cur[q] + ns - 1) % ns;
+        if (S.svalid[(int64_t)q * ns + prev]) g = (int64_t)floor(S.grace * (double)(tq - S.sticks[(int64_t)q * ns + prev]));
+      }
+      if (t > tq + g || t_after > tq) return;
+    }
   }
   const int slot = atomicAdd(counters, 1);
   list[slot] = p;
