@@ -26,6 +26,7 @@
 #include "dsp_dev.h"
 #include "dsp_guard.h"
 #include "dual_dev.h"
+#include "hlld_vjp.h"
 #include "mhd_dev.h"
 
 namespace dsp {
@@ -240,21 +241,9 @@ __global__ __launch_bounds__(256) void k_adj_flux(DevSet S, const int* __restric
     }
     bn = bface;
   }
-  // lam of the 15 inputs (l, r, bn): one forward-mode pass per input
+  // lam of the 15 inputs (l, r, bn): one reverse pass through the HLLD flux
   T g[15];
-#pragma unroll 1
-  for (int j = 0; j < 15; ++j) {
-    Dual<T> dl[7], dr[7], df[8];
-    for (int m = 0; m < 7; ++m) {
-      dl[m] = Dual<T>(l[m], j == m ? T(1) : T(0));
-      dr[m] = Dual<T>(r[m], j == 7 + m ? T(1) : T(0));
-    }
-    const Dual<T> dbn(bn, j == 14 ? T(1) : T(0));
-    hlld_flux<Dual<T>, DualExact<T>>(dl, dr, dbn, Dual<T>(T(S.gamma)), df);
-    T acc = T(0);
-    for (int q = 0; q < 7; ++q) acc += lf[q] * df[q].d;
-    g[j] = acc;
-  }
+  hlld_vjp<T>(l, r, bn, T(S.gamma), lf, g, g + 7, g[14]);
   if (fallback) {
     for (int m = 0; m < 7; ++m) {
       atomicAdd(&LW[order[m] * NC + ca], g[m]);
