@@ -193,7 +193,7 @@ def main():
     out["roofline"] = {"bound": "alu", "achieved": ach, "peak": FP32_VECTOR_PEAK, "unit": "TFLOP/s",
                        "frac": ach / FP32_VECTOR_PEAK,
                        "traffic": measured_traffic(res32["algo_bytes"] / launches),
-                       "kernel": "k_step2<float>", "launches": res32["kern_launches"],
+                       "kernel": "k_step2<float, 16>", "launches": res32["kern_launches"],
                        "avg_launch_ms": res32["kern_ms"] / launches,
                        "flops_per_update": per_update,
                        "algorithmic_bytes_per_update": res32["algo_bytes"] / max(res32["updates"], 1),

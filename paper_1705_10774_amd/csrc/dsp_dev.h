@@ -138,9 +138,9 @@ void launch_update(const DevSet& S, const int* list, int count, int nmax, T* slo
                    hipEvent_t ev0, hipEvent_t ev1);
 // returns 1 when the Courant rate and level were computed inside the step kernel
 template <class T>
-int launch_fused(const DevSet& S, const int* list, int count, int nmax, T* slots, T* pad, int64_t pad_stride,
-                  bool gfill, double* smax, const StepPtr& st, hipStream_t s, int dt_kind, double t_end, int clip,
-                  hipEvent_t ev0, hipEvent_t ev1);
+int launch_fused(const DevSet& S, const int* list, int count, int nmin, int nmax, T* slots, T* pad,
+                  int64_t pad_stride, bool gfill, double* smax, const StepPtr& st, hipStream_t s, int dt_kind,
+                  double t_end, int clip, hipEvent_t ev0, hipEvent_t ev1);
 template <class T>
 void launch_adjoint_step(const DevSet& S, const int* list, int count, int nmax, const WorkPtr<T>& W,
                          const WorkPtr<T>& L, const StepPtr& st, const T* lam_next, T* lam_prev,

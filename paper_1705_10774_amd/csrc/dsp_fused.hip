@@ -92,25 +92,63 @@ template <class T> struct PatchCtx {
 
 // guard-filled primitives of cell (i, j, k); the fields on its three low
 // faces are returned too (outputs are written last, so they may alias)
-template <class T, class M = Exact<T>>
+template <class T, class M = Exact<T>, int FN = 0>
 __device__ __forceinline__ void load_cell(const PatchCtx<T>& c, const RegionTab<T>& rt, int i, int j, int k,
                                           T gamma, T pfloor, T* w, T& bxl, T& byl, T& bzl) {
-  const T rho = fetch_fast(c.n, rt, -1, 0, i, j, k);
-  const T m0 = fetch_fast(c.n, rt, -1, 1, i, j, k);
-  const T m1 = fetch_fast(c.n, rt, -1, 2, i, j, k);
-  const T m2 = fetch_fast(c.n, rt, -1, 3, i, j, k);
-  const T en = fetch_fast(c.n, rt, -1, 4, i, j, k);
-  const T xl = fetch_fast(c.n, rt, 0, 0, i, j, k);
-  const T xr = fetch_fast(c.n, rt, 0, 0, i + 1, j, k);
-  const T yl = fetch_fast(c.n, rt, 1, 0, i, j, k);
-  const T yr = fetch_fast(c.n, rt, 1, 0, i, j + 1, k);
-  const T zl = fetch_fast(c.n, rt, 2, 0, i, j, k);
-  const T zr = fetch_fast(c.n, rt, 2, 0, i, j, k + 1);
+  const T rho = fetch_fast<T, FN>(FN ? FN : c.n, rt, -1, 0, i, j, k);
+  const T m0 = fetch_fast<T, FN>(FN ? FN : c.n, rt, -1, 1, i, j, k);
+  const T m1 = fetch_fast<T, FN>(FN ? FN : c.n, rt, -1, 2, i, j, k);
+  const T m2 = fetch_fast<T, FN>(FN ? FN : c.n, rt, -1, 3, i, j, k);
+  const T en = fetch_fast<T, FN>(FN ? FN : c.n, rt, -1, 4, i, j, k);
+  const T xl = fetch_fast<T, FN>(FN ? FN : c.n, rt, 0, 0, i, j, k);
+  const T xr = fetch_fast<T, FN>(FN ? FN : c.n, rt, 0, 0, i + 1, j, k);
+  const T yl = fetch_fast<T, FN>(FN ? FN : c.n, rt, 1, 0, i, j, k);
+  const T yr = fetch_fast<T, FN>(FN ? FN : c.n, rt, 1, 0, i, j + 1, k);
+  const T zl = fetch_fast<T, FN>(FN ? FN : c.n, rt, 2, 0, i, j, k);
+  const T zr = fetch_fast<T, FN>(FN ? FN : c.n, rt, 2, 0, i, j, k + 1);
   prim_of<T, M>(rho, m0, m1, m2, en, T(0.5) * (xl + xr), T(0.5) * (yl + yr), T(0.5) * (zl + zr), gamma, pfloor,
                 w);
   bxl = xl;
   byl = yl;
   bzl = zl;
+}
+
+// load_cell in two halves, for a fixed patch size: raw_issue starts the
+// reads of one cell (both time slices of each value), raw_finish blends and
+// converts them exactly as load_cell does, so independent work can run while
+// the reads are in flight.
+template <class T> struct RawCell {
+  T a[11], b[11];
+};
+template <class T, int FN>
+__device__ __forceinline__ void raw_issue(const RegionTab<T>& rt, int i, int j, int k, RawCell<T>& r) {
+  static_assert(FN > 0, "fixed patch size only");
+#pragma unroll
+  for (int v = 0; v < 5; ++v) fetch_pair<T, FN>(FN, rt, -1, v, i, j, k, r.a[v], r.b[v]);
+  fetch_pair<T, FN>(FN, rt, 0, 0, i, j, k, r.a[5], r.b[5]);
+  fetch_pair<T, FN>(FN, rt, 0, 0, i + 1, j, k, r.a[6], r.b[6]);
+  fetch_pair<T, FN>(FN, rt, 1, 0, i, j, k, r.a[7], r.b[7]);
+  fetch_pair<T, FN>(FN, rt, 1, 0, i, j + 1, k, r.a[8], r.b[8]);
+  fetch_pair<T, FN>(FN, rt, 2, 0, i, j, k, r.a[9], r.b[9]);
+  fetch_pair<T, FN>(FN, rt, 2, 0, i, j, k + 1, r.a[10], r.b[10]);
+}
+template <class T, class M, int FN>
+__device__ __forceinline__ void raw_finish(const RegionTab<T>& rt, int i, int j, int k, const RawCell<T>& r,
+                                           T gamma, T pfloor, T* w, T& bxl, T& byl, T& bzl) {
+  T v[11];
+  const T wc = blend_weight(FN, rt, -1, i, j, k);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) v[q] = r.a[q] + wc * (r.b[q] - r.a[q]);
+  const T wf[6] = {blend_weight(FN, rt, 0, i, j, k),     blend_weight(FN, rt, 0, i + 1, j, k),
+                   blend_weight(FN, rt, 1, i, j, k),     blend_weight(FN, rt, 1, i, j + 1, k),
+                   blend_weight(FN, rt, 2, i, j, k),     blend_weight(FN, rt, 2, i, j, k + 1)};
+#pragma unroll
+  for (int q = 0; q < 6; ++q) v[5 + q] = r.a[5 + q] + wf[q] * (r.b[5 + q] - r.a[5 + q]);
+  prim_of<T, M>(v[0], v[1], v[2], v[3], v[4], T(0.5) * (v[5] + v[6]), T(0.5) * (v[7] + v[8]),
+                T(0.5) * (v[9] + v[10]), gamma, pfloor, w);
+  bxl = v[5];
+  byl = v[7];
+  bzl = v[9];
 }
 
 // first-order fallback states of a face along d: the primitives at t^n of
@@ -388,12 +426,12 @@ __global__ __launch_bounds__(256) void k_courant(DevSet S, const int* __restrict
 // mode, one tile per patch): the Courant rate over the padded patch, its
 // level, and the step record the publish kernel reads.  Returns dt to every
 // thread of the workgroup.
-template <class T>
-__device__ double fused_local_dt(const DevSet& S, const PatchCtx<T>& c, const RegionTab<T>& rt, const StepPtr& st,
-                                 int bidx, int tid, int nthr, double* red) {
+template <class T, int FN = 0>
+__device__ __forceinline__ double fused_local_dt(const DevSet& S, const PatchCtx<T>& c, const RegionTab<T>& rt,
+                                                 const StepPtr& st, int bidx, int tid, int nthr, double* red) {
   // The largest signal-speed sum, divided by dx once: division by a positive
   // number is monotonic, so this is the largest of the per-cell rates.
-  const int n = c.n, N = n + 4;
+  const int n = FN ? FN : c.n, N = n + 4;
   T ms = T(0);
 #pragma unroll 4
   for (int cid = tid; cid < n * n * n; cid += nthr) {
@@ -406,7 +444,7 @@ __device__ double fused_local_dt(const DevSet& S, const PatchCtx<T>& c, const Re
     int i, j, k;
     shell_cell(r, n, i, j, k);
     T w[8], bxl, byl, bzl;
-    load_cell(c, rt, i, j, k, T(S.gamma), T(0), w, bxl, byl, bzl);
+    load_cell<T, Exact<T>, FN>(c, rt, i, j, k, T(S.gamma), T(0), w, bxl, byl, bzl);
     const T v = cell_sum(S, w);
     ms = v > ms ? v : ms;
   }
@@ -820,7 +858,7 @@ constexpr int NTHR2 = 1024;
 
 template <class T> struct Step2Smem {
   T w[3][8][MCOL];      // primitives of planes z-1, z, z+1 (slot = plane mod 3)
-  T bfc[2][3][MCOL];    // t^n field on the low x-, y- and z-face of each column (slot = plane mod 2)
+  T bfc[3][3][MCOL];    // t^n field on the low x-, y- and z-face of each column (slot = plane mod 3)
   union B {
     struct {
       T h[8][MPRED];    // half-step primitives
@@ -848,14 +886,19 @@ template <class T> struct Step2Smem {
 
 __device__ __forceinline__ int mod3(int z) { return (z + 3) % 3; }
 
-template <class T>
+// FN > 0: every patch has FN <= MT cells per edge (one tile each) and every
+// guard region is a single same-resolution box, so the patch and region
+// strides are compile-time constants; FN = 0 takes them at run time.
+template <class T, int FN>
 __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict__ list, int count,
                                                  T* __restrict__ slots, const T* __restrict__ pad,
                                                  int64_t pad_stride, StepPtr st, int tpa, int fuse_dt) {
   static_assert(sizeof(T) == 4, "the wide step kernel is the single-precision variant");
+  static_assert(FN >= 0 && FN <= MT, "a fixed patch size is one tile");
   using M = FastF32;
   __shared__ Step2Smem<T> sm;
   const int tid = threadIdx.x;
+  if (FN) tpa = 1;
   const int T2 = tpa * tpa;
   const int wg = blockIdx.x;
   const int bidx = (wg / (8 * T2)) * 8 + (wg % 8);
@@ -863,7 +906,7 @@ __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict
   if (bidx >= live_count(S, count)) return;
   PatchCtx<T> c;
   c.p = list[bidx];
-  const int n = c.n = S.n[c.p];
+  const int n = c.n = FN ? FN : S.n[c.p];
   const int nt = (n + MT - 1) / MT;
   const int tx = tile % tpa, ty = tile / tpa;
   if (tx >= nt || ty >= nt) return;
@@ -886,7 +929,7 @@ __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict
   if (tid == 0) traffic = 0;
   __syncthreads();
   if (tile == 0) count_traffic(S, c.p, box0, nbox, V, (int)sizeof(T), tid, NTHR2, &traffic);
-  const double dt = fuse_dt ? fused_local_dt(S, c, sm.rt, st, bidx, tid, NTHR2, red) : st.dt[bidx];
+  const double dt = fuse_dt ? fused_local_dt<T, FN>(S, c, sm.rt, st, bidx, tid, NTHR2, red) : st.dt[bidx];
   const T dtdx = T(dt / S.dx[c.p]);
   const T hdtdx = T(0.5) * dtdx;
   __syncthreads();
@@ -914,20 +957,30 @@ __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict
   auto own_c = [&](int v, int lo, int hi, bool first, bool last) {
     return (v >= lo && v < hi) || (first && v < 0) || (last && v >= n);
   };
-  auto load_plane = [&](int z) {  // primitives and low-face fields of plane z into the rings
-    T wv[8], bx, by, bz;
-    load_cell<T, M>(c, sm.rt, ci, cj, z, gamma, pfloor, wv, bx, by, bz);
-    const int s3 = mod3(z), s2 = z & 1;
+  // FN > 0: plane z + 2 is read during the face phase of plane z (its ring
+  // slot, that of plane z - 1, is free by then), which saves the load phase
+  // and its barrier; FN = 0 loads plane z + 1 in a phase of its own.
+  constexpr bool PIPE = FN > 0;
+  auto store_plane = [&](int z, const T* wv, T bx, T by, T bz) {
+    const int s3 = mod3(z);
 #pragma unroll
     for (int v = 0; v < 8; ++v) sm.w[s3][v][lane] = wv[v];
-    sm.bfc[s2][0][lane] = bx;
-    sm.bfc[s2][1][lane] = by;
-    sm.bfc[s2][2][lane] = bz;
+    sm.bfc[s3][0][lane] = bx;
+    sm.bfc[s3][1][lane] = by;
+    sm.bfc[s3][2][lane] = bz;
+  };
+  auto load_plane = [&](int z) {  // primitives and low-face fields of plane z into the rings
+    T wv[8], bx, by, bz;
+    load_cell<T, M, FN>(c, sm.rt, ci, cj, z, gamma, pfloor, wv, bx, by, bz);
+    store_plane(z, wv, bx, by, bz);
   };
   if (col) {
     load_plane(-2);
     load_plane(-1);
+    if (PIPE) load_plane(0);
   }
+  // without a load phase, the first predictor phase reads these planes next
+  if (PIPE) __syncthreads();
   T acc[5];  // x/y flux differences of the pending cell minus its bottom z-flux
   T dnew[5];
 #pragma unroll
@@ -937,9 +990,11 @@ __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict
 
   for (int z = -1; z <= n; ++z) {
     // ---- P1: load plane z+1
-    reopen();
-    if (col) load_plane(z + 1);
-    __syncthreads();
+    if (!PIPE) {
+      reopen();
+      if (col) load_plane(z + 1);
+      __syncthreads();
+    }
     // ---- P2: slopes, Hancock predictor, z-face states and cell EMF of plane z
     reopen();
     if (pred) {
@@ -997,6 +1052,11 @@ __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict
     __syncthreads();
     // ---- P3: x- and y-face fluxes of plane z, z-face fluxes at face z
     reopen();
+    const bool ld = PIPE && col && z + 2 <= n + 1;
+    RawCell<T> raw;
+    if constexpr (PIPE) {
+      if (ld) raw_issue<T, FN>(sm.rt, ci, cj, z + 2, raw);
+    }
     const int nface = nxf + nyf + (z >= 0 ? nzf : 0);
     for (int m = lane; m < nface; m += NTHR2) {
       T l[7], r[7], bn, f[8];
@@ -1019,7 +1079,7 @@ __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict
           cix = x0 - 1 + ir;
           cjx = y0 + gl;
         }
-        bface = sm.bfc[z & 1][d][(cix - (x0 - 2)) + (cjx - (y0 - 2)) * CX];
+        bface = sm.bfc[mod3(z)][d][(cix - (x0 - 2)) + (cjx - (y0 - 2)) * CX];
         const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
         const T(*slp)[MPRED] = (d == 0) ? sm.b.p.sx : sm.b.p.sy;
         const int ord[7] = {0, 1 + d, 1 + t1, 1 + t2, 4, 5 + t1, 5 + t2};
@@ -1066,7 +1126,7 @@ __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict
           l[k] = sm.zt[(z - 1) & 1][k][q];
           r[k] = sm.zb[k][q];
         }
-        const T bface = sm.bfc[z & 1][2][cq];
+        const T bface = sm.bfc[mod3(z)][2][cq];
         bn = bface + T(0.5) * (sm.dz[(z - 1) & 1][q] + sm.dz[z & 1][q]);
         if (!(l[0] > T(0)) || !(l[4] > T(0)) || !(r[0] > T(0)) || !(r[4] > T(0))) {
           {
@@ -1089,6 +1149,13 @@ __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict
         sm.fz[5][q] = f[5];
         sm.fz[6][q] = f[6];
         sm.fz[7][q] = f[7];
+      }
+    }
+    if constexpr (PIPE) {
+      if (ld) {
+        T wv[8], bx, by, bz;
+        raw_finish<T, M, FN>(sm.rt, ci, cj, z + 2, raw, gamma, pfloor, wv, bx, by, bz);
+        store_plane(z + 2, wv, bx, by, bz);
       }
     }
     __syncthreads();
@@ -1209,9 +1276,9 @@ __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict
 // ---------------------------------------------------------------------------
 
 template <class T>
-int launch_fused(const DevSet& S, const int* list, int count, int nmax, T* slots, T* pad, int64_t pad_stride,
-                  bool gfill, double* smax, const StepPtr& st, hipStream_t s, int dt_kind, double t_end, int clip,
-                  hipEvent_t ev0, hipEvent_t ev1) {
+int launch_fused(const DevSet& S, const int* list, int count, int nmin, int nmax, T* slots, T* pad,
+                  int64_t pad_stride, bool gfill, double* smax, const StepPtr& st, hipStream_t s, int dt_kind,
+                  double t_end, int clip, hipEvent_t ev0, hipEvent_t ev1) {
   const int N = nmax + 4;
   if (gfill)
     hipLaunchKernelGGL(k_gfill<T>, dim3(108, count), dim3(256), 0, s, S, list, count, (const T*)slots, pad,
@@ -1231,19 +1298,24 @@ int launch_fused(const DevSet& S, const int* list, int count, int nmax, T* slots
   const int T2 = tpa * tpa;
   const int groups = ((count + 7) / 8) * 8 * T2;
   if (ev0) (void)hipEventRecord(ev0, s);
-  if constexpr (sizeof(T) == 4)
-    hipLaunchKernelGGL(k_step2<T>, dim3(groups), dim3(NTHR2), 0, s, S, list, count, slots, (const T*)pad,
-                       pad_stride, st, tpa, fuse_dt);
-  else
+  if constexpr (sizeof(T) == 4) {
+    // equal 16^3 patches without padded guard regions: the fixed-size variant
+    if (nmin == 16 && nmax == 16 && !gfill)
+      hipLaunchKernelGGL((k_step2<T, 16>), dim3(groups), dim3(NTHR2), 0, s, S, list, count, slots, (const T*)pad,
+                         pad_stride, st, tpa, fuse_dt);
+    else
+      hipLaunchKernelGGL((k_step2<T, 0>), dim3(groups), dim3(NTHR2), 0, s, S, list, count, slots, (const T*)pad,
+                         pad_stride, st, tpa, fuse_dt);
+  } else
     hipLaunchKernelGGL(k_step<T>, dim3(groups), dim3(NTHR), 0, s, S, list, count, slots, (const T*)pad, pad_stride,
                        st, tpa, fuse_dt);
   if (ev1) (void)hipEventRecord(ev1, s);
   return fuse_dt;
 }
 
-template int launch_fused<float>(const DevSet&, const int*, int, int, float*, float*, int64_t, bool, double*,
+template int launch_fused<float>(const DevSet&, const int*, int, int, int, float*, float*, int64_t, bool, double*,
                                   const StepPtr&, hipStream_t, int, double, int, hipEvent_t, hipEvent_t);
-template int launch_fused<double>(const DevSet&, const int*, int, int, double*, double*, int64_t, bool, double*,
-                                   const StepPtr&, hipStream_t, int, double, int, hipEvent_t, hipEvent_t);
+template int launch_fused<double>(const DevSet&, const int*, int, int, int, double*, double*, int64_t, bool,
+                                   double*, const StepPtr&, hipStream_t, int, double, int, hipEvent_t, hipEvent_t);
 
 }  // namespace dsp

@@ -401,14 +401,48 @@ __device__ inline void region_tab_init(const DevSet& S, const T* slots, const T*
 // region is selected arithmetically, both slices are read (the same address
 // twice for an exact copy) and blended.  Offsets inside one slice fit in 32
 // bits.  comp is a constant at every call site.
+// The two reads of fetch_fast without the blend (issued early, blended later
+// with blend_weight): same region, same offsets.
+template <class T, int FNQ>
+__device__ __forceinline__ void fetch_pair(int n, const RegionTab<T>& R, int comp, int var, int i, int j, int k,
+                                           T& a, T& b) {
+  const int hx = n + (comp == 0 ? 1 : 0), hy = n + (comp == 1 ? 1 : 0), hz = n + (comp == 2 ? 1 : 0);
+  const int rx = (i >= 0) + (i >= hx);
+  const int ry = (j >= 0) + (j >= hy);
+  const int rz = (k >= 0) + (k >= hz);
+  const RegionEnt<T>& E = R.r[(comp + 1) * 27 + (rz * 3 + ry) * 3 + rx];
+  const int nq = FNQ ? FNQ : E.nq;
+  int e;
+  if (comp < 0) {
+    e = ((var * nq + k) * nq + j) * nq + i;
+  } else {
+    const int sx = nq + (comp == 0), sy = nq + (comp == 1);
+    e = (k * sy + j) * sx + i;
+  }
+  using gptr = const T __attribute__((address_space(1)))*;
+  a = ((gptr)E.pa)[e];
+  b = ((gptr)E.pb)[e];
+}
 template <class T>
+__device__ __forceinline__ T blend_weight(int n, const RegionTab<T>& R, int comp, int i, int j, int k) {
+  const int hx = n + (comp == 0 ? 1 : 0), hy = n + (comp == 1 ? 1 : 0), hz = n + (comp == 2 ? 1 : 0);
+  const int rx = (i >= 0) + (i >= hx);
+  const int ry = (j >= 0) + (j >= hy);
+  const int rz = (k >= 0) + (k >= hz);
+  return R.r[(comp + 1) * 27 + (rz * 3 + ry) * 3 + rx].w;
+}
+
+// FNQ > 0: every region's source patch has FNQ cells per edge (a set of
+// equal patches whose guard regions are all single same-resolution boxes),
+// so the offsets are compile-time strides.
+template <class T, int FNQ = 0>
 __device__ __forceinline__ T fetch_fast(int n, const RegionTab<T>& R, int comp, int var, int i, int j, int k) {
   const int hx = n + (comp == 0 ? 1 : 0), hy = n + (comp == 1 ? 1 : 0), hz = n + (comp == 2 ? 1 : 0);
   const int rx = (i >= 0) + (i >= hx);
   const int ry = (j >= 0) + (j >= hy);
   const int rz = (k >= 0) + (k >= hz);
   const RegionEnt<T> E = R.r[(comp + 1) * 27 + (rz * 3 + ry) * 3 + rx];
-  const int nq = E.nq;
+  const int nq = FNQ ? FNQ : E.nq;
   int e;
   if (comp < 0) {
     e = ((var * nq + k) * nq + j) * nq + i;

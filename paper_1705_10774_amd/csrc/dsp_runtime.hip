@@ -77,6 +77,7 @@ struct dsp_set {
   std::vector<void*> allocs;
   bool f32 = false;
   int nmax = 0;
+  int nmin = 1 << 30;
   int B = 0;  // batch capacity (patch slots of work memory)
   int klog_cap = 256;
   int64_t total_values = 0;
@@ -404,11 +405,11 @@ struct dsp_set {
     StepPtr s2{st.k + off, st.dtk + off, st.dt + off};
     if (fused) {
       if (f32)
-        dt_fused = launch_fused<float>(D, list + off, count, nmax, (float*)slots, (float*)work_pad, pad_stride,
-                                       any_generic, smax, s2, stream, dt_kind, t_end, clip, e0, e1);
+        dt_fused = launch_fused<float>(D, list + off, count, nmin, nmax, (float*)slots, (float*)work_pad,
+                                       pad_stride, any_generic, smax, s2, stream, dt_kind, t_end, clip, e0, e1);
       else
-        dt_fused = launch_fused<double>(D, list + off, count, nmax, (double*)slots, (double*)work_pad, pad_stride,
-                                        any_generic, smax, s2, stream, dt_kind, t_end, clip, e0, e1);
+        dt_fused = launch_fused<double>(D, list + off, count, nmin, nmax, (double*)slots, (double*)work_pad,
+                                        pad_stride, any_generic, smax, s2, stream, dt_kind, t_end, clip, e0, e1);
       return;
     }
     if (f32)
@@ -549,6 +550,7 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
     S->host_off[p + 1] = S->host_off[p] + H.V;
     minlen = std::min(minlen, H.len);
     S->nmax = std::max(S->nmax, H.n);
+    S->nmin = std::min(S->nmin, H.n);
   }
   S->total_values = S->host_off[npatch];
   S->bsize = minlen;
