@@ -111,10 +111,12 @@ __global__ __launch_bounds__(256) void k_adj_emf(DevSet S, const int* __restrict
   const int a = (int)(c / per);
   c -= a * per;
   const int bax = (a + 1) % 3, cax = (a + 2) % 3;
+  // edges e[a] in [0, n), the other two indices in [0, n]; x fastest
   int e[3];
-  e[a] = (int)(c % n);
-  e[bax] = (int)((c / n) % (n + 1));
-  e[cax] = (int)(c / ((int64_t)n * (n + 1)));
+  const int x0 = a == 0 ? n : n + 1, x1 = a == 1 ? n : n + 1;
+  e[0] = (int)(c % x0);
+  e[1] = (int)((c / x0) % x1);
+  e[2] = (int)(c / ((int64_t)x0 * x1));
   const int64_t fs = W.fm3;
   const T lamE = L.e[(int64_t)blk * L.e_stride + (int64_t)a * fs + wface(N, 0, e[0], e[1], e[2])];
   if (lamE == T(0)) return;
@@ -191,11 +193,14 @@ __global__ __launch_bounds__(256) void k_adj_flux(DevSet S, const int* __restric
   if (c >= 3 * per) return;
   const int d = (int)(c / per);
   c -= d * per;
+  // faces idx[d] in [0, n], the other two indices in [-1, n]; x fastest, so
+  // that neighbouring threads read neighbouring cells in every direction
   int idx[3];
   const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
-  idx[d] = (int)(c % (n + 1));
-  idx[t1] = (int)((c / (n + 1)) % M) - 1;
-  idx[t2] = (int)(c / ((int64_t)(n + 1) * M)) - 1;
+  const int e0 = d == 0 ? n + 1 : M, e1 = d == 1 ? n + 1 : M;
+  idx[0] = (int)(c % e0) - (d == 0 ? 0 : 1);
+  idx[1] = (int)((c / e0) % e1) - (d == 1 ? 0 : 1);
+  idx[2] = (int)(c / ((int64_t)e0 * e1)) - (d == 2 ? 0 : 1);
   int ia[3] = {idx[0], idx[1], idx[2]};
   ia[d] -= 1;
   const int64_t fs = W.fm3;
@@ -209,16 +214,23 @@ __global__ __launch_bounds__(256) void k_adj_flux(DevSet S, const int* __restric
   lf[4] = LF[4 * fs + of];
   lf[5] = LF[(5 + t1) * fs + of];
   lf[6] = LF[(5 + t2) * fs + of];
+  // The face's 15 cotangents go to the flux buffers, which no later kernel
+  // of this step reads: the left-state ones (and the fallback flag, in the
+  // slot of the normal field, which has no flux) over lf in L.f, the
+  // right-state ones and that of bn over the forward fluxes in W.f.
+  // k_adj_flux_sum adds them into the cells without atomics.
+  T* GL = L.f + (int64_t)b * L.f_stride + (int64_t)d * 8 * fs;
+  T* GR = W.f + (int64_t)b * W.f_stride + (int64_t)d * 8 * fs;
   bool any = false;
   for (int q = 0; q < 7; ++q) any = any || lf[q] != T(0);
-  if (!any) return;
+  if (!any) {  // L.f already holds zeros here
+    for (int v = 0; v < 8; ++v) GR[v * fs + of] = T(0);
+    return;
+  }
   const T* Wp = W.w + (int64_t)b * W.w_stride;
   const T* Hp = W.h + (int64_t)b * W.w_stride;
   const T* Sp = W.s + (int64_t)b * W.s_stride;
   const T* Pd = W.pad + (int64_t)b * W.pad_stride;
-  T* LW = L.w + (int64_t)b * L.w_stride;
-  T* LH = L.h + (int64_t)b * L.w_stride;
-  T* LS = L.s + (int64_t)b * L.s_stride;
   T* LP = L.pad + (int64_t)b * L.pad_stride;
   const int64_t NC = (int64_t)N * N * N;
   const int64_t ca = wcell(N, 0, ia[0], ia[1], ia[2]), cb = wcell(N, 0, idx[0], idx[1], idx[2]);
@@ -244,28 +256,75 @@ __global__ __launch_bounds__(256) void k_adj_flux(DevSet S, const int* __restric
   // lam of the 15 inputs (l, r, bn): one reverse pass through the HLLD flux
   T g[15];
   hlld_vjp<T>(l, r, bn, T(S.gamma), lf, g, g + 7, g[14]);
-  if (fallback) {
-    for (int m = 0; m < 7; ++m) {
-      atomicAdd(&LW[order[m] * NC + ca], g[m]);
-      atomicAdd(&LW[order[m] * NC + cb], g[7 + m]);
-    }
-    atomicAdd(&LP[opf], g[14]);
-    return;
-  }
   for (int m = 0; m < 7; ++m) {
-    const int v = order[m];
-    atomicAdd(&LH[v * NC + ca], g[m]);
-    atomicAdd(&LS[(int64_t)(d * 8 + v) * NC + ca], T(0.5) * g[m]);
-    atomicAdd(&LH[v * NC + cb], g[7 + m]);
-    atomicAdd(&LS[(int64_t)(d * 8 + v) * NC + cb], T(-0.5) * g[7 + m]);
+    GL[order[m] * fs + of] = g[m];
+    GR[order[m] * fs + of] = g[7 + m];
   }
-  // bn = bface + (H_a - W_a + H_b - W_b)/2 for the normal component
-  const T hb = T(0.5) * g[14];
-  atomicAdd(&LP[opf], g[14]);
-  atomicAdd(&LH[(5 + d) * NC + ca], hb);
-  atomicAdd(&LW[(5 + d) * NC + ca], -hb);
-  atomicAdd(&LH[(5 + d) * NC + cb], hb);
-  atomicAdd(&LW[(5 + d) * NC + cb], -hb);
+  GL[(5 + d) * fs + of] = fallback ? T(1) : T(0);
+  GR[(5 + d) * fs + of] = g[14];
+  LP[opf] += g[14];  // the face's own entry: one writer
+}
+
+// Sum of the face cotangents of k_adj_flux into cell c of [-1, n]^3: for each
+// direction, the face above c (c its left cell) and the face below (c its
+// right cell).  Face states l = H + S/2 and r = H - S/2 along the face
+// normal; a fallback face took the t^n primitives W instead.  The normal
+// field of the face, bn = B_face + (H_a - W_a + H_b - W_b)/2, gives each of
+// its two cells lam_bn/2 on H and -lam_bn/2 on W (not for a fallback face).
+template <class T>
+__global__ __launch_bounds__(256) void k_adj_flux_sum(DevSet S, const int* __restrict__ list, int count,
+                                                      WorkPtr<T> W, WorkPtr<T> L) {
+  const int b = blockIdx.y;
+  if (b >= count) return;
+  const int p = list[b];
+  const int n = S.n[p], N = n + 4, M = n + 2;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= (int64_t)M * M * M) return;
+  const int cc[3] = {(int)(c % M) - 1, (int)((c / M) % M) - 1, (int)(c / ((int64_t)M * M)) - 1};
+  const int64_t fs = W.fm3, NC = (int64_t)N * N * N;
+  const int64_t oc = wcell(N, 0, cc[0], cc[1], cc[2]);
+  T aH[8], aW[8];
+  for (int v = 0; v < 8; ++v) aH[v] = aW[v] = T(0);
+  T* LS = L.s + (int64_t)b * L.s_stride;
+  for (int d = 0; d < 3; ++d) {
+    const T* GL = L.f + (int64_t)b * L.f_stride + (int64_t)d * 8 * fs;
+    const T* GR = W.f + (int64_t)b * W.f_stride + (int64_t)d * 8 * fs;
+    T aS[8];
+    for (int v = 0; v < 8; ++v) aS[v] = T(0);
+    for (int side = 0; side < 2; ++side) {
+      // side 0: the face above (c is its left cell); side 1: the face below
+      int f[3] = {cc[0], cc[1], cc[2]};
+      if (side == 0) f[d] += 1;
+      if (f[d] < 0 || f[d] > n) continue;
+      const int64_t of = wface(N, 0, f[0], f[1], f[2]);
+      const T* G = side == 0 ? GL : GR;
+      const bool fb = GL[(5 + d) * fs + of] != T(0);
+      const T sg = side == 0 ? T(0.5) : T(-0.5);
+      for (int v = 0; v < 8; ++v) {
+        if (v == 5 + d) continue;
+        const T g = G[v * fs + of];
+        if (fb) {
+          aW[v] += g;
+        } else {
+          aH[v] += g;
+          aS[v] += sg * g;
+        }
+      }
+      if (!fb) {
+        const T hb = T(0.5) * GR[(5 + d) * fs + of];
+        aH[5 + d] += hb;
+        aW[5 + d] -= hb;
+      }
+    }
+    for (int v = 0; v < 8; ++v)
+      if (aS[v] != T(0)) LS[(int64_t)(d * 8 + v) * NC + oc] += aS[v];
+  }
+  T* LW = L.w + (int64_t)b * L.w_stride;
+  T* LH = L.h + (int64_t)b * L.w_stride;
+  for (int v = 0; v < 8; ++v) {
+    if (aH[v] != T(0)) LH[v * NC + oc] += aH[v];
+    if (aW[v] != T(0)) LW[v * NC + oc] += aW[v];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -494,6 +553,8 @@ void launch_adjoint_step(const DevSet& S, const int* list, int count, int nmax, 
   hipLaunchKernelGGL(k_adj_emf<T>, dim3(blocks(3LL * n * (n + 1) * (n + 1)), count), dim3(256), 0, s, S, list, count,
                      W, L);
   hipLaunchKernelGGL(k_adj_flux<T>, dim3(blocks(3LL * (n + 1) * M * M), count), dim3(256), 0, s, S, list, count, W,
+                     L);
+  hipLaunchKernelGGL(k_adj_flux_sum<T>, dim3(blocks((int64_t)M * M * M), count), dim3(256), 0, s, S, list, count, W,
                      L);
   hipLaunchKernelGGL(k_adj_pred<T>, dim3(blocks((int64_t)M * M * M), count), dim3(256), 0, s, S, list, count, W, L,
                      st);

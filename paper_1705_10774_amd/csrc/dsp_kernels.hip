@@ -310,12 +310,14 @@ __global__ void k_flux(DevSet S, const int* __restrict__ list, int count, WorkPt
   if (c >= 3 * per) return;
   const int d = (int)(c / per);
   c -= d * per;
-  // index order: face index fastest along d's own axis layout
+  // faces idx[d] in [0, n], the other two indices in [-1, n]; x fastest, so
+  // that neighbouring threads read neighbouring cells in every direction
   int idx[3];
   const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
-  idx[d] = (int)(c % (n + 1));
-  idx[t1] = (int)((c / (n + 1)) % M) - 1;
-  idx[t2] = (int)(c / ((int64_t)(n + 1) * M)) - 1;
+  const int e0 = d == 0 ? n + 1 : M, e1 = d == 1 ? n + 1 : M;
+  idx[0] = (int)(c % e0) - (d == 0 ? 0 : 1);
+  idx[1] = (int)((c / e0) % e1) - (d == 1 ? 0 : 1);
+  idx[2] = (int)(c / ((int64_t)e0 * e1)) - (d == 2 ? 0 : 1);
   int ia[3] = {idx[0], idx[1], idx[2]};
   ia[d] -= 1;
   const T* Wp = W.w + (int64_t)b * W.w_stride;
@@ -377,10 +379,12 @@ __global__ void k_emf(DevSet S, const int* __restrict__ list, int count, WorkPtr
   const int a = (int)(c / per);
   c -= a * per;
   const int bax = (a + 1) % 3, cax = (a + 2) % 3;
+  // edges e[a] in [0, n), the other two indices in [0, n]; x fastest
   int e[3];
-  e[a] = (int)(c % n);
-  e[bax] = (int)((c / n) % (n + 1));
-  e[cax] = (int)(c / ((int64_t)n * (n + 1)));
+  const int x0 = a == 0 ? n : n + 1, x1 = a == 1 ? n : n + 1;
+  e[0] = (int)(c % x0);
+  e[1] = (int)((c / x0) % x1);
+  e[2] = (int)(c / ((int64_t)x0 * x1));
   const T* Hp = W.h + (int64_t)blk * W.w_stride;
   const T* Fb = W.f + (int64_t)blk * W.f_stride + (int64_t)bax * 8 * W.fm3;
   const T* Fc = W.f + (int64_t)blk * W.f_stride + (int64_t)cax * 8 * W.fm3;
@@ -455,10 +459,12 @@ __global__ void k_ni_emf(DevSet S, const int* __restrict__ list, int count, Work
   const int a = (int)(c0 / per);
   c0 -= a * per;
   const int bax = (a + 1) % 3, cax = (a + 2) % 3;
+  // edges e[a] in [0, n), the other two indices in [0, n]; x fastest
   int e[3];
-  e[a] = (int)(c0 % n);
-  e[bax] = (int)((c0 / n) % (n + 1));
-  e[cax] = (int)(c0 / ((int64_t)n * (n + 1)));
+  const int x0 = a == 0 ? n : n + 1, x1 = a == 1 ? n : n + 1;
+  e[0] = (int)(c0 % x0);
+  e[1] = (int)((c0 / x0) % x1);
+  e[2] = (int)(c0 / ((int64_t)x0 * x1));
   const T* Pd = W.pad + (int64_t)blk * W.pad_stride;
   const T* Wp = W.w + (int64_t)blk * W.w_stride;
   const T dx = (T)S.dx[p];
@@ -530,10 +536,12 @@ __global__ void k_ni_flux(DevSet S, const int* __restrict__ list, int count, Wor
   const int d = (int)(c0 / per);
   c0 -= d * per;
   const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+  // faces f[d] in [0, n], the other two indices in [0, n); x fastest
   int f[3];
-  f[d] = (int)(c0 % (n + 1));
-  f[t1] = (int)((c0 / (n + 1)) % n);
-  f[t2] = (int)(c0 / ((int64_t)(n + 1) * n));
+  const int x0 = d == 0 ? n + 1 : n, x1 = d == 1 ? n + 1 : n;
+  f[0] = (int)(c0 % x0);
+  f[1] = (int)((c0 / x0) % x1);
+  f[2] = (int)(c0 / ((int64_t)x0 * x1));
   const T* Pd = W.pad + (int64_t)blk * W.pad_stride;
   const T* En = W.s + (int64_t)blk * W.s_stride;
   T e1 = T(0), e2 = T(0), b1 = T(0), b2 = T(0);
