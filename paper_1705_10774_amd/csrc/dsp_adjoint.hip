@@ -16,16 +16,15 @@
 //
 // The upwind choices of the EMFs, the first-order fallback and the Riemann
 // solver's wave pattern are those of the forward state: the result is the
-// derivative along the branches the forward step takes.  The local Jacobians
-// of the Riemann solver and of the predictor come from running the same device
-// functions on forward-mode numbers (dual_dev.h), one input at a time.
-// Scatters into shared cells and faces use atomic additions.
+// derivative along the branches the forward step takes.  The Riemann solver
+// and the predictor have hand-written reverse passes (hlld_vjp.h, k_adj_pred).
+// The face and slope terms are gathered per cell (one writer per entry); the
+// update, EMF, primitive and fill kernels scatter with atomic additions.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "dsp_dev.h"
 #include "dsp_guard.h"
-#include "dual_dev.h"
 #include "hlld_vjp.h"
 #include "mhd_dev.h"
 
@@ -360,26 +359,47 @@ __global__ __launch_bounds__(256) void k_adj_pred(DevSet S, const int* __restric
   for (int d = 0; d < 3; ++d)
     for (int v = 0; v < 8; ++v) sl[d][v] = Sp[(int64_t)(d * 8 + v) * NC + o];
   const T hdtdx = (T)(0.5 * st.dt[b] / S.dx[p]);
-  const Dual<T> g(T(S.gamma)), hd(hdtdx);
-  // inputs 0..7: primitives, 8..31: slopes (d, v); sl[d][5 + d] is not an input
-#pragma unroll 1
-  for (int jdir = 0; jdir < 32; ++jdir) {
-    if (jdir >= 8) {
-      const int d = (jdir - 8) / 8, v = (jdir - 8) % 8;
-      if (v == 5 + d) continue;
-    }
-    Dual<T> dw[8], dsl[3][8], dH[8];
-    for (int v = 0; v < 8; ++v) dw[v] = Dual<T>(w[v], jdir == v ? T(1) : T(0));
-    for (int d = 0; d < 3; ++d)
-      for (int v = 0; v < 8; ++v) dsl[d][v] = Dual<T>(sl[d][v], jdir == 8 + d * 8 + v ? T(1) : T(0));
-    hancock<Dual<T>, DualExact<T>>(dw, dsl, hd, g, dH);
-    T acc = T(0);
-    for (int v = 0; v < 8; ++v) acc += lh[v] * dH[v].d;
-    if (jdir < 8)
-      LW[jdir * NC + o] += acc;
-    else
-      LS[(int64_t)(jdir - 8) * NC + o] += acc;
+  const T gamma = T(S.gamma);
+  // H = w - hdtdx sum(w, sl), with sum the Hancock terms of each direction
+  // (mhd_dev.h, hancock): reverse mode by hand.  a = -hdtdx lam_H is the
+  // cotangent of sum; sl[d][5 + d] is not an input.
+  const T ir = T(1) / w[0];
+  T a[8], gw[8];
+  for (int v = 0; v < 8; ++v) {
+    a[v] = -hdtdx * lh[v];
+    gw[v] = lh[v];
   }
+  T gir = T(0);  // cotangent of 1/rho
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+    const T un = w[1 + d], bn = w[5 + d], b1 = w[5 + t1], b2 = w[5 + t2];
+    const T* sd = sl[d];
+    const T A0 = a[0], A1 = a[1 + d], A2 = a[1 + t1], A3 = a[1 + t2], A4 = a[4], A5 = a[5 + t1], A6 = a[5 + t2];
+    // slopes of direction d
+    T gs[8];
+    gs[0] = A0 * un;
+    gs[1 + d] = A0 * w[0] + A1 * un + A4 * gamma * w[4] + A5 * b1 + A6 * b2;
+    gs[1 + t1] = A2 * un - A5 * bn;
+    gs[1 + t2] = A3 * un - A6 * bn;
+    gs[4] = A1 * ir + A4 * un;
+    gs[5 + t1] = A1 * b1 * ir - A2 * bn * ir + A5 * un;
+    gs[5 + t2] = A1 * b2 * ir - A3 * bn * ir + A6 * un;
+    gs[5 + d] = T(0);
+    for (int v = 0; v < 8; ++v)
+      if (v != 5 + d) LS[(int64_t)(d * 8 + v) * NC + o] += gs[v];
+    // primitives
+    gw[1 + d] += A0 * sd[0] + A1 * sd[1 + d] + A2 * sd[1 + t1] + A3 * sd[1 + t2] + A4 * sd[4] +
+                 A5 * sd[5 + t1] + A6 * sd[5 + t2];
+    gw[0] += A0 * sd[1 + d];
+    gir += A1 * (sd[4] + b1 * sd[5 + t1] + b2 * sd[5 + t2]) - A2 * bn * sd[5 + t1] - A3 * bn * sd[5 + t2];
+    gw[4] += A4 * gamma * sd[1 + d];
+    gw[5 + t1] += A1 * sd[5 + t1] * ir + A5 * sd[1 + d];
+    gw[5 + t2] += A1 * sd[5 + t2] * ir + A6 * sd[1 + d];
+    gw[5 + d] += -(A2 * sd[5 + t1] + A3 * sd[5 + t2]) * ir - A5 * sd[1 + t1] - A6 * sd[1 + t2];
+  }
+  gw[0] -= gir * ir * ir;
+  for (int v = 0; v < 8; ++v) LW[v * NC + o] += gw[v];
 }
 
 // ---------------------------------------------------------------------------
@@ -387,36 +407,52 @@ __global__ __launch_bounds__(256) void k_adj_pred(DevSet S, const int* __restric
 
 template <class T>
 __global__ __launch_bounds__(256) void k_adj_slope(DevSet S, const int* __restrict__ list, int count, WorkPtr<T> W, WorkPtr<T> L) {
+  // Gathered per padded cell c: the slope of cell x = c + s e_d (x in
+  // [-1, n]^3) is van Leer of dl = w(x) - w(x - e_d), dr = w(x + e_d) - w(x),
+  // with partials 2 dr^2 / (dl + dr)^2 on dl and 2 dl^2 / (dl + dr)^2 on dr,
+  // so c receives lam_s(x) times -gl (s = 1), gl - gr (s = 0) or gr (s = -1).
   const int b = blockIdx.y;
   if (b >= count) return;
   const int p = list[b];
-  const int n = S.n[p], N = n + 4, M = n + 2;
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= (int64_t)M * M * M) return;
-  const int i = (int)(c % M) - 1, j = (int)((c / M) % M) - 1, k = (int)(c / ((int64_t)M * M)) - 1;
+  const int n = S.n[p], N = n + 4;
   const int64_t NC = (int64_t)N * N * N;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= NC) return;
+  const int cc[3] = {(int)(c % N) - 2, (int)((c / N) % N) - 2, (int)(c / ((int64_t)N * N)) - 2};
   const T* Wp = W.w + (int64_t)b * W.w_stride;
   const T* LS = L.s + (int64_t)b * L.s_stride;
   T* LW = L.w + (int64_t)b * L.w_stride;
-  const int64_t o = wcell(N, 0, i, j, k);
+  auto inside = [&](const int* x) {
+    return x[0] >= -1 && x[0] <= n && x[1] >= -1 && x[1] <= n && x[2] >= -1 && x[2] <= n;
+  };
+  T acc[8];
+  for (int v = 0; v < 8; ++v) acc[v] = T(0);
   for (int d = 0; d < 3; ++d) {
-    int im = i, jm = j, km = k, ip = i, jp = j, kp = k;
-    if (d == 0) { im--; ip++; } else if (d == 1) { jm--; jp++; } else { km--; kp++; }
-    const int64_t om = wcell(N, 0, im, jm, km), op = wcell(N, 0, ip, jp, kp);
-    for (int v = 0; v < 8; ++v) {
-      if (v == 5 + d) continue;
-      const T ls = LS[(int64_t)(d * 8 + v) * NC + o];
-      if (ls == T(0)) continue;
-      const T w0 = Wp[v * NC + o];
-      const T dl = w0 - Wp[v * NC + om], dr = Wp[v * NC + op] - w0;
-      if (!(dl * dr > T(0))) continue;  // limited to zero: no dependence
-      const T sum = dl + dr;
-      const T gl = T(2) * dr * dr / (sum * sum), gr = T(2) * dl * dl / (sum * sum);
-      atomicAdd(&LW[v * NC + om], -ls * gl);
-      atomicAdd(&LW[v * NC + o], ls * (gl - gr));
-      atomicAdd(&LW[v * NC + op], ls * gr);
+    for (int s = -1; s <= 1; ++s) {
+      int x[3] = {cc[0], cc[1], cc[2]};
+      x[d] += s;
+      if (!inside(x)) continue;
+      int xm[3] = {x[0], x[1], x[2]}, xp[3] = {x[0], x[1], x[2]};
+      xm[d] -= 1;
+      xp[d] += 1;
+      const int64_t o = wcell(N, 0, x[0], x[1], x[2]);
+      const int64_t om = wcell(N, 0, xm[0], xm[1], xm[2]), op = wcell(N, 0, xp[0], xp[1], xp[2]);
+      for (int v = 0; v < 8; ++v) {
+        if (v == 5 + d) continue;
+        const T ls = LS[(int64_t)(d * 8 + v) * NC + o];
+        if (ls == T(0)) continue;
+        const T w0 = Wp[v * NC + o];
+        const T dl = w0 - Wp[v * NC + om], dr = Wp[v * NC + op] - w0;
+        if (!(dl * dr > T(0))) continue;  // limited to zero: no dependence
+        const T sum = dl + dr;
+        const T gl = T(2) * dr * dr / (sum * sum), gr = T(2) * dl * dl / (sum * sum);
+        acc[v] += s == 0 ? ls * (gl - gr) : (s > 0 ? -ls * gl : ls * gr);
+      }
     }
   }
+  const int64_t oc = wcell(N, 0, cc[0], cc[1], cc[2]);
+  for (int v = 0; v < 8; ++v)
+    if (acc[v] != T(0)) LW[v * NC + oc] += acc[v];
 }
 
 // ---------------------------------------------------------------------------
@@ -558,7 +594,7 @@ void launch_adjoint_step(const DevSet& S, const int* list, int count, int nmax, 
                      L);
   hipLaunchKernelGGL(k_adj_pred<T>, dim3(blocks((int64_t)M * M * M), count), dim3(256), 0, s, S, list, count, W, L,
                      st);
-  hipLaunchKernelGGL(k_adj_slope<T>, dim3(blocks((int64_t)M * M * M), count), dim3(256), 0, s, S, list, count, W, L);
+  hipLaunchKernelGGL(k_adj_slope<T>, dim3(blocks((int64_t)N * N * N), count), dim3(256), 0, s, S, list, count, W, L);
   hipLaunchKernelGGL(k_adj_prim<T>, dim3(blocks((int64_t)N * N * N), count), dim3(256), 0, s, S, list, count, W, L);
   hipLaunchKernelGGL(k_adj_fill<T>, dim3(blocks(5LL * N * N * N + 3LL * N * N * (N + 1)), count), dim3(256), 0, s,
                      S, list, count, L, lam_prev, host_off);
