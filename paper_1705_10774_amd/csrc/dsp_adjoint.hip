@@ -182,7 +182,7 @@ __global__ __launch_bounds__(256) void k_adj_emf(DevSet S, const int* __restrict
 // interface fluxes
 
 template <class T>
-__global__ __launch_bounds__(256) void k_adj_flux(DevSet S, const int* __restrict__ list, int count, WorkPtr<T> W, WorkPtr<T> L) {
+__global__ __launch_bounds__(256, 2) void k_adj_flux(DevSet S, const int* __restrict__ list, int count, WorkPtr<T> W, WorkPtr<T> L) {
   const int b = blockIdx.y;
   if (b >= count) return;
   const int p = list[b];
