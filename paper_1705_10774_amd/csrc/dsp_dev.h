@@ -29,6 +29,8 @@ struct GBox {
   int64_t wrap[3];
 };
 
+struct Bracket;
+
 struct DevSet {
   int npatch, nslots, kmax, dt_mode, exact_time, klog_cap;
   double gamma, courant, dt_base, dt_fixed, p_floor;
@@ -63,6 +65,8 @@ struct DevSet {
   const int* nb_idx;
   const int* rbox_off;  // [npatch * 108 + 1]: boxes of (patch, component + 1, region)
   const GBox* boxes;
+  Bracket* brk;  // per box: its time bracket for the staged guard fill (k_brackets)
+  int maxbox;    // most boxes of one patch
   // counters and error bits
   int* err;
   unsigned long long* floor_hits;

@@ -31,6 +31,20 @@
 namespace dsp {
 
 // ---------------------------------------------------------------------------
+// k_brackets: the time bracket of every guard box of the listed patches at
+// the patch's current time (one thread per box), so that k_fill reads it
+// instead of searching the source's slices for every element.
+
+__global__ void k_brackets(DevSet S, const int* __restrict__ list, int count) {
+  const int b = blockIdx.y;
+  if (b >= count) return;
+  const int p = list[b];
+  const int m = S.rbox_off[p * 108] + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (m >= S.rbox_off[p * 108 + 108]) return;
+  S.brk[m] = bracket(S, S.boxes[m].q, S.ticks[p], S.tcur[p]);
+}
+
+// ---------------------------------------------------------------------------
 // k_fill: one thread per padded element (5 N^3 cell values, then 3 face
 // arrays) of patch list[b].
 
@@ -89,7 +103,7 @@ __global__ void k_fill(DevSet S, const int* __restrict__ list, int count, T* __r
     if (i < G.lo[0] || i > G.hi[0] || j < G.lo[1] || j > G.hi[1] || k < G.lo[2] || k > G.hi[2])
       continue;
     const int q = G.q;
-    const Bracket br = bracket(S, q, S.ticks[p], S.tcur[p]);
+    const Bracket br = S.brk[m];
     T val;
     if (G.same) {
       const int qi = i + G.shift[0], qj = j + G.shift[1], qk = k + G.shift[2];
@@ -795,6 +809,7 @@ void launch_update(const DevSet& S, const int* list, int count, int nmax, T* slo
   auto blocks = [&](int64_t elems) { return (unsigned)((elems + TPB - 1) / TPB); };
   (void)hipMemsetAsync(W.smax, 0, sizeof(double) * count, s);
   const int64_t fill_elems = 5LL * N * N * N + 3LL * N * N * (N + 1);
+  hipLaunchKernelGGL(k_brackets, dim3(blocks(S.maxbox > 0 ? S.maxbox : 1), count), dim3(TPB), 0, s, S, list, count);
   hipLaunchKernelGGL(k_fill<T>, dim3(blocks(fill_elems), count), dim3(TPB), 0, s, S, list, count, slots, W);
   hipLaunchKernelGGL(k_prim<T>, dim3(blocks((int64_t)N * N * N), count), dim3(TPB), 0, s, S, list, count, W);
   launch_dt(S, list, count, st, W.smax, s, dt_kind, t_end, clip);

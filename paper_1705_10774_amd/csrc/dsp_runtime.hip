@@ -26,6 +26,7 @@
 
 #include "../../include/dsp.h"
 #include "dsp_dev.h"
+#include "dsp_guard.h"
 
 using namespace dsp;
 
@@ -729,6 +730,8 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
   D.nb_idx = (const int*)up(nb_idx.data(), sizeof(int) * std::max<size_t>(1, nb_idx.size()));
   D.rbox_off = (const int*)up(rbox_off.data(), sizeof(int) * rbox_off.size());
   D.boxes = (const GBox*)up(boxes.data(), sizeof(GBox) * std::max<size_t>(1, boxes.size()));
+  D.brk = (Bracket*)A(sizeof(Bracket) * std::max<size_t>(1, boxes.size()));
+  for (int p = 0; p < npatch; ++p) D.maxbox = std::max(D.maxbox, rbox_off[(p + 1) * 108] - rbox_off[p * 108]);
   s->d_err = (int*)A(sizeof(int) * 2);
   s->d_cnt = (unsigned long long*)A(sizeof(unsigned long long) * 4);  // floor, fallback, updates, bytes
   D.err = s->d_err;
