@@ -498,12 +498,16 @@ __device__ __forceinline__ void face_states(const StepSmem<T>& sm, int d, int pa
   }
 }
 
-template <class T>
+// FN as for k_step2: a compile-time patch size for sets of equal one-tile
+// patches whose guard regions are single same-resolution boxes.
+template <class T, int FN>
 __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__ list, int count,
                                                T* __restrict__ slots, const T* __restrict__ pad,
                                                int64_t pad_stride, StepPtr st, int tpa, int fuse_dt) {
+  static_assert(FN >= 0 && FN <= MT, "a fixed patch size is one tile");
   __shared__ StepSmem<T> sm;
   const int tid = threadIdx.x;
+  if (FN) tpa = 1;
   const int T2 = tpa * tpa;  // tile slots per patch
   const int w = blockIdx.x;
   const int bidx = (w / (8 * T2)) * 8 + (w % 8);
@@ -511,7 +515,7 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
   if (bidx >= live_count(S, count)) return;
   PatchCtx<T> c;
   c.p = list[bidx];
-  const int n = c.n = S.n[c.p];
+  const int n = c.n = FN ? FN : S.n[c.p];
   const int nt = (n + MT - 1) / MT;
   const int tx = tile % tpa, ty = tile / tpa;
   if (tx >= nt || ty >= nt) return;
@@ -534,7 +538,7 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
   if (tid == 0) traffic = 0;
   __syncthreads();
   if (tile == 0) count_traffic(S, c.p, box0, nbox, V, (int)sizeof(T), tid, NTHR, &traffic);
-  const double dt = fuse_dt ? fused_local_dt(S, c, sm.rt, st, bidx, tid, NTHR, red) : st.dt[bidx];
+  const double dt = fuse_dt ? fused_local_dt<T, FN>(S, c, sm.rt, st, bidx, tid, NTHR, red) : st.dt[bidx];
   const T dtdx = T(dt / S.dx[c.p]);
   const T hdtdx = T(0.5) * dtdx;
   __syncthreads();
@@ -557,8 +561,8 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
   T Wm[8], W0[8], Wp[8];
   T bx0 = 0, by0 = 0, bz0 = 0, bxp = 0, byp = 0, bzp = 0, dummy;
   if (col) {
-    load_cell(c, sm.rt, ci, cj, -2, gamma, pfloor, Wm, dummy, dummy, dummy);
-    load_cell(c, sm.rt, ci, cj, -1, gamma, pfloor, W0, bx0, by0, bz0);
+    load_cell<T, Exact<T>, FN>(c, sm.rt, ci, cj, -2, gamma, pfloor, Wm, dummy, dummy, dummy);
+    load_cell<T, Exact<T>, FN>(c, sm.rt, ci, cj, -1, gamma, pfloor, W0, bx0, by0, bz0);
   }
   T tl[7];     // top state of the previous plane's z-face (rotated z, x, y)
   T dzl = 0;   // normal-field increment of the previous plane
@@ -573,7 +577,7 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
   for (int z = -1; z <= n; ++z) {
     // ---- P1: load plane z+1; publish plane z primitives and lo-face fields
     if (col) {
-      load_cell(c, sm.rt, ci, cj, z + 1, gamma, pfloor, Wp, bxp, byp, bzp);
+      load_cell<T, Exact<T>, FN>(c, sm.rt, ci, cj, z + 1, gamma, pfloor, Wp, bxp, byp, bzp);
 #pragma unroll
       for (int v = 0; v < 8; ++v) sm.a.w[v][tid] = W0[v];
       sm.bf[0][tid] = bx0;
@@ -1306,9 +1310,14 @@ int launch_fused(const DevSet& S, const int* list, int count, int nmin, int nmax
     else
       hipLaunchKernelGGL((k_step2<T, 0>), dim3(groups), dim3(NTHR2), 0, s, S, list, count, slots, (const T*)pad,
                          pad_stride, st, tpa, fuse_dt);
-  } else
-    hipLaunchKernelGGL(k_step<T>, dim3(groups), dim3(NTHR), 0, s, S, list, count, slots, (const T*)pad, pad_stride,
-                       st, tpa, fuse_dt);
+  } else {
+    if (nmin == 16 && nmax == 16 && !gfill)
+      hipLaunchKernelGGL((k_step<T, 16>), dim3(groups), dim3(NTHR), 0, s, S, list, count, slots, (const T*)pad,
+                         pad_stride, st, tpa, fuse_dt);
+    else
+      hipLaunchKernelGGL((k_step<T, 0>), dim3(groups), dim3(NTHR), 0, s, S, list, count, slots, (const T*)pad,
+                         pad_stride, st, tpa, fuse_dt);
+  }
   if (ev1) (void)hipEventRecord(ev1, s);
   return fuse_dt;
 }
