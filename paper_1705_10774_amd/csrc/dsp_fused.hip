@@ -113,35 +113,36 @@ __device__ __forceinline__ void load_cell(const PatchCtx<T>& c, const RegionTab<
   bzl = zl;
 }
 
-// load_cell in two halves, for a fixed patch size: raw_issue starts the
-// reads of one cell (both time slices of each value), raw_finish blends and
-// converts them exactly as load_cell does, so independent work can run while
-// the reads are in flight.
+// load_cell in two halves: raw_issue starts the reads of one cell (both time
+// slices of each value), raw_finish blends and converts them exactly as
+// load_cell does, so independent work can run while the reads are in flight.
+// n: cells per edge of the patch (FN when FN > 0).
 template <class T> struct RawCell {
   T a[11], b[11];
 };
 template <class T, int FN>
-__device__ __forceinline__ void raw_issue(const RegionTab<T>& rt, int i, int j, int k, RawCell<T>& r) {
-  static_assert(FN > 0, "fixed patch size only");
+__device__ __forceinline__ void raw_issue(int n, const RegionTab<T>& rt, int i, int j, int k, RawCell<T>& r) {
+  if (FN) n = FN;
 #pragma unroll
-  for (int v = 0; v < 5; ++v) fetch_pair<T, FN>(FN, rt, -1, v, i, j, k, r.a[v], r.b[v]);
-  fetch_pair<T, FN>(FN, rt, 0, 0, i, j, k, r.a[5], r.b[5]);
-  fetch_pair<T, FN>(FN, rt, 0, 0, i + 1, j, k, r.a[6], r.b[6]);
-  fetch_pair<T, FN>(FN, rt, 1, 0, i, j, k, r.a[7], r.b[7]);
-  fetch_pair<T, FN>(FN, rt, 1, 0, i, j + 1, k, r.a[8], r.b[8]);
-  fetch_pair<T, FN>(FN, rt, 2, 0, i, j, k, r.a[9], r.b[9]);
-  fetch_pair<T, FN>(FN, rt, 2, 0, i, j, k + 1, r.a[10], r.b[10]);
+  for (int v = 0; v < 5; ++v) fetch_pair<T, FN>(n, rt, -1, v, i, j, k, r.a[v], r.b[v]);
+  fetch_pair<T, FN>(n, rt, 0, 0, i, j, k, r.a[5], r.b[5]);
+  fetch_pair<T, FN>(n, rt, 0, 0, i + 1, j, k, r.a[6], r.b[6]);
+  fetch_pair<T, FN>(n, rt, 1, 0, i, j, k, r.a[7], r.b[7]);
+  fetch_pair<T, FN>(n, rt, 1, 0, i, j + 1, k, r.a[8], r.b[8]);
+  fetch_pair<T, FN>(n, rt, 2, 0, i, j, k, r.a[9], r.b[9]);
+  fetch_pair<T, FN>(n, rt, 2, 0, i, j, k + 1, r.a[10], r.b[10]);
 }
 template <class T, class M, int FN>
-__device__ __forceinline__ void raw_finish(const RegionTab<T>& rt, int i, int j, int k, const RawCell<T>& r,
+__device__ __forceinline__ void raw_finish(int n, const RegionTab<T>& rt, int i, int j, int k, const RawCell<T>& r,
                                            T gamma, T pfloor, T* w, T& bxl, T& byl, T& bzl) {
+  if (FN) n = FN;
   T v[11];
-  const T wc = blend_weight(FN, rt, -1, i, j, k);
+  const T wc = blend_weight(n, rt, -1, i, j, k);
 #pragma unroll
   for (int q = 0; q < 5; ++q) v[q] = r.a[q] + wc * (r.b[q] - r.a[q]);
-  const T wf[6] = {blend_weight(FN, rt, 0, i, j, k),     blend_weight(FN, rt, 0, i + 1, j, k),
-                   blend_weight(FN, rt, 1, i, j, k),     blend_weight(FN, rt, 1, i, j + 1, k),
-                   blend_weight(FN, rt, 2, i, j, k),     blend_weight(FN, rt, 2, i, j, k + 1)};
+  const T wf[6] = {blend_weight(n, rt, 0, i, j, k),     blend_weight(n, rt, 0, i + 1, j, k),
+                   blend_weight(n, rt, 1, i, j, k),     blend_weight(n, rt, 1, i, j + 1, k),
+                   blend_weight(n, rt, 2, i, j, k),     blend_weight(n, rt, 2, i, j, k + 1)};
 #pragma unroll
   for (int q = 0; q < 6; ++q) v[5 + q] = r.a[5 + q] + wf[q] * (r.b[5 + q] - r.a[5 + q]);
   prim_of<T, M>(v[0], v[1], v[2], v[3], v[4], T(0.5) * (v[5] + v[6]), T(0.5) * (v[7] + v[8]),
@@ -961,10 +962,10 @@ __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict
   auto own_c = [&](int v, int lo, int hi, bool first, bool last) {
     return (v >= lo && v < hi) || (first && v < 0) || (last && v >= n);
   };
-  // FN > 0: plane z + 2 is read during the face phase of plane z (its ring
-  // slot, that of plane z - 1, is free by then), which saves the load phase
-  // and its barrier; FN = 0 loads plane z + 1 in a phase of its own.
-  constexpr bool PIPE = FN > 0;
+  // Plane z + 2 is read during the face phase of plane z (its ring slot,
+  // that of plane z - 1, is free by then), which saves a load phase and its
+  // barrier.  PIPE = false keeps the load of plane z + 1 in a phase of its own.
+  constexpr bool PIPE = true;
   auto store_plane = [&](int z, const T* wv, T bx, T by, T bz) {
     const int s3 = mod3(z);
 #pragma unroll
@@ -1059,7 +1060,7 @@ __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict
     const bool ld = PIPE && col && z + 2 <= n + 1;
     RawCell<T> raw;
     if constexpr (PIPE) {
-      if (ld) raw_issue<T, FN>(sm.rt, ci, cj, z + 2, raw);
+      if (ld) raw_issue<T, FN>(n, sm.rt, ci, cj, z + 2, raw);
     }
     const int nface = nxf + nyf + (z >= 0 ? nzf : 0);
     for (int m = lane; m < nface; m += NTHR2) {
@@ -1158,7 +1159,7 @@ __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict
     if constexpr (PIPE) {
       if (ld) {
         T wv[8], bx, by, bz;
-        raw_finish<T, M, FN>(sm.rt, ci, cj, z + 2, raw, gamma, pfloor, wv, bx, by, bz);
+        raw_finish<T, M, FN>(n, sm.rt, ci, cj, z + 2, raw, gamma, pfloor, wv, bx, by, bz);
         store_plane(z + 2, wv, bx, by, bz);
       }
     }
