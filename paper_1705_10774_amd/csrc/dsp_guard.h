@@ -204,6 +204,9 @@ __device__ T cross_value_from(const DevSet& S, int q, int comp, const int64_t* X
     a[d] = A < 0 ? 0 : (A > len ? len : A);
     b[d] = B < 0 ? 0 : (B > len ? len : B);
   }
+  // offsets in source cells: numerators are exact integers in double, so
+  // scaling by 1/sdx is within an ulp of the quotient
+  const double isdx = 1.0 / (double)sdx;
   auto minmod = [](T x, T y) -> T {
     if (x * y <= T(0)) return T(0);
     return (fabs(x) < fabs(y)) ? x : y;
@@ -243,7 +246,7 @@ __device__ T cross_value_from(const DevSet& S, int q, int comp, const int64_t* X
             int64_t x0 = a[d] > (int64_t)ci[d] * sdx ? a[d] : (int64_t)ci[d] * sdx;
             int64_t x1 = b[d] < (int64_t)(ci[d] + 1) * sdx ? b[d] : (int64_t)(ci[d] + 1) * sdx;
             ov *= (double)(x1 - x0);
-            off[d] = (0.5 * (double)(x0 + x1) - ((double)ci[d] + 0.5) * (double)sdx) / (double)sdx;
+            off[d] = (0.5 * (double)(x0 + x1) - ((double)ci[d] + 0.5) * (double)sdx) * isdx;
           }
           if (ov <= 0.0) continue;
           const T v0 = get(i, j, k);
@@ -278,7 +281,7 @@ __device__ T cross_value_from(const DevSet& S, int q, int comp, const int64_t* X
         int64_t x0 = a[dd] > (int64_t)ti[m] * sdx ? a[dd] : (int64_t)ti[m] * sdx;
         int64_t x1 = b[dd] < (int64_t)(ti[m] + 1) * sdx ? b[dd] : (int64_t)(ti[m] + 1) * sdx;
         ov *= (double)(x1 - x0);
-        off[m] = (0.5 * (double)(x0 + x1) - ((double)ti[m] + 0.5) * (double)sdx) / (double)sdx;
+        off[m] = (0.5 * (double)(x0 + x1) - ((double)ti[m] + 0.5) * (double)sdx) * isdx;
       }
       if (ov <= 0.0) continue;
       T vv = T(0);
