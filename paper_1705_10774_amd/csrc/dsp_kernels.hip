@@ -668,8 +668,15 @@ __global__ void k_publish(DevSet S, const int* __restrict__ list, int count, Ste
 // ---------------------------------------------------------------------------
 // k_scan: readiness of every patch (Eq. (1), with the grace) and the ready list.
 
-__global__ void k_scan(DevSet S, int64_t T_end, int* __restrict__ list, int* __restrict__ counters) {
+__global__ void k_scan(DevSet S, int64_t T_end, int* __restrict__ list, int* __restrict__ counters,
+                       int* __restrict__ clear) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  // the other counter pair, which the next round's scan uses (the round
+  // before this one has finished reading it)
+  if (clear && p == 0) {
+    clear[0] = 0;
+    clear[1] = 0;
+  }
   if (p >= S.npatch) return;
   if (*S.err) return;  // an error stops the scheduling: later rounds find nothing to do
   if (S.frozen[p]) return;  // boundary patches never update
@@ -841,9 +848,10 @@ void launch_publish(const DevSet& S, const int* list, int count, const StepPtr& 
   hipLaunchKernelGGL(k_publish, dim3((count + 255) / 256), dim3(256), 0, s, S, list, count, st);
 }
 
-void launch_scan(const DevSet& S, int64_t T_end, int* list, int* counters, hipStream_t s) {
-  (void)hipMemsetAsync(counters, 0, 2 * sizeof(int), s);
-  hipLaunchKernelGGL(k_scan, dim3((S.npatch + 255) / 256), dim3(256), 0, s, S, T_end, list, counters);
+void launch_scan(const DevSet& S, int64_t T_end, int* list, int* counters, hipStream_t s, int* clear) {
+  // counters must be zero: cleared here, or by the previous scan (clear)
+  if (!clear) (void)hipMemsetAsync(counters, 0, 2 * sizeof(int), s);
+  hipLaunchKernelGGL(k_scan, dim3((S.npatch + 255) / 256), dim3(256), 0, s, S, T_end, list, counters, clear);
 }
 
 template <class T>

@@ -662,7 +662,7 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
   s->smax = (double*)A(sizeof(double) * s->B);
   s->d_list = (int*)A(sizeof(int) * npatch);
   s->d_single = (int*)A(sizeof(int) * 4);
-  s->d_counters = (int*)A(sizeof(int) * 4);
+  s->d_counters = (int*)A(sizeof(int) * 8);
   s->st.k = (int*)A(sizeof(int) * npatch);
   s->st.dtk = (int64_t*)A(sizeof(int64_t) * npatch);
   s->st.dt = (double*)A(sizeof(double) * npatch);
@@ -821,9 +821,11 @@ static int init_common(dsp_set* s, const double* U, const void* U_dev, double t0
   return 0;
 }
 
-static int read_err(dsp_set* s, int* counters_out) {
+static int read_err(dsp_set* s, int* counters_out, const int* counters = nullptr) {
   int hbuf[4] = {0, 0, 0, 0};
-  int e = hipck(hipMemcpyAsync(hbuf, s->d_counters, sizeof(int) * 2, hipMemcpyDeviceToHost, s->stream), "readback");
+  int e = hipck(hipMemcpyAsync(hbuf, counters ? counters : s->d_counters, sizeof(int) * 2, hipMemcpyDeviceToHost,
+                               s->stream),
+                "readback");
   if (!e) e = hipck(hipMemcpyAsync(hbuf + 2, s->d_err, sizeof(int), hipMemcpyDeviceToHost, s->stream), "readback");
   if (!e) e = hipck(hipStreamSynchronize(s->stream), "round");
   if (e) return e;
@@ -881,18 +883,22 @@ static int run_global(dsp_set* s, double t_end, int64_t T, int max_steps) {
 // patch reached t_end find an empty ready list and do nothing.
 static int run_local_device(dsp_set* s, double t_end, int64_t T, int64_t& rounds_done) {
   const int K = 16;
-  int e = hipck(hipMemsetAsync(s->d_counters + 2, 0, sizeof(int), s->stream), "rounds");
+  // two counter pairs, used by alternate rounds: each scan clears the pair
+  // of the round after it, so no clearing operation runs between rounds
+  int* const pair[2] = {s->d_counters + 4, s->d_counters + 6};
+  int e = hipck(hipMemsetAsync(s->d_counters + 2, 0, sizeof(int) * 6, s->stream), "rounds");
   if (e) return e;
-  s->D.live = s->d_counters;
   s->D.rounds = s->d_counters + 2;
   while (!e) {
-    for (int r = 0; r < K; ++r) {
-      launch_scan(s->D, T, s->d_list, s->d_counters, s->stream);
+    for (int r = 0; r < K; ++r) {  // K is even: every chunk starts on pair 0
+      int* const cur = pair[r & 1];
+      s->D.live = cur;
+      launch_scan(s->D, T, s->d_list, cur, s->stream, pair[(r + 1) & 1]);
       s->update_batch(0, s->np, 0, t_end, 0, s->d_list);
       launch_publish(s->D, s->d_list, s->np, s->st, s->stream);
     }
     int cnt[2];
-    e = read_err(s, cnt);
+    e = read_err(s, cnt, pair[(K - 1) & 1]);
     if (e) break;
     if (cnt[1] == 0) break;
     if (cnt[0] == 0) e = fail(DSP_ESTATE, "no ready patch but not done");
