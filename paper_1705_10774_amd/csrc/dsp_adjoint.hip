@@ -37,51 +37,66 @@ namespace dsp {
 template <class T>
 __global__ __launch_bounds__(256) void k_adj_update(DevSet S, const int* __restrict__ list, int count, WorkPtr<T> L, StepPtr st,
                              const T* __restrict__ lam, const int64_t* __restrict__ host_off) {
+  // Gathered, one writer per entry: the cells (lam to the padded state), the
+  // faces (lam of the face field to the padded state; the flux cotangents
+  // +dtdx lam of the cell above and -dtdx lam of the cell below) and the
+  // edges (the four faces whose curl the edge EMF enters).  L.f and L.e are
+  // zero on entry and first written here.
   const int blk = blockIdx.y;
   if (blk >= count) return;
   const int p = list[blk];
   const int n = S.n[p], N = n + 4;
-  const int64_t n3 = (int64_t)n * n * n, nf = (int64_t)n * n * (n + 1);
+  const int64_t n3 = (int64_t)n * n * n, nf = (int64_t)n * n * (n + 1), ne = (int64_t)n * (n + 1) * (n + 1);
   int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n3 + 3 * nf) return;
+  if (c >= n3 + 3 * nf + 3 * ne) return;
   const T* lo = lam + host_off[p];
   T* LP = L.pad + (int64_t)blk * L.pad_stride;
   const T dtdx = (T)(st.dt[blk] / S.dx[p]);
   const int64_t fs = L.fm3;
   if (c < n3) {
     const int i = (int)(c % n), j = (int)((c / n) % n), k = (int)(c / ((int64_t)n * n));
-    for (int v = 0; v < 5; ++v) {
-      const T lv = lo[scell(n, v, i, j, k)];
-      LP[pcell(N, v, i, j, k)] += lv;
-      for (int d = 0; d < 3; ++d) {
-        T* LF = L.f + (int64_t)blk * L.f_stride + (int64_t)d * 8 * fs + (int64_t)v * fs;
-        int r[3] = {i, j, k};
-        r[d] += 1;
-        atomicAdd(&LF[wface(N, 0, r[0], r[1], r[2])], -dtdx * lv);
-        atomicAdd(&LF[wface(N, 0, i, j, k)], dtdx * lv);
-      }
-    }
+    for (int v = 0; v < 5; ++v) LP[pcell(N, v, i, j, k)] += lo[scell(n, v, i, j, k)];
     return;
   }
   c -= n3;
-  const int d = (int)(c / nf);
-  c -= d * nf;
-  const int sx = n + (d == 0), sy = n + (d == 1);
-  const int i = (int)(c % sx), j = (int)((c / sx) % sy), k = (int)(c / ((int64_t)sx * sy));
-  const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
-  const T lv = lo[sface(n, d, i, j, k)];
-  LP[pface(N, d, i, j, k)] += lv;
-  T* E1 = L.e + (int64_t)blk * L.e_stride + (int64_t)t1 * fs;
-  T* E2 = L.e + (int64_t)blk * L.e_stride + (int64_t)t2 * fs;
-  int p1[3] = {i, j, k}, p2[3] = {i, j, k};
-  p1[t1] += 1;
-  p2[t2] += 1;
-  const int64_t o0 = wface(N, 0, i, j, k);
-  // curl = (E2(p1) - E2(o)) - (E1(p2) - E1(o)); out = P - dtdx curl
-  atomicAdd(&E2[wface(N, 0, p1[0], p1[1], p1[2])], -dtdx * lv);
-  atomicAdd(&E2[o0], dtdx * lv);
-  atomicAdd(&E1[wface(N, 0, p2[0], p2[1], p2[2])], dtdx * lv);
-  atomicAdd(&E1[o0], -dtdx * lv);
+  if (c < 3 * nf) {
+    const int d = (int)(c / nf);
+    c -= d * nf;
+    const int sx = n + (d == 0), sy = n + (d == 1);
+    int f[3] = {(int)(c % sx), (int)((c / sx) % sy), (int)(c / ((int64_t)sx * sy))};
+    LP[pface(N, d, f[0], f[1], f[2])] += lo[sface(n, d, f[0], f[1], f[2])];
+    const int64_t of = wface(N, 0, f[0], f[1], f[2]);
+    T* LF = L.f + (int64_t)blk * L.f_stride + (int64_t)d * 8 * fs;
+    const bool above = f[d] < n, below = f[d] > 0;
+    int g[3] = {f[0], f[1], f[2]};
+    g[d] -= 1;
+    for (int v = 0; v < 5; ++v) {
+      const T a = above ? dtdx * lo[scell(n, v, f[0], f[1], f[2])] : T(0);
+      const T b = below ? -dtdx * lo[scell(n, v, g[0], g[1], g[2])] : T(0);
+      LF[v * fs + of] = a + b;
+    }
+    return;
+  }
+  c -= 3 * nf;
+  const int ax = (int)(c / ne);
+  c -= ax * ne;
+  const int x0 = ax == 0 ? n : n + 1, x1 = ax == 1 ? n : n + 1;
+  const int x[3] = {(int)(c % x0), (int)((c / x0) % x1), (int)(c / ((int64_t)x0 * x1))};
+  // lam of face (d, q) of the face field, 0 off the patch's faces
+  auto lamf = [&](int d, const int* q) -> T {
+    for (int e = 0; e < 3; ++e)
+      if (q[e] < 0 || q[e] > (e == d ? n : n - 1)) return T(0);
+    return lo[sface(n, d, q[0], q[1], q[2])];
+  };
+  // faces of direction d1 = ax + 1 see this edge as their E_t2 (at q and at
+  // q + e_t1), faces of direction d2 = ax + 2 as their E_t1 (at q and q + e_t2)
+  const int d1 = (ax + 1) % 3, d2 = (ax + 2) % 3;
+  const int t1 = (d1 + 1) % 3, t2 = (d2 + 2) % 3;
+  int q1[3] = {x[0], x[1], x[2]}, q2[3] = {x[0], x[1], x[2]};
+  q1[t1] -= 1;
+  q2[t2] -= 1;
+  const T e = (dtdx * lamf(d1, x) - dtdx * lamf(d1, q1)) + (dtdx * lamf(d2, q2) - dtdx * lamf(d2, x));
+  L.e[(int64_t)blk * L.e_stride + (int64_t)ax * fs + wface(N, 0, x[0], x[1], x[2])] = e;
 }
 
 // ---------------------------------------------------------------------------
@@ -584,8 +599,9 @@ void launch_adjoint_step(const DevSet& S, const int* list, int count, int nmax, 
   const int n = nmax, N = n + 4, M = n + 2;
   auto blocks = [](int64_t items) { return (unsigned)((items + 255) / 256); };
   const int64_t n3 = (int64_t)n * n * n, nf = (int64_t)n * n * (n + 1);
-  hipLaunchKernelGGL(k_adj_update<T>, dim3(blocks(n3 + 3 * nf), count), dim3(256), 0, s, S, list, count, L, st,
-                     lam_next, host_off);
+  const int64_t ne = (int64_t)n * (n + 1) * (n + 1);
+  hipLaunchKernelGGL(k_adj_update<T>, dim3(blocks(n3 + 3 * nf + 3 * ne), count), dim3(256), 0, s, S, list, count, L,
+                     st, lam_next, host_off);
   hipLaunchKernelGGL(k_adj_emf<T>, dim3(blocks(3LL * n * (n + 1) * (n + 1)), count), dim3(256), 0, s, S, list, count,
                      W, L);
   hipLaunchKernelGGL(k_adj_flux<T>, dim3(blocks(3LL * (n + 1) * M * M), count), dim3(256), 0, s, S, list, count, W,
