@@ -41,12 +41,14 @@ __global__ __launch_bounds__(256) void k_adj_update(DevSet S, const int* __restr
   // faces (lam of the face field to the padded state; the flux cotangents
   // +dtdx lam of the cell above and -dtdx lam of the cell below) and the
   // edges (the four faces whose curl the edge EMF enters).  L.f and L.e are
-  // zero on entry and first written here.
+  // first written here, every entry that later kernels read: all eight
+  // slots of the faces of [-1, n] in the transverse directions (zero where
+  // no cell updates), and every edge; so they need no clearing.
   const int blk = blockIdx.y;
   if (blk >= count) return;
   const int p = list[blk];
-  const int n = S.n[p], N = n + 4;
-  const int64_t n3 = (int64_t)n * n * n, nf = (int64_t)n * n * (n + 1), ne = (int64_t)n * (n + 1) * (n + 1);
+  const int n = S.n[p], N = n + 4, M = n + 2;
+  const int64_t n3 = (int64_t)n * n * n, nf = (int64_t)(n + 1) * M * M, ne = (int64_t)n * (n + 1) * (n + 1);
   int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n3 + 3 * nf + 3 * ne) return;
   const T* lo = lam + host_off[p];
@@ -60,14 +62,19 @@ __global__ __launch_bounds__(256) void k_adj_update(DevSet S, const int* __restr
   }
   c -= n3;
   if (c < 3 * nf) {
+    // faces f[d] in [0, n], the other two indices in [-1, n]; x fastest
     const int d = (int)(c / nf);
     c -= d * nf;
-    const int sx = n + (d == 0), sy = n + (d == 1);
-    int f[3] = {(int)(c % sx), (int)((c / sx) % sy), (int)(c / ((int64_t)sx * sy))};
-    LP[pface(N, d, f[0], f[1], f[2])] += lo[sface(n, d, f[0], f[1], f[2])];
+    const int e0 = d == 0 ? n + 1 : M, e1 = d == 1 ? n + 1 : M;
+    int f[3] = {(int)(c % e0) - (d == 0 ? 0 : 1), (int)((c / e0) % e1) - (d == 1 ? 0 : 1),
+                (int)(c / ((int64_t)e0 * e1)) - (d == 2 ? 0 : 1)};
+    bool inner = true;  // a face of the patch (its face field and its two cells)
+    for (int e = 0; e < 3; ++e)
+      if (e != d) inner = inner && f[e] >= 0 && f[e] < n;
+    if (inner) LP[pface(N, d, f[0], f[1], f[2])] += lo[sface(n, d, f[0], f[1], f[2])];
     const int64_t of = wface(N, 0, f[0], f[1], f[2]);
     T* LF = L.f + (int64_t)blk * L.f_stride + (int64_t)d * 8 * fs;
-    const bool above = f[d] < n, below = f[d] > 0;
+    const bool above = inner && f[d] < n, below = inner && f[d] > 0;
     int g[3] = {f[0], f[1], f[2]};
     g[d] -= 1;
     for (int v = 0; v < 5; ++v) {
@@ -75,6 +82,7 @@ __global__ __launch_bounds__(256) void k_adj_update(DevSet S, const int* __restr
       const T b = below ? -dtdx * lo[scell(n, v, g[0], g[1], g[2])] : T(0);
       LF[v * fs + of] = a + b;
     }
+    for (int v = 5; v < 8; ++v) LF[v * fs + of] = T(0);
     return;
   }
   c -= 3 * nf;
@@ -330,8 +338,9 @@ __global__ __launch_bounds__(256) void k_adj_flux_sum(DevSet S, const int* __res
         aW[5 + d] -= hb;
       }
     }
+    // the first writer of the slope cotangents of [-1, n]^3 (no clearing)
     for (int v = 0; v < 8; ++v)
-      if (aS[v] != T(0)) LS[(int64_t)(d * 8 + v) * NC + oc] += aS[v];
+      if (v != 5 + d) LS[(int64_t)(d * 8 + v) * NC + oc] = aS[v];
   }
   T* LW = L.w + (int64_t)b * L.w_stride;
   T* LH = L.h + (int64_t)b * L.w_stride;
@@ -598,9 +607,9 @@ void launch_adjoint_step(const DevSet& S, const int* list, int count, int nmax, 
                          const int64_t* host_off, hipStream_t s) {
   const int n = nmax, N = n + 4, M = n + 2;
   auto blocks = [](int64_t items) { return (unsigned)((items + 255) / 256); };
-  const int64_t n3 = (int64_t)n * n * n, nf = (int64_t)n * n * (n + 1);
-  const int64_t ne = (int64_t)n * (n + 1) * (n + 1);
-  hipLaunchKernelGGL(k_adj_update<T>, dim3(blocks(n3 + 3 * nf + 3 * ne), count), dim3(256), 0, s, S, list, count, L,
+  const int64_t n3 = (int64_t)n * n * n;
+  const int64_t ne = (int64_t)n * (n + 1) * (n + 1), nfm = (int64_t)(n + 1) * M * M;
+  hipLaunchKernelGGL(k_adj_update<T>, dim3(blocks(n3 + 3 * nfm + 3 * ne), count), dim3(256), 0, s, S, list, count, L,
                      st, lam_next, host_off);
   hipLaunchKernelGGL(k_adj_emf<T>, dim3(blocks(3LL * n * (n + 1) * (n + 1)), count), dim3(256), 0, s, S, list, count,
                      W, L);

@@ -1161,8 +1161,11 @@ static int adjoint_run(dsp_set* s, const T* ckpt, const T* lamT, T* lam0, int ns
     for (int j = len - 1; j >= 0 && !e; --j) {
       e = staged_fixed_step<T>(s, states + (size_t)j * V, (T*)nullptr);
       if (e) break;
-      for (int q = 0; q < 6; ++q) {
-        const int64_t sizes[6] = {s->pad_stride, s->w_stride, s->w_stride, s->s_stride, s->f_stride, s->e_stride};
+      // padded state, primitives and half-step state take atomic or
+      // accumulated cotangents; the slope, flux and edge buffers are written
+      // whole by their first writer in the step (k_adj_flux_sum, k_adj_update)
+      for (int q = 0; q < 3; ++q) {
+        const int64_t sizes[3] = {s->pad_stride, s->w_stride, s->w_stride};
         (void)hipMemsetAsync(s->adj_l[q], 0, sizeof(T) * (size_t)sizes[q] * s->np, s->stream);
       }
       (void)hipMemsetAsync(lb, 0, sizeof(T) * V, s->stream);
