@@ -152,6 +152,7 @@ void launch_adjoint_step(const DevSet& S, const int* list, int count, int nmax, 
 void launch_dt(const DevSet& S, const int* list, int count, const StepPtr& st, const double* smax, hipStream_t s,
                int dt_kind, double t_end, int clip);
 void launch_publish(const DevSet& S, const int* list, int count, const StepPtr& st, hipStream_t s);
+void launch_reset_times(const DevSet& S, unsigned long long* cnt, hipStream_t s);
 void launch_scan(const DevSet& S, int64_t T_end, int* list, int* counters, hipStream_t s, int* clear = nullptr);
 template <class T> void launch_stats(const DevSet& S, const T* slots, double* out, hipStream_t s);
 template <class T>

@@ -844,6 +844,32 @@ void launch_dt(const DevSet& S, const int* list, int count, const StepPtr& st, c
     hipLaunchKernelGGL(k_dt_global, dim3(1), dim3(256), 0, s, S, list, count, st, smax, t_end, clip);
 }
 
+// Time records of every patch back to t = 0 with one valid slice (slot 0),
+// as a fresh initialisation at t0 = 0 in the exact-time modes, on the device;
+// the statistics counters are cleared, the error flags are kept.
+__global__ void k_reset_times(DevSet S, unsigned long long* cnt) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p == 0)
+    for (int q = 0; q < 4; ++q) cnt[q] = 0ULL;
+  if (p >= S.npatch) return;
+  const int ns = S.nslots;
+  S.cur[p] = 0;
+  S.ticks[p] = 0;
+  S.tcur[p] = 0.0;
+  for (int q = 0; q < ns; ++q) {
+    S.sticks[(int64_t)p * ns + q] = 0;
+    S.stime[(int64_t)p * ns + q] = 0.0;
+    S.svalid[(int64_t)p * ns + q] = q == 0 ? 1 : 0;
+  }
+  S.steps[p] = 0;
+  S.khash[p] = 1469598103934665603ull;
+  for (int m = 0; m < S.klog_cap; ++m) S.klog[(int64_t)p * S.klog_cap + m] = -2;
+}
+
+void launch_reset_times(const DevSet& S, unsigned long long* cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset_times, dim3((S.npatch + 255) / 256), dim3(256), 0, s, S, cnt);
+}
+
 void launch_publish(const DevSet& S, const int* list, int count, const StepPtr& st, hipStream_t s) {
   hipLaunchKernelGGL(k_publish, dim3((count + 255) / 256), dim3(256), 0, s, S, list, count, st);
 }

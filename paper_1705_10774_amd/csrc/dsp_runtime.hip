@@ -1129,8 +1129,11 @@ extern "C++" {
 // intermediate in the adjoint's work buffers; U_out (nullable) receives the
 // new state.
 template <class T> static int staged_fixed_step(dsp_set* s, const T* U_in, T* U_out) {
-  int e = reset_fixed(s, U_in);
-  if (e) return e;
+  // queued on the stream without a host round trip: time records reset on
+  // the device, the state unpacked from U_in; errors stay flagged until the
+  // caller reads them
+  launch_reset_times(s->D, s->d_cnt, s->stream);
+  launch_unpack<T>(s->D, (T*)s->slots, U_in, s->d_host_off, s->stream);
   launch_update<T>(s->D, s->d_list, s->np, s->nmax, (T*)s->slots, s->adj_work<T>(false), s->st, s->stream, 1, 0.0,
                    0, nullptr, nullptr);
   if (U_out) {
@@ -1151,6 +1154,7 @@ static int adjoint_run(dsp_set* s, const T* ckpt, const T* lamT, T* lam0, int ns
   T* la = (T*)s->adj_la;
   T* lb = (T*)s->adj_lb;
   e = hipck(hipMemcpyAsync(la, lamT, sizeof(T) * V, hipMemcpyDeviceToDevice, s->stream), "adjoint");
+  if (!e) e = hipck(hipMemsetAsync(s->d_err, 0, sizeof(int) * 2, s->stream), "adjoint");
   const WorkPtr<T> W = s->adj_work<T>(false), L = s->adj_work<T>(true);
   const int nseg = (nsteps + 7) / 8;
   for (int seg = nseg - 1; seg >= 0 && !e; --seg) {
@@ -1170,9 +1174,9 @@ static int adjoint_run(dsp_set* s, const T* ckpt, const T* lamT, T* lam0, int ns
       }
       (void)hipMemsetAsync(lb, 0, sizeof(T) * V, s->stream);
       launch_adjoint_step<T>(s->D, s->d_list, s->np, s->nmax, W, L, s->st, la, lb, s->d_host_off, s->stream);
-      e = read_err(s, nullptr);
       std::swap(la, lb);
     }
+    if (!e) e = read_err(s, nullptr);  // once per segment: the error flags stick
   }
   if (!e) e = hipck(hipMemcpyAsync(lam0, la, sizeof(T) * V, hipMemcpyDeviceToDevice, s->stream), "adjoint");
   if (!e) e = hipck(hipStreamSynchronize(s->stream), "adjoint");
