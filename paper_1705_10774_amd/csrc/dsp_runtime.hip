@@ -871,8 +871,12 @@ static int run_global(dsp_set* s, double t_end, int64_t T, int max_steps) {
     s->rounds++;
     nstep++;
     (void)hipMemsetAsync(s->d_counters, 0, sizeof(int) * 2, s->stream);
-    e = read_err(s, nullptr);
-    if (e) return e;
+    // a fixed number of steps is queued whole; the error flags stay set, so
+    // one check after the last step sees an error of any of them
+    if (max_steps < 0 || nstep >= max_steps) {
+      e = read_err(s, nullptr);
+      if (e) return e;
+    }
   }
 }
 
