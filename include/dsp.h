@@ -205,7 +205,10 @@ int dsp_fixed_steps_fwd(dsp_set* set, const void* U0_dev, void* UT_dev, int32_t 
 /* Reverse (adjoint) of nsteps fixed-dt steps: given lamT_dev = dJ/dU_T
  * (device, host layout, set precision), writes lam0_dev = dJ/dU_0, recomputing
  * forward states from the checkpoints written by dsp_fixed_steps_fwd.
- * seg: steps per checkpoint segment (must be 8). */
+ * seg: steps per checkpoint segment (must be 8).  The library allocates the
+ * work buffers on first use: the forward intermediates of all 8 steps of a
+ * segment when they take at most 16 GiB (each step is then recomputed once),
+ * else of one step (each step recomputed twice). */
 int dsp_fixed_steps_adj(dsp_set* set, const void* ckpt_dev, const void* lamT_dev,
                         void* lam0_dev, int32_t nsteps, int32_t seg);
 

@@ -359,10 +359,13 @@ struct dsp_set {
   // one launch sequence for list[off .. off+count)
   bool fused = true;  // fused marching kernel (false: staged kernels)
   bool any_generic = false;  // some guard region is not one same-resolution box
-  // adjoint: staged work buffers of the recomputed forward step, their
-  // cotangents, the states of one checkpoint segment and two cotangent
-  // vectors (allocated on first use)
+  // adjoint: staged work buffers of the recomputed forward steps (one set
+  // per step of a checkpoint segment when they fit in kAdjKeepBytes, else
+  // one set, refilled by a second recompute), their cotangents, the states
+  // of one segment and two cotangent vectors (allocated on first use)
+  static constexpr size_t kAdjKeepBytes = (size_t)16 << 30;
   bool adj_ready = false;
+  int adj_copies = 1;
   void* adj_w[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   void* adj_l[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   void *adj_states = nullptr, *adj_la = nullptr, *adj_lb = nullptr;
@@ -370,8 +373,13 @@ struct dsp_set {
     if (adj_ready) return 0;
     const size_t tsz = f32 ? 4 : 8;
     const int64_t sizes[6] = {pad_stride, w_stride, w_stride, s_stride, f_stride, e_stride};
+    size_t one = 0;
+    for (int q = 0; q < 6; ++q) one += tsz * (size_t)sizes[q] * np;
+    adj_copies = 8 * one <= kAdjKeepBytes ? 8 : 1;
+    const char* rc = getenv("DSP_ADJ_RECOMPUTE");  // "1": one set, each step recomputed twice
+    if (rc && std::string(rc) == "1") adj_copies = 1;
     for (int q = 0; q < 6; ++q) {
-      adj_w[q] = dalloc(tsz * (size_t)sizes[q] * np);
+      adj_w[q] = dalloc(tsz * (size_t)sizes[q] * np * adj_copies);
       adj_l[q] = dalloc(tsz * (size_t)sizes[q] * np);
     }
     adj_states = dalloc(tsz * (size_t)total_values * 8);
@@ -381,20 +389,21 @@ struct dsp_set {
     adj_ready = true;
     return 0;
   }
-  template <class T> WorkPtr<T> adj_work(bool cot) const {
+  // copy: which step's set of the forward work buffers (0 for cot)
+  template <class T> WorkPtr<T> adj_work(bool cot, int copy = 0) const {
     void* const* b = cot ? adj_l : adj_w;
     WorkPtr<T> W;
-    W.pad = (T*)b[0];
+    W.pad = (T*)b[0] + (int64_t)copy * pad_stride * np;
     W.pad_stride = pad_stride;
-    W.w = (T*)b[1];
-    W.h = (T*)b[2];
+    W.w = (T*)b[1] + (int64_t)copy * w_stride * np;
+    W.h = (T*)b[2] + (int64_t)copy * w_stride * np;
     W.w_stride = w_stride;
-    W.s = (T*)b[3];
+    W.s = (T*)b[3] + (int64_t)copy * s_stride * np;
     W.s_stride = s_stride;
-    W.f = (T*)b[4];
+    W.f = (T*)b[4] + (int64_t)copy * f_stride * np;
     W.f_stride = f_stride;
     W.fm3 = fm3;
-    W.e = (T*)b[5];
+    W.e = (T*)b[5] + (int64_t)copy * e_stride * np;
     W.e_stride = e_stride;
     W.smax = smax;
     return W;
@@ -1132,14 +1141,14 @@ extern "C++" {
 // One fixed step with the staged kernels from state U_in, leaving every
 // intermediate in the adjoint's work buffers; U_out (nullable) receives the
 // new state.
-template <class T> static int staged_fixed_step(dsp_set* s, const T* U_in, T* U_out) {
+template <class T> static int staged_fixed_step(dsp_set* s, const T* U_in, T* U_out, int copy) {
   // queued on the stream without a host round trip: time records reset on
   // the device, the state unpacked from U_in; errors stay flagged until the
   // caller reads them
   launch_reset_times(s->D, s->d_cnt, s->stream);
   launch_unpack<T>(s->D, (T*)s->slots, U_in, s->d_host_off, s->stream);
-  launch_update<T>(s->D, s->d_list, s->np, s->nmax, (T*)s->slots, s->adj_work<T>(false), s->st, s->stream, 1, 0.0,
-                   0, nullptr, nullptr);
+  launch_update<T>(s->D, s->d_list, s->np, s->nmax, (T*)s->slots, s->adj_work<T>(false, copy), s->st, s->stream, 1,
+                   0.0, 0, nullptr, nullptr);
   if (U_out) {
     launch_publish(s->D, s->d_list, s->np, s->st, s->stream);
     launch_pack<T>(s->D, (const T*)s->slots, U_out, s->d_host_off, s->stream);
@@ -1159,16 +1168,23 @@ static int adjoint_run(dsp_set* s, const T* ckpt, const T* lamT, T* lam0, int ns
   T* lb = (T*)s->adj_lb;
   e = hipck(hipMemcpyAsync(la, lamT, sizeof(T) * V, hipMemcpyDeviceToDevice, s->stream), "adjoint");
   if (!e) e = hipck(hipMemsetAsync(s->d_err, 0, sizeof(int) * 2, s->stream), "adjoint");
-  const WorkPtr<T> W = s->adj_work<T>(false), L = s->adj_work<T>(true);
+  const WorkPtr<T> L = s->adj_work<T>(true);
+  // with a set of work buffers per step, the segment's forward pass keeps
+  // every step's intermediates and the reverse pass uses them directly
+  const bool keep = s->adj_copies >= 8;
   const int nseg = (nsteps + 7) / 8;
   for (int seg = nseg - 1; seg >= 0 && !e; --seg) {
     const int len = std::min(8, nsteps - 8 * seg);
     e = hipck(hipMemcpyAsync(states, ckpt + (size_t)seg * V, sizeof(T) * V, hipMemcpyDeviceToDevice, s->stream),
               "adjoint");
-    for (int j = 1; j < len && !e; ++j) e = staged_fixed_step<T>(s, states + (size_t)(j - 1) * V, states + (size_t)j * V);
+    const int nfwd = keep ? len : len - 1;  // steps j < nfwd run forward here (into set j when kept)
+    for (int j = 0; j < nfwd && !e; ++j)
+      e = staged_fixed_step<T>(s, states + (size_t)j * V, j + 1 < len ? states + (size_t)(j + 1) * V : (T*)nullptr,
+                               keep ? j : 0);
     for (int j = len - 1; j >= 0 && !e; --j) {
-      e = staged_fixed_step<T>(s, states + (size_t)j * V, (T*)nullptr);
+      if (!keep) e = staged_fixed_step<T>(s, states + (size_t)j * V, (T*)nullptr, 0);
       if (e) break;
+      const WorkPtr<T> W = s->adj_work<T>(false, keep ? j : 0);
       // padded state, primitives and half-step state take atomic or
       // accumulated cotangents; the slope, flux and edge buffers are written
       // whole by their first writer in the step (k_adj_flux_sum, k_adj_update)

@@ -54,6 +54,28 @@ def test_adjoint_dot_product_fp64(orc, nsteps):
     assert abs(lhs - rhs) <= 1e-12 * scale
 
 
+def test_adjoint_recompute_path_matches_kept_intermediates(monkeypatch):
+    """The reverse run keeps each step's forward intermediates when they fit;
+    DSP_ADJ_RECOMPUTE=1 forces the path that recomputes them from the
+    segment's states instead.  Both give the same cotangent (up to the order
+    of the atomic additions)."""
+    nsteps = 11
+    rng = np.random.default_rng(311)
+    lam = {}
+    for mode in ("kept", "recompute"):
+        if mode == "recompute":
+            monkeypatch.setenv("DSP_ADJ_RECOMPUTE", "1")
+        torch, dsp, pr, s, dt = _setup()
+        U0 = torch.from_numpy(pr.U0).cuda()
+        if mode == "kept":
+            lamT = rng.normal(size=pr.U0.size)
+        UT, ckpt = s.fixed_steps_fwd(U0, nsteps)
+        lam[mode] = s.fixed_steps_adj(ckpt, torch.from_numpy(lamT).cuda(), nsteps).cpu().numpy()
+        s.close()
+    scale = np.abs(lam["kept"]).max()
+    assert np.abs(lam["kept"] - lam["recompute"]).max() <= 1e-12 * scale
+
+
 def test_adjoint_gradient_vs_central_difference():
     torch, dsp, pr, s, dt = _setup()
     nsteps = pr.nsteps
