@@ -121,46 +121,26 @@ template <class T> __device__ __forceinline__ void up_adj(T u, T lam, T& la, T& 
   }
 }
 
+// Cotangent weights of edge (a, e), e[a] in [0, n), the others in [0, n]:
+// E = (A + B + C + D)/4 + ((dc34 - dc14) + (db34 - db14))/4 with
+//   dc14 = up(uA, c01 - D, c11 - C), dc34 = up(uB, D - c00, C - c10),
+//   db14 = up(uC, c10 - B, c11 - A), db34 = up(uD, B - c00, A - c01),
+// A, B the b-face and C, D the c-face EMFs and c.. the cell EMFs around the
+// edge; l[0..3] = lam of A, B, C, D, l[4..7] = lam of c00, c10, c01, c11.
 template <class T>
-__global__ __launch_bounds__(256) void k_adj_emf(DevSet S, const int* __restrict__ list, int count, WorkPtr<T> W, WorkPtr<T> L) {
-  const int blk = blockIdx.y;
-  if (blk >= count) return;
-  const int p = list[blk];
-  const int n = S.n[p], N = n + 4;
-  const int64_t per = (int64_t)n * (n + 1) * (n + 1);
-  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= 3 * per) return;
-  const int a = (int)(c / per);
-  c -= a * per;
+__device__ __forceinline__ void emf_weights(const WorkPtr<T>& W, int blk, int N, int a, const int* e, T lamE, T* l) {
   const int bax = (a + 1) % 3, cax = (a + 2) % 3;
-  // edges e[a] in [0, n), the other two indices in [0, n]; x fastest
-  int e[3];
-  const int x0 = a == 0 ? n : n + 1, x1 = a == 1 ? n : n + 1;
-  e[0] = (int)(c % x0);
-  e[1] = (int)((c / x0) % x1);
-  e[2] = (int)(c / ((int64_t)x0 * x1));
   const int64_t fs = W.fm3;
-  const T lamE = L.e[(int64_t)blk * L.e_stride + (int64_t)a * fs + wface(N, 0, e[0], e[1], e[2])];
-  if (lamE == T(0)) return;
-  const T* Hp = W.h + (int64_t)blk * W.w_stride;
   const T* Fb = W.f + (int64_t)blk * W.f_stride + (int64_t)bax * 8 * fs;
   const T* Fc = W.f + (int64_t)blk * W.f_stride + (int64_t)cax * 8 * fs;
-  T* LH = L.h + (int64_t)blk * L.w_stride;
-  T* LFb = L.f + (int64_t)blk * L.f_stride + (int64_t)bax * 8 * fs;
-  T* LFc = L.f + (int64_t)blk * L.f_stride + (int64_t)cax * 8 * fs;
-  const int64_t NC = (int64_t)N * N * N;
-  int pA[3] = {e[0], e[1], e[2]}, pB[3] = {e[0], e[1], e[2]};
+  int pB[3] = {e[0], e[1], e[2]}, pD[3] = {e[0], e[1], e[2]};
   pB[cax] -= 1;
-  int pC[3] = {e[0], e[1], e[2]}, pD[3] = {e[0], e[1], e[2]};
   pD[bax] -= 1;
-  const int64_t oA = wface(N, 0, pA[0], pA[1], pA[2]), oB = wface(N, 0, pB[0], pB[1], pB[2]);
-  const int64_t oC = wface(N, 0, pC[0], pC[1], pC[2]), oD = wface(N, 0, pD[0], pD[1], pD[2]);
+  const int64_t oA = wface(N, 0, e[0], e[1], e[2]), oB = wface(N, 0, pB[0], pB[1], pB[2]);
+  const int64_t oD = wface(N, 0, pD[0], pD[1], pD[2]);
   // upwind speeds (the slot of the normal component holds them)
   const T uA = Fb[(5 + bax) * fs + oA], uB = Fb[(5 + bax) * fs + oB];
-  const T uC = Fc[(5 + cax) * fs + oC], uD = Fc[(5 + cax) * fs + oD];
-  // E = (A + B + C + D)/4 + ((dc34 - dc14) + (db34 - db14))/4 with
-  //   dc14 = up(uA, c01 - D, c11 - C), dc34 = up(uB, D - c00, C - c10),
-  //   db14 = up(uC, c10 - B, c11 - A), db34 = up(uD, B - c00, A - c01)
+  const T uC = Fc[(5 + cax) * fs + oA], uD = Fc[(5 + cax) * fs + oD];
   const T q = T(0.25) * lamE;
   T lA = q, lB = q, lC = q, lD = q, l00 = 0, l10 = 0, l01 = 0, l11 = 0;
   T x, y;
@@ -176,29 +156,108 @@ __global__ __launch_bounds__(256) void k_adj_emf(DevSet S, const int* __restrict
   x = y = T(0);  // db34: weight +q
   up_adj(uD, q, x, y);
   lB += x; l00 -= x; lA += y; l01 -= y;
-  // face EMFs: A = -Fb[B_c](oA), B = -Fb[B_c](oB), C = Fc[B_b](oC), D = Fc[B_b](oD)
-  atomicAdd(&LFb[(5 + cax) * fs + oA], -lA);
-  atomicAdd(&LFb[(5 + cax) * fs + oB], -lB);
-  atomicAdd(&LFc[(5 + bax) * fs + oC], lC);
-  atomicAdd(&LFc[(5 + bax) * fs + oD], lD);
-  // cell EMF E_a = v_c B_b - v_b B_c of the half-step state
-  auto cell = [&](int db, int dc, T lc) {
-    if (lc == T(0)) return;
-    int qq[3] = {e[0], e[1], e[2]};
-    qq[bax] += db;
-    qq[cax] += dc;
-    const int64_t o = wcell(N, 0, qq[0], qq[1], qq[2]);
+  l[0] = lA; l[1] = lB; l[2] = lC; l[3] = lD;
+  l[4] = l00; l[5] = l10; l[6] = l01; l[7] = l11;
+}
+
+// Pass 1: the weights of every edge, stored in the slope-cotangent buffer
+// (free until k_adj_flux_sum writes it): 8 per edge and direction, edges
+// x-fastest in the box [0, n)_a x [0, n]^2.
+template <class T>
+__global__ __launch_bounds__(256) void k_adj_emf(DevSet S, const int* __restrict__ list, int count, WorkPtr<T> W, WorkPtr<T> L) {
+  const int blk = blockIdx.y;
+  if (blk >= count) return;
+  const int p = list[blk];
+  const int n = S.n[p], N = n + 4;
+  const int64_t ne = (int64_t)n * (n + 1) * (n + 1);
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= 3 * ne) return;
+  const int a = (int)(c / ne);
+  c -= a * ne;
+  const int x0 = a == 0 ? n : n + 1, x1 = a == 1 ? n : n + 1;
+  const int e[3] = {(int)(c % x0), (int)((c / x0) % x1), (int)(c / ((int64_t)x0 * x1))};
+  const T lamE = L.e[(int64_t)blk * L.e_stride + (int64_t)a * W.fm3 + wface(N, 0, e[0], e[1], e[2])];
+  T l[8];
+  if (lamE == T(0)) {
+    for (int k = 0; k < 8; ++k) l[k] = T(0);
+  } else {
+    emf_weights(W, blk, N, a, e, lamE, l);
+  }
+  T* G = L.s + (int64_t)blk * L.s_stride + (int64_t)a * 8 * ne;
+  for (int k = 0; k < 8; ++k) G[k * ne + c] = l[k];
+}
+
+// Pass 2, one writer per entry: the face EMFs' weights to the induction
+// fluxes of the faces (A = -F_b[B_c], B likewise one c-cell lower, C = F_c[B_b],
+// D likewise one b-cell lower), the cell-EMF weights (E_a = v_c B_b - v_b B_c
+// of the half-step state) to the cells.  Faces of [-1, n] across, cells of
+// [-1, n]^3.
+template <class T>
+__global__ __launch_bounds__(256) void k_adj_emf_sum(DevSet S, const int* __restrict__ list, int count, WorkPtr<T> W,
+                                                     WorkPtr<T> L) {
+  const int blk = blockIdx.y;
+  if (blk >= count) return;
+  const int p = list[blk];
+  const int n = S.n[p], N = n + 4, M = n + 2;
+  const int64_t ne = (int64_t)n * (n + 1) * (n + 1), nfm = (int64_t)(n + 1) * M * M;
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= 3 * nfm + (int64_t)M * M * M) return;
+  const T* G = L.s + (int64_t)blk * L.s_stride;
+  // weight k of a-edge q (0 off the edge box)
+  auto wt = [&](int a, const int* q, int k) -> T {
+    const int x0 = a == 0 ? n : n + 1, x1 = a == 1 ? n : n + 1, x2 = a == 2 ? n : n + 1;
+    if (q[0] < 0 || q[0] >= x0 || q[1] < 0 || q[1] >= x1 || q[2] < 0 || q[2] >= x2) return T(0);
+    return G[((int64_t)a * 8 + k) * ne + ((int64_t)q[2] * x1 + q[1]) * x0 + q[0]];
+  };
+  const int64_t fs = W.fm3;
+  if (c < 3 * nfm) {
+    const int d = (int)(c / nfm);
+    c -= d * nfm;
+    const int e0 = d == 0 ? n + 1 : M, e1 = d == 1 ? n + 1 : M;
+    const int f[3] = {(int)(c % e0) - (d == 0 ? 0 : 1), (int)((c / e0) % e1) - (d == 1 ? 0 : 1),
+                      (int)(c / ((int64_t)e0 * e1)) - (d == 2 ? 0 : 1)};
+    const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+    // edges a1 = d + 2 (b-axis d, c-axis t1): A at the edge, B one t1-cell up
+    const int a1 = (d + 2) % 3, a2 = (d + 1) % 3;
+    int g1[3] = {f[0], f[1], f[2]}, g2[3] = {f[0], f[1], f[2]};
+    g1[t1] += 1;
+    g2[t2] += 1;
+    const T s1 = -wt(a1, f, 0) - wt(a1, g1, 1);
+    // edges a2 = d + 1 (c-axis d, b-axis t2): C at the edge, D one t2-cell up
+    const T s2 = wt(a2, f, 2) + wt(a2, g2, 3);
+    T* LF = L.f + (int64_t)blk * L.f_stride + (int64_t)d * 8 * fs;
+    const int64_t of = wface(N, 0, f[0], f[1], f[2]);
+    LF[(5 + t1) * fs + of] += s1;
+    LF[(5 + t2) * fs + of] += s2;
+    return;
+  }
+  c -= 3 * nfm;
+  const int qq[3] = {(int)(c % M) - 1, (int)((c / M) % M) - 1, (int)(c / ((int64_t)M * M)) - 1};
+  const int64_t NC = (int64_t)N * N * N;
+  const int64_t o = wcell(N, 0, qq[0], qq[1], qq[2]);
+  const T* Hp = W.h + (int64_t)blk * W.w_stride;
+  T* LH = L.h + (int64_t)blk * L.w_stride;
+  T acc[8];
+  for (int v = 0; v < 8; ++v) acc[v] = T(0);
+  for (int a = 0; a < 3; ++a) {
+    const int bax = (a + 1) % 3, cax = (a + 2) % 3;
+    // the cell is c00 of edge qq + e_b + e_c, c10 of qq + e_c, c01 of qq + e_b, c11 of qq
+    int e00[3] = {qq[0], qq[1], qq[2]}, e10[3] = {qq[0], qq[1], qq[2]}, e01[3] = {qq[0], qq[1], qq[2]};
+    e00[bax] += 1;
+    e00[cax] += 1;
+    e10[cax] += 1;
+    e01[bax] += 1;
+    const T lc = wt(a, e00, 4) + wt(a, e10, 5) + wt(a, e01, 6) + wt(a, qq, 7);
+    if (lc == T(0)) continue;
     const T vc = Hp[(1 + cax) * NC + o], bb = Hp[(5 + bax) * NC + o];
     const T vb = Hp[(1 + bax) * NC + o], bc = Hp[(5 + cax) * NC + o];
-    atomicAdd(&LH[(1 + cax) * NC + o], lc * bb);
-    atomicAdd(&LH[(5 + bax) * NC + o], lc * vc);
-    atomicAdd(&LH[(1 + bax) * NC + o], -lc * bc);
-    atomicAdd(&LH[(5 + cax) * NC + o], -lc * vb);
-  };
-  cell(-1, -1, l00);
-  cell(0, -1, l10);
-  cell(-1, 0, l01);
-  cell(0, 0, l11);
+    acc[1 + cax] += lc * bb;
+    acc[5 + bax] += lc * vc;
+    acc[1 + bax] -= lc * bc;
+    acc[5 + cax] -= lc * vb;
+  }
+  for (int v = 0; v < 8; ++v)
+    if (acc[v] != T(0)) LH[v * NC + o] += acc[v];
 }
 
 // ---------------------------------------------------------------------------
@@ -613,6 +672,8 @@ void launch_adjoint_step(const DevSet& S, const int* list, int count, int nmax, 
                      st, lam_next, host_off);
   hipLaunchKernelGGL(k_adj_emf<T>, dim3(blocks(3LL * n * (n + 1) * (n + 1)), count), dim3(256), 0, s, S, list, count,
                      W, L);
+  hipLaunchKernelGGL(k_adj_emf_sum<T>, dim3(blocks(3 * nfm + (int64_t)M * M * M), count), dim3(256), 0, s, S, list,
+                     count, W, L);
   hipLaunchKernelGGL(k_adj_flux<T>, dim3(blocks(3LL * (n + 1) * M * M), count), dim3(256), 0, s, S, list, count, W,
                      L);
   hipLaunchKernelGGL(k_adj_flux_sum<T>, dim3(blocks((int64_t)M * M * M), count), dim3(256), 0, s, S, list, count, W,
