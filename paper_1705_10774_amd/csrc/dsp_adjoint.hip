@@ -18,8 +18,8 @@
 // solver's wave pattern are those of the forward state: the result is the
 // derivative along the branches the forward step takes.  The Riemann solver
 // and the predictor have hand-written reverse passes (hlld_vjp.h, k_adj_pred).
-// The update, face and slope terms are gathered (one writer per entry); the
-// EMF, primitive and fill kernels scatter with atomic additions.
+// The update, EMF, face and slope terms are gathered (one writer per entry);
+// the primitive and fill kernels scatter with atomic additions.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
