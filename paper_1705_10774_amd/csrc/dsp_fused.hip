@@ -187,7 +187,7 @@ __device__ __attribute__((noinline)) FaceStates<T> fallback_states(const PatchCt
 constexpr int GSTAGE = 8192;  // staged source values per workgroup
 
 template <class T>
-__global__ __launch_bounds__(256) void k_gfill(DevSet S, const int* __restrict__ list, int count,
+__global__ __launch_bounds__(256, 4) void k_gfill(DevSet S, const int* __restrict__ list, int count,
                                                const T* __restrict__ slots, T* __restrict__ pad,
                                                int64_t pad_stride) {
   __shared__ T stage[GSTAGE];
