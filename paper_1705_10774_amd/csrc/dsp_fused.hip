@@ -33,7 +33,6 @@ constexpr int MPX = MT + 2;              // predictor cells per edge
 constexpr int MPRED = MPX * MPX;         // 324
 constexpr int MXF = (MT + 1) * (MT + 2); // x-faces (or y-faces) per plane: 306
 constexpr int NTHR = 512;
-constexpr int MAXBOX = 256;              // guard boxes per patch (checked on the host)
 
 template <class T> struct StepSmem {
   // region A: primitives of plane z (load -> predictor), then the plane's
@@ -187,7 +186,7 @@ __device__ __attribute__((noinline)) FaceStates<T> fallback_states(const PatchCt
 constexpr int GSTAGE = 8192;  // staged source values per workgroup
 
 template <class T>
-__global__ __launch_bounds__(256, 4) void k_gfill(DevSet S, const int* __restrict__ list, int count,
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 1) void k_gfill(DevSet S, const int* __restrict__ list, int count,
                                                const T* __restrict__ slots, T* __restrict__ pad,
                                                int64_t pad_stride) {
   __shared__ T stage[GSTAGE];
