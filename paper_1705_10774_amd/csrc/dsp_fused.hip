@@ -1264,13 +1264,16 @@ __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict
         const T curl = (EY(ci + 1, cj) - EY(ci, cj)) - (EX(ci, cj + 1) - EX(ci, cj));
         outp[sface(n, 2, ci, cj, z)] = old[7] - dtdx * curl;
       }
-      for (int m = lane; m < nxf; m += NTHR2) {
-        sm.px[0][m] = sm.fx[5][m];
-        sm.px[1][m] = sm.fx[7][m];
+      // copied by the threads past the columns, which have no update here
+      static_assert(MCOL + 2 * MXF <= NTHR2, "one copy per thread past the columns");
+      const int mx = lane - MCOL, my = lane - MCOL - MXF;
+      if (mx >= 0 && mx < nxf) {
+        sm.px[0][mx] = sm.fx[5][mx];
+        sm.px[1][mx] = sm.fx[7][mx];
       }
-      for (int m = lane; m < nyf; m += NTHR2) {
-        sm.py[0][m] = sm.fy[6][m];
-        sm.py[1][m] = sm.fy[7][m];
+      if (my >= 0 && my < nyf) {
+        sm.py[0][my] = sm.fy[6][my];
+        sm.py[1][my] = sm.fy[7][my];
       }
     }
     __syncthreads();
