@@ -113,7 +113,11 @@ def main():
         pr5 = I.cfg5_adjoint(prec=I.F64)
         s = dsp.PatchSet(pr5.cfg, pr5.patches)
         U5 = torch.from_numpy(pr5.U0).to(dev)
-        s.fixed_steps_fwd(U5, pr5.nsteps)
+        # warm-up of both passes: the reverse allocates its work buffers on
+        # first use, which the timed run must not include
+        UTw, ckw = s.fixed_steps_fwd(U5, pr5.nsteps)
+        s.fixed_steps_adj(ckw, torch.ones_like(UTw), pr5.nsteps)
+        del UTw, ckw
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         UT5, ck5 = s.fixed_steps_fwd(U5, pr5.nsteps)
