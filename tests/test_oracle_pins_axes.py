@@ -1,0 +1,214 @@
+"""Pins of the oracle's y- and z-direction arithmetic.
+
+1. Axis permutation: plane-parallel problems run along x, y and z give
+   bitwise-permuted results (see tests/plane_problems.py for why bit for bit).
+   The x-direction path is pinned by the one-dimensional closed forms (linear
+   waves, Sod); this carries those pins over to the y- and z-direction
+   predictor terms, face fluxes, E_x / E_y edge EMFs with their upwinding and
+   the non-ideal E_x.
+2. An oblique, non-degenerate fast magnetosonic wave on a moving background
+   with a wavevector that has three different components: the eigenvector of
+   the 7x7 primitive Jacobian from numpy.linalg.eig, the phase speed
+   omega = (u_n + c_f)|k|, second-order convergence in all three directions at
+   once.  The Jacobian is the textbook one of one-dimensional ideal MHD
+   (Sec. 4.3 names constrained transport; the system is the standard one),
+   written out here from the equations, not taken from the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1705_10774_amd import inputs as I
+from tests import plane_problems as PP
+
+NT = 8
+
+
+def _run(orc, pr, order=2):
+    s = orc.OracleSet.from_problem(pr)
+    s.set_order(order, 1, NT)
+    s.advance_to(pr.t_end)
+    U = s.read_state()
+    st, kh = s.read_schedule()
+    stats = s.stats()
+    s.close()
+    return U, st, kh, stats
+
+
+@pytest.mark.parametrize("kind", ["sod", "briowu", "alfven_y", "alfven_z", "beltrami_ni"])
+def test_axis_permutation_bitwise(orc, kind):
+    px = PP.plane_problem(kind)
+    Ux, stx, khx, sx = _run(orc, px)
+    assert sx[13] >= 6  # steps (fixed) or rounds (local) actually taken
+    # the problem moved (a result equal to the initial state pins nothing)
+    assert not np.array_equal(Ux, px.U0)
+    for times in (1, 2):
+        pp = PP.permute_problem(px, times)
+        Up, stp, khp, _ = _run(orc, pp)
+        assert np.array_equal(stp, stx) and np.array_equal(khp, khx)
+        want = PP.permute_result(Ux, px.patches, times)
+        if not np.array_equal(Up, want):
+            d = np.abs(Up - want)
+            pytest.fail(f"{pp.name}: not the permuted x result; max |diff| {d.max():.3e} "
+                        f"at {int(d.argmax())} of {d.size}")
+
+
+def test_axis_permutation_catches_a_swap(orc):
+    """The comparison is not vacuous: the x-run compared with the y-run
+    permuted the wrong way (a transposition instead of a cyclic shift of the
+    axes) differs."""
+    px = PP.plane_problem("briowu")
+    Ux = _run(orc, px)[0]
+    py = PP.permute_problem(px, 1)
+    Uy = _run(orc, py)[0]
+    wrong = PP.permute_result(Ux, px.patches, 2)
+    assert not np.array_equal(Uy, wrong)
+
+
+# ---------------------------------------------------------------------------
+# oblique fast wave
+
+
+GAMMA = 5.0 / 3.0
+RHO0, P0 = 1.0, 0.6
+B0 = np.array([0.9, -0.55, 0.4])
+V0 = np.array([0.11, -0.07, 0.05])
+KVEC = np.array([1.0, -2.0, 2.0])  # wavenumbers per unit length (box 1 x 1/2 x 1/2)
+AMP = 1e-6
+
+
+def _frame():
+    nh = KVEC / np.linalg.norm(KVEC)
+    a = np.array([0.0, 0.0, 1.0])
+    t1 = np.cross(nh, a)
+    t1 /= np.linalg.norm(t1)
+    t2 = np.cross(nh, t1)
+    return nh, t1, t2
+
+
+def _jacobian(rho, un, p, bn, bt1, bt2, g):
+    """A(W) of dW/dt + A dW/dn = 0 for W = (rho, un, ut1, ut2, p, Bt1, Bt2) of
+    one-dimensional ideal MHD (mu0 = 1) along n, B_n constant."""
+    A = np.zeros((7, 7))
+    A[0, 0], A[0, 1] = un, rho
+    A[1, 1], A[1, 4], A[1, 5], A[1, 6] = un, 1 / rho, bt1 / rho, bt2 / rho
+    A[2, 2], A[2, 5] = un, -bn / rho
+    A[3, 3], A[3, 6] = un, -bn / rho
+    A[4, 1], A[4, 4] = g * p, un
+    A[5, 1], A[5, 2], A[5, 5] = bt1, -bn, un
+    A[6, 1], A[6, 3], A[6, 6] = bt2, -bn, un
+    return A
+
+
+def _fast_mode():
+    nh, t1, t2 = _frame()
+    un, bn, bt1, bt2 = V0 @ nh, B0 @ nh, B0 @ t1, B0 @ t2
+    A = _jacobian(RHO0, un, P0, bn, bt1, bt2, GAMMA)
+    lam, R = np.linalg.eig(A)
+    lam = lam.real
+    m = int(np.argmax(lam))
+    r = R[:, m].real
+    r = r / r[0]
+    # closed form of the fast speed (the standard textbook form, not the
+    # oracle's cancellation-free one)
+    a2, b2, bn2 = GAMMA * P0 / RHO0, (B0 @ B0) / RHO0, bn * bn / RHO0
+    cf = math.sqrt(0.5 * (a2 + b2 + math.sqrt((a2 + b2) ** 2 - 4 * a2 * bn2)))
+    assert abs(lam[m] - (un + cf)) < 1e-12
+    # non-degenerate: the seven speeds are distinct and the fast, Alfven and
+    # slow speeds well separated
+    ls = np.sort(lam)
+    assert np.min(np.diff(ls)) > 0.05
+    return lam[m], r, (nh, t1, t2)
+
+
+def _edge_pot(c, coords, kv):
+    """Vector potential component c of amplitude vector `c` at the sample
+    points coords (tensor grid), cos(k.x) times the component."""
+    x, y, z = coords
+    ph = 2 * np.pi * (kv[0] * x[None, None, :] + kv[1] * y[None, :, None] + kv[2] * z[:, None, None])
+    return c * np.cos(ph)
+
+
+def _fast_wave_problem(n, t_end=0.05):
+    """Box 1 x 1/2 x 1/2 as 4 x 2 x 2 patches of n^3 (side 1/4)."""
+    lam, r, (nh, t1, t2) = _fast_mode()
+    size = 0.25
+    patches = [I.Patch((px * size, py * size, pz * size), size, n)
+               for pz in range(2) for py in range(2) for px in range(4)]
+    kv = KVEC
+    kk = 2 * np.pi * kv
+    # lab-frame eigenvector: density, velocity, pressure, transverse field
+    dv = r[1] * nh + r[2] * t1 + r[3] * t2
+    dB = r[5] * t1 + r[6] * t2
+    apot = np.cross(kk, dB) / (kk @ kk)  # curl(apot cos(k.x)) = dB sin(k.x)
+    rho, vel, pres, bf = [], [], [], []
+    for q in patches:
+        dx = q.size / q.n
+        xc = I.cell_coords(q)
+        ph = 2 * np.pi * (kv[0] * xc[0][None, None, :] + kv[1] * xc[1][None, :, None] + kv[2] * xc[2][:, None, None])
+        s = AMP * np.sin(ph)
+        rho.append(RHO0 + r[0] * s)
+        vel.append([V0[d] + dv[d] * s for d in range(3)])
+        pres.append(P0 + r[4] * s)
+        # face field = B0 + discrete curl of the potential sampled on the edges,
+        # which keeps the discrete divergence zero
+        xf = [q.origin[d] + np.arange(q.n + 1) * dx for d in range(3)]
+        # A_x on x-edges (x cell, y face, z face), A_y on y-edges, A_z on z-edges
+        Ax = _edge_pot(AMP * apot[0], (xc[0], xf[1], xf[2]), kv)  # [nz+1, ny+1, nx]
+        Ay = _edge_pot(AMP * apot[1], (xf[0], xc[1], xf[2]), kv)  # [nz+1, ny, nx+1]
+        Az = _edge_pot(AMP * apot[2], (xf[0], xf[1], xc[2]), kv)  # [nz, ny+1, nx+1]
+        bx = B0[0] + (Az[:, 1:, :] - Az[:, :-1, :]) / dx - (Ay[1:, :, :] - Ay[:-1, :, :]) / dx
+        by = B0[1] + (Ax[1:, :, :] - Ax[:-1, :, :]) / dx - (Az[:, :, 1:] - Az[:, :, :-1]) / dx
+        bz = B0[2] + (Ay[:, :, 1:] - Ay[:, :, :-1]) / dx - (Ax[:, 1:, :] - Ax[:, :-1, :]) / dx
+        bf.append((bx, by, bz))
+    U = I.assemble(patches, rho, vel, pres, bf, GAMMA)
+    cfg = I.Config(gamma=GAMMA, dt_mode=I.DT_GLOBAL_EXACT, box_hi=(1.0, 0.5, 0.5))
+    return I.Problem("oblique_fast", cfg, patches, U, t_end), lam, r, dv, dB
+
+
+def _fast_wave_error(orc, n):
+    pr, lam, r, dv, dB = _fast_wave_problem(n)
+    U = _run(orc, pr)[0]
+    om = lam * 2 * np.pi * np.linalg.norm(KVEC)
+    err, cnt = 0.0, 0
+    for q, v in zip(pr.patches, I.patch_views(U, pr.patches)):
+        xc = I.cell_coords(q)
+        ph = 2 * np.pi * (KVEC[0] * xc[0][None, None, :] + KVEC[1] * xc[1][None, :, None] +
+                          KVEC[2] * xc[2][:, None, None]) - om * pr.t_end
+        s = AMP * np.sin(ph)
+        rho = RHO0 + r[0] * s
+        err += np.abs(v[0] - rho).sum() / abs(r[0])
+        for d in range(3):
+            m_ex = rho * (V0[d] + dv[d] * s)
+            err += np.abs(v[1 + d] - m_ex).sum() / (abs(dv[d]) + 1e-30) if abs(dv[d]) > 1e-3 else 0.0
+        for d in range(3):
+            fc = I.face_coords(q, d)
+            phf = 2 * np.pi * (KVEC[0] * fc[0][None, None, :] + KVEC[1] * fc[1][None, :, None] +
+                               KVEC[2] * fc[2][:, None, None]) - om * pr.t_end
+            b_ex = B0[d] + dB[d] * AMP * np.sin(phf)
+            if abs(dB[d]) > 1e-3:
+                err += np.abs(v[5 + d] - b_ex).mean() * v[0].size / abs(dB[d])
+        cnt += v[0].size
+    return err / cnt / AMP, pr
+
+
+def test_oblique_fast_wave_second_order(orc):
+    ns = (8, 16, 32)
+    e = [_fast_wave_error(orc, n)[0] for n in ns]
+    r1, r2 = math.log2(e[0] / e[1]), math.log2(e[1] / e[2])
+    print("oblique fast wave: errors", e, "rates", r1, r2)
+    assert r2 >= 1.9 and r1 >= 1.7, (e, r1, r2)
+    assert e[2] < 0.05  # relative to the amplitude, after a phase of ~1.2 rad
+
+
+def test_oblique_fast_wave_wrong_speed_fails(orc):
+    """The error measure sees the phase: against a wave at rest (omega = 0)
+    the same run is far off."""
+    pr, lam, r, dv, dB = _fast_wave_problem(16)
+    U = _run(orc, pr)[0]
+    v = I.patch_views(U, pr.patches)[0]
+    q = pr.patches[0]
+    xc = I.cell_coords(q)
+    ph = 2 * np.pi * (KVEC[0] * xc[0][None, None, :] + KVEC[1] * xc[1][None, :, None] + KVEC[2] * xc[2][:, None, None])
+    still = RHO0 + r[0] * AMP * np.sin(ph)
+    assert np.abs(v[0] - still).mean() / (abs(r[0]) * AMP) > 0.3
