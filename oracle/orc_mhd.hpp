@@ -11,6 +11,7 @@
 // Everything is written out literally, one quantity at a time, so it can be
 // checked against those methods by eye.  No blocking, fusion or reordering.
 #pragma once
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstddef>
@@ -267,7 +268,11 @@ template <class R> double courant_rate(const Box3<Prim<R>>& W, int n, double dx,
 // the contact speed S_M.  Its sign is the sign of the mass flux in exact
 // arithmetic (S_L < S_M < S_R, rho* > 0), and it is exactly zero when both
 // normal velocities vanish and the total pressures agree, where the computed
-// mass flux is zero only up to rounding.
+// mass flux is zero only up to rounding.  A contact speed within the
+// degeneracy threshold of the outer speeds, |S_M| <= eps_deg max(-S_L, S_R),
+// is taken as zero: at that size its sign is rounding noise (on a symmetry
+// plane of the flow, say), and the edge EMFs average the two sides there
+// instead of following it.
 template <class R>
 void hlld(const R* wl, const R* wr, R bn, const Phys& ph, R* F) {
   const double g = ph.gamma;
@@ -382,7 +387,9 @@ void hlld(const R* wl, const R* wr, R bn, const Phys& ph, R* F) {
   } else {
     for (int q = 0; q < 7; ++q) F[q] = FR[q];
   }
-  F[7] = (SL > 0.0) ? SL : ((SR < 0.0) ? SR : SM);
+  R up = SM;
+  if (std::fabs(val(SM)) <= ph.eps_deg * std::max(-val(SL), val(SR))) up = R(0.0);
+  F[7] = (SL > 0.0) ? SL : ((SR < 0.0) ? SR : up);
 }
 
 // ---------------------------------------------------------------------------
