@@ -225,6 +225,20 @@ int dsp_fixed_steps_adj(dsp_set* set, const void* ckpt_dev, const void* lamT_dev
 int dsp_save_snapshot(const dsp_set* set, const char* path);
 int dsp_load_snapshot(dsp_set* set, const char* path);
 
+/* HLLD flux (Miyoshi & Kusano 2005; the face flux of the step, Sec. 4.1) of
+ * nface independent faces, evaluated on the current device with the step
+ * kernels' own arithmetic in precision prec (DSP_F32: the hardware
+ * reciprocal and square root of the single-precision step; DSP_F64: IEEE).
+ * Host arrays, FP64, caller-owned: wl, wr [nface][7] rotated primitive
+ * states (rho, u_n, u_t1, u_t2, p, B_t1, B_t2) left and right of the face
+ * (rounded to prec on the device), bn [nface] the normal field; flux8
+ * [nface][8] receives the fluxes of (rho, m_n, m_t1, m_t2, E, B_t1, B_t2) and
+ * the upwind speed that orients the edge EMFs (S_L if S_L > 0, S_R if
+ * S_R < 0, else the contact speed).  Independent of any set; allocates and
+ * frees its own device buffers.  Errors: DSP_EINVAL, DSP_EHIP. */
+int dsp_hlld_faces(int32_t prec, const double* wl, const double* wr, const double* bn, int64_t nface,
+                   double gamma, double* flux8);
+
 /* Free every device allocation of the set (NULL is a no-op). */
 void dsp_destroy(dsp_set* set);
 

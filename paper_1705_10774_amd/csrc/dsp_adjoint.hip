@@ -686,11 +686,15 @@ void launch_adjoint_step(const DevSet& S, const int* list, int count, int nmax, 
                      S, list, count, L, lam_prev, host_off);
 }
 
+#ifdef DSP_TU_F32
 template void launch_adjoint_step<float>(const DevSet&, const int*, int, int, const WorkPtr<float>&,
                                          const WorkPtr<float>&, const StepPtr&, const float*, float*,
                                          const int64_t*, hipStream_t);
+#endif
+#ifdef DSP_TU_F64
 template void launch_adjoint_step<double>(const DevSet&, const int*, int, int, const WorkPtr<double>&,
                                           const WorkPtr<double>&, const StepPtr&, const double*, double*,
                                           const int64_t*, hipStream_t);
+#endif
 
 }  // namespace dsp

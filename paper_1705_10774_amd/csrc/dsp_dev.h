@@ -149,6 +149,7 @@ template <class T>
 void launch_adjoint_step(const DevSet& S, const int* list, int count, int nmax, const WorkPtr<T>& W,
                          const WorkPtr<T>& L, const StepPtr& st, const T* lam_next, T* lam_prev,
                          const int64_t* host_off, hipStream_t s);
+void launch_brackets(const DevSet& S, const int* list, int count, hipStream_t s);
 void launch_dt(const DevSet& S, const int* list, int count, const StepPtr& st, const double* smax, hipStream_t s,
                int dt_kind, double t_end, int clip);
 void launch_publish(const DevSet& S, const int* list, int count, const StepPtr& st, hipStream_t s);
@@ -161,6 +162,9 @@ template <class T>
 void launch_scatter(const DevSet& S, T* slots, const double* src, const int64_t* host_off, hipStream_t s);
 template <class T>
 void launch_pack(const DevSet& S, const T* slots, T* dst, const int64_t* host_off, hipStream_t s);
+template <class T>
+void launch_hlld_faces(const double* wl, const double* wr, const double* bn, int64_t nface, double gamma, double* out,
+                       hipStream_t s);
 template <class T>
 void launch_unpack(const DevSet& S, T* slots, const T* src, const int64_t* host_off, hipStream_t s);
 

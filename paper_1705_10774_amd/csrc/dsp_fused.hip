@@ -1325,9 +1325,13 @@ int launch_fused(const DevSet& S, const int* list, int count, int nmin, int nmax
   return fuse_dt;
 }
 
+#ifdef DSP_TU_F32
 template int launch_fused<float>(const DevSet&, const int*, int, int, int, float*, float*, int64_t, bool, double*,
                                   const StepPtr&, hipStream_t, int, double, int, hipEvent_t, hipEvent_t);
+#endif
+#ifdef DSP_TU_F64
 template int launch_fused<double>(const DevSet&, const int*, int, int, int, double*, double*, int64_t, bool,
                                    double*, const StepPtr&, hipStream_t, int, double, int, hipEvent_t, hipEvent_t);
+#endif
 
 }  // namespace dsp

@@ -21,6 +21,13 @@
 //              round, so every read of the round saw the old metadata).
 // Kernels that read per-patch data take a list of patch ids; a patch's
 // interior size n may differ between patches (uneven sets).
+//
+// The source is compiled three times: with DSP_TU_COMMON for the kernels that
+// do not depend on the precision (readiness scan, levels, publish, time
+// records, guard-box brackets), with DSP_TU_F32 for the single-precision
+// instantiations and with DSP_TU_F64 for the double-precision ones, which are
+// built without floating-point contraction (IEEE operations one at a time,
+// as the FP64 oracle computes them).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -35,6 +42,7 @@ namespace dsp {
 // the patch's current time (one thread per box), so that k_fill reads it
 // instead of searching the source's slices for every element.
 
+#ifdef DSP_TU_COMMON
 __global__ void k_brackets(DevSet S, const int* __restrict__ list, int count) {
   const int b = blockIdx.y;
   if (b >= count) return;
@@ -43,6 +51,7 @@ __global__ void k_brackets(DevSet S, const int* __restrict__ list, int count) {
   if (m >= S.rbox_off[p * 108 + 108]) return;
   S.brk[m] = bracket(S, S.boxes[m].q, S.ticks[p], S.tcur[p]);
 }
+#endif  // DSP_TU_COMMON
 
 // ---------------------------------------------------------------------------
 // k_fill: one thread per padded element (5 N^3 cell values, then 3 face
@@ -207,6 +216,7 @@ __global__ void k_prim(DevSet S, const int* __restrict__ list, int count, WorkPt
 // ---------------------------------------------------------------------------
 // time-step choice
 
+#ifdef DSP_TU_COMMON
 __global__ void k_dt_local(DevSet S, const int* __restrict__ list, int count, StepPtr st,
                            const double* smax) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -272,6 +282,7 @@ __global__ void k_dt_global(DevSet S, const int* __restrict__ list, int count, S
     st.dt[b] = dt;
   }
 }
+#endif  // DSP_TU_COMMON
 
 // ---------------------------------------------------------------------------
 // k_pred: slopes (per direction) and half-step predictor on [-1, n]^3.
@@ -635,6 +646,7 @@ __global__ void k_update(DevSet S, const int* __restrict__ list, int count, T* _
 // ---------------------------------------------------------------------------
 // k_publish: the new slice becomes current (Sec. 3A), ticks advance.
 
+#ifdef DSP_TU_COMMON
 __global__ void k_publish(DevSet S, const int* __restrict__ list, int count, StepPtr st) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= live_count(S, count)) return;
@@ -722,6 +734,7 @@ __global__ void k_scan(DevSet S, int64_t T_end, int* __restrict__ list, int* __r
   const int slot = atomicAdd(counters, 1);
   list[slot] = p;
 }
+#endif  // DSP_TU_COMMON
 
 // ---------------------------------------------------------------------------
 // diagnostics: per-patch FP64 sums (one workgroup per patch, fixed-order tree
@@ -805,6 +818,28 @@ __global__ void k_unpack(DevSet S, T* __restrict__ slots, const T* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// k_hlld_faces: the HLLD flux of a batch of independent faces with the step
+// kernels' own arithmetic (single precision: hardware reciprocal and square
+// root, as the fused single-precision step; double: IEEE), for element-wise
+// checks of the flux on its own.  One thread per face; FP64 in and out.
+
+template <class T, class M>
+__global__ void k_hlld_faces(const double* __restrict__ wl, const double* __restrict__ wr,
+                             const double* __restrict__ bn, int64_t nface, double gamma, double* __restrict__ out) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nface) return;
+  T l[7], r[7], F[8];
+#pragma unroll
+  for (int q = 0; q < 7; ++q) {
+    l[q] = (T)wl[7 * f + q];
+    r[q] = (T)wr[7 * f + q];
+  }
+  hlld_flux<T, M>(l, r, (T)bn[f], (T)gamma, F);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) out[8 * f + q] = (double)F[q];
+}
+
+// ---------------------------------------------------------------------------
 // launchers (explicit instantiation for float and double)
 
 template <class T>
@@ -816,7 +851,7 @@ void launch_update(const DevSet& S, const int* list, int count, int nmax, T* slo
   auto blocks = [&](int64_t elems) { return (unsigned)((elems + TPB - 1) / TPB); };
   (void)hipMemsetAsync(W.smax, 0, sizeof(double) * count, s);
   const int64_t fill_elems = 5LL * N * N * N + 3LL * N * N * (N + 1);
-  hipLaunchKernelGGL(k_brackets, dim3(blocks(S.maxbox > 0 ? S.maxbox : 1), count), dim3(TPB), 0, s, S, list, count);
+  launch_brackets(S, list, count, s);
   hipLaunchKernelGGL(k_fill<T>, dim3(blocks(fill_elems), count), dim3(TPB), 0, s, S, list, count, slots, W);
   hipLaunchKernelGGL(k_prim<T>, dim3(blocks((int64_t)N * N * N), count), dim3(TPB), 0, s, S, list, count, W);
   launch_dt(S, list, count, st, W.smax, s, dt_kind, t_end, clip);
@@ -834,6 +869,12 @@ void launch_update(const DevSet& S, const int* list, int count, int nmax, T* slo
   }
   hipLaunchKernelGGL(k_update<T>, dim3(blocks((int64_t)nmax * nmax * nmax + 3LL * nmax * nmax * (nmax + 1)), count),
                      dim3(TPB), 0, s, S, list, count, slots, W, st);
+}
+
+#ifdef DSP_TU_COMMON
+void launch_brackets(const DevSet& S, const int* list, int count, hipStream_t s) {
+  hipLaunchKernelGGL(k_brackets, dim3((unsigned)((S.maxbox > 0 ? S.maxbox : 1) + 255) / 256, count), dim3(256), 0, s,
+                     S, list, count);
 }
 
 void launch_dt(const DevSet& S, const int* list, int count, const StepPtr& st, const double* smax, hipStream_t s,
@@ -879,6 +920,7 @@ void launch_scan(const DevSet& S, int64_t T_end, int* list, int* counters, hipSt
   if (!clear) (void)hipMemsetAsync(counters, 0, 2 * sizeof(int), s);
   hipLaunchKernelGGL(k_scan, dim3((S.npatch + 255) / 256), dim3(256), 0, s, S, T_end, list, counters, clear);
 }
+#endif  // DSP_TU_COMMON
 
 template <class T>
 void launch_stats(const DevSet& S, const T* slots, double* out, hipStream_t s) {
@@ -902,7 +944,21 @@ void launch_unpack(const DevSet& S, T* slots, const T* src, const int64_t* host_
   hipLaunchKernelGGL(k_unpack<T>, dim3(64, S.npatch), dim3(256), 0, s, S, slots, src, host_off);
 }
 
+template <class T>
+void launch_hlld_faces(const double* wl, const double* wr, const double* bn, int64_t nface, double gamma, double* out,
+                       hipStream_t s) {
+  if (nface <= 0) return;
+  const unsigned blocks = (unsigned)((nface + 255) / 256);
+  if constexpr (sizeof(T) == 4)
+    hipLaunchKernelGGL((k_hlld_faces<float, FastF32>), dim3(blocks), dim3(256), 0, s, wl, wr, bn, nface, gamma, out);
+  else
+    hipLaunchKernelGGL((k_hlld_faces<double, Exact<double>>), dim3(blocks), dim3(256), 0, s, wl, wr, bn, nface, gamma,
+                       out);
+}
+
 #define DSP_INST(T)                                                                                    \
+  template void launch_hlld_faces<T>(const double*, const double*, const double*, int64_t, double, double*, \
+                                     hipStream_t);                                                     \
   template void launch_update<T>(const DevSet&, const int*, int, int, T*, const WorkPtr<T>&,          \
                                  const StepPtr&, hipStream_t, int, double, int, hipEvent_t, hipEvent_t); \
   template void launch_stats<T>(const DevSet&, const T*, double*, hipStream_t);                        \
@@ -910,7 +966,11 @@ void launch_unpack(const DevSet& S, T* slots, const T* src, const int64_t* host_
   template void launch_scatter<T>(const DevSet&, T*, const double*, const int64_t*, hipStream_t);      \
   template void launch_pack<T>(const DevSet&, const T*, T*, const int64_t*, hipStream_t);              \
   template void launch_unpack<T>(const DevSet&, T*, const T*, const int64_t*, hipStream_t);
+#ifdef DSP_TU_F32
 DSP_INST(float)
+#endif
+#ifdef DSP_TU_F64
 DSP_INST(double)
+#endif
 
 }  // namespace dsp

@@ -1407,6 +1407,38 @@ int dsp_load_snapshot(dsp_set* s, const char* path) {
   return 0;
 }
 
+// HLLD flux of a batch of independent faces, with the step kernels' own
+// arithmetic in the requested precision (a check of the flux on its own).
+int dsp_hlld_faces(int32_t prec, const double* wl, const double* wr, const double* bn, int64_t nface, double gamma,
+                   double* flux8) {
+  if (prec != DSP_F32 && prec != DSP_F64) return fail(DSP_EINVAL, "invalid precision");
+  if (nface < 0 || (nface > 0 && (!wl || !wr || !bn || !flux8))) return fail(DSP_EINVAL, "bad argument");
+  if (!(gamma > 1.0)) return fail(DSP_EINVAL, "gamma must exceed 1");
+  if (nface == 0) return 0;
+  const size_t nw = sizeof(double) * 7 * (size_t)nface, nb = sizeof(double) * (size_t)nface,
+               nf = sizeof(double) * 8 * (size_t)nface;
+  double *dl = nullptr, *dr = nullptr, *db = nullptr, *df = nullptr;
+  int e = hipck(hipMalloc(&dl, nw), "hipMalloc");
+  if (!e) e = hipck(hipMalloc(&dr, nw), "hipMalloc");
+  if (!e) e = hipck(hipMalloc(&db, nb), "hipMalloc");
+  if (!e) e = hipck(hipMalloc(&df, nf), "hipMalloc");
+  if (!e) e = hipck(hipMemcpy(dl, wl, nw, hipMemcpyHostToDevice), "upload");
+  if (!e) e = hipck(hipMemcpy(dr, wr, nw, hipMemcpyHostToDevice), "upload");
+  if (!e) e = hipck(hipMemcpy(db, bn, nb, hipMemcpyHostToDevice), "upload");
+  if (!e) {
+    (void)hipGetLastError();  // clear an error left by an earlier call, so the check below is this launch's
+    if (prec == DSP_F32)
+      launch_hlld_faces<float>(dl, dr, db, nface, gamma, df, nullptr);
+    else
+      launch_hlld_faces<double>(dl, dr, db, nface, gamma, df, nullptr);
+    e = hipck(hipGetLastError(), "launch");
+  }
+  if (!e) e = hipck(hipMemcpy(flux8, df, nf, hipMemcpyDeviceToHost), "download");
+  for (double* q : {dl, dr, db, df})
+    if (q) (void)hipFree(q);
+  return e;
+}
+
 void dsp_destroy(dsp_set* s) { delete s; }
 
 }  // extern "C"

@@ -44,7 +44,11 @@ __device__ __forceinline__ T fast_speed(T a2, T b2, T bt2) {
 // (mass, mn, mt1, mt2, energy, bt1, bt2) and, in f[7], the upwind speed that
 // orients the edge EMFs: S_L if S_L > 0, S_R if S_R < 0, else the contact
 // speed S_M (the mass flux's sign in exact arithmetic, and exactly zero where
-// both normal velocities vanish and the total pressures agree).  Regions are
+// both normal velocities vanish and the total pressures agree), taken as zero
+// when |S_M| <= eps max(-S_L, S_R) with eps the degeneracy threshold of the
+// precision: a contact speed at the rounding level of the signal speeds (a
+// symmetry plane of the flow) has no direction, and the edge EMFs average
+// the two sides there.  Regions are
 // chosen outermost first:
 // F_L if S_L > 0, F*_L if S*_L >= 0, F**_L if S_M >= 0, F**_R if S*_R >= 0,
 // F*_R if S_R >= 0, else F_R.  Degenerate star states (vanishing
@@ -93,7 +97,7 @@ __device__ __forceinline__ void hlld_flux(const T* l, const T* r, T bn, T gamma,
   }
   const T dl = (SL - ul) * rl, dr = (SR - ur) * rr;
   const T SM = M::div(dr * ur - dl * ul - ptr + ptl, dr - dl);
-  f[7] = SM;
+  f[7] = (fabs(SM) <= Eps<T>::deg * ((-SL > SR) ? -SL : SR)) ? T(0) : SM;
   const T pts = M::div(dr * ptl - dl * ptr + dr * dl * (ur - ul), dr - dl);
 
   // single-star state of one side

@@ -3,7 +3,13 @@ the same seeded inputs.
 
 Bars: the update schedule (steps and level hash per patch) bit-exact; FP64
 state within 1e-10 and FP32 within 1e-4, as the largest per-variable relative
-L1 difference max_v |U_gpu - U_orc|_1 / |U_orc|_1; uniform states bitwise."""
+L1 difference max_v |U_gpu - U_orc|_1 / |U_orc|_1; uniform states bitwise.
+Element by element (elem_rel: the largest difference of any cell or face
+value, relative to the largest value of its group of variables), FP64 within
+1e-10 as well over short runs and within 1e-9 over whole runs of hundreds of
+steps per patch (rounding-order differences of the two implementations
+accumulate; chaotic flows amplify them further); FP32 element-wise errors are
+printed and held to the bounds stated at each test."""
 import dataclasses
 import os
 
@@ -41,6 +47,30 @@ def rel_l1(Ug, Uo, patches, floor=1e-4, verbose=True):
         worst = max(worst, num / den)
     if verbose:
         print("rel L1 per variable:", " ".join(f"{n}={e:.2e}" for n, e in zip(NAMES, per)))
+    return worst
+
+
+GROUPS = (("rho", (0,)), ("m", (1, 2, 3)), ("E", (4,)), ("B", (5, 6, 7)))
+
+
+def elem_rel(Ug, Uo, patches, verbose=True):
+    """Element-wise difference: max over the 8 variables of the largest
+    |U_gpu - U_orc| over every cell (or face) of every patch, divided by the
+    largest |U_orc| of the variable's group (density, momentum, energy,
+    field).  A component that is zero up to rounding (m_z of a plane problem,
+    B_z of a blast in an x-y field) is thus measured against its group's
+    scale, and one wrong value anywhere shows at its full size."""
+    Vg, Vo = I.patch_views(Ug, patches), I.patch_views(Uo, patches)
+    worst, per = 0.0, []
+    for _, vs in GROUPS:
+        scale = max(max(np.abs(b[v]).max() for b in Vo) for v in vs)
+        scale = scale if scale > 0 else 1.0
+        for v in vs:
+            e = max(np.abs(a[v] - b[v]).max() for a, b in zip(Vg, Vo)) / scale
+            per.append((v, e))
+            worst = max(worst, e)
+    if verbose:
+        print("element-wise per variable:", " ".join(f"{NAMES[v]}={e:.2e}" for v, e in sorted(per)))
     return worst
 
 
@@ -120,7 +150,7 @@ def test_cfg1_alfven_fp64_full(orc):
     print("perturbation-relative L1 (my, By):", pert, "steps", stg[13], sto[13])
     assert stg[13] == sto[13] > 250  # same number of global steps
     assert np.array_equal(sg, so) and np.array_equal(kg, ko)
-    assert err <= 1e-10
+    assert err <= 1e-10 and elem_rel(Ug, Uo, pr.patches) <= 1e-10
     assert max(pert) <= 1e-8
     assert stg[9] <= 1e-13 * 16  # div B at rounding (per unit length, |B| ~ 1)
 
@@ -136,6 +166,7 @@ def test_local_dt_fp64_schedule_and_state(orc, n):
     assert np.array_equal(kg, ko)
     assert stg[0] == sto[0]
     assert rel_l1(Ug, Uo, pr.patches) <= 1e-10
+    assert elem_rel(Ug, Uo, pr.patches) <= 1e-10
     assert stg[11] == sto[11]  # first-order fallback faces
 
 
@@ -146,8 +177,10 @@ def test_local_dt_fp32(orc):
     Uo, so, ko, sto = orc_run(orc, pr, t_end=T)
     assert np.array_equal(sg, so) and np.array_equal(kg, ko)
     err = rel_l1(Ug, Uo, pr.patches)
-    print("fp32 rel L1", err)
+    el = elem_rel(Ug, Uo, pr.patches)
+    print("fp32 rel L1", err, "element-wise", el)
     assert err <= 1e-4
+    assert el <= 1e-3  # Mach-5 flow with shocks: FP32 rounding, locally amplified
 
 
 def test_plain_equals_batched_fp64():
@@ -180,8 +213,10 @@ def test_cfg2_full_size_first_base_step(orc, prec):
     assert set(so.tolist()) == {1, 2}
     assert np.array_equal(sg, so) and np.array_equal(kg, ko)
     err = rel_l1(Ug, Uo, pr.patches)
-    print("cfg2 first dt_base rel L1", prec, err)
+    el = elem_rel(Ug, Uo, pr.patches)
+    print("cfg2 first dt_base rel L1", prec, err, "element-wise", el)
     assert err <= (1e-10 if prec == I.F64 else 1e-4)
+    assert el <= (1e-10 if prec == I.F64 else 1e-3)
 
 
 def test_gpu_error_codes():
@@ -228,28 +263,85 @@ def mini_uneven(prec):
                     dt_base=2.0 ** -11)
 
 
+@pytest.fixture(scope="module")
+def mini_oracle_full(orc):
+    """The oracle's reduced configuration 3 over its whole run (8 dt_base)."""
+    pr = mini_uneven(I.F64)
+    return orc_run(orc, pr, t_end=8 * pr.cfg.dt_base)
+
+
 @pytest.mark.parametrize("prec", [I.F64, I.F32])
-def test_cross_resolution_schedule_and_state(orc, prec):
-    """Uneven patch sizes: guard values resampled across resolutions, local
-    levels k = 1 .. 5 within two dt_base."""
+def test_cross_resolution_schedule_and_state(mini_oracle_full, prec):
+    """Uneven patch sizes (configuration 3 in small) over the whole run of
+    8 dt_base: guard values resampled across resolutions, local levels
+    k = 1 .. 7 (8 to 128 steps per patch)."""
     pr = mini_uneven(prec)
-    T = 2 * pr.cfg.dt_base
+    T = 8 * pr.cfg.dt_base
     Ug, sg, kg, stg = gpu_run(pr, t_end=T)
-    Uo, so, ko, sto = orc_run(orc, pr, t_end=T)
+    Uo, so, ko, sto = mini_oracle_full
     assert len(set(so.tolist())) >= 4
     assert np.array_equal(sg, so) and np.array_equal(kg, ko)
     err = rel_l1(Ug, Uo, pr.patches)
-    print("cross-resolution rel L1", prec, err)
+    el = elem_rel(Ug, Uo, pr.patches)
+    print("cross-resolution rel L1", prec, err, "element-wise", el)
     assert err <= (1e-10 if prec == I.F64 else 1e-4)
+    # up to 128 steps per patch: FP64 element-wise within the whole-run bar;
+    # FP32: smooth flow at single-precision rounding
+    assert el <= (1e-9 if prec == I.F64 else 1e-4)
+
+
+@pytest.fixture(scope="module")
+def smr_oracle_full(orc):
+    """The oracle's configuration 4 (centred blast) over its whole run."""
+    pr = I.cfg4_smr()
+    return orc_run(orc, pr)
+
+
+def test_smr_blast_full_run_fp64(smr_oracle_full):
+    """Configuration 4 (three nested levels, blast wave centred in the box)
+    over its whole run to t = 0.01: coarse-fine guard resampling plus levels
+    spanning a factor 64; the blast's symmetry planes put faces with zero
+    mass flux in exact arithmetic on both sides."""
+    pr = I.cfg4_smr()
+    Ug, sg, kg, stg = gpu_run(pr)
+    Uo, so, ko, sto = smr_oracle_full
+    assert max(so.tolist()) >= 256
+    assert np.array_equal(sg, so) and np.array_equal(kg, ko)
+    assert stg[10] == sto[10] and stg[11] == sto[11]  # floor hits, fallback faces
+    rel_l1(Ug, Uo, pr.patches)
+    err = rel_l1_grouped(Ug, Uo, pr.patches)
+    el = elem_rel(Ug, Uo, pr.patches)
+    print("smr full run fp64: grouped rel L1", err, "element-wise", el)
+    assert err <= 1e-10 and el <= 1e-10
+    # div B at rounding: |B| ~ 1 over the finest cells (dx = 1/256)
+    assert stg[9] <= 1e-10
+
+
+def test_smr_blast_full_run_fp32(smr_oracle_full):
+    """The same run in FP32 against the FP64 oracle (reported: a shock
+    problem, where FP32 rounding moves the blast front by a fraction of a
+    cell)."""
+    pr = I.cfg4_smr(prec=I.F32)
+    Ug, sg, kg, stg = gpu_run(pr)
+    Uo, so, ko, sto = smr_oracle_full
+    flips = int((sg != so).sum())
+    print("smr full run fp32: patches whose schedule differs from the FP64 oracle:", flips,
+          "steps", int(sg.sum()), "vs", int(so.sum()))
+    rel_l1(Ug, Uo, pr.patches)
+    err = rel_l1_grouped(Ug, Uo, pr.patches)
+    el = elem_rel(Ug, Uo, pr.patches)
+    print("smr full run fp32: grouped rel L1", err, "element-wise", el, "div B", stg[9])
+    assert np.isfinite(Ug).all()
+    assert flips == 0 and err <= 1e-4
+    # div B per unit length: FP32 rounding of each CT update (6e-8 of |B| ~ 1
+    # over dx = 1/256 on the finest level) in a random walk over 256 steps
+    assert stg[9] <= 5e-3
 
 
 @pytest.mark.parametrize("prec", [I.F64, I.F32])
 def test_smr_blast_first_base_step(orc, prec):
-    """Configuration 4 (three nested levels, blast wave) up to the first
-    dt_base: coarse-fine guard resampling plus levels spanning a factor 64."""
-    pr = I.cfg4_smr()
-    if prec == I.F32:
-        pr = dataclasses.replace(pr, cfg=dataclasses.replace(pr.cfg, prec=I.F32))
+    """Configuration 4 up to the first dt_base, FP32 included."""
+    pr = I.cfg4_smr(prec=prec)
     T = pr.cfg.dt_base
     Ug, sg, kg, stg = gpu_run(pr, t_end=T)
     Uo, so, ko, sto = orc_run(orc, pr, t_end=T)
@@ -257,10 +349,27 @@ def test_smr_blast_first_base_step(orc, prec):
     assert np.array_equal(sg, so) and np.array_equal(kg, ko)
     rel_l1(Ug, Uo, pr.patches)
     err = rel_l1_grouped(Ug, Uo, pr.patches)
-    print("smr rel L1", prec, err)
+    el = elem_rel(Ug, Uo, pr.patches)
+    print("smr first dt_base rel L1", prec, err, "element-wise", el)
     assert err <= (1e-10 if prec == I.F64 else 1e-4)
-    # div B at rounding: |B| ~ 1 over the finest cells (dx = 1/256)
-    assert stg[9] <= (1e-10 if prec == I.F64 else 1e-3)
+    if prec == I.F64:
+        assert el <= 1e-10
+
+
+def test_smr_blast_n8_fp64(orc):
+    """The three-level blast with n = 8 patches (dx = 1/128 on the finest
+    level) over one dt_base in FP64: schedule bit-exact, state within 1e-10."""
+    pr = I.cfg4_smr(n=8)
+    T = pr.cfg.dt_base
+    Ug, sg, kg, stg = gpu_run(pr, t_end=T)
+    Uo, so, ko, sto = orc_run(orc, pr, t_end=T)
+    assert max(so.tolist()) >= 16
+    assert np.array_equal(sg, so) and np.array_equal(kg, ko)
+    rel_l1(Ug, Uo, pr.patches)
+    err = rel_l1_grouped(Ug, Uo, pr.patches)
+    el = elem_rel(Ug, Uo, pr.patches)
+    print("smr n=8 rel L1", err, "element-wise", el)
+    assert err <= 1e-10 and el <= 1e-10
 
 
 def test_kernel_record():
@@ -303,8 +412,11 @@ def test_cfg2_full_run(cfg2_oracle_full, prec):
     assert np.array_equal(sg, so) and np.array_equal(kg, ko)
     assert stg[0] == sto[0] and stg[10] == sto[10] and stg[11] == sto[11]
     err = rel_l1(Ug, Uo, pr.patches)
-    print("cfg2 full run rel L1", prec, err)
+    el = elem_rel(Ug, Uo, pr.patches)
+    print("cfg2 full run rel L1", prec, err, "element-wise", el)
     assert err <= (1e-10 if prec == I.F64 else 1e-4)
+    # FP64: chaotic Mach-5 flow, rounding-order differences grow along the run
+    assert el <= (1e-8 if prec == I.F64 else 3e-2)
 
 
 def test_cfg2_smooth_fp32_full_run(orc):
@@ -314,5 +426,6 @@ def test_cfg2_smooth_fp32_full_run(orc):
     Uo, so, ko, sto = orc_run(orc, pr)
     assert np.array_equal(sg, so) and np.array_equal(kg, ko)
     err = rel_l1(Ug, Uo, pr.patches)
-    print("cfg2-smooth fp32 rel L1", err)
-    assert err <= 1e-4
+    el = elem_rel(Ug, Uo, pr.patches)
+    print("cfg2-smooth fp32 rel L1", err, "element-wise", el)
+    assert err <= 1e-4 and el <= 1e-3

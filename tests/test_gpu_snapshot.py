@@ -86,3 +86,35 @@ def test_snapshot_refuses_mismatch_and_damage(tmp_path):
     d.load(f)
     assert np.array_equal(d.read_state(), U)
     d.close()
+
+
+@pytest.mark.parametrize("make", [spread, smr], ids=["spread", "smr"])
+@pytest.mark.parametrize("prec", [I.F64, I.F32], ids=["f64", "f32"])
+def test_restart_matches_oracle(orc, tmp_path, make, prec):
+    """A run saved at 2 dt_base, restored into a new set and continued to
+    5 dt_base equals the oracle's uninterrupted run: the schedule bit for bit,
+    the state within the precision's tolerance (relative L1 and element-wise)."""
+    from tests.test_gpu_parity import elem_rel, orc_run, rel_l1, rel_l1_grouped
+    dsp = _dsp()
+    pr = make(prec)
+    dtb = pr.cfg.dt_base
+    a = dsp.PatchSet.from_problem(pr)
+    a.advance_to(2 * dtb)
+    f = tmp_path / "snap.bin"
+    a.save(f)
+    a.close()
+    b = dsp.PatchSet.from_problem(pr)
+    b.load(f)
+    b.advance_to(5 * dtb)
+    Ub = b.read_state()
+    sb, kb = b.read_schedule()
+    b.close()
+    Uo, so, ko, _ = orc_run(orc, pr, t_end=5 * dtb, prec=I.F64)
+    assert np.array_equal(sb, so) and np.array_equal(kb, ko)
+    err = rel_l1_grouped(Ub, Uo, pr.patches) if make is smr else rel_l1(Ub, Uo, pr.patches)
+    el = elem_rel(Ub, Uo, pr.patches)
+    print(make.__name__, prec, "restart vs oracle: rel L1", err, "element-wise", el)
+    if prec == I.F64:
+        assert err <= 1e-10 and el <= 1e-10
+    else:
+        assert err <= 1e-4

@@ -129,8 +129,9 @@ def _edge_pot(c, coords, kv):
     return c * np.cos(ph)
 
 
-def _fast_wave_problem(n, t_end=0.05):
-    """Box 1 x 1/2 x 1/2 as 4 x 2 x 2 patches of n^3 (side 1/4)."""
+def _fast_wave_problem(n, t_end=0.05, amp=AMP):
+    """Box 1 x 1/2 x 1/2 as 4 x 2 x 2 patches of n^3 (side 1/4), wave of
+    relative amplitude amp."""
     lam, r, (nh, t1, t2) = _fast_mode()
     size = 0.25
     patches = [I.Patch((px * size, py * size, pz * size), size, n)
@@ -146,7 +147,7 @@ def _fast_wave_problem(n, t_end=0.05):
         dx = q.size / q.n
         xc = I.cell_coords(q)
         ph = 2 * np.pi * (kv[0] * xc[0][None, None, :] + kv[1] * xc[1][None, :, None] + kv[2] * xc[2][:, None, None])
-        s = AMP * np.sin(ph)
+        s = amp * np.sin(ph)
         rho.append(RHO0 + r[0] * s)
         vel.append([V0[d] + dv[d] * s for d in range(3)])
         pres.append(P0 + r[4] * s)
@@ -154,9 +155,9 @@ def _fast_wave_problem(n, t_end=0.05):
         # which keeps the discrete divergence zero
         xf = [q.origin[d] + np.arange(q.n + 1) * dx for d in range(3)]
         # A_x on x-edges (x cell, y face, z face), A_y on y-edges, A_z on z-edges
-        Ax = _edge_pot(AMP * apot[0], (xc[0], xf[1], xf[2]), kv)  # [nz+1, ny+1, nx]
-        Ay = _edge_pot(AMP * apot[1], (xf[0], xc[1], xf[2]), kv)  # [nz+1, ny, nx+1]
-        Az = _edge_pot(AMP * apot[2], (xf[0], xf[1], xc[2]), kv)  # [nz, ny+1, nx+1]
+        Ax = _edge_pot(amp * apot[0], (xc[0], xf[1], xf[2]), kv)  # [nz+1, ny+1, nx]
+        Ay = _edge_pot(amp * apot[1], (xf[0], xc[1], xf[2]), kv)  # [nz+1, ny, nx+1]
+        Az = _edge_pot(amp * apot[2], (xf[0], xf[1], xc[2]), kv)  # [nz, ny+1, nx+1]
         bx = B0[0] + (Az[:, 1:, :] - Az[:, :-1, :]) / dx - (Ay[1:, :, :] - Ay[:-1, :, :]) / dx
         by = B0[1] + (Ax[1:, :, :] - Ax[:-1, :, :]) / dx - (Az[:, :, 1:] - Az[:, :, :-1]) / dx
         bz = B0[2] + (Ay[:, :, 1:] - Ay[:, :, :-1]) / dx - (Ax[:, 1:, :] - Ax[:, :-1, :]) / dx
