@@ -185,11 +185,15 @@ int dsp_stats(const dsp_set* set, double out[16]);
 int dsp_kernel_time(const dsp_set* set, double* ms, int64_t* launches);
 
 /* Dominant-kernel record of the last advance (or fixed-step run):
- *  [0] GPU time (ms, HIP events) summed over the patch-step launches
- *  [1] number of those launches
+ *  [0] GPU time (ms, HIP events on the set's stream) summed over the update
+ *      launch sequences of the rounds: the fused step kernel, preceded by
+ *      the cross-resolution guard resampling and the separate Courant pass
+ *      when a round needs them
+ *  [1] number of those launch sequences
  *  [2] their algorithmic HBM bytes: per patch update the own slice read and
- *      written plus every value of the two guard layers the stencil reads,
- *      from one time slice (exact time) or two (interpolated)
+ *      written plus every value of the two guard layers the stencil reads
+ *      (all five cell variables of a guard cell, one component of a guard
+ *      face), from one time slice (exact time) or two (interpolated)
  *  [3] 0: staged kernels (no byte count); 1: fused step kernel; 2: fused step
  *      kernel that also computed each patch's Courant rate and level (local
  *      steps of single-tile patches) */

@@ -468,17 +468,21 @@ __device__ __forceinline__ double fused_local_dt(const DevSet& S, const PatchCtx
 
 // Algorithmic HBM traffic of one patch update, added to S.algo_bytes: the own
 // slice read and written once, every guard value of the two stencil layers
-// read from one slice (exact time) or two (interpolated).  Called by every
-// thread of the first tile's workgroup (one box per thread, summed in LDS);
-// the caller synchronises the workgroup before thread 0 publishes the sum.
+// read from one slice (exact time) or two (interpolated).  The boxes of the
+// cell-centred regions (the first 27 keys of the patch) carry all five cell
+// variables, the face boxes one field component.  Called by every thread of
+// the first tile's workgroup (one box per thread, summed in LDS); the caller
+// synchronises the workgroup before thread 0 publishes the sum.
 __device__ inline void count_traffic(const DevSet& S, int p, int box0, int nbox, int64_t V, int tsz, int tid,
                                      int nthr, unsigned long long* acc) {
   if (tid == 0) atomicAdd(acc, 2ULL * (unsigned long long)V * (unsigned long long)tsz);
+  const int ncellbox = S.rbox_off[p * 108 + 27] - box0;
   for (int m = tid; m < nbox; m += nthr) {
     const GBox& G = S.boxes[box0 + m];
     const Bracket b = bracket(S, G.q, S.ticks[p], S.tcur[p]);
     const unsigned long long cnt =
-        (unsigned long long)(G.hi[0] - G.lo[0] + 1) * (G.hi[1] - G.lo[1] + 1) * (G.hi[2] - G.lo[2] + 1);
+        (unsigned long long)(G.hi[0] - G.lo[0] + 1) * (G.hi[1] - G.lo[1] + 1) * (G.hi[2] - G.lo[2] + 1) *
+        (m < ncellbox ? 5ULL : 1ULL);
     atomicAdd(acc, cnt * (b.oa == b.ob ? 1ULL : (b.oc < 0 ? 2ULL : 3ULL)) * (unsigned long long)tsz);
   }
 }
@@ -1287,6 +1291,9 @@ int launch_fused(const DevSet& S, const int* list, int count, int nmin, int nmax
                   int64_t pad_stride, bool gfill, double* smax, const StepPtr& st, hipStream_t s, int dt_kind,
                   double t_end, int clip, hipEvent_t ev0, hipEvent_t ev1) {
   const int N = nmax + 4;
+  // the events bracket the round's whole update sequence: guard resampling,
+  // separate Courant pass (if any) and the step
+  if (ev0) (void)hipEventRecord(ev0, s);
   if (gfill)
     hipLaunchKernelGGL(k_gfill<T>, dim3(108, count), dim3(256), 0, s, S, list, count, (const T*)slots, pad,
                        pad_stride);
@@ -1304,7 +1311,6 @@ int launch_fused(const DevSet& S, const int* list, int count, int nmin, int nmax
   }
   const int T2 = tpa * tpa;
   const int groups = ((count + 7) / 8) * 8 * T2;
-  if (ev0) (void)hipEventRecord(ev0, s);
   if constexpr (sizeof(T) == 4) {
     // equal 16^3 patches without padded guard regions: the fixed-size variant
     if (nmin == 16 && nmax == 16 && !gfill)
