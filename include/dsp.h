@@ -243,6 +243,20 @@ int dsp_load_snapshot(dsp_set* set, const char* path);
 int dsp_hlld_faces(int32_t prec, const double* wl, const double* wr, const double* bn, int64_t nface,
                    double gamma, double* flux8);
 
+/* dsp_hlld_faces for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernel and arguments, but the device staging of the inputs and
+ * outputs is a fixed file-scope device array of 12 MiB per GPU (held until
+ * the process ends), so the call makes no hipMalloc, hipFree or other
+ * allocating call.  At most 65536 faces per call (DSP_EINVAL beyond).  The
+ * array's device address is looked up once per device on the first call
+ * (hipGetSymbolAddress).  Every call on one GPU uses the same array: calls
+ * that overlap on one GPU (several host threads) race and must be
+ * serialised by the caller.  Synchronous (returns after the copy back).
+ * Errors: DSP_EINVAL, DSP_EHIP. */
+int dsp_hlld_faces_noalloc(int32_t prec, const double* wl, const double* wr, const double* bn,
+                           int64_t nface, double gamma, double* flux8);
+
 /* Free every device allocation of the set (NULL is a no-op). */
 void dsp_destroy(dsp_set* set);
 

@@ -20,6 +20,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <set>
 #include <string>
 #include <vector>
@@ -1436,6 +1437,71 @@ int dsp_hlld_faces(int32_t prec, const double* wl, const double* wr, const doubl
   if (!e) e = hipck(hipMemcpy(flux8, df, nf, hipMemcpyDeviceToHost), "download");
   for (double* q : {dl, dr, db, df})
     if (q) (void)hipFree(q);
+  return e;
+}
+
+// ---------------------------------------------------------------------------
+// The face-flux check without allocation: the staging of the inputs and
+// outputs lives in a file-scope device array (each GPU holds its own copy
+// until the process ends).  Host code never passes the array's name to a
+// kernel or a copy: its device address is taken once per device with
+// hipGetSymbolAddress and kept.
+
+namespace {
+constexpr int64_t kScratchFaces = 65536;   // largest batch of dsp_hlld_faces_noalloc
+constexpr int64_t kScratchPerFace = 7 + 7 + 1 + 8;  // wl, wr, bn, flux8
+__device__ __align__(256) double scratch[kScratchFaces * kScratchPerFace];  // 12 MiB per GPU
+std::mutex g_scratch_mu;
+std::map<int, double*> g_scratch_ptr;  // device ordinal -> device address of that GPU's scratch
+
+int scratch_address(double** out) {
+  int dev = -1;
+  int e = hipck(hipGetDevice(&dev), "hipGetDevice");
+  if (e) return e;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it == g_scratch_ptr.end()) {
+    void* p = nullptr;
+    e = hipck(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress");
+    if (e) return e;
+    if (!p) return fail(DSP_EHIP, "hipGetSymbolAddress returned no address");
+    it = g_scratch_ptr.emplace(dev, (double*)p).first;
+  }
+  *out = it->second;
+  return 0;
+}
+}  // namespace
+
+int dsp_hlld_faces_noalloc(int32_t prec, const double* wl, const double* wr, const double* bn, int64_t nface,
+                           double gamma, double* flux8) {
+  if (prec != DSP_F32 && prec != DSP_F64) return fail(DSP_EINVAL, "invalid precision");
+  if (nface < 0 || (nface > 0 && (!wl || !wr || !bn || !flux8))) return fail(DSP_EINVAL, "bad argument");
+  if (nface > kScratchFaces)
+    return fail(DSP_EINVAL, "at most " + std::to_string(kScratchFaces) + " faces per call without allocation");
+  if (!(gamma > 1.0)) return fail(DSP_EINVAL, "gamma must exceed 1");
+  double* base = nullptr;
+  int e = scratch_address(&base);
+  if (e || nface == 0) return e;
+  // the batch is packed at the start of the array; nothing in it needs to
+  // start at zero (every value the kernel reads is copied in first)
+  double* dl = base;
+  double* dr = dl + 7 * nface;
+  double* db = dr + 7 * nface;
+  double* df = db + nface;
+  const size_t nw = sizeof(double) * 7 * (size_t)nface, nb = sizeof(double) * (size_t)nface,
+               nf = sizeof(double) * 8 * (size_t)nface;
+  e = hipck(hipMemcpy(dl, wl, nw, hipMemcpyHostToDevice), "upload");
+  if (!e) e = hipck(hipMemcpy(dr, wr, nw, hipMemcpyHostToDevice), "upload");
+  if (!e) e = hipck(hipMemcpy(db, bn, nb, hipMemcpyHostToDevice), "upload");
+  if (!e) {
+    (void)hipGetLastError();  // clear an error left by an earlier call, so the check below is this launch's
+    if (prec == DSP_F32)
+      launch_hlld_faces<float>(dl, dr, db, nface, gamma, df, nullptr);
+    else
+      launch_hlld_faces<double>(dl, dr, db, nface, gamma, df, nullptr);
+    e = hipck(hipGetLastError(), "launch");
+  }
+  if (!e) e = hipck(hipMemcpy(flux8, df, nf, hipMemcpyDeviceToHost), "download");
   return e;
 }
 

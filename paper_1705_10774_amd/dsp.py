@@ -25,8 +25,8 @@ DSP_DT_LOCAL, DSP_DT_GLOBAL_QUANT, DSP_DT_GLOBAL_EXACT, DSP_DT_FIXED = 0, 1, 2, 
 # every entry point declared in include/dsp.h
 EXPORTS = ["dsp_create", "dsp_init", "dsp_init_device", "dsp_advance_to", "dsp_advance_to_plain", "dsp_read_state",
            "dsp_read_schedule", "dsp_stats", "dsp_kernel_time", "dsp_kernel_stats", "dsp_fixed_steps_fwd",
-           "dsp_fixed_steps_adj", "dsp_save_snapshot", "dsp_load_snapshot", "dsp_hlld_faces", "dsp_destroy",
-           "dsp_last_error"]
+           "dsp_fixed_steps_adj", "dsp_save_snapshot", "dsp_load_snapshot", "dsp_hlld_faces",
+           "dsp_hlld_faces_noalloc", "dsp_destroy", "dsp_last_error"]
 
 
 class dsp_config(C.Structure):
@@ -83,6 +83,7 @@ def load():
     L.dsp_save_snapshot.argtypes = [vp, C.c_char_p]
     L.dsp_load_snapshot.argtypes = [vp, C.c_char_p]
     L.dsp_hlld_faces.argtypes = [C.c_int32, dp, dp, dp, C.c_int64, C.c_double, dp]
+    L.dsp_hlld_faces_noalloc.argtypes = [C.c_int32, dp, dp, dp, C.c_int64, C.c_double, dp]
     L.dsp_destroy.argtypes = [vp]
     L.dsp_destroy.restype = None
     L.dsp_last_error.restype = C.c_char_p
@@ -215,16 +216,18 @@ def dsp_load_snapshot(h, path):
     _check(load().dsp_load_snapshot(h, str(path).encode()))
 
 
-def dsp_hlld_faces(prec, wl, wr, bn, gamma=5.0 / 3.0):
+def dsp_hlld_faces(prec, wl, wr, bn, gamma=5.0 / 3.0, noalloc=False):
     """Fluxes [nface, 8] of faces with states wl, wr [nface, 7] and normal
-    field bn [nface] (see include/dsp.h)."""
+    field bn [nface] (see include/dsp.h); noalloc: the entry point that
+    stages in the library's fixed device array instead of allocating."""
     wl = np.ascontiguousarray(wl, dtype=np.float64).reshape(-1, 7)
     wr = np.ascontiguousarray(wr, dtype=np.float64).reshape(-1, 7)
     bn = np.ascontiguousarray(bn, dtype=np.float64).reshape(-1)
     if not (wl.shape[0] == wr.shape[0] == bn.shape[0]):
         raise ValueError("wl, wr and bn must describe the same number of faces")
     out = np.empty((bn.shape[0], 8))
-    _check(load().dsp_hlld_faces(int(prec), _dp(wl), _dp(wr), _dp(bn), bn.shape[0], float(gamma), _dp(out)))
+    fn = load().dsp_hlld_faces_noalloc if noalloc else load().dsp_hlld_faces
+    _check(fn(int(prec), _dp(wl), _dp(wr), _dp(bn), bn.shape[0], float(gamma), _dp(out)))
     return out
 
 
