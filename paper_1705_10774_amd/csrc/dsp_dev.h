@@ -20,14 +20,24 @@ enum : int { ERR_NONFINITE = 1, ERR_NEGATIVE = 2, ERR_KMAX = 4, ERR_STATE = 8 };
 // source patch.  Indices are the patch's own padded indices (inclusive);
 // same = 1: equal resolution, source index = own index + shift; same = 0:
 // resampled across resolutions, wrap = lattice shift of the periodic image.
+// direct = 1 (resampled boxes only): the box exceeds the per-axis tables or
+// the LDS staging of the guard-resampling kernel and is resampled straight
+// from the source slices by a kernel of its own.
 struct GBox {
   int lo[3], hi[3];
   int q;
   int same;
   int shift[3];
-  int pad_;
+  int direct;
   int64_t wrap[3];
 };
+
+// limits of the staged guard resampling (see k_gfill): target indices per
+// axis of a box, source indices a target index overlaps per axis, LDS bytes
+// of staged source values
+constexpr int GMAXT = 72;
+constexpr int GMAXC = 4;
+constexpr int GSTAGE_BYTES = 40960;
 
 struct Bracket;
 
@@ -66,7 +76,9 @@ struct DevSet {
   const int* rbox_off;  // [npatch * 108 + 1]: boxes of (patch, component + 1, region)
   const GBox* boxes;
   Bracket* brk;  // per box: its time bracket for the staged guard fill (k_brackets)
+  int brk_ready;  // brk holds this round's brackets of the listed patches' boxes
   int maxbox;    // most boxes of one patch
+  int any_direct;  // some resampled box is flagged direct (k_gfill_direct runs)
   // counters and error bits
   int* err;
   unsigned long long* floor_hits;

@@ -178,98 +178,427 @@ __device__ __attribute__((noinline)) FaceStates<T> fallback_states(const PatchCt
 // Guard regions that are not a single same-resolution box (several sources,
 // or another resolution): values written into the entry's padded buffer, so
 // the marching kernel reads every guard region with one addressing rule.
-// One workgroup per (region, patch).  A box from a patch of another
-// resolution first interpolates the block of source values it reads (slope
-// neighbours included) in time into LDS, once per variable; every target
-// value then resamples from there, with the arithmetic of cross_value.
+// One workgroup per (region, patch).
+//
+// A box from a patch of another resolution is resampled as cross_value
+// defines it: the mean over the target cell (or face) of the source's
+// piecewise-linear, minmod-limited reconstruction of its time-interpolated
+// data.  The source cells a target cell overlaps form a tensor product of
+// per-axis ranges, and the overlap volume is the product of per-axis
+// lengths, so the workgroup first tabulates per axis and target index the
+// overlapped source indices with their weights (overlap length over the sum
+// of the axis's overlaps) and the offsets of the overlap centres from the
+// source cell centres (along a face field's own axis: the two bracketing
+// source faces and their linear weights).  It then stages the
+// time-interpolated source values of a chunk of the box (all variables,
+// slope neighbours included) in LDS, and every target value of the chunk
+// sums over its overlapped cells from there.  Boxes whose overlaps exceed
+// the tables (resolution ratios above three) or whose smallest chunk does
+// not fit the stage are flagged by the host (GBox::direct) and resampled
+// straight from the slices by k_gfill_direct.
 
-constexpr int GSTAGE = 8192;  // staged source values per workgroup
 
+template <class T> struct GfillSmem {
+  T stage[GSTAGE_BYTES / sizeof(T)];
+  T w[3][GMAXT][GMAXC];    // per-axis weights
+  T off[3][GMAXT][GMAXC];  // per-axis offsets of the overlap centres (source cells)
+  int i0[3][GMAXT];        // first overlapped source index
+  int cnt[3][GMAXT];       // number of overlapped source indices (0: table overflow)
+  int ch_tb, ch_nv, ch_direct;  // chunk: last target index along the chunk axis, variables
+  int r0[3], r1[3];        // staged source index range of the chunk
+};
+
+// Table entry of target index t (relative to the box) along axis d.
 template <class T>
-__global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 1) void k_gfill(DevSet S, const int* __restrict__ list, int count,
-                                               const T* __restrict__ slots, T* __restrict__ pad,
-                                               int64_t pad_stride) {
-  __shared__ T stage[GSTAGE];
+__device__ inline void gfill_axis(const DevSet& S, int p, int q, int comp, const GBox& G, int d, int t,
+                                  GfillSmem<T>& sm) {
+  const int nq = S.n[q];
+  const int64_t sdx = S.dxl[q], len = S.len[q], loq = S.lo[3 * q + d], tdx = S.dxl[p];
+  const int64_t X = S.lo[3 * p + d] + (int64_t)(G.lo[d] + t) * tdx + (d == comp ? 0 : tdx / 2) + G.wrap[d];
+  auto clamp = [&](int64_t v) { return v < 0 ? (int64_t)0 : (v > len ? len : v); };
+  if (d == comp) {  // the two source faces bracketing the target face
+    const int64_t A = clamp(X - loq);
+    int f0 = (int)(A / sdx);
+    int64_t rem = A - (int64_t)f0 * sdx;
+    if (f0 >= nq) {
+      f0 = nq;
+      rem = 0;
+    }
+    const double wn = (double)rem / (double)sdx;
+    sm.i0[d][t] = f0;
+    sm.cnt[d][t] = wn == 0.0 ? 1 : 2;
+    sm.w[d][t][0] = T(1.0 - wn);
+    sm.w[d][t][1] = T(wn);
+    sm.off[d][t][0] = sm.off[d][t][1] = T(0);
+    return;
+  }
+  const int64_t A = clamp(X - tdx / 2 - loq), B = clamp(X + tdx / 2 - loq);
+  int c0 = (int)(A / sdx), c1 = (int)((B - 1) / sdx);
+  c0 = c0 < 0 ? 0 : (c0 > nq - 1 ? nq - 1 : c0);
+  c1 = c1 < 0 ? 0 : (c1 > nq - 1 ? nq - 1 : c1);
+  // two passes over the overlapped cells: the total overlap, then the
+  // normalised weights and the offsets (overlap lengths are exact integers)
+  double tot = 0.0;
+  int k = 0, first = -1;
+  for (int c = c0; c <= c1; ++c) {
+    const int64_t a = A > (int64_t)c * sdx ? A : (int64_t)c * sdx;
+    const int64_t b = B < (int64_t)(c + 1) * sdx ? B : (int64_t)(c + 1) * sdx;
+    if (b - a <= 0) continue;
+    if (first < 0) first = c;
+    tot += (double)(b - a);
+    ++k;
+  }
+  if (k > GMAXC) {  // more overlapped cells than the table holds (the host flags such boxes)
+    sm.cnt[d][t] = 0;
+    return;
+  }
+  sm.i0[d][t] = first;
+  sm.cnt[d][t] = k;
+  for (int m = 0; m < k; ++m) {
+    const int c = first + m;
+    const int64_t a = A > (int64_t)c * sdx ? A : (int64_t)c * sdx;
+    const int64_t b = B < (int64_t)(c + 1) * sdx ? B : (int64_t)(c + 1) * sdx;
+    sm.w[d][t][m] = T((double)(b - a) / tot);
+    sm.off[d][t][m] = T((0.5 * (double)(a + b) - ((double)c + 0.5) * (double)sdx) / (double)sdx);
+  }
+}
+
+// Boxes flagged direct, resampled straight from the source slices: one
+// workgroup per (region, patch) as k_gfill, one thread per element.
+template <class T>
+__global__ __launch_bounds__(256) void k_gfill_direct(DevSet S, const int* __restrict__ list, int count,
+                                                      const T* __restrict__ slots, T* __restrict__ pad,
+                                                      int64_t pad_stride) {
   const int key = blockIdx.x;
   const int b = blockIdx.y;
   if (b >= live_count(S, count)) return;
   const int p = list[b];
-  const int comp = key / 27 - 1, reg = key % 27;
-  if (reg == 13 || region_direct(S, p, key)) return;
-  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int comp = key / 27 - 1;
   const int n = S.n[p], N = n + 4;
   const int nvar = comp < 0 ? 5 : 1;
   const int m0 = S.rbox_off[p * 108 + key], m1 = S.rbox_off[p * 108 + key + 1];
   const int64_t dxl = S.dxl[p];
   T* dst = pad + (int64_t)b * pad_stride;
-  // lattice position of target element (i, j, k), in the source's periodic image
-  auto lattice = [&](const GBox& G, int i, int j, int k, int64_t* X) {
-    const int idx[3] = {i, j, k};
-    for (int d = 0; d < 3; ++d)
-      X[d] = S.lo[3 * p + d] + (int64_t)idx[d] * dxl + (d == comp ? 0 : dxl / 2) + G.wrap[d];
-  };
-  // an element of an earlier box of the region belongs to that box
-  auto earlier = [&](int m, int i, int j, int k) {
-    for (int mm = m0; mm < m; ++mm) {
-      const GBox& H = S.boxes[mm];
-      if (i >= H.lo[0] && i <= H.hi[0] && j >= H.lo[1] && j <= H.hi[1] && k >= H.lo[2] && k <= H.hi[2]) return true;
-    }
-    return false;
-  };
   for (int m = m0; m < m1; ++m) {
     const GBox G = S.boxes[m];
-    const Bracket br = bracket(S, G.q, S.ticks[p], S.tcur[p]);
+    if (!G.direct) continue;
+    const Bracket br = S.brk[m];
     const int ex = G.hi[0] - G.lo[0] + 1, ey = G.hi[1] - G.lo[1] + 1, ez = G.hi[2] - G.lo[2] + 1;
-    const int cnt = ex * ey * ez;
-    const int nq = S.n[G.q];
-    if (G.same) {
-      for (int e = tid; e < cnt * nvar; e += nthr) {
-        int r = e;
-        const int i = G.lo[0] + r % ex;
-        r /= ex;
-        const int j = G.lo[1] + r % ey;
-        r /= ey;
-        const int k = G.lo[2] + r % ez;
-        const int var = r / ez;
-        if (earlier(m, i, j, k)) continue;
-        const int qi = i + G.shift[0], qj = j + G.shift[1], qk = k + G.shift[2];
-        const int64_t se = (comp < 0) ? scell(nq, var, qi, qj, qk) : sface(nq, comp, qi, qj, qk);
-        dst[(comp < 0) ? pcell(N, var, i, j, k) : pface(N, comp, i, j, k)] = tlerp(slots, br, se);
+    for (int e = threadIdx.x; e < ex * ey * ez * nvar; e += blockDim.x) {
+      int r = e;
+      const int i = G.lo[0] + r % ex;
+      r /= ex;
+      const int j = G.lo[1] + r % ey;
+      r /= ey;
+      const int k = G.lo[2] + r % ez;
+      const int var = r / ez;
+      const int idx[3] = {i, j, k};
+      int64_t X[3];
+      for (int d = 0; d < 3; ++d) X[d] = S.lo[3 * p + d] + (int64_t)idx[d] * dxl + (d == comp ? 0 : dxl / 2) + G.wrap[d];
+      dst[(comp < 0) ? pcell(N, var, i, j, k) : pface(N, comp, i, j, k)] =
+          cross_value(S, slots, br, G.q, comp, var, X, dxl);
+    }
+  }
+}
+
+// Time-interpolated values (tlerp) of count elements, U per thread at a
+// time: every read of a batch is issued before the first value is used, so
+// the read latencies overlap instead of adding up along the loop.  off(e):
+// the element's offset within a slice; put(e, v) stores the value.
+template <class T, int U, class Off, class Put>
+__device__ __forceinline__ void tlerp_batched(const T* slots, const Bracket& br, int count, int tid, int nthr,
+                                              Off&& off, Put&& put) {
+  using gptr = const T __attribute__((address_space(1)))*;
+  const gptr g = (gptr)slots;
+  const bool two = br.oa != br.ob, three = br.oc >= 0;
+  const T w = (T)br.w, wc = (T)br.wc;
+  for (int e0 = tid; e0 < count; e0 += nthr * U) {
+    T a[U], b[U], c[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * nthr;
+      if (e < count) {
+        const int64_t se = off(e);
+        a[u] = g[br.oa + se];
+        b[u] = two ? g[br.ob + se] : a[u];
+        c[u] = three ? g[br.oc + se] : a[u];
       }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * nthr;
+      if (e < count) {
+        T v = a[u];
+        if (two) v = three ? a[u] + w * (b[u] - a[u]) + wc * (c[u] - a[u]) : a[u] + w * (b[u] - a[u]);
+        put(e, v);
+      }
+    }
+  }
+}
+
+template <class T>
+__device__ __forceinline__ T minmod_slope(T vm, T v0, T vp) {
+  const T a = v0 - vm, b = vp - v0;
+  if (a * b <= T(0)) return T(0);
+  return (fabs(a) < fabs(b)) ? a : b;
+}
+
+// q = r / d for 0 <= r < 2^22 and 1 <= d < 2^11 without an integer division:
+// the single-precision estimate r * (1/d) is within one of the quotient,
+// and one correction step makes it exact.
+__device__ __forceinline__ int small_div(int r, int d, float inv) {
+  int q = (int)((float)r * inv);
+  const int rem = r - q * d;
+  q += rem >= d ? 1 : 0;
+  q -= rem < 0 ? 1 : 0;
+  return q;
+}
+
+constexpr int GFILL_ROWS = 512;  // patch rows of the resampling grid (a row strides over the ready list)
+
+template <class T>
+__global__ __launch_bounds__(256) void k_gfill(DevSet S, const int* __restrict__ list, int count,
+                                               const T* __restrict__ slots, T* __restrict__ pad,
+                                               int64_t pad_stride) {
+  constexpr int GSTAGE = GSTAGE_BYTES / (int)sizeof(T);
+  __shared__ GfillSmem<T> sm;
+  const int key = blockIdx.x;
+  const int live = live_count(S, count);
+  const int comp = key / 27 - 1, reg = key % 27;
+  if (reg == 13) return;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int nvar = comp < 0 ? 5 : 1;
+  for (int b = blockIdx.y; b < live; b += gridDim.y) {
+  const int p = list[b];
+  if (region_direct(S, p, key)) continue;
+  const int n = S.n[p], N = n + 4;
+  const int m0 = S.rbox_off[p * 108 + key], m1 = S.rbox_off[p * 108 + key + 1];
+  T* dst = pad + (int64_t)b * pad_stride;
+  // padded-buffer offset (32 bits: a padded patch holds fewer than 2^31 values)
+  const int N2 = N * N;
+  auto dst_off = [&](int var, int i, int j, int k) -> int {
+    if (comp < 0) return var * N2 * N + ((k + 2) * N + (j + 2)) * N + (i + 2);
+    const int sx = N + (comp == 0), sy = N + (comp == 1);
+    return 5 * N2 * N + comp * N2 * (N + 1) + ((k + 2) * sy + (j + 2)) * sx + (i + 2);
+  };
+  // the boxes of a region are disjoint (the host checks that they tile it)
+  for (int m = m0; m < m1; ++m) {
+    const GBox G = S.boxes[m];
+    if (G.direct) continue;  // k_gfill_direct
+    const Bracket br = S.brk[m];  // the round's bracket of this box (k_brackets)
+    const int ext[3] = {G.hi[0] - G.lo[0] + 1, G.hi[1] - G.lo[1] + 1, G.hi[2] - G.lo[2] + 1};
+    const int cnt = ext[0] * ext[1] * ext[2];
+    const int q = G.q, nq = S.n[q];
+    if (G.same) {
+      const float ie0 = 1.0f / (float)ext[0], ie1 = 1.0f / (float)ext[1], ie2 = 1.0f / (float)ext[2];
+      auto decode = [&](int e, int& var, int& i, int& j, int& k) {
+        int r = e;
+        int qq = small_div(r, ext[0], ie0);
+        i = G.lo[0] + (r - qq * ext[0]);
+        r = qq;
+        qq = small_div(r, ext[1], ie1);
+        j = G.lo[1] + (r - qq * ext[1]);
+        r = qq;
+        qq = small_div(r, ext[2], ie2);
+        k = G.lo[2] + (r - qq * ext[2]);
+        var = qq;
+      };
+      tlerp_batched<T, 8>(
+          slots, br, cnt * nvar, tid, nthr,
+          [&](int e) -> int64_t {
+            int var, i, j, k;
+            decode(e, var, i, j, k);
+            const int qi = i + G.shift[0], qj = j + G.shift[1], qk = k + G.shift[2];
+            return (comp < 0) ? scell(nq, var, qi, qj, qk) : sface(nq, comp, qi, qj, qk);
+          },
+          [&](int e, T v) {
+            int var, i, j, k;
+            decode(e, var, i, j, k);
+            dst[dst_off(var, i, j, k)] = v;
+          });
       continue;
     }
-    int64_t Xlo[3], Xhi[3];
-    lattice(G, G.lo[0], G.lo[1], G.lo[2], Xlo);
-    lattice(G, G.hi[0], G.hi[1], G.hi[2], Xhi);
-    int r0[3], r1[3];
-    cross_source_range(S, G.q, comp, Xlo, Xhi, dxl, r0, r1);
-    const int sx = r1[0] - r0[0] + 1, sy = r1[1] - r0[1] + 1, sz = r1[2] - r0[2] + 1;
-    const bool staged = (int64_t)sx * sy * sz <= GSTAGE;
-    for (int var = 0; var < nvar; ++var) {
-      if (staged) {
-        __syncthreads();  // the previous variable's readers are done
-        for (int e = tid; e < sx * sy * sz; e += nthr) {
-          const int ii = r0[0] + e % sx, jj = r0[1] + (e / sx) % sy, kk = r0[2] + e / (sx * sy);
-          const int64_t se = (comp < 0) ? scell(nq, var, ii, jj, kk) : sface(nq, comp, ii, jj, kk);
-          stage[e] = tlerp(slots, br, se);
-        }
-        __syncthreads();
+    __syncthreads();  // the previous box's readers of the tables are done
+    if (tid == 0) sm.ch_direct = 0;
+    const bool fits = ext[0] <= GMAXT && ext[1] <= GMAXT && ext[2] <= GMAXT;
+    __syncthreads();
+    if (fits)
+      for (int t = tid; t < ext[0] + ext[1] + ext[2]; t += nthr) {
+        const int d = t < ext[0] ? 0 : (t < ext[0] + ext[1] ? 1 : 2);
+        const int tt = t - (d > 0 ? ext[0] : 0) - (d > 1 ? ext[1] : 0);
+        gfill_axis<T>(S, p, q, comp, G, d, tt, sm);
+        if (sm.cnt[d][tt] == 0) sm.ch_direct = 1;  // table overflow
       }
-      for (int e = tid; e < cnt; e += nthr) {
-        const int i = G.lo[0] + e % ex, j = G.lo[1] + (e / ex) % ey, k = G.lo[2] + e / (ex * ey);
-        if (earlier(m, i, j, k)) continue;
-        int64_t X[3];
-        lattice(G, i, j, k, X);
-        T v;
-        if (staged)
-          v = cross_value_from<T>(S, G.q, comp, X, dxl, [&](int a, int c, int d) -> T {
-            return stage[((d - r0[2]) * sy + (c - r0[1])) * sx + (a - r0[0])];
-          });
-        else
-          v = cross_value(S, slots, br, G.q, comp, var, X, dxl);
-        dst[(comp < 0) ? pcell(N, var, i, j, k) : pface(N, comp, i, j, k)] = v;
+    else if (tid == 0)
+      sm.ch_direct = 1;
+    __syncthreads();
+    if (sm.ch_direct) {  // the host's limits should have flagged this box
+      if (tid == 0) atomicOr(S.err, ERR_STATE);
+      continue;
+    }
+    // chunk axis: the longest; along it, chunks of target indices whose
+    // staged source block (all variables when they fit) fills the stage
+    int ca = 0;
+    if (ext[1] > ext[ca]) ca = 1;
+    if (ext[2] > ext[ca]) ca = 2;
+    const int cb = (ca + 1) % 3, cc = (ca + 2) % 3;
+    // source range of target indices [a, b] along axis d: the overlapped
+    // indices, plus the slope neighbours across (not along a face's own axis)
+    auto range = [&](int d, int a, int bb, int& r0, int& r1) {
+      r0 = sm.i0[d][a];
+      r1 = sm.i0[d][bb] + sm.cnt[d][bb] - 1;
+      if (d != comp) {
+        r0 = r0 > 0 ? r0 - 1 : 0;
+        r1 = r1 < nq - 1 ? r1 + 1 : nq - 1;
+      }
+    };
+    int rb0, rb1, rc0, rc1;
+    range(cb, 0, ext[cb] - 1, rb0, rb1);
+    range(cc, 0, ext[cc] - 1, rc0, rc1);
+    const int across = (rb1 - rb0 + 1) * (rc1 - rc0 + 1);
+    auto size = [&](int a, int bb) {
+      int x0, x1;
+      range(ca, a, bb, x0, x1);
+      return across * (x1 - x0 + 1);
+    };
+    int ta = 0, v0 = 0;
+    while (ta < ext[ca]) {
+      // chunk: every variable over the most target indices that fit (each
+      // thread tests one extent; the sizes grow with the extent), else one
+      // target index with as many variables as fit
+      __syncthreads();
+      if (tid == 0) sm.ch_tb = ta;
+      __syncthreads();
+      int nv;
+      if (v0 == 0 && size(ta, ta) * nvar <= GSTAGE) {
+        nv = nvar;
+        const int t = ta + tid;
+        if (tid > 0 && t < ext[ca] && size(ta, t) * nvar <= GSTAGE) atomicMax(&sm.ch_tb, t);
+      } else {
+        nv = GSTAGE / size(ta, ta);
+        nv = nv > nvar - v0 ? nvar - v0 : nv;
+      }
+      __syncthreads();
+      if (nv < 1) {  // not even one variable of one index: the host's limits should have flagged it
+        if (tid == 0) atomicOr(S.err, ERR_STATE);
+        break;
+      }
+      const int tb = sm.ch_tb;
+      int r0[3], r1[3];
+      range(ca, ta, tb, r0[ca], r1[ca]);
+      r0[cb] = rb0;
+      r1[cb] = rb1;
+      r0[cc] = rc0;
+      r1[cc] = rc1;
+      const int r00 = r0[0], r01 = r0[1], r02 = r0[2];
+      const int sx = r1[0] - r00 + 1, sy = r1[1] - r01 + 1, sz = r1[2] - r02 + 1;
+      const int sxy = sx * sy, sblk = sxy * sz;
+      const float isx = 1.0f / (float)sx, isxy = 1.0f / (float)sxy, isblk = 1.0f / (float)sblk;
+      tlerp_batched<T, 8>(
+          slots, br, nv * sblk, tid, nthr,
+          [&](int e) -> int64_t {
+            const int v = small_div(e, sblk, isblk), r = e - v * sblk;
+            const int kq = small_div(r, sxy, isxy), rr = r - kq * sxy;
+            const int jq = small_div(rr, sx, isx);
+            const int ii = r00 + (rr - jq * sx), jj = r01 + jq, kk = r02 + kq;
+            return (comp < 0) ? scell(nq, v0 + v, ii, jj, kk) : sface(nq, comp, ii, jj, kk);
+          },
+          [&](int e, T v) { sm.stage[e] = v; });
+      __syncthreads();
+      // target elements of the chunk: ta..tb along the chunk axis, all of the
+      // others (per-axis indices kept in scalars: no private arrays indexed at
+      // run time in the hot loop)
+      const int ce0 = ca == 0 ? tb - ta + 1 : ext[0], ce1 = ca == 1 ? tb - ta + 1 : ext[1];
+      const int ce2 = ca == 2 ? tb - ta + 1 : ext[2];
+      const int ce01 = ce0 * ce1, ccnt = ce01 * ce2;
+      const float ice0 = 1.0f / (float)ce0, ice01 = 1.0f / (float)ce01, iccnt = 1.0f / (float)ccnt;
+      for (int e = tid; e < nv * ccnt; e += nthr) {
+        const int v = small_div(e, ccnt, iccnt), r = e - v * ccnt;
+        int t2 = small_div(r, ce01, ice01);
+        const int r2 = r - t2 * ce01;
+        int t1 = small_div(r2, ce0, ice0);
+        int t0 = r2 - t1 * ce0;
+        t0 += ca == 0 ? ta : 0;
+        t1 += ca == 1 ? ta : 0;
+        t2 += ca == 2 ? ta : 0;
+        const T* st = sm.stage + v * sblk;
+        T acc = T(0);
+        if (comp < 0) {
+          const int cz = sm.cnt[2][t2], cy = sm.cnt[1][t1], cx = sm.cnt[0][t0];
+          const int kz = sm.i0[2][t2], jy = sm.i0[1][t1], ix = sm.i0[0][t0];
+          for (int c = 0; c < cz; ++c) {
+            const int kk = kz + c;
+            const T wz = sm.w[2][t2][c], oz = sm.off[2][t2][c];
+            const bool zm = kk - 1 >= 0, zp = kk + 1 <= nq - 1;
+            for (int bq = 0; bq < cy; ++bq) {
+              const int jj = jy + bq;
+              const T wy = sm.w[1][t1][bq], oy = sm.off[1][t1][bq];
+              const bool ym = jj - 1 >= 0, yp = jj + 1 <= nq - 1;
+              const T wyz = wy * wz;
+              const int rowb = (kk - r02) * sxy + (jj - r01) * sx - r00;
+              for (int a = 0; a < cx; ++a) {
+                const int ii = ix + a;
+                const T wx = sm.w[0][t0][a], ox = sm.off[0][t0][a];
+                const int o = rowb + ii;
+                const T c0 = st[o];
+                const bool xm = ii - 1 >= 0, xp = ii + 1 <= nq - 1;
+                const T gx = (xm && xp) ? minmod_slope(st[o - 1], c0, st[o + 1])
+                             : xp ? st[o + 1] - c0 : (xm ? c0 - st[o - 1] : T(0));
+                const T gy = (ym && yp) ? minmod_slope(st[o - sx], c0, st[o + sx])
+                             : yp ? st[o + sx] - c0 : (ym ? c0 - st[o - sx] : T(0));
+                const T gz = (zm && zp) ? minmod_slope(st[o - sxy], c0, st[o + sxy])
+                             : zp ? st[o + sxy] - c0 : (zm ? c0 - st[o - sxy] : T(0));
+                acc = acc + (wx * wyz) * (((c0 + ox * gx) + oy * gy) + oz * gz);
+              }
+            }
+          }
+        } else {
+          // face field of component d = comp: index f along d, u along
+          // t1 = d + 1, w along t2 = d + 2 (cyclic); stage strides of the three
+          const int d = comp;
+          const int tn = d == 0 ? t0 : (d == 1 ? t1 : t2);
+          const int tu = d == 0 ? t1 : (d == 1 ? t2 : t0);
+          const int tw = d == 0 ? t2 : (d == 1 ? t0 : t1);
+          const int au = d == 2 ? 0 : d + 1, aw = d == 0 ? 2 : d - 1;  // the axes t1, t2
+          const int su = au == 0 ? 1 : (au == 1 ? sx : sxy), sw = aw == 0 ? 1 : (aw == 1 ? sx : sxy);
+          const int sn = d == 0 ? 1 : (d == 1 ? sx : sxy);
+          const int rn = d == 0 ? r00 : (d == 1 ? r01 : r02);
+          const int ru = au == 0 ? r00 : (au == 1 ? r01 : r02);
+          const int rw = aw == 0 ? r00 : (aw == 1 ? r01 : r02);
+          const int cu_n = sm.cnt[au][tu], cw_n = sm.cnt[aw][tw], cs_n = sm.cnt[d][tn];
+          for (int cu = 0; cu < cu_n; ++cu) {
+            const int u = sm.i0[au][tu] + cu;
+            const T wu = sm.w[au][tu][cu], ou = sm.off[au][tu][cu];
+            const bool um = u - 1 >= 0, up = u + 1 <= nq - 1;
+            for (int cw = 0; cw < cw_n; ++cw) {
+              const int w = sm.i0[aw][tw] + cw;
+              const T ww = sm.w[aw][tw][cw], ow = sm.off[aw][tw][cw];
+              const bool wm = w - 1 >= 0, wp = w + 1 <= nq - 1;
+              T lin2 = T(0);
+              for (int side = 0; side < cs_n; ++side) {
+                const int f = sm.i0[d][tn] + side;
+                const int o = (f - rn) * sn + (u - ru) * su + (w - rw) * sw;
+                const T c0 = st[o];
+                const T gu = (um && up) ? minmod_slope(st[o - su], c0, st[o + su])
+                             : up ? st[o + su] - c0 : (um ? c0 - st[o - su] : T(0));
+                const T gw = (wm && wp) ? minmod_slope(st[o - sw], c0, st[o + sw])
+                             : wp ? st[o + sw] - c0 : (wm ? c0 - st[o - sw] : T(0));
+                lin2 = lin2 + sm.w[d][tn][side] * ((c0 + ou * gu) + ow * gw);
+              }
+              acc = acc + (wu * ww) * lin2;
+            }
+          }
+        }
+        dst[dst_off(v0 + v, G.lo[0] + t0, G.lo[1] + t1, G.lo[2] + t2)] = acc;
+      }
+      v0 += nv;
+      if (v0 >= nvar) {
+        v0 = 0;
+        ta = tb + 1;
       }
     }
+  }
+  __syncthreads();  // the next patch row reuses the tables and the stage
   }
 }
 
@@ -1287,16 +1616,27 @@ __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict
 // ---------------------------------------------------------------------------
 
 template <class T>
-int launch_fused(const DevSet& S, const int* list, int count, int nmin, int nmax, T* slots, T* pad,
+int launch_fused(const DevSet& S0, const int* list, int count, int nmin, int nmax, T* slots, T* pad,
                   int64_t pad_stride, bool gfill, double* smax, const StepPtr& st, hipStream_t s, int dt_kind,
                   double t_end, int clip, hipEvent_t ev0, hipEvent_t ev1) {
   const int N = nmax + 4;
+  // with the resampling, the round's brackets are computed first and every
+  // kernel of the round reads them
+  DevSet S = S0;
+  S.brk_ready = gfill ? 1 : 0;
   // the events bracket the round's whole update sequence: guard resampling,
   // separate Courant pass (if any) and the step
   if (ev0) (void)hipEventRecord(ev0, s);
-  if (gfill)
-    hipLaunchKernelGGL(k_gfill<T>, dim3(108, count), dim3(256), 0, s, S, list, count, (const T*)slots, pad,
-                       pad_stride);
+  if (gfill) {
+    // the time bracket of every guard box of the listed patches, once (a
+    // chain of dependent reads that every resampling workgroup would repeat)
+    launch_brackets(S, list, count, s);
+    hipLaunchKernelGGL(k_gfill<T>, dim3(108, std::min(count, GFILL_ROWS)), dim3(256), 0, s, S, list, count,
+                       (const T*)slots, pad, pad_stride);
+    if (S.any_direct)
+      hipLaunchKernelGGL(k_gfill_direct<T>, dim3(108, count), dim3(256), 0, s, S, list, count, (const T*)slots,
+                         pad, pad_stride);
+  }
   const int tpa = (nmax + MT - 1) / MT;
   // a local step of single-tile patches takes its Courant rate and level
   // inside the step kernel; otherwise a separate pass (the global modes

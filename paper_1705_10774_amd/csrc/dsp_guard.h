@@ -383,8 +383,9 @@ __device__ inline void region_tab_init(const DevSet& S, const T* slots, const T*
     E.w = T(0);
     E.nq = n;
   } else if (region_direct(S, p, key)) {
-    const GBox& G = S.boxes[S.rbox_off[p * 108 + key]];
-    const Bracket b = bracket(S, G.q, S.ticks[p], S.tcur[p]);
+    const int m = S.rbox_off[p * 108 + key];
+    const GBox& G = S.boxes[m];
+    const Bracket b = S.brk_ready ? S.brk[m] : bracket(S, G.q, S.ticks[p], S.tcur[p]);
     const int nq = S.n[G.q];
     const int64_t e0 = (comp < 0) ? scell(nq, 0, G.shift[0], G.shift[1], G.shift[2])
                                   : sface(nq, comp, G.shift[0], G.shift[1], G.shift[2]);

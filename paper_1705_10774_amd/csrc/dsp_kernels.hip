@@ -45,7 +45,7 @@ namespace dsp {
 #ifdef DSP_TU_COMMON
 __global__ void k_brackets(DevSet S, const int* __restrict__ list, int count) {
   const int b = blockIdx.y;
-  if (b >= count) return;
+  if (b >= live_count(S, count)) return;
   const int p = list[b];
   const int m = S.rbox_off[p * 108] + (int)(blockIdx.x * blockDim.x + threadIdx.x);
   if (m >= S.rbox_off[p * 108 + 108]) return;

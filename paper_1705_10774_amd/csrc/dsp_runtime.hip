@@ -460,6 +460,34 @@ struct dsp_set {
 
 namespace {
 
+// Whether the staged guard resampling (k_gfill) can take a box resampled
+// from source Q into patch P: along every axis across a cell (or across a
+// face) a target index overlaps at most GMAXC source indices, the box has at
+// most GMAXT indices per axis, and the smallest chunk (one variable, one
+// index along the box's longest axis) with its slope neighbours fits the LDS
+// stage.  Upper bounds of what the kernel computes: a run of e target
+// indices of length L source cells overlaps at most ceil(e L) + 1 source
+// indices, plus one slope neighbour on each side.
+bool staged_resampling_fits(const HPatch& P, const HPatch& Q, int comp, const GBox& g, int prec) {
+  const int64_t stage = GSTAGE_BYTES / (prec == DSP_F32 ? 4 : 8);
+  int ext[3], ca = 0;
+  for (int d = 0; d < 3; ++d) {
+    ext[d] = g.hi[d] - g.lo[d] + 1;
+    if (ext[d] > GMAXT) return false;
+  }
+  if (ext[1] > ext[ca]) ca = 1;
+  if (ext[2] > ext[ca]) ca = 2;
+  auto span = [&](int64_t e) { return (e * P.dxl + Q.dxl - 1) / Q.dxl + 1; };  // ceil(e L) + 1
+  if (span(1) > GMAXC) return false;
+  int64_t size = 1;
+  for (int d = 0; d < 3; ++d) {
+    const int64_t nsrc = Q.n + (d == comp ? 1 : 0);
+    const int64_t b = span(d == ca ? 1 : ext[d]) + 2;
+    size *= b < nsrc ? b : nsrc;
+  }
+  return size <= stage;
+}
+
 bool tolat(double x, int64_t scale, int64_t& out) {
   const double y = x * (double)scale;
   const double r = std::nearbyint(y);
@@ -598,7 +626,10 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
     e = S->build_boxes(p, 2, keys, nullptr);
     if (e) return e;
     for (int k = 0; k < 108; ++k) {
-      for (const GBox& g : keys[k]) boxes.push_back(g);
+      for (GBox g : keys[k]) {
+        g.direct = (!g.same && !staged_resampling_fits(S->P[p], S->P[g.q], k / 27 - 1, g, c.prec)) ? 1 : 0;
+        boxes.push_back(g);
+      }
       rbox_off.push_back((int)boxes.size());
     }
   }
@@ -742,6 +773,16 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
   D.boxes = (const GBox*)up(boxes.data(), sizeof(GBox) * std::max<size_t>(1, boxes.size()));
   D.brk = (Bracket*)A(sizeof(Bracket) * std::max<size_t>(1, boxes.size()));
   for (int p = 0; p < npatch; ++p) D.maxbox = std::max(D.maxbox, rbox_off[(p + 1) * 108] - rbox_off[p * 108]);
+  D.any_direct = 0;
+  for (const GBox& g : boxes) D.any_direct |= g.direct;
+  if (getenv("DSP_DEBUG")) {
+    int nd = 0, nx = 0;
+    for (const GBox& g : boxes) {
+      nd += g.direct;
+      nx += g.same ? 0 : 1;
+    }
+    fprintf(stderr, "dsp_create: %d of %d resampled guard boxes resample without staging\n", nd, nx);
+  }
   s->d_err = (int*)A(sizeof(int) * 2);
   s->d_cnt = (unsigned long long*)A(sizeof(unsigned long long) * 4);  // floor, fallback, updates, bytes
   D.err = s->d_err;
