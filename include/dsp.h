@@ -216,6 +216,36 @@ int dsp_fixed_steps_fwd(dsp_set* set, const void* U0_dev, void* UT_dev, int32_t 
 int dsp_fixed_steps_adj(dsp_set* set, const void* ckpt_dev, const void* lamT_dev,
                         void* lam0_dev, int32_t nsteps, int32_t seg);
 
+/* Dispatch of LOCAL steps (Sec. 3B).  DSP_DISPATCH_ROUNDS: every round
+ * updates the whole ready set (readiness scan, guard resampling, step,
+ * publish as a queued launch sequence per round).  DSP_DISPATCH_QUEUE: the
+ * paper's dispatcher mode (i) on the device -- one persistent kernel whose
+ * workgroups take ready patches from a device queue, update and publish
+ * them and push the neighbours that became ready, launched as a captured
+ * hipGraph (queue seed + persistent kernel) replayed by each advance.  The
+ * queue mode is available for single-precision sets of patches of at most
+ * 16^3 cells (one tile per patch) without a grace; with g = 0 both modes give
+ * bitwise the same results.  New sets start in the queue mode when it is
+ * available (environment DSP_DISPATCH=rounds overrides).  Every wait of the
+ * persistent kernel is bounded (DSP_QUEUE_TIMEOUT_S, default 30 s; then
+ * DSP_ESTATE). */
+enum { DSP_DISPATCH_ROUNDS = 0, DSP_DISPATCH_QUEUE = 1 };
+/* Select the dispatch mode (DSP_EINVAL: the queue mode is not available for
+ * this set) and, for the queue mode, the number of persistent workgroups
+ * (0: one per compute unit, at most the number of patches). */
+int dsp_set_dispatch(dsp_set* set, int32_t mode, int32_t workers);
+/* Current mode, whether the queue mode is available, and its workgroups. */
+int dsp_get_dispatch(const dsp_set* set, int32_t* mode, int32_t* queue_available, int32_t* workers);
+/* Autotuner: times LOCAL advances of t_probe (a multiple of dt_base) from the
+ * set's current state with each candidate dispatch (rounds; the queue with
+ * all, three quarters and half of the workgroups, when available), restores
+ * the state, and selects the fastest.  cache_path (nullable): a text file of
+ * JSON lines, one per tuned (device, set shape) key; an entry for this key
+ * is used without timing, a new result is appended.  Allocates a copy of
+ * the set's state for the duration of the call.  ms_out (nullable, 4
+ * entries) receives the timings (-1: not a candidate). */
+int dsp_autotune(dsp_set* set, double t_probe, const char* cache_path, double* ms_out);
+
 /* Snapshot files (restart; output of the task list, Sec. 3E).  The file
  * holds the whole state of the set: for every patch (id order) its size and
  * level, time (ticks and FP64), current slot, step count, level hash and level

@@ -14,7 +14,7 @@
 
 namespace dsp {
 
-enum : int { ERR_NONFINITE = 1, ERR_NEGATIVE = 2, ERR_KMAX = 4, ERR_STATE = 8 };
+enum : int { ERR_NONFINITE = 1, ERR_NEGATIVE = 2, ERR_KMAX = 4, ERR_STATE = 8, ERR_TIMEOUT = 16 };
 
 // A box of guard elements of one patch that take their values from one
 // source patch.  Indices are the patch's own padded indices (inclusive);
@@ -128,6 +128,24 @@ struct StepPtr {
   double* dt;
 };
 
+// Device ready queue of the persistent dispatcher (k_persist): a ring of
+// patch ids (id + 1; 0 = empty slot) filled by tickets, and per-patch
+// ownership (0: idle, 1: queued or being updated).  Every field is written
+// by the seed kernels before the persistent launch and then only through
+// agent-scope atomics.
+struct QueueState {
+  int* buf;               // ring of cap entries
+  int cap;
+  unsigned* head;         // tickets taken by workers
+  unsigned* tail;         // tickets given to pushed patches
+  int* state;             // [npatch] ownership
+  int* done;              // patches that reached the end time
+  int* remaining;         // patches the advance has to bring to the end time
+  int* finished;          // 1 once done == remaining
+  const int64_t* tend;    // end time (ticks), written before each launch
+  uint64_t timeout;       // limit of every wait, in s_memrealtime ticks (100 MHz)
+};
+
 // Level k of a local step (dt = dt_base 2^-k) from the patch Courant rate.
 __device__ inline int level_for(const DevSet& S, double smax, int64_t ticks) {
   // k_c = 0 if r <= 1 else ceil(log2 r) exactly (frexp), r = dt_base smax / C;
@@ -157,6 +175,14 @@ template <class T>
 int launch_fused(const DevSet& S, const int* list, int count, int nmin, int nmax, T* slots, T* pad,
                   int64_t pad_stride, bool gfill, double* smax, const StepPtr& st, hipStream_t s, int dt_kind,
                   double t_end, int clip, hipEvent_t ev0, hipEvent_t ev1);
+// Persistent dispatcher (single-precision sets of one-tile patches, no
+// grace): clears the queue (grid over max(cap, npatch)), then seeds it with
+// the patches ready at the start; k_persist runs with `workers` workgroups
+// until every patch has reached *Q.tend.  fn: 16 for sets of equal 16^3
+// patches without resampled guard regions, else 0.
+void launch_queue_seed(const DevSet& S, const QueueState& Q, hipStream_t s);
+void launch_persist(const DevSet& S, const QueueState& Q, float* slots, float* pad, int64_t pad_stride,
+                    const StepPtr& st, int workers, int fn, bool gfill, hipStream_t s);
 template <class T>
 void launch_adjoint_step(const DevSet& S, const int* list, int count, int nmax, const WorkPtr<T>& W,
                          const WorkPtr<T>& L, const StepPtr& st, const T* lam_next, T* lam_prev,

@@ -356,24 +356,18 @@ __device__ __forceinline__ int small_div(int r, int d, float inv) {
 
 constexpr int GFILL_ROWS = 512;  // patch rows of the resampling grid (a row strides over the ready list)
 
+// Guard region `key` of patch p into its padded buffer dst, by the whole
+// workgroup (every thread calls it; the workgroup synchronises inside).  The
+// time brackets of the region's boxes are in S.brk.
 template <class T>
-__global__ __launch_bounds__(256) void k_gfill(DevSet S, const int* __restrict__ list, int count,
-                                               const T* __restrict__ slots, T* __restrict__ pad,
-                                               int64_t pad_stride) {
+__device__ void gfill_region(const DevSet& S, GfillSmem<T>& sm, const T* __restrict__ slots, T* __restrict__ dst,
+                             int p, int key) {
   constexpr int GSTAGE = GSTAGE_BYTES / (int)sizeof(T);
-  __shared__ GfillSmem<T> sm;
-  const int key = blockIdx.x;
-  const int live = live_count(S, count);
-  const int comp = key / 27 - 1, reg = key % 27;
-  if (reg == 13) return;
+  const int comp = key / 27 - 1;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int nvar = comp < 0 ? 5 : 1;
-  for (int b = blockIdx.y; b < live; b += gridDim.y) {
-  const int p = list[b];
-  if (region_direct(S, p, key)) continue;
   const int n = S.n[p], N = n + 4;
   const int m0 = S.rbox_off[p * 108 + key], m1 = S.rbox_off[p * 108 + key + 1];
-  T* dst = pad + (int64_t)b * pad_stride;
   // padded-buffer offset (32 bits: a padded patch holds fewer than 2^31 values)
   const int N2 = N * N;
   auto dst_off = [&](int var, int i, int j, int k) -> int {
@@ -598,7 +592,21 @@ __global__ __launch_bounds__(256) void k_gfill(DevSet S, const int* __restrict__
       }
     }
   }
-  __syncthreads();  // the next patch row reuses the tables and the stage
+  __syncthreads();  // the next region reuses the tables and the stage
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_gfill(DevSet S, const int* __restrict__ list, int count,
+                                               const T* __restrict__ slots, T* __restrict__ pad,
+                                               int64_t pad_stride) {
+  __shared__ GfillSmem<T> sm;
+  const int key = blockIdx.x;
+  const int live = live_count(S, count);
+  if (key % 27 == 13) return;
+  for (int b = blockIdx.y; b < live; b += gridDim.y) {
+    const int p = list[b];
+    if (region_direct(S, p, key)) continue;
+    gfill_region<T>(S, sm, slots, pad + (int64_t)b * pad_stride, p, key);
   }
 }
 
@@ -1219,6 +1227,8 @@ template <class T> struct Step2Smem {
   T py[2][MXF];         // previous plane: y-face upwind speed and Bz induction flux
   T ecc[2][3][MPRED];   // cell-centred EMF -v x B of the half-step state (slot = plane mod 2)
   RegionTab<T> rt;
+  unsigned long long traffic;  // algorithmic bytes of the update (tile 0)
+  double red[NTHR2 / 64];      // one slot per wavefront: the Courant-rate maximum
 };
 
 __device__ __forceinline__ int mod3(int z) { return (z + 3) % 3; }
@@ -1226,23 +1236,18 @@ __device__ __forceinline__ int mod3(int z) { return (z + 3) % 3; }
 // FN > 0: every patch has FN <= MT cells per edge (one tile each) and every
 // guard region is a single same-resolution box, so the patch and region
 // strides are compile-time constants; FN = 0 takes them at run time.
+// One tile of one patch update by one workgroup of NTHR2 threads: bidx is the
+// entry of the step record (st) and of the padded buffer, p the patch.
 template <class T, int FN>
-__global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict__ list, int count,
-                                                 T* __restrict__ slots, const T* __restrict__ pad,
-                                                 int64_t pad_stride, StepPtr st, int tpa, int fuse_dt) {
+__device__ __forceinline__ void step2_tile(const DevSet& S, Step2Smem<T>& sm, T* __restrict__ slots,
+                                           const T* __restrict__ pad, int64_t pad_stride, const StepPtr& st,
+                                           int bidx, int p, int tile, int tpa, int fuse_dt) {
   static_assert(sizeof(T) == 4, "the wide step kernel is the single-precision variant");
   static_assert(FN >= 0 && FN <= MT, "a fixed patch size is one tile");
   using M = FastF32;
-  __shared__ Step2Smem<T> sm;
   const int tid = threadIdx.x;
-  if (FN) tpa = 1;
-  const int T2 = tpa * tpa;
-  const int wg = blockIdx.x;
-  const int bidx = (wg / (8 * T2)) * 8 + (wg % 8);
-  const int tile = (wg / 8) % T2;
-  if (bidx >= live_count(S, count)) return;
   PatchCtx<T> c;
-  c.p = list[bidx];
+  c.p = p;
   const int n = c.n = FN ? FN : S.n[c.p];
   const int nt = (n + MT - 1) / MT;
   const int tx = tile % tpa, ty = tile / tpa;
@@ -1261,16 +1266,14 @@ __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict
   for (int m = tid; m < 108; m += NTHR2)
     region_tab_init(S, (const T*)slots, (const T*)c.ownp, pad + (int64_t)bidx * pad_stride, n + 4, c.p, sm.rt, m);
   const T gamma = T(S.gamma), pfloor = T(S.p_floor);
-  __shared__ unsigned long long traffic;
-  __shared__ double red[NTHR2 / 64];
-  if (tid == 0) traffic = 0;
+  if (tid == 0) sm.traffic = 0;
   __syncthreads();
-  if (tile == 0) count_traffic(S, c.p, box0, nbox, V, (int)sizeof(T), tid, NTHR2, &traffic);
-  const double dt = fuse_dt ? fused_local_dt<T, FN>(S, c, sm.rt, st, bidx, tid, NTHR2, red) : st.dt[bidx];
+  if (tile == 0) count_traffic(S, c.p, box0, nbox, V, (int)sizeof(T), tid, NTHR2, &sm.traffic);
+  const double dt = fuse_dt ? fused_local_dt<T, FN>(S, c, sm.rt, st, bidx, tid, NTHR2, sm.red) : st.dt[bidx];
   const T dtdx = T(dt / S.dx[c.p]);
   const T hdtdx = T(0.5) * dtdx;
   __syncthreads();
-  if (tile == 0 && tid == 0) atomicAdd(S.algo_bytes, traffic);
+  if (tile == 0 && tid == 0) atomicAdd(S.algo_bytes, sm.traffic);
 
   // column of this thread (load phase) and its predictor cell.  The lane
   // indices are re-declared opaque at the start of every phase (reopen), so
@@ -1612,6 +1615,245 @@ __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict
     __syncthreads();
   }
 }
+
+template <class T, int FN>
+__global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict__ list, int count,
+                                                 T* __restrict__ slots, const T* __restrict__ pad,
+                                                 int64_t pad_stride, StepPtr st, int tpa, int fuse_dt) {
+  __shared__ Step2Smem<T> sm;
+  if (FN) tpa = 1;
+  const int T2 = tpa * tpa;
+  const int wg = blockIdx.x;
+  const int bidx = (wg / (8 * T2)) * 8 + (wg % 8);
+  const int tile = (wg / 8) % T2;
+  if (bidx >= live_count(S, count)) return;
+  step2_tile<T, FN>(S, sm, slots, pad, pad_stride, st, bidx, list[bidx], tile, tpa, fuse_dt);
+}
+
+#ifdef DSP_TU_F32
+// ---------------------------------------------------------------------------
+// Persistent dispatcher: the paper's mode (i) of the dispatcher (Sec. 3B), in
+// which workers take the head of a ready queue, on the device.  One
+// persistent launch of `workers` workgroups (one per CU: the step needs the
+// whole LDS) replaces the rounds.  A worker takes a ticket, waits until the
+// ticket's ring slot holds a patch, updates it (guard brackets, resampled
+// guard regions, Courant level, the fused step), publishes it, and tests the
+// patch and its neighbours for readiness (Eq. (1) with g = 0), pushing each
+// that became ready.
+//
+// Exactly-once push: a patch is pushed only by the thread that owns it, and
+// ownership moves from idle to queued with a compare-and-swap.  The owner
+// re-tests readiness after taking ownership (its first test may have read a
+// patch that was being published) and gives ownership back when the patch
+// is not ready.  With g = 0 readiness is monotone while a patch is idle (its
+// time is fixed and its neighbours' times only grow), so a patch that
+// passes both tests stays ready.  No wake-up is lost: every publish is
+// followed by a sequentially consistent fence before the publisher tests its
+// neighbours, so of two concurrent publishers at least one sees the other's
+// time.  With g = 0 the result does not depend on the order of the updates
+// (the rounds give the same bits).
+//
+// Visibility across XCDs (each has its own L2): a worker's new slice and
+// metadata are released at agent scope before its patch becomes idle, and a
+// worker acquires at agent scope before it reads guard data; the queue words
+// are agent-scope atomics.  Every wait is bounded by Q.timeout and also ends
+// when the queue is finished or an error is flagged, so the grid always
+// drains.
+
+__device__ __forceinline__ int q_load(const int* a) {
+  return __hip_atomic_load(a, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void q_store(int* a, int v) {
+  __hip_atomic_store(a, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int64_t q_load64(const int64_t* a) {
+  return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Eq. (1) with g = 0 and the free-slot rule (as the readiness scan)
+__device__ inline bool queue_ready(const DevSet& S, int q, int64_t Tend) {
+  if (S.frozen[q]) return false;
+  const int64_t t = q_load64(S.ticks + q);
+  if (t >= Tend) return false;
+  const int ns = S.nslots;
+  const int64_t ob = (int64_t)q * ns;
+  const int cur = S.cur[q];
+  const int oldest = (cur + 1) % ns, after = (cur + 1 + (S.torder > 1 ? 2 : 1)) % ns;
+  const int64_t t_after = S.svalid[ob + oldest] ? S.sticks[ob + after] : INT64_MIN;
+  for (int m = S.nb_off[q]; m < S.nb_off[q + 1]; ++m) {
+    const int r = S.nb_idx[m];
+    if (S.frozen[r]) continue;
+    const int64_t tr = q_load64(S.ticks + r);
+    if (t > tr || t_after > tr) return false;
+  }
+  return true;
+}
+
+__device__ inline bool q_expired(const QueueState& Q, uint64_t t0) {
+  return __builtin_amdgcn_s_memrealtime() - t0 > Q.timeout;
+}
+
+__device__ inline void q_push(const DevSet& S, const QueueState& Q, int q, uint64_t t0) {
+  const unsigned t = __hip_atomic_fetch_add(Q.tail, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+  int* slot = Q.buf + (t % (unsigned)Q.cap);
+  // the ring holds four times as many entries as patches (each queued at
+  // most once), so the slot is free but for a worker that has not yet
+  // cleared it
+  while (q_load(slot) != 0) {
+    if (q_expired(Q, t0)) {
+      atomicOr(S.err, ERR_TIMEOUT);
+      return;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  q_store(slot, q + 1);
+}
+
+// push q if it is ready and idle (see the protocol above)
+__device__ inline void q_try_push(const DevSet& S, const QueueState& Q, int q, int64_t Tend, uint64_t t0) {
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    if (!queue_ready(S, q, Tend)) return;
+    int idle = 0;
+    if (!__hip_atomic_compare_exchange_strong(Q.state + q, &idle, 1, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
+                                              __HIP_MEMORY_SCOPE_AGENT))
+      return;  // queued or being updated: its owner tests it again
+    if (queue_ready(S, q, Tend)) {
+      q_push(S, Q, q, t0);
+      return;
+    }
+    q_store(Q.state + q, 0);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+  }
+}
+
+__global__ void k_queue_reset(DevSet S, QueueState Q) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < Q.cap) Q.buf[i] = 0;
+  if (i < S.npatch) Q.state[i] = 0;
+  if (i == 0) {
+    *Q.head = 0u;
+    *Q.tail = 0u;
+    *Q.done = 0;
+    *Q.remaining = 0;
+    *Q.finished = 0;
+  }
+}
+
+// the patches to advance, and the queue seeded with those ready now
+__global__ void k_queue_seed(DevSet S, QueueState Q) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= S.npatch) return;
+  const int64_t Tend = *Q.tend;
+  if (S.frozen[p] || S.ticks[p] >= Tend) return;
+  atomicAdd(Q.remaining, 1);
+  if (!queue_ready(S, p, Tend)) return;
+  Q.state[p] = 1;
+  q_push(S, Q, p, __builtin_amdgcn_s_memrealtime());
+}
+
+// S.brk_ready = 1 (each worker computes its patch's brackets first) and
+// S.live = nullptr, as set by launch_persist.
+template <int FN>
+__global__ __launch_bounds__(NTHR2) void k_persist(DevSet S, QueueState Q, float* __restrict__ slots,
+                                                   float* __restrict__ pad, int64_t pad_stride, StepPtr st,
+                                                   int gfill) {
+  union PersistSmem {
+    Step2Smem<float> step;
+    GfillSmem<float> gf;
+  };
+  __shared__ PersistSmem sm;
+  __shared__ int s_p;
+  const int w = blockIdx.x, tid = threadIdx.x;
+  const int64_t Tend = *Q.tend;
+  const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+  while (true) {
+    // ---- take the next ticket and wait for its patch
+    if (tid == 0) {
+      int p = -1;
+      if (q_load(Q.remaining) > 0) {
+        const unsigned t = __hip_atomic_fetch_add(Q.head, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        int* slot = Q.buf + (t % (unsigned)Q.cap);
+        while (true) {
+          const int v = q_load(slot);
+          if (v != 0) {
+            q_store(slot, 0);
+            p = v - 1;
+            break;
+          }
+          if (q_load(Q.finished) || q_load(S.err)) break;
+          if (q_expired(Q, t0)) {
+            atomicOr(S.err, ERR_TIMEOUT);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+      }
+      s_p = p;
+    }
+    __syncthreads();
+    const int p = s_p;
+    if (p < 0) break;
+    // guard data and metadata published by other workers (other XCDs)
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    // ---- brackets of the patch's guard boxes at its time
+    const int box0 = S.rbox_off[p * 108], nbox = S.rbox_off[p * 108 + 108] - box0;
+    for (int m = tid; m < nbox; m += NTHR2) S.brk[box0 + m] = bracket(S, S.boxes[box0 + m].q, S.ticks[p], S.tcur[p]);
+    __syncthreads();
+    // ---- guard regions resampled across resolutions, into this worker's padded buffer
+    if constexpr (FN == 0) {  // a fixed size (FN > 0) means no resampled region
+      if (gfill) {
+        for (int key = 0; key < 108; ++key)
+          if (key % 27 != 13 && !region_direct(S, p, key))
+            gfill_region<float>(S, sm.gf, slots, pad + (int64_t)w * pad_stride, p, key);
+        __syncthreads();
+      }
+    }
+    // ---- Courant level and the fused step (record entry w)
+    step2_tile<float, FN>(S, sm.step, slots, pad, pad_stride, st, w, p, 0, 1, 1);
+    __syncthreads();
+    // ---- publish, give the patch back, count it when it has arrived
+    if (tid == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // the new slice and the step record
+      publish_patch(S, p, st, w);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      q_store(Q.state + p, 0);
+      if (S.ticks[p] >= Tend) {
+        const int d = __hip_atomic_fetch_add(Q.done, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1;
+        if (d == q_load(Q.remaining)) q_store(Q.finished, 1);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+    }
+    __syncthreads();
+    // ---- readiness of the patch and of its neighbours
+    const int nb0 = S.nb_off[p], nnb = S.nb_off[p + 1] - nb0;
+    if (tid <= nnb) {
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+      q_try_push(S, Q, tid == 0 ? p : S.nb_idx[nb0 + tid - 1], Tend, t0);
+    }
+    __syncthreads();
+  }
+}
+
+void launch_queue_seed(const DevSet& S, const QueueState& Q, hipStream_t s) {
+  const int n = std::max(Q.cap, S.npatch);
+  hipLaunchKernelGGL(k_queue_reset, dim3((n + 255) / 256), dim3(256), 0, s, S, Q);
+  hipLaunchKernelGGL(k_queue_seed, dim3((S.npatch + 255) / 256), dim3(256), 0, s, S, Q);
+}
+
+void launch_persist(const DevSet& S0, const QueueState& Q, float* slots, float* pad, int64_t pad_stride,
+                    const StepPtr& st, int workers, int fn, bool gfill, hipStream_t s) {
+  DevSet S = S0;
+  S.brk_ready = 1;
+  S.live = nullptr;
+  if (fn == 16)
+    hipLaunchKernelGGL((k_persist<16>), dim3(workers), dim3(NTHR2), 0, s, S, Q, slots, pad, pad_stride, st,
+                       gfill ? 1 : 0);
+  else
+    hipLaunchKernelGGL((k_persist<0>), dim3(workers), dim3(NTHR2), 0, s, S, Q, slots, pad, pad_stride, st,
+                       gfill ? 1 : 0);
+}
+
+#endif  // DSP_TU_F32
 
 // ---------------------------------------------------------------------------
 

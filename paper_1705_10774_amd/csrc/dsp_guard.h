@@ -133,6 +133,35 @@ __device__ inline Bracket bracket(const DevSet& S, int q, int64_t tk, double tt)
   return br;
 }
 
+// Publish the update of patch p whose step record is entry b of st (Sec. 3A):
+// the new slot becomes current, the time advances, the step count, level log
+// and level hash record the level.
+__device__ inline void publish_patch(const DevSet& S, int p, const StepPtr& st, int b) {
+  const int ns = S.nslots;
+  const int nxt = (S.cur[p] + 1) % ns;
+  const int64_t e = (int64_t)p * ns + nxt;
+  if (S.exact_time) {
+    S.tcur[p] = S.tcur[p] + st.dt[b];
+    S.stime[e] = S.tcur[p];
+  } else {
+    S.ticks[p] += st.dtk[b];
+    S.sticks[e] = S.ticks[p];
+    S.tcur[p] = ldexp((double)S.ticks[p], -S.kmax) * S.dt_base;
+  }
+  S.svalid[e] = 1;
+  S.cur[p] = nxt;
+  const int k = st.k[b];
+  const int64_t m = S.steps[p];
+  if (m < S.klog_cap) S.klog[(int64_t)p * S.klog_cap + m] = (int8_t)k;
+  S.steps[p] = m + 1;
+  uint64_t h = S.khash[p];
+  h ^= (uint64_t)(uint8_t)(k & 0xff);
+  h *= 1099511628211ULL;
+  S.khash[p] = h;
+  const int n = S.n[p];
+  atomicAdd(S.updates, (unsigned long long)n * n * n);
+}
+
 template <class T>
 __device__ __forceinline__ T tlerp(const T* slots, const Bracket& br, int64_t e) {
   const T a = slots[br.oa + e];

@@ -651,30 +651,7 @@ __global__ void k_publish(DevSet S, const int* __restrict__ list, int count, Ste
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= live_count(S, count)) return;
   if (b == 0 && S.rounds) atomicAdd(S.rounds, 1);
-  const int p = list[b];
-  const int ns = S.nslots;
-  const int nxt = (S.cur[p] + 1) % ns;
-  const int64_t e = (int64_t)p * ns + nxt;
-  if (S.exact_time) {
-    S.tcur[p] = S.tcur[p] + st.dt[b];
-    S.stime[e] = S.tcur[p];
-  } else {
-    S.ticks[p] += st.dtk[b];
-    S.sticks[e] = S.ticks[p];
-    S.tcur[p] = ldexp((double)S.ticks[p], -S.kmax) * S.dt_base;
-  }
-  S.svalid[e] = 1;
-  S.cur[p] = nxt;
-  const int k = st.k[b];
-  const int64_t m = S.steps[p];
-  if (m < S.klog_cap) S.klog[(int64_t)p * S.klog_cap + m] = (int8_t)k;
-  S.steps[p] = m + 1;
-  uint64_t h = S.khash[p];
-  h ^= (uint64_t)(uint8_t)(k & 0xff);
-  h *= 1099511628211ULL;
-  S.khash[p] = h;
-  const int n = S.n[p];
-  atomicAdd(S.updates, (unsigned long long)n * n * n);
+  publish_patch(S, list[b], st, b);
 }
 
 // ---------------------------------------------------------------------------

@@ -133,6 +133,19 @@ struct dsp_set {
     return p;
   }
   void release() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+    if (gstream) (void)hipStreamDestroy(gstream);
+    gstream = nullptr;
+    if (tend_host) (void)hipHostFree(tend_host);
+    tend_host = nullptr;
+    for (hipEvent_t& e : qev)
+      if (e) {
+        (void)hipEventDestroy(e);
+        e = nullptr;
+      }
     for (void* p : allocs) {
       if (use_alloc)
         alloc.free(alloc.ctx, p);
@@ -410,6 +423,18 @@ struct dsp_set {
     return W;
   }
   int dt_fused = 0;          // the last step launch also computed the Courant rate and level
+  // persistent dispatcher (work queue): eligible sets, its queue, workers,
+  // and the captured graph of its launches (seed + persistent kernel)
+  bool queue_ok = false;
+  int dispatch = DSP_DISPATCH_ROUNDS;  // how dsp_advance_to runs LOCAL steps
+  int workers = 0;
+  int queue_fn = 0;
+  QueueState Q{};
+  int64_t* tend_host = nullptr;  // pinned: the end time copied into Q.tend before a launch
+  hipStream_t gstream = nullptr;  // stream of the graph launches
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipEvent_t qev[2] = {nullptr, nullptr};
   void update_batch(int off, int count, int dt_kind, double t_end, int clip, const int* list) {
     hipEvent_t e0 = next_event(true), e1 = next_event(false);
     ev_used++;
@@ -436,6 +461,7 @@ struct dsp_set {
     if (bits & ERR_NEGATIVE) return fail(DSP_ENEGATIVE, "non-positive density or pressure");
     if (bits & ERR_KMAX) return fail(DSP_EKMAX, "time-step level exceeds kmax");
     if (bits & ERR_STATE) return fail(DSP_ESTATE, "guard data not available (internal)");
+    if (bits & ERR_TIMEOUT) return fail(DSP_ESTATE, "the persistent dispatcher timed out waiting for work");
     return 0;
   }
 
@@ -791,6 +817,40 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
   D.updates = s->d_cnt + 2;
   D.algo_bytes = s->d_cnt + 3;
   if (s->alloc_failed) return fail(DSP_ENOMEM, "device allocation failed: " + s->alloc_msg);
+  {
+    // persistent dispatcher: single-precision sets of one-tile patches in
+    // LOCAL mode without a grace, whose resampled boxes all stage (the worker
+    // has no separate direct pass), on the fused path
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    s->queue_ok = s->fused && s->f32 && c.dt_mode == DSP_DT_LOCAL && c.grace == 0.0 && s->nmax <= 16 &&
+                  !D.any_direct && cus > 0;
+    if (s->queue_ok) {
+      s->workers = std::min(cus, std::min(npatch, s->B));  // one workgroup per CU: the step takes the LDS
+      s->queue_fn = (s->nmin == 16 && s->nmax == 16 && !s->any_generic) ? 16 : 0;
+      QueueState& Q = s->Q;
+      Q.cap = 4 * npatch;
+      Q.buf = (int*)A(sizeof(int) * Q.cap);
+      Q.state = (int*)A(sizeof(int) * npatch);
+      int* ctr = (int*)A(sizeof(int) * 8);
+      Q.head = (unsigned*)ctr;
+      Q.tail = (unsigned*)(ctr + 1);
+      Q.done = ctr + 2;
+      Q.remaining = ctr + 3;
+      Q.finished = ctr + 4;
+      int64_t* tend = (int64_t*)A(sizeof(int64_t));
+      Q.tend = tend;
+      double tmo = 30.0;
+      if (const char* e = getenv("DSP_QUEUE_TIMEOUT_S")) tmo = std::max(0.1, atof(e));
+      Q.timeout = (uint64_t)(tmo * 1e8);  // s_memrealtime runs at 100 MHz
+      if (s->alloc_failed) return fail(DSP_ENOMEM, "device allocation failed: " + s->alloc_msg);
+      if (hipHostMalloc((void**)&s->tend_host, sizeof(int64_t), hipHostMallocDefault) != hipSuccess)
+        return fail(DSP_ENOMEM, "pinned host allocation failed");
+      const char* dm = getenv("DSP_DISPATCH");
+      s->dispatch = (dm && std::string(dm) == "rounds") ? DSP_DISPATCH_ROUNDS : DSP_DISPATCH_QUEUE;
+    }
+  }
   int e = hipck(hipMemcpy(s->d_host_off, s->host_off.data(), sizeof(int64_t) * (npatch + 1), hipMemcpyHostToDevice),
                 "hipMemcpy");
   if (e) return e;
@@ -967,6 +1027,48 @@ static int run_local_device(dsp_set* s, double t_end, int64_t T, int64_t& rounds
   return e ? e : e2;
 }
 
+// LOCAL steps with the persistent dispatcher: one replay of the captured
+// graph (queue reset and seed, the persistent kernel) on the set's graph
+// stream, ordered after the set's stream.
+static int run_queue(dsp_set* s, int64_t T) {
+  int e = 0;
+  if (!s->gstream) {
+    // a stream of default priority of its own (capturable; ordered with the
+    // set's stream by the synchronisations around each launch)
+    e = hipck(hipStreamCreateWithFlags(&s->gstream, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+    if (!e) e = hipck(hipEventCreate(&s->qev[0]), "hipEventCreate");
+    if (!e) e = hipck(hipEventCreate(&s->qev[1]), "hipEventCreate");
+    if (e) return e;
+  }
+  if (!s->gexec) {
+    e = hipck(hipStreamBeginCapture(s->gstream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    if (e) return e;
+    launch_queue_seed(s->D, s->Q, s->gstream);
+    launch_persist(s->D, s->Q, (float*)s->slots, (float*)s->work_pad, s->pad_stride, s->st, s->workers, s->queue_fn,
+                   s->any_generic, s->gstream);
+    e = hipck(hipStreamEndCapture(s->gstream, &s->graph), "hipStreamEndCapture");
+    if (!e) e = hipck(hipGraphInstantiate(&s->gexec, s->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    if (e) return e;
+  }
+  e = hipck(hipStreamSynchronize(s->stream), "stream");  // the set's earlier work (init, counters)
+  if (e) return e;
+  *s->tend_host = T;
+  e = hipck(hipMemcpyAsync((void*)s->Q.tend, s->tend_host, sizeof(int64_t), hipMemcpyHostToDevice, s->gstream),
+            "end time");
+  if (!e) e = hipck(hipEventRecord(s->qev[0], s->gstream), "event");
+  if (!e) e = hipck(hipGraphLaunch(s->gexec, s->gstream), "hipGraphLaunch");
+  if (!e) e = hipck(hipEventRecord(s->qev[1], s->gstream), "event");
+  if (!e) e = hipck(hipStreamSynchronize(s->gstream), "persistent dispatcher");
+  if (e) return e;
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, s->qev[0], s->qev[1]);
+  s->kern_ms = ms;
+  s->kern_launches = 1;
+  s->dt_fused = 1;
+  s->rounds += 1;
+  return read_err(s, nullptr);
+}
+
 int dsp_advance_to(dsp_set* s, double t_end) {
   if (!s || !s->initialised) return fail(DSP_ESTATE, "set not initialised");
   auto w0 = std::chrono::steady_clock::now();
@@ -981,6 +1083,10 @@ int dsp_advance_to(dsp_set* s, double t_end) {
     if (e) return e;
     if (s->cfg.dt_mode == DSP_DT_GLOBAL_QUANT) {
       e = run_global(s, t_end, T, -1);
+    } else if (s->queue_ok && s->dispatch == DSP_DISPATCH_QUEUE) {
+      e = run_queue(s, T);
+      s->last_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - w0).count();
+      return e;
     } else if (s->fused && s->B >= s->np && !getenv("DSP_HOST_ROUNDS")) {
       int64_t done = 0;
       e = run_local_device(s, t_end, T, done);
@@ -1006,6 +1112,166 @@ int dsp_advance_to(dsp_set* s, double t_end) {
   s->end_timing(real_launches);
   s->last_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - w0).count();
   return e;
+}
+
+int dsp_set_dispatch(dsp_set* s, int32_t mode, int32_t workers) {
+  if (!s) return fail(DSP_EINVAL, "null handle");
+  if (mode != DSP_DISPATCH_ROUNDS && mode != DSP_DISPATCH_QUEUE) return fail(DSP_EINVAL, "unknown dispatch mode");
+  if (mode == DSP_DISPATCH_QUEUE && !s->queue_ok)
+    return fail(DSP_EINVAL, "the queue dispatch needs a single-precision LOCAL set of patches of at most 16^3 "
+                            "cells without a grace");
+  if (workers < 0) return fail(DSP_EINVAL, "negative worker count");
+  if (mode == DSP_DISPATCH_QUEUE) {
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int cap = std::min(cus, std::min(s->np, s->B));
+    const int w = workers == 0 ? cap : std::min(workers, cap);
+    if (w != s->workers) {  // the captured graph holds the launch shape
+      if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+      if (s->graph) (void)hipGraphDestroy(s->graph);
+      s->gexec = nullptr;
+      s->graph = nullptr;
+      s->workers = w;
+    }
+  }
+  s->dispatch = mode;
+  return 0;
+}
+
+int dsp_get_dispatch(const dsp_set* s, int32_t* mode, int32_t* queue_available, int32_t* workers) {
+  if (!s) return fail(DSP_EINVAL, "null handle");
+  if (mode) *mode = s->dispatch;
+  if (queue_available) *queue_available = s->queue_ok ? 1 : 0;
+  if (workers) *workers = s->workers;
+  return 0;
+}
+
+extern "C++" {
+namespace {
+// every device array that an advance changes, for the autotuner's save and restore
+std::vector<std::pair<void*, size_t>> mutable_state(dsp_set* s) {
+  const size_t np = (size_t)s->np, ns = (size_t)s->cfg.nslots, tsz = s->f32 ? 4 : 8;
+  const DevSet& D = s->D;
+  return {{s->slots, (size_t)s->total_values * ns * tsz},
+          {D.cur, sizeof(int) * np},
+          {D.ticks, sizeof(int64_t) * np},
+          {D.tcur, sizeof(double) * np},
+          {D.sticks, sizeof(int64_t) * np * ns},
+          {D.stime, sizeof(double) * np * ns},
+          {D.svalid, np * ns},
+          {D.steps, sizeof(int64_t) * np},
+          {D.khash, sizeof(uint64_t) * np},
+          {D.klog, np * (size_t)s->klog_cap},
+          {s->d_cnt, sizeof(unsigned long long) * 4},
+          {s->d_err, sizeof(int) * 2}};
+}
+
+std::string tune_key(const dsp_set* s) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  hipDeviceProp_t prop;
+  std::string name = "gpu";
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) name = prop.gcnArchName;
+  char buf[256];
+  snprintf(buf, sizeof(buf), "%s np=%d n=%d..%d prec=%d resampled=%d", name.c_str(), s->np, s->nmin, s->nmax,
+           (int)s->cfg.prec, s->any_generic ? 1 : 0);
+  return buf;
+}
+}  // namespace
+}  // extern "C++"
+
+int dsp_autotune(dsp_set* s, double t_probe, const char* cache_path, double* ms_out) {
+  if (!s || !s->initialised) return fail(DSP_ESTATE, "set not initialised");
+  if (s->cfg.dt_mode != DSP_DT_LOCAL) return fail(DSP_EINVAL, "the autotuner covers LOCAL steps");
+  if (ms_out)
+    for (int m = 0; m < 4; ++m) ms_out[m] = -1.0;
+  const std::string key = tune_key(s);
+  // candidates: rounds, then the queue with 1, 3/4 and 1/2 of its workgroups
+  int cus = 0, dev = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const int wmax = std::min(cus, std::min(s->np, s->B));
+  const int cand_mode[4] = {DSP_DISPATCH_ROUNDS, DSP_DISPATCH_QUEUE, DSP_DISPATCH_QUEUE, DSP_DISPATCH_QUEUE};
+  const int cand_w[4] = {0, wmax, std::max(1, wmax * 3 / 4), std::max(1, wmax / 2)};
+  const int ncand = s->queue_ok ? 4 : 1;
+  // a cached choice for this key
+  if (cache_path) {
+    FILE* f = fopen(cache_path, "r");
+    if (f) {
+      char line[1024];
+      int mode = -1, workers = 0;
+      while (fgets(line, sizeof(line), f)) {
+        const std::string l(line);
+        if (l.find("\"key\": \"" + key + "\"") == std::string::npos) continue;
+        const size_t a = l.find("\"dispatch\": "), b = l.find("\"workers\": ");
+        if (a != std::string::npos && b != std::string::npos) {
+          mode = atoi(line + a + 12);
+          workers = atoi(line + b + 11);
+        }
+      }
+      fclose(f);
+      if (mode == DSP_DISPATCH_ROUNDS || (mode == DSP_DISPATCH_QUEUE && s->queue_ok))
+        return dsp_set_dispatch(s, mode, workers);
+    }
+  }
+  // the probe window from the set's current time
+  std::vector<double> tc(s->np);
+  int e = hipck(hipMemcpy(tc.data(), s->D.tcur, sizeof(double) * s->np, hipMemcpyDeviceToHost), "time");
+  if (e) return e;
+  const double t0 = *std::min_element(tc.begin(), tc.end());
+  // save the state
+  std::vector<std::pair<void*, size_t>> items = mutable_state(s);
+  std::vector<void*> saved(items.size(), nullptr);
+  for (size_t m = 0; m < items.size() && !e; ++m) {
+    e = hipck(hipMalloc(&saved[m], items[m].second), "hipMalloc");
+    if (!e) e = hipck(hipMemcpy(saved[m], items[m].first, items[m].second, hipMemcpyDeviceToDevice), "save");
+  }
+  const int64_t rounds0 = s->rounds;
+  const int mode0 = s->dispatch, workers0 = s->workers;
+  double best = 1e300;
+  int bi = 0;
+  for (int c = 0; c < ncand && !e; ++c) {
+    e = dsp_set_dispatch(s, cand_mode[c], cand_w[c]);
+    if (e) break;
+    double ms = 0.0;
+    for (int rep = 0; rep < 2 && !e; ++rep) {  // the first run also captures the graph
+      for (size_t m = 0; m < items.size() && !e; ++m)
+        e = hipck(hipMemcpy(items[m].first, saved[m], items[m].second, hipMemcpyDeviceToDevice), "restore");
+      if (e) break;
+      e = hipck(hipDeviceSynchronize(), "restore");
+      const auto w0 = std::chrono::steady_clock::now();
+      if (!e) e = dsp_advance_to(s, t0 + t_probe);
+      ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - w0).count();
+    }
+    if (e) break;
+    if (ms_out) ms_out[c] = ms;
+    if (ms < best) {
+      best = ms;
+      bi = c;
+    }
+  }
+  // restore the state and choose
+  for (size_t m = 0; m < items.size(); ++m) {
+    if (saved[m] && !e) e = hipck(hipMemcpy(items[m].first, saved[m], items[m].second, hipMemcpyDeviceToDevice), "restore");
+    if (saved[m]) (void)hipFree(saved[m]);
+  }
+  s->rounds = rounds0;
+  if (e) {
+    (void)dsp_set_dispatch(s, mode0, workers0);
+    return e;
+  }
+  e = dsp_set_dispatch(s, cand_mode[bi], cand_w[bi]);
+  if (e) return e;
+  if (cache_path) {
+    FILE* f = fopen(cache_path, "a");
+    if (f) {
+      fprintf(f, "{\"key\": \"%s\", \"dispatch\": %d, \"workers\": %d, \"ms\": %.4f}\n", key.c_str(), cand_mode[bi],
+              cand_mode[bi] == DSP_DISPATCH_QUEUE ? s->workers : 0, best);
+      fclose(f);
+    }
+  }
+  return 0;
 }
 
 int dsp_advance_to_plain(dsp_set* s, double t_end) {

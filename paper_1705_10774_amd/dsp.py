@@ -26,7 +26,9 @@ DSP_DT_LOCAL, DSP_DT_GLOBAL_QUANT, DSP_DT_GLOBAL_EXACT, DSP_DT_FIXED = 0, 1, 2, 
 EXPORTS = ["dsp_create", "dsp_init", "dsp_init_device", "dsp_advance_to", "dsp_advance_to_plain", "dsp_read_state",
            "dsp_read_schedule", "dsp_stats", "dsp_kernel_time", "dsp_kernel_stats", "dsp_fixed_steps_fwd",
            "dsp_fixed_steps_adj", "dsp_save_snapshot", "dsp_load_snapshot", "dsp_hlld_faces",
-           "dsp_hlld_faces_noalloc", "dsp_destroy", "dsp_last_error"]
+           "dsp_hlld_faces_noalloc", "dsp_set_dispatch", "dsp_get_dispatch", "dsp_autotune", "dsp_destroy",
+           "dsp_last_error"]
+DSP_DISPATCH_ROUNDS, DSP_DISPATCH_QUEUE = 0, 1
 
 
 class dsp_config(C.Structure):
@@ -84,6 +86,9 @@ def load():
     L.dsp_load_snapshot.argtypes = [vp, C.c_char_p]
     L.dsp_hlld_faces.argtypes = [C.c_int32, dp, dp, dp, C.c_int64, C.c_double, dp]
     L.dsp_hlld_faces_noalloc.argtypes = [C.c_int32, dp, dp, dp, C.c_int64, C.c_double, dp]
+    L.dsp_set_dispatch.argtypes = [vp, C.c_int32, C.c_int32]
+    L.dsp_get_dispatch.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    L.dsp_autotune.argtypes = [vp, C.c_double, C.c_char_p, dp]
     L.dsp_destroy.argtypes = [vp]
     L.dsp_destroy.restype = None
     L.dsp_last_error.restype = C.c_char_p
@@ -231,6 +236,24 @@ def dsp_hlld_faces(prec, wl, wr, bn, gamma=5.0 / 3.0, noalloc=False):
     return out
 
 
+def dsp_set_dispatch(h, mode, workers=0):
+    _check(load().dsp_set_dispatch(h, int(mode), int(workers)))
+
+
+def dsp_get_dispatch(h):
+    """(mode, queue available, workers)"""
+    m, a, w = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(load().dsp_get_dispatch(h, C.byref(m), C.byref(a), C.byref(w)))
+    return m.value, bool(a.value), w.value
+
+
+def dsp_autotune(h, t_probe, cache_path=None):
+    """Times the dispatch candidates (ms per candidate, -1 where not one)."""
+    out = np.zeros(4)
+    _check(load().dsp_autotune(h, float(t_probe), str(cache_path).encode() if cache_path else None, _dp(out)))
+    return out
+
+
 def dsp_destroy(h):
     if h:
         load().dsp_destroy(h)
@@ -289,6 +312,15 @@ class PatchSet:
 
     def save(self, path):
         dsp_save_snapshot(self.h, path)
+
+    def set_dispatch(self, mode, workers=0):
+        dsp_set_dispatch(self.h, mode, workers)
+
+    def dispatch(self):
+        return dsp_get_dispatch(self.h)
+
+    def autotune(self, t_probe, cache_path=None):
+        return dsp_autotune(self.h, t_probe, cache_path)
 
     def load(self, path):
         dsp_load_snapshot(self.h, path)
