@@ -88,6 +88,9 @@ def main():
     ap.add_argument("--cpu-rounds", type=int, default=3, help="rounds of the CPU oracle sample")
     ap.add_argument("--only", choices=["cfg3", "cfg2", "cfg2-fp64", "adjoint"],
                     help="run one leg alone (for profiling)")
+    ap.add_argument("--dispatch", choices=["auto", "rounds", "queue"], default="auto",
+                    help="dispatch of the local steps: the autotuner's choice, the rounds, or the persistent queue "
+                         "(where available)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 3 plain device copies of 256 MiB (scale for the FETCH_SIZE / "
                          "WRITE_SIZE counters)")
@@ -115,11 +118,23 @@ def main():
         return
     flops = json.load(open(os.path.join(ROOT, "tests", "golden", "flops_per_update.json")))
 
-    def run_batched(pr, t_end, steps, warmup, prec):
+    def run_batched(pr, t_end, steps, warmup, prec, dispatch=None):
         """steps timed runs t 0 -> t_end from a device-resident initial state."""
         s = dsp.PatchSet(dataclasses.replace(pr.cfg, prec=prec), pr.patches)
         tdt = torch.float32 if prec == I.F32 else torch.float64
         U0 = torch.from_numpy(pr.U0).to(dev).to(tdt).contiguous()
+        dispatch = dispatch or args.dispatch
+        avail = s.dispatch()[1]
+        if dispatch == "rounds" or (dispatch == "queue" and not avail):
+            s.set_dispatch(dsp.DSP_DISPATCH_ROUNDS)
+        elif dispatch == "queue":
+            s.set_dispatch(dsp.DSP_DISPATCH_QUEUE)
+        elif avail and pr.cfg.dt_mode == I.DT_LOCAL:
+            # the autotuner picks rounds or the persistent queue on the first
+            # dt_base of this workload (timed from the initial state, which
+            # it restores)
+            s.init_device(U0.data_ptr())
+            s.autotune(pr.cfg.dt_base)
         for _ in range(warmup):
             s.init_device(U0.data_ptr())
             s.advance_to(t_end)
@@ -132,11 +147,13 @@ def main():
         t1 = time.perf_counter()
         st = s.stats()
         ks = s.kernel_stats()  # update launches of the last step: ms, launches, algorithmic bytes
+        mode = s.dispatch()[0]
         s.close()
         del U0
         return dict(sec=(t1 - t0) / max(steps, 1), updates=st[0], rounds=st[13], kern_ms=ks[0],
                     kern_launches=ks[1], algo_bytes=ks[2], fused=ks[3], floor_hits=st[10],
-                    cells=pr.cells, patches=len(pr.patches))
+                    cells=pr.cells, patches=len(pr.patches),
+                    dispatch="queue" if mode == dsp.DSP_DISPATCH_QUEUE else "rounds")
 
     def run_adjoint():
         # adjoint: 64 patches of 16^3, 32 fixed FP64 steps, checkpoints every 8
@@ -169,6 +186,7 @@ def main():
         prec = I.F32 if args.only == "cfg2" else I.F64
         r = run_batched(pr, pr.t_end, args.steps, args.warmup, prec)
         print(json.dumps({args.only: {"value": r["updates"] / r["sec"], "ms_per_step": r["sec"] * 1e3,
+                                      "dispatch": r["dispatch"],
                                       "roofline": roofline(r, "k_step2<float, 16>" if prec == I.F32 else
                                                            "k_step<double, 16>", "", flops)}}), flush=True)
         return

@@ -1670,7 +1670,9 @@ __device__ __forceinline__ int64_t q_load64(const int64_t* a) {
   return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Eq. (1) with g = 0 and the free-slot rule (as the readiness scan)
+// Eq. (1) with g = 0 and the free-slot rule (as the readiness scan).  The
+// neighbours' times are read eight at a time before any is tested, so the
+// reads overlap instead of following each other.
 __device__ inline bool queue_ready(const DevSet& S, int q, int64_t Tend) {
   if (S.frozen[q]) return false;
   const int64_t t = q_load64(S.ticks + q);
@@ -1680,11 +1682,17 @@ __device__ inline bool queue_ready(const DevSet& S, int q, int64_t Tend) {
   const int cur = S.cur[q];
   const int oldest = (cur + 1) % ns, after = (cur + 1 + (S.torder > 1 ? 2 : 1)) % ns;
   const int64_t t_after = S.svalid[ob + oldest] ? S.sticks[ob + after] : INT64_MIN;
-  for (int m = S.nb_off[q]; m < S.nb_off[q + 1]; ++m) {
-    const int r = S.nb_idx[m];
-    if (S.frozen[r]) continue;
-    const int64_t tr = q_load64(S.ticks + r);
-    if (t > tr || t_after > tr) return false;
+  const int m0 = S.nb_off[q], m1 = S.nb_off[q + 1];
+  for (int mb = m0; mb < m1; mb += 8) {
+    int rs[8];
+    int64_t tr[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) rs[u] = mb + u < m1 ? S.nb_idx[mb + u] : -1;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) tr[u] = (rs[u] >= 0 && !S.frozen[rs[u]]) ? q_load64(S.ticks + rs[u]) : INT64_MAX;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (t > tr[u] || t_after > tr[u]) return false;
   }
   return true;
 }
@@ -1785,16 +1793,18 @@ __global__ __launch_bounds__(NTHR2) void k_persist(DevSet S, QueueState Q, float
             atomicOr(S.err, ERR_TIMEOUT);
             break;
           }
-          __builtin_amdgcn_s_sleep(2);
+          __builtin_amdgcn_s_sleep(20);
         }
       }
+      // guard data and metadata published by other workers (other XCDs):
+      // one acquire invalidates the CU's and the XCD's caches for every
+      // wavefront of the workgroup, which reads only after the barrier
+      if (p >= 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       s_p = p;
     }
     __syncthreads();
     const int p = s_p;
     if (p < 0) break;
-    // guard data and metadata published by other workers (other XCDs)
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     // ---- brackets of the patch's guard boxes at its time
     const int box0 = S.rbox_off[p * 108], nbox = S.rbox_off[p * 108 + 108] - box0;
     for (int m = tid; m < nbox; m += NTHR2) S.brk[box0 + m] = bracket(S, S.boxes[box0 + m].q, S.ticks[p], S.tcur[p]);
@@ -1815,8 +1825,7 @@ __global__ __launch_bounds__(NTHR2) void k_persist(DevSet S, QueueState Q, float
     if (tid == 0) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // the new slice and the step record
       publish_patch(S, p, st, w);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      q_store(Q.state + p, 0);
+      q_store(Q.state + p, 0);  // a release store: after the metadata
       if (S.ticks[p] >= Tend) {
         const int d = __hip_atomic_fetch_add(Q.done, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1;
         if (d == q_load(Q.remaining)) q_store(Q.finished, 1);
@@ -1824,12 +1833,10 @@ __global__ __launch_bounds__(NTHR2) void k_persist(DevSet S, QueueState Q, float
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
     }
     __syncthreads();
-    // ---- readiness of the patch and of its neighbours
+    // ---- readiness of the patch and of its neighbours, one thread each
+    // (after thread 0's sequentially consistent fence and the barrier)
     const int nb0 = S.nb_off[p], nnb = S.nb_off[p + 1] - nb0;
-    if (tid <= nnb) {
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
-      q_try_push(S, Q, tid == 0 ? p : S.nb_idx[nb0 + tid - 1], Tend, t0);
-    }
+    for (int c = tid; c <= nnb; c += NTHR2) q_try_push(S, Q, c == 0 ? p : S.nb_idx[nb0 + c - 1], Tend, t0);
     __syncthreads();
   }
 }
