@@ -18,8 +18,8 @@
 // solver's wave pattern are those of the forward state: the result is the
 // derivative along the branches the forward step takes.  The Riemann solver
 // and the predictor have hand-written reverse passes (hlld_vjp.h, k_adj_pred).
-// The update, EMF, face and slope terms are gathered (one writer per entry);
-// the primitive and fill kernels scatter with atomic additions.
+// Every kernel gathers (one writer per entry, a fixed order of every sum), so
+// the reverse run is deterministic: two runs give the same bits.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -552,7 +552,7 @@ __global__ __launch_bounds__(256) void k_adj_prim(DevSet S, const int* __restric
   if (c >= NC) return;
   const int i = (int)(c % N) - 2, j = (int)((c / N) % N) - 2, k = (int)(c / ((int64_t)N * N)) - 2;
   const int64_t o = wcell(N, 0, i, j, k);
-  const T* LW = L.w + (int64_t)b * L.w_stride;
+  T* LW = L.w + (int64_t)b * L.w_stride;
   T lw[8];
   bool any = false;
   for (int v = 0; v < 8; ++v) {
@@ -586,76 +586,87 @@ __global__ __launch_bounds__(256) void k_adj_prim(DevSet S, const int* __restric
   LP[pcell(N, 0, i, j, k)] += lrho;
   for (int d = 0; d < 3; ++d) LP[pcell(N, 1 + d, i, j, k)] += lm[d];
   LP[pcell(N, 4, i, j, k)] += lp * gm1;
-  for (int d = 0; d < 3; ++d) {
-    atomicAdd(&LP[fl[d]], T(0.5) * lb[d]);
-    atomicAdd(&LP[fr[d]], T(0.5) * lb[d]);
-  }
+  // the cell-centred field's cotangent goes to the two faces it averages
+  // (k_adj_prim_faces): kept in place of the cell's own B cotangent, which
+  // nothing reads after this kernel (a cell with no cotangent keeps its
+  // zeros, which equal its lb)
+  for (int d = 0; d < 3; ++d) LW[(5 + d) * NC + o] = lb[d];
+}
+
+// faces of the padded patch: half the B cotangent of each of the (at most
+// two) padded cells a face bounds
+template <class T>
+__global__ __launch_bounds__(256) void k_adj_prim_faces(DevSet S, const int* __restrict__ list, int count, WorkPtr<T> L) {
+  const int b = blockIdx.y;
+  if (b >= count) return;
+  const int p = list[b];
+  const int n = S.n[p], N = n + 4;
+  const int64_t NC = (int64_t)N * N * N, NF = (int64_t)N * N * (N + 1);
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= 3 * NF) return;
+  const int d = (int)(c / NF);
+  c -= d * NF;
+  const int sx = N + (d == 0), sy = N + (d == 1);
+  int f[3] = {(int)(c % sx) - 2, (int)((c / sx) % sy) - 2, (int)(c / ((int64_t)sx * sy)) - 2};
+  const T* LB = L.w + (int64_t)b * L.w_stride + (5 + d) * NC;
+  const T right = (f[d] <= n + 1) ? LB[wcell(N, 0, f[0], f[1], f[2])] : T(0);
+  f[d] -= 1;
+  const T left = (f[d] >= -2) ? LB[wcell(N, 0, f[0], f[1], f[2])] : T(0);
+  f[d] += 1;
+  L.pad[(int64_t)b * L.pad_stride + pface(N, d, f[0], f[1], f[2])] += T(0.5) * left + T(0.5) * right;
 }
 
 // ---------------------------------------------------------------------------
 // guard fill: every padded element is the patch's own value (interior) or a
-// copy of one source element (same resolution, same time in a fixed step)
+// copy of one source element (same resolution, same time in a fixed step).
+// Gathered: each state element of patch q takes the cotangent of its own
+// padded element plus those of the guard elements that copy it, found
+// through the boxes that read from q (rev).  The list holds every patch in
+// id order, so the padded buffers of patch p sit in block p.
 
 template <class T>
 __global__ __launch_bounds__(256) void k_adj_fill(DevSet S, const int* __restrict__ list, int count, WorkPtr<T> L,
                            T* __restrict__ lam, const int64_t* __restrict__ host_off) {
   const int b = blockIdx.y;
   if (b >= count) return;
-  const int p = list[b];
-  const int n = S.n[p], N = n + 4;
-  const int64_t ncell = (int64_t)N * N * N, nface = (int64_t)N * N * (N + 1);
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= 5 * ncell + 3 * nface) return;
-  const T lv = L.pad[(int64_t)b * L.pad_stride + e];
-  if (lv == T(0)) return;
+  const int q = list[b];
+  const int n = S.n[q], N = n + 4;
+  const int64_t n3 = (int64_t)n * n * n, nf = (int64_t)n * n * (n + 1);
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 5 * n3 + 3 * nf) return;
   int comp, var, i, j, k;
-  if (e < 5 * ncell) {
+  if (e < 5 * n3) {
     comp = -1;
-    var = (int)(e / ncell);
-    int64_t r = e - var * ncell;
-    i = (int)(r % N) - 2;
-    r /= N;
-    j = (int)(r % N) - 2;
-    k = (int)(r / N) - 2;
+    var = (int)(e / n3);
+    const int64_t r = e - var * n3;
+    i = (int)(r % n);
+    j = (int)((r / n) % n);
+    k = (int)(r / ((int64_t)n * n));
   } else {
-    int64_t r = e - 5 * ncell;
-    comp = (int)(r / nface);
+    int64_t r = e - 5 * n3;
+    comp = (int)(r / nf);
     var = 0;
-    r -= comp * nface;
-    const int sx = N + (comp == 0), sy = N + (comp == 1);
-    i = (int)(r % sx) - 2;
-    r /= sx;
-    j = (int)(r % sy) - 2;
-    k = (int)(r / sy) - 2;
+    r -= comp * nf;
+    const int sx = n + (comp == 0), sy = n + (comp == 1);
+    i = (int)(r % sx);
+    j = (int)((r / sx) % sy);
+    k = (int)(r / ((int64_t)sx * sy));
   }
-  const int idx[3] = {i, j, k};
-  int rg[3];
-  bool interior = true;
-  for (int d = 0; d < 3; ++d) {
-    const int hi = n + (d == comp ? 1 : 0);
-    rg[d] = idx[d] < 0 ? 0 : (idx[d] < hi ? 1 : 2);
-    interior = interior && rg[d] == 1;
+  auto padded = [&](int pp, int a, int bb, int c) -> T {
+    const int NP = S.n[pp] + 4;
+    const int64_t pe = (comp < 0) ? pcell(NP, var, a, bb, c) : pface(NP, comp, a, bb, c);
+    return L.pad[(int64_t)pp * L.pad_stride + pe];
+  };
+  T acc = L.pad[(int64_t)q * L.pad_stride + ((comp < 0) ? pcell(N, var, i, j, k) : pface(N, comp, i, j, k))];
+  const int g = q * 4 + comp + 1;
+  for (int r = S.rev_off[g]; r < S.rev_off[g + 1]; ++r) {
+    const int2 mp = S.rev[r];
+    const GBox& G = S.boxes[mp.x];
+    const int a = i - G.shift[0], bb = j - G.shift[1], c = k - G.shift[2];
+    if (a < G.lo[0] || a > G.hi[0] || bb < G.lo[1] || bb > G.hi[1] || c < G.lo[2] || c > G.hi[2]) continue;
+    acc += padded(mp.y, a, bb, c);
   }
-  if (interior) {
-    const int64_t se = (comp < 0) ? scell(n, var, i, j, k) : sface(n, comp, i, j, k);
-    atomicAdd(&lam[host_off[p] + se], lv);
-    return;
-  }
-  const int key = p * 108 + (comp + 1) * 27 + (rg[2] * 3 + rg[1]) * 3 + rg[0];
-  for (int m = S.rbox_off[key]; m < S.rbox_off[key + 1]; ++m) {
-    const GBox& G = S.boxes[m];
-    if (i < G.lo[0] || i > G.hi[0] || j < G.lo[1] || j > G.hi[1] || k < G.lo[2] || k > G.hi[2]) continue;
-    if (!G.same) {
-      atomicOr(S.err, ERR_STATE);  // resampled guards are not differentiated here
-      return;
-    }
-    const int nq = S.n[G.q];
-    const int qi = i + G.shift[0], qj = j + G.shift[1], qk = k + G.shift[2];
-    const int64_t se = (comp < 0) ? scell(nq, var, qi, qj, qk) : sface(nq, comp, qi, qj, qk);
-    atomicAdd(&lam[host_off[G.q] + se], lv);
-    return;
-  }
-  atomicOr(S.err, ERR_STATE);
+  lam[host_off[q] + e] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -682,8 +693,10 @@ void launch_adjoint_step(const DevSet& S, const int* list, int count, int nmax, 
                      st);
   hipLaunchKernelGGL(k_adj_slope<T>, dim3(blocks((int64_t)N * N * N), count), dim3(256), 0, s, S, list, count, W, L);
   hipLaunchKernelGGL(k_adj_prim<T>, dim3(blocks((int64_t)N * N * N), count), dim3(256), 0, s, S, list, count, W, L);
-  hipLaunchKernelGGL(k_adj_fill<T>, dim3(blocks(5LL * N * N * N + 3LL * N * N * (N + 1)), count), dim3(256), 0, s,
-                     S, list, count, L, lam_prev, host_off);
+  hipLaunchKernelGGL(k_adj_prim_faces<T>, dim3(blocks(3LL * N * N * (N + 1)), count), dim3(256), 0, s, S, list, count,
+                     L);
+  hipLaunchKernelGGL(k_adj_fill<T>, dim3(blocks(5 * n3 + 3LL * n * n * (n + 1)), count), dim3(256), 0, s, S, list,
+                     count, L, lam_prev, host_off);
 }
 
 #ifdef DSP_TU_F32

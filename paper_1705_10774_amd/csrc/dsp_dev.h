@@ -75,6 +75,10 @@ struct DevSet {
   const int* nb_idx;
   const int* rbox_off;  // [npatch * 108 + 1]: boxes of (patch, component + 1, region)
   const GBox* boxes;
+  // reverse of the same-resolution boxes: per (source patch, component + 1)
+  // the boxes that copy from it, as (box index, owning patch)
+  const int* rev_off;  // [npatch * 4 + 1]
+  const int2* rev;
   Bracket* brk;  // per box: its time bracket for the staged guard fill (k_brackets)
   int brk_ready;  // brk holds this round's brackets of the listed patches' boxes
   int maxbox;    // most boxes of one patch
@@ -200,6 +204,7 @@ template <class T>
 void launch_scatter(const DevSet& S, T* slots, const double* src, const int64_t* host_off, hipStream_t s);
 template <class T>
 void launch_pack(const DevSet& S, const T* slots, T* dst, const int64_t* host_off, hipStream_t s);
+template <class T> void launch_poison(const DevSet& S, T* slots, hipStream_t s);
 template <class T>
 void launch_hlld_faces(const double* wl, const double* wr, const double* bn, int64_t nface, double gamma, double* out,
                        hipStream_t s);

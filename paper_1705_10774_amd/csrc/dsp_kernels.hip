@@ -921,6 +921,25 @@ void launch_unpack(const DevSet& S, T* slots, const T* src, const int64_t* host_
   hipLaunchKernelGGL(k_unpack<T>, dim3(64, S.npatch), dim3(256), 0, s, S, slots, src, host_off);
 }
 
+// Every ring slot but slot 0 of every patch set to NaN (a checking switch:
+// a guard value read from a slot that was never written then shows up as a
+// non-finite state at once).
+template <class T>
+__global__ void k_poison(DevSet S, T* __restrict__ slots) {
+  const int p = blockIdx.y;
+  const int64_t V = S.slice_len[p];
+  T* base = slots + S.slot_off[p] + V;
+  const int64_t n = V * (S.nslots - 1);
+  const T nan = __builtin_nan("");
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    base[e] = nan;
+}
+
+template <class T>
+void launch_poison(const DevSet& S, T* slots, hipStream_t s) {
+  if (S.nslots > 1) hipLaunchKernelGGL(k_poison<T>, dim3(64, S.npatch), dim3(256), 0, s, S, slots);
+}
+
 template <class T>
 void launch_hlld_faces(const double* wl, const double* wr, const double* bn, int64_t nface, double gamma, double* out,
                        hipStream_t s) {
@@ -934,6 +953,7 @@ void launch_hlld_faces(const double* wl, const double* wr, const double* bn, int
 }
 
 #define DSP_INST(T)                                                                                    \
+  template void launch_poison<T>(const DevSet&, T*, hipStream_t);                                      \
   template void launch_hlld_faces<T>(const double*, const double*, const double*, int64_t, double, double*, \
                                      hipStream_t);                                                     \
   template void launch_update<T>(const DevSet&, const int*, int, int, T*, const WorkPtr<T>&,          \

@@ -425,6 +425,7 @@ struct dsp_set {
   int dt_fused = 0;          // the last step launch also computed the Courant rate and level
   // persistent dispatcher (work queue): eligible sets, its queue, workers,
   // and the captured graph of its launches (seed + persistent kernel)
+  bool poison = false;  // DSP_POISON=1: unwritten ring slots hold NaN (a check for wrong-slot guard reads)
   bool queue_ok = false;
   int dispatch = DSP_DISPATCH_ROUNDS;  // how dsp_advance_to runs LOCAL steps
   int workers = 0;
@@ -567,6 +568,10 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
   S->np = npatch;
   S->stream = (hipStream_t)hip_stream;
   S->f32 = (c.prec == DSP_F32);
+  {
+    const char* pz = getenv("DSP_POISON");
+    S->poison = pz && std::string(pz) == "1";
+  }
   if (alloc) {
     if (!alloc->alloc || !alloc->free) return fail(DSP_EINVAL, "allocator without alloc/free");
     S->use_alloc = true;
@@ -798,6 +803,24 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
   D.rbox_off = (const int*)up(rbox_off.data(), sizeof(int) * rbox_off.size());
   D.boxes = (const GBox*)up(boxes.data(), sizeof(GBox) * std::max<size_t>(1, boxes.size()));
   D.brk = (Bracket*)A(sizeof(Bracket) * std::max<size_t>(1, boxes.size()));
+  {
+    // boxes grouped by (source patch, component) for the adjoint's gathered
+    // guard fill; within a group in box order, which fixes the order of its sums
+    std::vector<int> roff((size_t)npatch * 4 + 1, 0);
+    for (int p = 0; p < npatch; ++p)
+      for (int k = 0; k < 108; ++k)
+        for (int m = rbox_off[p * 108 + k]; m < rbox_off[p * 108 + k + 1]; ++m)
+          if (boxes[m].same) ++roff[(size_t)boxes[m].q * 4 + k / 27 + 1];
+    for (size_t g = 0; g + 1 < roff.size(); ++g) roff[g + 1] += roff[g];
+    std::vector<int2> rev(std::max(1, roff.back()));
+    std::vector<int> fillp(roff.begin(), roff.end() - 1);
+    for (int p = 0; p < npatch; ++p)
+      for (int k = 0; k < 108; ++k)
+        for (int m = rbox_off[p * 108 + k]; m < rbox_off[p * 108 + k + 1]; ++m)
+          if (boxes[m].same) rev[fillp[(size_t)boxes[m].q * 4 + k / 27]++] = make_int2(m, p);
+    D.rev_off = (const int*)up(roff.data(), sizeof(int) * roff.size());
+    D.rev = (const int2*)up(rev.data(), sizeof(int2) * rev.size());
+  }
   for (int p = 0; p < npatch; ++p) D.maxbox = std::max(D.maxbox, rbox_off[(p + 1) * 108] - rbox_off[p * 108]);
   D.any_direct = 0;
   for (const GBox& g : boxes) D.any_direct |= g.direct;
@@ -914,6 +937,12 @@ static int init_common(dsp_set* s, const double* U, const void* U_dev, double t0
   if (e) return e;
   (void)hipMemsetAsync(s->d_err, 0, sizeof(int) * 2, s->stream);
   (void)hipMemsetAsync(s->d_cnt, 0, sizeof(unsigned long long) * 4, s->stream);
+  if (s->poison) {  // checking switch: slots not yet written hold NaN
+    if (s->f32)
+      launch_poison<float>(D, (float*)s->slots, s->stream);
+    else
+      launch_poison<double>(D, (double*)s->slots, s->stream);
+  }
   if (U) {
     if (s->f32)
       launch_scatter<float>(D, (float*)s->slots, s->d_hostbuf, s->d_host_off, s->stream);
@@ -1493,14 +1522,14 @@ static int adjoint_run(dsp_set* s, const T* ckpt, const T* lamT, T* lam0, int ns
       if (!keep) e = staged_fixed_step<T>(s, states + (size_t)j * V, (T*)nullptr, 0);
       if (e) break;
       const WorkPtr<T> W = s->adj_work<T>(false, keep ? j : 0);
-      // padded state, primitives and half-step state take atomic or
-      // accumulated cotangents; the slope, flux and edge buffers are written
-      // whole by their first writer in the step (k_adj_flux_sum, k_adj_update)
+      // padded state, primitives and half-step state take accumulated
+      // cotangents; the slope, flux and edge buffers are written whole by
+      // their first writer in the step (k_adj_flux_sum, k_adj_update), and
+      // lam^k whole by the gathered guard fill
       for (int q = 0; q < 3; ++q) {
         const int64_t sizes[3] = {s->pad_stride, s->w_stride, s->w_stride};
         (void)hipMemsetAsync(s->adj_l[q], 0, sizeof(T) * (size_t)sizes[q] * s->np, s->stream);
       }
-      (void)hipMemsetAsync(lb, 0, sizeof(T) * V, s->stream);
       launch_adjoint_step<T>(s->D, s->d_list, s->np, s->nmax, W, L, s->st, la, lb, s->d_host_off, s->stream);
       std::swap(la, lb);
     }
