@@ -37,7 +37,31 @@ struct GBox {
 // of staged source values
 constexpr int GMAXT = 72;
 constexpr int GMAXC = 4;
-constexpr int GSTAGE_BYTES = 40960;
+constexpr int GSTAGE_BYTES = 24576;
+
+// Per-axis overlap table entry of one target index of a resampled box: the
+// first overlapped source index, the number of overlapped indices, their
+// normalised weights and the offsets of the overlap centres from the source
+// cell centres in source cells (along a face field's own axis: the two
+// bracketing source faces and their linear weights, offsets 0).
+template <class T> struct GTab {
+  int i0, cnt;
+  T w[GMAXC], off[GMAXC];
+};
+
+// One work item of the guard resampling: a chunk of the target elements of
+// box m whose source block (slope neighbours included) fits the LDS stage,
+// or (tab[0] < 0) a whole same-resolution box of a padded region, copied.
+// The chunk spans target indices [ta, tb] along axis ca and the whole box
+// along the other two, variables [v0, v0 + nv); its staged source indices
+// are r0 .. r1 per axis.  tab[d]: pool entry of target index 0 of the box's
+// axis-d table.  Planned on the host at create (the geometry is static).
+struct GItem {
+  int m, comp;
+  int ca, ta, tb, v0, nv;
+  int r0[3], r1[3];
+  int tab[3];
+};
 
 struct Bracket;
 
@@ -75,6 +99,11 @@ struct DevSet {
   const int* nb_idx;
   const int* rbox_off;  // [npatch * 108 + 1]: boxes of (patch, component + 1, region)
   const GBox* boxes;
+  // guard resampling plan: per patch its work items (gitem_off [npatch + 1]),
+  // and the pool of per-axis tables (GTab<T> of the set's precision)
+  const int* gitem_off;
+  const GItem* gitems;
+  const void* gtab;
   // reverse of the same-resolution boxes: per (source patch, component + 1)
   // the boxes that copy from it, as (box index, owning patch)
   const int* rev_off;  // [npatch * 4 + 1]

@@ -178,90 +178,31 @@ __device__ __attribute__((noinline)) FaceStates<T> fallback_states(const PatchCt
 // Guard regions that are not a single same-resolution box (several sources,
 // or another resolution): values written into the entry's padded buffer, so
 // the marching kernel reads every guard region with one addressing rule.
-// One workgroup per (region, patch).
 //
 // A box from a patch of another resolution is resampled as cross_value
 // defines it: the mean over the target cell (or face) of the source's
 // piecewise-linear, minmod-limited reconstruction of its time-interpolated
 // data.  The source cells a target cell overlaps form a tensor product of
 // per-axis ranges, and the overlap volume is the product of per-axis
-// lengths, so the workgroup first tabulates per axis and target index the
-// overlapped source indices with their weights (overlap length over the sum
-// of the axis's overlaps) and the offsets of the overlap centres from the
-// source cell centres (along a face field's own axis: the two bracketing
-// source faces and their linear weights).  It then stages the
-// time-interpolated source values of a chunk of the box (all variables,
-// slope neighbours included) in LDS, and every target value of the chunk
-// sums over its overlapped cells from there.  Boxes whose overlaps exceed
-// the tables (resolution ratios above three) or whose smallest chunk does
-// not fit the stage are flagged by the host (GBox::direct) and resampled
-// straight from the slices by k_gfill_direct.
-
+// lengths, so per axis and target index a table (GTab) holds the overlapped
+// source indices with their weights (overlap length over the sum of the
+// axis's overlaps) and the offsets of the overlap centres from the source
+// cell centres (along a face field's own axis: the two bracketing source
+// faces and their linear weights).  The geometry is static, so the host
+// builds the tables once at create, shared between boxes of equal geometry,
+// and cuts every box into work items (GItem) whose time-interpolated source
+// block (all variables when they fit, slope neighbours included) fits the
+// LDS stage.  A work item stages its tables and its source block, waits at
+// one barrier, and every target value of the item sums over its overlapped
+// cells from there.  Boxes whose overlaps exceed the tables (resolution
+// ratios above three) or whose smallest chunk does not fit the stage are
+// flagged by the host (GBox::direct) and resampled straight from the slices
+// by k_gfill_direct.
 
 template <class T> struct GfillSmem {
   T stage[GSTAGE_BYTES / sizeof(T)];
-  T w[3][GMAXT][GMAXC];    // per-axis weights
-  T off[3][GMAXT][GMAXC];  // per-axis offsets of the overlap centres (source cells)
-  int i0[3][GMAXT];        // first overlapped source index
-  int cnt[3][GMAXT];       // number of overlapped source indices (0: table overflow)
-  int ch_tb, ch_nv, ch_direct;  // chunk: last target index along the chunk axis, variables
-  int r0[3], r1[3];        // staged source index range of the chunk
+  GTab<T> tab[3][GMAXT];  // the item's box tables, indexed by target index
 };
-
-// Table entry of target index t (relative to the box) along axis d.
-template <class T>
-__device__ inline void gfill_axis(const DevSet& S, int p, int q, int comp, const GBox& G, int d, int t,
-                                  GfillSmem<T>& sm) {
-  const int nq = S.n[q];
-  const int64_t sdx = S.dxl[q], len = S.len[q], loq = S.lo[3 * q + d], tdx = S.dxl[p];
-  const int64_t X = S.lo[3 * p + d] + (int64_t)(G.lo[d] + t) * tdx + (d == comp ? 0 : tdx / 2) + G.wrap[d];
-  auto clamp = [&](int64_t v) { return v < 0 ? (int64_t)0 : (v > len ? len : v); };
-  if (d == comp) {  // the two source faces bracketing the target face
-    const int64_t A = clamp(X - loq);
-    int f0 = (int)(A / sdx);
-    int64_t rem = A - (int64_t)f0 * sdx;
-    if (f0 >= nq) {
-      f0 = nq;
-      rem = 0;
-    }
-    const double wn = (double)rem / (double)sdx;
-    sm.i0[d][t] = f0;
-    sm.cnt[d][t] = wn == 0.0 ? 1 : 2;
-    sm.w[d][t][0] = T(1.0 - wn);
-    sm.w[d][t][1] = T(wn);
-    sm.off[d][t][0] = sm.off[d][t][1] = T(0);
-    return;
-  }
-  const int64_t A = clamp(X - tdx / 2 - loq), B = clamp(X + tdx / 2 - loq);
-  int c0 = (int)(A / sdx), c1 = (int)((B - 1) / sdx);
-  c0 = c0 < 0 ? 0 : (c0 > nq - 1 ? nq - 1 : c0);
-  c1 = c1 < 0 ? 0 : (c1 > nq - 1 ? nq - 1 : c1);
-  // two passes over the overlapped cells: the total overlap, then the
-  // normalised weights and the offsets (overlap lengths are exact integers)
-  double tot = 0.0;
-  int k = 0, first = -1;
-  for (int c = c0; c <= c1; ++c) {
-    const int64_t a = A > (int64_t)c * sdx ? A : (int64_t)c * sdx;
-    const int64_t b = B < (int64_t)(c + 1) * sdx ? B : (int64_t)(c + 1) * sdx;
-    if (b - a <= 0) continue;
-    if (first < 0) first = c;
-    tot += (double)(b - a);
-    ++k;
-  }
-  if (k > GMAXC) {  // more overlapped cells than the table holds (the host flags such boxes)
-    sm.cnt[d][t] = 0;
-    return;
-  }
-  sm.i0[d][t] = first;
-  sm.cnt[d][t] = k;
-  for (int m = 0; m < k; ++m) {
-    const int c = first + m;
-    const int64_t a = A > (int64_t)c * sdx ? A : (int64_t)c * sdx;
-    const int64_t b = B < (int64_t)(c + 1) * sdx ? B : (int64_t)(c + 1) * sdx;
-    sm.w[d][t][m] = T((double)(b - a) / tot);
-    sm.off[d][t][m] = T((0.5 * (double)(a + b) - ((double)c + 0.5) * (double)sdx) / (double)sdx);
-  }
-}
 
 // Boxes flagged direct, resampled straight from the source slices: one
 // workgroup per (region, patch) as k_gfill, one thread per element.
@@ -355,19 +296,19 @@ __device__ __forceinline__ int small_div(int r, int d, float inv) {
 }
 
 constexpr int GFILL_ROWS = 512;  // patch rows of the resampling grid (a row strides over the ready list)
+constexpr int GFILL_COLS = 32;   // workgroups per patch row (a column strides over the patch's items)
 
-// Guard region `key` of patch p into its padded buffer dst, by the whole
-// workgroup (every thread calls it; the workgroup synchronises inside).  The
-// time brackets of the region's boxes are in S.brk.
+// Work item it of patch p into its padded buffer dst, by the whole
+// workgroup (every thread calls it).  The time bracket of the item's box is
+// in S.brk.  A resampling item ends with a barrier (the next item reuses the
+// stage); a copy item uses no LDS and has none.
 template <class T>
-__device__ void gfill_region(const DevSet& S, GfillSmem<T>& sm, const T* __restrict__ slots, T* __restrict__ dst,
-                             int p, int key) {
+__device__ void gfill_item(const DevSet& S, GfillSmem<T>& sm, const T* __restrict__ slots, T* __restrict__ dst,
+                           int p, const GItem& it) {
   constexpr int GSTAGE = GSTAGE_BYTES / (int)sizeof(T);
-  const int comp = key / 27 - 1;
+  const int comp = it.comp;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int nvar = comp < 0 ? 5 : 1;
   const int n = S.n[p], N = n + 4;
-  const int m0 = S.rbox_off[p * 108 + key], m1 = S.rbox_off[p * 108 + key + 1];
   // padded-buffer offset (32 bits: a padded patch holds fewer than 2^31 values)
   const int N2 = N * N;
   auto dst_off = [&](int var, int i, int j, int k) -> int {
@@ -375,224 +316,164 @@ __device__ void gfill_region(const DevSet& S, GfillSmem<T>& sm, const T* __restr
     const int sx = N + (comp == 0), sy = N + (comp == 1);
     return 5 * N2 * N + comp * N2 * (N + 1) + ((k + 2) * sy + (j + 2)) * sx + (i + 2);
   };
-  // the boxes of a region are disjoint (the host checks that they tile it)
-  for (int m = m0; m < m1; ++m) {
-    const GBox G = S.boxes[m];
-    if (G.direct) continue;  // k_gfill_direct
-    const Bracket br = S.brk[m];  // the round's bracket of this box (k_brackets)
-    const int ext[3] = {G.hi[0] - G.lo[0] + 1, G.hi[1] - G.lo[1] + 1, G.hi[2] - G.lo[2] + 1};
+  const GBox G = S.boxes[it.m];
+  const Bracket br = S.brk[it.m];  // the round's bracket of this box (k_brackets)
+  const int ext[3] = {G.hi[0] - G.lo[0] + 1, G.hi[1] - G.lo[1] + 1, G.hi[2] - G.lo[2] + 1};
+  const int q = G.q, nq = S.n[q];
+  if (it.tab[0] < 0) {  // a same-resolution box of a padded region: a time-interpolated copy
     const int cnt = ext[0] * ext[1] * ext[2];
-    const int q = G.q, nq = S.n[q];
-    if (G.same) {
-      const float ie0 = 1.0f / (float)ext[0], ie1 = 1.0f / (float)ext[1], ie2 = 1.0f / (float)ext[2];
-      auto decode = [&](int e, int& var, int& i, int& j, int& k) {
-        int r = e;
-        int qq = small_div(r, ext[0], ie0);
-        i = G.lo[0] + (r - qq * ext[0]);
-        r = qq;
-        qq = small_div(r, ext[1], ie1);
-        j = G.lo[1] + (r - qq * ext[1]);
-        r = qq;
-        qq = small_div(r, ext[2], ie2);
-        k = G.lo[2] + (r - qq * ext[2]);
-        var = qq;
-      };
-      tlerp_batched<T, 8>(
-          slots, br, cnt * nvar, tid, nthr,
-          [&](int e) -> int64_t {
-            int var, i, j, k;
-            decode(e, var, i, j, k);
-            const int qi = i + G.shift[0], qj = j + G.shift[1], qk = k + G.shift[2];
-            return (comp < 0) ? scell(nq, var, qi, qj, qk) : sface(nq, comp, qi, qj, qk);
-          },
-          [&](int e, T v) {
-            int var, i, j, k;
-            decode(e, var, i, j, k);
-            dst[dst_off(var, i, j, k)] = v;
-          });
-      continue;
-    }
-    __syncthreads();  // the previous box's readers of the tables are done
-    if (tid == 0) sm.ch_direct = 0;
-    const bool fits = ext[0] <= GMAXT && ext[1] <= GMAXT && ext[2] <= GMAXT;
-    __syncthreads();
-    if (fits)
-      for (int t = tid; t < ext[0] + ext[1] + ext[2]; t += nthr) {
-        const int d = t < ext[0] ? 0 : (t < ext[0] + ext[1] ? 1 : 2);
-        const int tt = t - (d > 0 ? ext[0] : 0) - (d > 1 ? ext[1] : 0);
-        gfill_axis<T>(S, p, q, comp, G, d, tt, sm);
-        if (sm.cnt[d][tt] == 0) sm.ch_direct = 1;  // table overflow
-      }
-    else if (tid == 0)
-      sm.ch_direct = 1;
-    __syncthreads();
-    if (sm.ch_direct) {  // the host's limits should have flagged this box
-      if (tid == 0) atomicOr(S.err, ERR_STATE);
-      continue;
-    }
-    // chunk axis: the longest; along it, chunks of target indices whose
-    // staged source block (all variables when they fit) fills the stage
-    int ca = 0;
-    if (ext[1] > ext[ca]) ca = 1;
-    if (ext[2] > ext[ca]) ca = 2;
-    const int cb = (ca + 1) % 3, cc = (ca + 2) % 3;
-    // source range of target indices [a, b] along axis d: the overlapped
-    // indices, plus the slope neighbours across (not along a face's own axis)
-    auto range = [&](int d, int a, int bb, int& r0, int& r1) {
-      r0 = sm.i0[d][a];
-      r1 = sm.i0[d][bb] + sm.cnt[d][bb] - 1;
-      if (d != comp) {
-        r0 = r0 > 0 ? r0 - 1 : 0;
-        r1 = r1 < nq - 1 ? r1 + 1 : nq - 1;
-      }
+    const float ie0 = 1.0f / (float)ext[0], ie1 = 1.0f / (float)ext[1], ie2 = 1.0f / (float)ext[2];
+    auto decode = [&](int e, int& var, int& i, int& j, int& k) {
+      int r = e;
+      int qq = small_div(r, ext[0], ie0);
+      i = G.lo[0] + (r - qq * ext[0]);
+      r = qq;
+      qq = small_div(r, ext[1], ie1);
+      j = G.lo[1] + (r - qq * ext[1]);
+      r = qq;
+      qq = small_div(r, ext[2], ie2);
+      k = G.lo[2] + (r - qq * ext[2]);
+      var = qq;
     };
-    int rb0, rb1, rc0, rc1;
-    range(cb, 0, ext[cb] - 1, rb0, rb1);
-    range(cc, 0, ext[cc] - 1, rc0, rc1);
-    const int across = (rb1 - rb0 + 1) * (rc1 - rc0 + 1);
-    auto size = [&](int a, int bb) {
-      int x0, x1;
-      range(ca, a, bb, x0, x1);
-      return across * (x1 - x0 + 1);
-    };
-    int ta = 0, v0 = 0;
-    while (ta < ext[ca]) {
-      // chunk: every variable over the most target indices that fit (each
-      // thread tests one extent; the sizes grow with the extent), else one
-      // target index with as many variables as fit
-      __syncthreads();
-      if (tid == 0) sm.ch_tb = ta;
-      __syncthreads();
-      int nv;
-      if (v0 == 0 && size(ta, ta) * nvar <= GSTAGE) {
-        nv = nvar;
-        const int t = ta + tid;
-        if (tid > 0 && t < ext[ca] && size(ta, t) * nvar <= GSTAGE) atomicMax(&sm.ch_tb, t);
-      } else {
-        nv = GSTAGE / size(ta, ta);
-        nv = nv > nvar - v0 ? nvar - v0 : nv;
-      }
-      __syncthreads();
-      if (nv < 1) {  // not even one variable of one index: the host's limits should have flagged it
-        if (tid == 0) atomicOr(S.err, ERR_STATE);
-        break;
-      }
-      const int tb = sm.ch_tb;
-      int r0[3], r1[3];
-      range(ca, ta, tb, r0[ca], r1[ca]);
-      r0[cb] = rb0;
-      r1[cb] = rb1;
-      r0[cc] = rc0;
-      r1[cc] = rc1;
-      const int r00 = r0[0], r01 = r0[1], r02 = r0[2];
-      const int sx = r1[0] - r00 + 1, sy = r1[1] - r01 + 1, sz = r1[2] - r02 + 1;
-      const int sxy = sx * sy, sblk = sxy * sz;
-      const float isx = 1.0f / (float)sx, isxy = 1.0f / (float)sxy, isblk = 1.0f / (float)sblk;
-      tlerp_batched<T, 8>(
-          slots, br, nv * sblk, tid, nthr,
-          [&](int e) -> int64_t {
-            const int v = small_div(e, sblk, isblk), r = e - v * sblk;
-            const int kq = small_div(r, sxy, isxy), rr = r - kq * sxy;
-            const int jq = small_div(rr, sx, isx);
-            const int ii = r00 + (rr - jq * sx), jj = r01 + jq, kk = r02 + kq;
-            return (comp < 0) ? scell(nq, v0 + v, ii, jj, kk) : sface(nq, comp, ii, jj, kk);
-          },
-          [&](int e, T v) { sm.stage[e] = v; });
-      __syncthreads();
-      // target elements of the chunk: ta..tb along the chunk axis, all of the
-      // others (per-axis indices kept in scalars: no private arrays indexed at
-      // run time in the hot loop)
-      const int ce0 = ca == 0 ? tb - ta + 1 : ext[0], ce1 = ca == 1 ? tb - ta + 1 : ext[1];
-      const int ce2 = ca == 2 ? tb - ta + 1 : ext[2];
-      const int ce01 = ce0 * ce1, ccnt = ce01 * ce2;
-      const float ice0 = 1.0f / (float)ce0, ice01 = 1.0f / (float)ce01, iccnt = 1.0f / (float)ccnt;
-      for (int e = tid; e < nv * ccnt; e += nthr) {
-        const int v = small_div(e, ccnt, iccnt), r = e - v * ccnt;
-        int t2 = small_div(r, ce01, ice01);
-        const int r2 = r - t2 * ce01;
-        int t1 = small_div(r2, ce0, ice0);
-        int t0 = r2 - t1 * ce0;
-        t0 += ca == 0 ? ta : 0;
-        t1 += ca == 1 ? ta : 0;
-        t2 += ca == 2 ? ta : 0;
-        const T* st = sm.stage + v * sblk;
-        T acc = T(0);
-        if (comp < 0) {
-          const int cz = sm.cnt[2][t2], cy = sm.cnt[1][t1], cx = sm.cnt[0][t0];
-          const int kz = sm.i0[2][t2], jy = sm.i0[1][t1], ix = sm.i0[0][t0];
-          for (int c = 0; c < cz; ++c) {
-            const int kk = kz + c;
-            const T wz = sm.w[2][t2][c], oz = sm.off[2][t2][c];
-            const bool zm = kk - 1 >= 0, zp = kk + 1 <= nq - 1;
-            for (int bq = 0; bq < cy; ++bq) {
-              const int jj = jy + bq;
-              const T wy = sm.w[1][t1][bq], oy = sm.off[1][t1][bq];
-              const bool ym = jj - 1 >= 0, yp = jj + 1 <= nq - 1;
-              const T wyz = wy * wz;
-              const int rowb = (kk - r02) * sxy + (jj - r01) * sx - r00;
-              for (int a = 0; a < cx; ++a) {
-                const int ii = ix + a;
-                const T wx = sm.w[0][t0][a], ox = sm.off[0][t0][a];
-                const int o = rowb + ii;
-                const T c0 = st[o];
-                const bool xm = ii - 1 >= 0, xp = ii + 1 <= nq - 1;
-                const T gx = (xm && xp) ? minmod_slope(st[o - 1], c0, st[o + 1])
-                             : xp ? st[o + 1] - c0 : (xm ? c0 - st[o - 1] : T(0));
-                const T gy = (ym && yp) ? minmod_slope(st[o - sx], c0, st[o + sx])
-                             : yp ? st[o + sx] - c0 : (ym ? c0 - st[o - sx] : T(0));
-                const T gz = (zm && zp) ? minmod_slope(st[o - sxy], c0, st[o + sxy])
-                             : zp ? st[o + sxy] - c0 : (zm ? c0 - st[o - sxy] : T(0));
-                acc = acc + (wx * wyz) * (((c0 + ox * gx) + oy * gy) + oz * gz);
-              }
-            }
-          }
-        } else {
-          // face field of component d = comp: index f along d, u along
-          // t1 = d + 1, w along t2 = d + 2 (cyclic); stage strides of the three
-          const int d = comp;
-          const int tn = d == 0 ? t0 : (d == 1 ? t1 : t2);
-          const int tu = d == 0 ? t1 : (d == 1 ? t2 : t0);
-          const int tw = d == 0 ? t2 : (d == 1 ? t0 : t1);
-          const int au = d == 2 ? 0 : d + 1, aw = d == 0 ? 2 : d - 1;  // the axes t1, t2
-          const int su = au == 0 ? 1 : (au == 1 ? sx : sxy), sw = aw == 0 ? 1 : (aw == 1 ? sx : sxy);
-          const int sn = d == 0 ? 1 : (d == 1 ? sx : sxy);
-          const int rn = d == 0 ? r00 : (d == 1 ? r01 : r02);
-          const int ru = au == 0 ? r00 : (au == 1 ? r01 : r02);
-          const int rw = aw == 0 ? r00 : (aw == 1 ? r01 : r02);
-          const int cu_n = sm.cnt[au][tu], cw_n = sm.cnt[aw][tw], cs_n = sm.cnt[d][tn];
-          for (int cu = 0; cu < cu_n; ++cu) {
-            const int u = sm.i0[au][tu] + cu;
-            const T wu = sm.w[au][tu][cu], ou = sm.off[au][tu][cu];
-            const bool um = u - 1 >= 0, up = u + 1 <= nq - 1;
-            for (int cw = 0; cw < cw_n; ++cw) {
-              const int w = sm.i0[aw][tw] + cw;
-              const T ww = sm.w[aw][tw][cw], ow = sm.off[aw][tw][cw];
-              const bool wm = w - 1 >= 0, wp = w + 1 <= nq - 1;
-              T lin2 = T(0);
-              for (int side = 0; side < cs_n; ++side) {
-                const int f = sm.i0[d][tn] + side;
-                const int o = (f - rn) * sn + (u - ru) * su + (w - rw) * sw;
-                const T c0 = st[o];
-                const T gu = (um && up) ? minmod_slope(st[o - su], c0, st[o + su])
-                             : up ? st[o + su] - c0 : (um ? c0 - st[o - su] : T(0));
-                const T gw = (wm && wp) ? minmod_slope(st[o - sw], c0, st[o + sw])
-                             : wp ? st[o + sw] - c0 : (wm ? c0 - st[o - sw] : T(0));
-                lin2 = lin2 + sm.w[d][tn][side] * ((c0 + ou * gu) + ow * gw);
-              }
-              acc = acc + (wu * ww) * lin2;
-            }
-          }
-        }
-        dst[dst_off(v0 + v, G.lo[0] + t0, G.lo[1] + t1, G.lo[2] + t2)] = acc;
-      }
-      v0 += nv;
-      if (v0 >= nvar) {
-        v0 = 0;
-        ta = tb + 1;
-      }
+    tlerp_batched<T, 8>(
+        slots, br, cnt * it.nv, tid, nthr,
+        [&](int e) -> int64_t {
+          int var, i, j, k;
+          decode(e, var, i, j, k);
+          const int qi = i + G.shift[0], qj = j + G.shift[1], qk = k + G.shift[2];
+          return (comp < 0) ? scell(nq, var, qi, qj, qk) : sface(nq, comp, qi, qj, qk);
+        },
+        [&](int e, T v) {
+          int var, i, j, k;
+          decode(e, var, i, j, k);
+          dst[dst_off(var, i, j, k)] = v;
+        });
+    return;
+  }
+  // the box's tables (the chunk axis only over the chunk) and the staged block
+  const GTab<T>* pool = (const GTab<T>*)S.gtab;
+  const int ca = it.ca, ta = it.ta, tb = it.tb;
+  {
+    const int l0 = ca == 0 ? tb - ta + 1 : ext[0], l1 = ca == 1 ? tb - ta + 1 : ext[1];
+    const int l2 = ca == 2 ? tb - ta + 1 : ext[2];
+    for (int e = tid; e < l0 + l1 + l2; e += nthr) {
+      const int d = e < l0 ? 0 : (e < l0 + l1 ? 1 : 2);
+      const int t = e - (d > 0 ? l0 : 0) - (d > 1 ? l1 : 0) + (d == ca ? ta : 0);
+      sm.tab[d][t] = pool[it.tab[d] + t];
     }
   }
-  __syncthreads();  // the next region reuses the tables and the stage
+  const int r00 = it.r0[0], r01 = it.r0[1], r02 = it.r0[2];
+  const int sx = it.r1[0] - r00 + 1, sy = it.r1[1] - r01 + 1, sz = it.r1[2] - r02 + 1;
+  const int sxy = sx * sy, sblk = sxy * sz;
+  const int v0 = it.v0, nv = it.nv;
+  if (nv * sblk > GSTAGE) {  // the host plans every item to fit
+    if (tid == 0) atomicOr(S.err, ERR_STATE);
+    return;
+  }
+  {
+    const float isx = 1.0f / (float)sx, isxy = 1.0f / (float)sxy, isblk = 1.0f / (float)sblk;
+    tlerp_batched<T, 8>(
+        slots, br, nv * sblk, tid, nthr,
+        [&](int e) -> int64_t {
+          const int v = small_div(e, sblk, isblk), r = e - v * sblk;
+          const int kq = small_div(r, sxy, isxy), rr = r - kq * sxy;
+          const int jq = small_div(rr, sx, isx);
+          const int ii = r00 + (rr - jq * sx), jj = r01 + jq, kk = r02 + kq;
+          return (comp < 0) ? scell(nq, v0 + v, ii, jj, kk) : sface(nq, comp, ii, jj, kk);
+        },
+        [&](int e, T v) { sm.stage[e] = v; });
+  }
+  __syncthreads();
+  // target elements of the chunk: ta..tb along the chunk axis, all of the
+  // others (per-axis indices kept in scalars: no private arrays indexed at
+  // run time in the hot loop)
+  const int ce0 = ca == 0 ? tb - ta + 1 : ext[0], ce1 = ca == 1 ? tb - ta + 1 : ext[1];
+  const int ce2 = ca == 2 ? tb - ta + 1 : ext[2];
+  const int ce01 = ce0 * ce1, ccnt = ce01 * ce2;
+  const float ice0 = 1.0f / (float)ce0, ice01 = 1.0f / (float)ce01, iccnt = 1.0f / (float)ccnt;
+  for (int e = tid; e < nv * ccnt; e += nthr) {
+    const int v = small_div(e, ccnt, iccnt), r = e - v * ccnt;
+    int t2 = small_div(r, ce01, ice01);
+    const int r2 = r - t2 * ce01;
+    int t1 = small_div(r2, ce0, ice0);
+    int t0 = r2 - t1 * ce0;
+    t0 += ca == 0 ? ta : 0;
+    t1 += ca == 1 ? ta : 0;
+    t2 += ca == 2 ? ta : 0;
+    const T* st = sm.stage + v * sblk;
+    T acc = T(0);
+    if (comp < 0) {
+      const GTab<T>& Z = sm.tab[2][t2];
+      const GTab<T>& Y = sm.tab[1][t1];
+      const GTab<T>& X = sm.tab[0][t0];
+      for (int c = 0; c < Z.cnt; ++c) {
+        const int kk = Z.i0 + c;
+        const T wz = Z.w[c], oz = Z.off[c];
+        const bool zm = kk - 1 >= 0, zp = kk + 1 <= nq - 1;
+        for (int bq = 0; bq < Y.cnt; ++bq) {
+          const int jj = Y.i0 + bq;
+          const T wy = Y.w[bq], oy = Y.off[bq];
+          const bool ym = jj - 1 >= 0, yp = jj + 1 <= nq - 1;
+          const T wyz = wy * wz;
+          const int rowb = (kk - r02) * sxy + (jj - r01) * sx - r00;
+          for (int a = 0; a < X.cnt; ++a) {
+            const int ii = X.i0 + a;
+            const T wx = X.w[a], ox = X.off[a];
+            const int o = rowb + ii;
+            const T c0 = st[o];
+            const bool xm = ii - 1 >= 0, xp = ii + 1 <= nq - 1;
+            const T gx = (xm && xp) ? minmod_slope(st[o - 1], c0, st[o + 1])
+                         : xp ? st[o + 1] - c0 : (xm ? c0 - st[o - 1] : T(0));
+            const T gy = (ym && yp) ? minmod_slope(st[o - sx], c0, st[o + sx])
+                         : yp ? st[o + sx] - c0 : (ym ? c0 - st[o - sx] : T(0));
+            const T gz = (zm && zp) ? minmod_slope(st[o - sxy], c0, st[o + sxy])
+                         : zp ? st[o + sxy] - c0 : (zm ? c0 - st[o - sxy] : T(0));
+            acc = acc + (wx * wyz) * (((c0 + ox * gx) + oy * gy) + oz * gz);
+          }
+        }
+      }
+    } else {
+      // face field of component d = comp: index f along d, u along
+      // t1 = d + 1, w along t2 = d + 2 (cyclic); stage strides of the three
+      const int d = comp;
+      const int tn = d == 0 ? t0 : (d == 1 ? t1 : t2);
+      const int tu = d == 0 ? t1 : (d == 1 ? t2 : t0);
+      const int tw = d == 0 ? t2 : (d == 1 ? t0 : t1);
+      const int au = d == 2 ? 0 : d + 1, aw = d == 0 ? 2 : d - 1;  // the axes t1, t2
+      const int su = au == 0 ? 1 : (au == 1 ? sx : sxy), sw = aw == 0 ? 1 : (aw == 1 ? sx : sxy);
+      const int sn = d == 0 ? 1 : (d == 1 ? sx : sxy);
+      const int rn = d == 0 ? r00 : (d == 1 ? r01 : r02);
+      const int ru = au == 0 ? r00 : (au == 1 ? r01 : r02);
+      const int rw = aw == 0 ? r00 : (aw == 1 ? r01 : r02);
+      const GTab<T>& U = sm.tab[au][tu];
+      const GTab<T>& W = sm.tab[aw][tw];
+      const GTab<T>& F = sm.tab[d][tn];
+      for (int cu = 0; cu < U.cnt; ++cu) {
+        const int u = U.i0 + cu;
+        const T wu = U.w[cu], ou = U.off[cu];
+        const bool um = u - 1 >= 0, up = u + 1 <= nq - 1;
+        for (int cw = 0; cw < W.cnt; ++cw) {
+          const int w = W.i0 + cw;
+          const T ww = W.w[cw], ow = W.off[cw];
+          const bool wm = w - 1 >= 0, wp = w + 1 <= nq - 1;
+          T lin2 = T(0);
+          for (int side = 0; side < F.cnt; ++side) {
+            const int f = F.i0 + side;
+            const int o = (f - rn) * sn + (u - ru) * su + (w - rw) * sw;
+            const T c0 = st[o];
+            const T gu = (um && up) ? minmod_slope(st[o - su], c0, st[o + su])
+                         : up ? st[o + su] - c0 : (um ? c0 - st[o - su] : T(0));
+            const T gw = (wm && wp) ? minmod_slope(st[o - sw], c0, st[o + sw])
+                         : wp ? st[o + sw] - c0 : (wm ? c0 - st[o - sw] : T(0));
+            lin2 = lin2 + F.w[side] * ((c0 + ou * gu) + ow * gw);
+          }
+          acc = acc + (wu * ww) * lin2;
+        }
+      }
+    }
+    dst[dst_off(v0 + v, G.lo[0] + t0, G.lo[1] + t1, G.lo[2] + t2)] = acc;
+  }
+  __syncthreads();  // the next item reuses the tables and the stage
 }
 
 template <class T>
@@ -600,13 +481,12 @@ __global__ __launch_bounds__(256) void k_gfill(DevSet S, const int* __restrict__
                                                const T* __restrict__ slots, T* __restrict__ pad,
                                                int64_t pad_stride) {
   __shared__ GfillSmem<T> sm;
-  const int key = blockIdx.x;
   const int live = live_count(S, count);
-  if (key % 27 == 13) return;
   for (int b = blockIdx.y; b < live; b += gridDim.y) {
     const int p = list[b];
-    if (region_direct(S, p, key)) continue;
-    gfill_region<T>(S, sm, slots, pad + (int64_t)b * pad_stride, p, key);
+    const int i1 = S.gitem_off[p + 1];
+    for (int it = S.gitem_off[p] + blockIdx.x; it < i1; it += gridDim.x)
+      gfill_item<T>(S, sm, slots, pad + (int64_t)b * pad_stride, p, S.gitems[it]);
   }
 }
 
@@ -1812,9 +1692,8 @@ __global__ __launch_bounds__(NTHR2) void k_persist(DevSet S, QueueState Q, float
     // ---- guard regions resampled across resolutions, into this worker's padded buffer
     if constexpr (FN == 0) {  // a fixed size (FN > 0) means no resampled region
       if (gfill) {
-        for (int key = 0; key < 108; ++key)
-          if (key % 27 != 13 && !region_direct(S, p, key))
-            gfill_region<float>(S, sm.gf, slots, pad + (int64_t)w * pad_stride, p, key);
+        for (int it = S.gitem_off[p]; it < S.gitem_off[p + 1]; ++it)
+          gfill_item<float>(S, sm.gf, slots, pad + (int64_t)w * pad_stride, p, S.gitems[it]);
         __syncthreads();
       }
     }
@@ -1880,7 +1759,7 @@ int launch_fused(const DevSet& S0, const int* list, int count, int nmin, int nma
     // the time bracket of every guard box of the listed patches, once (a
     // chain of dependent reads that every resampling workgroup would repeat)
     launch_brackets(S, list, count, s);
-    hipLaunchKernelGGL(k_gfill<T>, dim3(108, std::min(count, GFILL_ROWS)), dim3(256), 0, s, S, list, count,
+    hipLaunchKernelGGL(k_gfill<T>, dim3(GFILL_COLS, std::min(count, GFILL_ROWS)), dim3(256), 0, s, S, list, count,
                        (const T*)slots, pad, pad_stride);
     if (S.any_direct)
       hipLaunchKernelGGL(k_gfill_direct<T>, dim3(108, count), dim3(256), 0, s, S, list, count, (const T*)slots,

@@ -487,33 +487,155 @@ struct dsp_set {
 
 namespace {
 
-// Whether the staged guard resampling (k_gfill) can take a box resampled
-// from source Q into patch P: along every axis across a cell (or across a
-// face) a target index overlaps at most GMAXC source indices, the box has at
-// most GMAXT indices per axis, and the smallest chunk (one variable, one
-// index along the box's longest axis) with its slope neighbours fits the LDS
-// stage.  Upper bounds of what the kernel computes: a run of e target
-// indices of length L source cells overlaps at most ceil(e L) + 1 source
-// indices, plus one slope neighbour on each side.
-bool staged_resampling_fits(const HPatch& P, const HPatch& Q, int comp, const GBox& g, int prec) {
-  const int64_t stage = GSTAGE_BYTES / (prec == DSP_F32 ? 4 : 8);
-  int ext[3], ca = 0;
-  for (int d = 0; d < 3; ++d) {
-    ext[d] = g.hi[d] - g.lo[d] + 1;
-    if (ext[d] > GMAXT) return false;
+// Static plan of the staged guard resampling (k_gfill), built once at
+// create: the per-axis overlap tables of every resampled box (one copy per
+// distinct geometry) and the work items of every patch.  The tables follow
+// cross_value's reading of the overlap (exact integer lattice lengths, the
+// weights and centre offsets in double); the chunks cut a box along its
+// longest axis into runs of target indices whose time-interpolated source
+// block, with its slope neighbours, fits the LDS stage: every variable over
+// as many indices as fit, else one index with as many variables as fit.
+struct GTabH {
+  int i0, cnt;
+  double w[GMAXC], off[GMAXC];
+};
+
+struct GfillPlan {
+  std::vector<GTabH> pool;
+  std::map<std::array<int64_t, 7>, int> seen;  // geometry -> pool offset (-1: over the table limits)
+
+  // Axis-d table of box g (target patch H, source patch Q): the pool entry
+  // of target index 0, or -1 when a target index overlaps more than GMAXC
+  // source indices.
+  int table(const HPatch& H, const HPatch& Q, int comp, const GBox& g, int d) {
+    const int ext = g.hi[d] - g.lo[d] + 1;
+    const int64_t sdx = Q.dxl, len = Q.len, tdx = H.dxl;
+    const int64_t X0 = H.lo[d] + (int64_t)g.lo[d] * tdx + (d == comp ? 0 : tdx / 2) + g.wrap[d] - Q.lo[d];
+    const std::array<int64_t, 7> key{d == comp ? 1 : 0, Q.n, sdx, len, tdx, ext, X0};
+    const auto f = seen.find(key);
+    if (f != seen.end()) return f->second;
+    const int at = (int)pool.size(), nq = Q.n;
+    auto clamp = [&](int64_t v) { return v < 0 ? (int64_t)0 : (v > len ? len : v); };
+    for (int t = 0; t < ext; ++t) {
+      const int64_t X = X0 + (int64_t)t * tdx;
+      GTabH e{};
+      if (d == comp) {  // the two source faces bracketing the target face
+        const int64_t A = clamp(X);
+        int f0 = (int)(A / sdx);
+        int64_t rem = A - (int64_t)f0 * sdx;
+        if (f0 >= nq) {
+          f0 = nq;
+          rem = 0;
+        }
+        const double wn = (double)rem / (double)sdx;
+        e.i0 = f0;
+        e.cnt = wn == 0.0 ? 1 : 2;
+        e.w[0] = 1.0 - wn;
+        e.w[1] = wn;
+      } else {
+        const int64_t A = clamp(X - tdx / 2), B = clamp(X + tdx / 2);
+        const int c0 = std::min(std::max((int)(A / sdx), 0), nq - 1);
+        const int c1 = std::min(std::max((int)((B - 1) / sdx), 0), nq - 1);
+        double tot = 0.0;
+        int k = 0, first = -1;
+        for (int c = c0; c <= c1; ++c) {
+          const int64_t a = std::max(A, (int64_t)c * sdx), b = std::min(B, (int64_t)(c + 1) * sdx);
+          if (b - a <= 0) continue;
+          if (first < 0) first = c;
+          tot += (double)(b - a);
+          ++k;
+        }
+        if (k > GMAXC || k == 0) {
+          pool.resize(at);
+          seen[key] = -1;
+          return -1;
+        }
+        e.i0 = first;
+        e.cnt = k;
+        for (int m = 0; m < k; ++m) {
+          const int c = first + m;
+          const int64_t a = std::max(A, (int64_t)c * sdx), b = std::min(B, (int64_t)(c + 1) * sdx);
+          e.w[m] = (double)(b - a) / tot;
+          e.off[m] = (0.5 * (double)(a + b) - ((double)c + 0.5) * (double)sdx) / (double)sdx;
+        }
+      }
+      pool.push_back(e);
+    }
+    seen[key] = at;
+    return at;
   }
-  if (ext[1] > ext[ca]) ca = 1;
-  if (ext[2] > ext[ca]) ca = 2;
-  auto span = [&](int64_t e) { return (e * P.dxl + Q.dxl - 1) / Q.dxl + 1; };  // ceil(e L) + 1
-  if (span(1) > GMAXC) return false;
-  int64_t size = 1;
-  for (int d = 0; d < 3; ++d) {
-    const int64_t nsrc = Q.n + (d == comp ? 1 : 0);
-    const int64_t b = span(d == ca ? 1 : ext[d]) + 2;
-    size *= b < nsrc ? b : nsrc;
+
+  // Work items of resampled box m (g, from Q into H) appended to out;
+  // false (nothing appended) if the box exceeds the tables or the stage.
+  bool box(const HPatch& H, const HPatch& Q, int comp, const GBox& g, int m, int prec, std::vector<GItem>& out) {
+    const int64_t stage = GSTAGE_BYTES / (prec == DSP_F32 ? 4 : 8);
+    int ext[3], tab[3];
+    for (int d = 0; d < 3; ++d) {
+      ext[d] = g.hi[d] - g.lo[d] + 1;
+      if (ext[d] > GMAXT) return false;
+    }
+    for (int d = 0; d < 3; ++d)
+      if ((tab[d] = table(H, Q, comp, g, d)) < 0) return false;
+    const int nq = Q.n, nvar = comp < 0 ? 5 : 1;
+    int ca = 0;
+    if (ext[1] > ext[ca]) ca = 1;
+    if (ext[2] > ext[ca]) ca = 2;
+    const int cb = (ca + 1) % 3, cc = (ca + 2) % 3;
+    // source range of target indices [a, b] along axis d: the overlapped
+    // indices, plus the slope neighbours across (not along a face's own axis)
+    auto range = [&](int d, int a, int b, int& r0, int& r1) {
+      r0 = pool[tab[d] + a].i0;
+      r1 = pool[tab[d] + b].i0 + pool[tab[d] + b].cnt - 1;
+      if (d != comp) {
+        r0 = std::max(r0 - 1, 0);
+        r1 = std::min(r1 + 1, nq - 1);
+      }
+    };
+    int rb0, rb1, rc0, rc1;
+    range(cb, 0, ext[cb] - 1, rb0, rb1);
+    range(cc, 0, ext[cc] - 1, rc0, rc1);
+    const int64_t across = (int64_t)(rb1 - rb0 + 1) * (rc1 - rc0 + 1);
+    auto size = [&](int a, int b) {
+      int x0, x1;
+      range(ca, a, b, x0, x1);
+      return across * (x1 - x0 + 1);
+    };
+    std::vector<GItem> its;
+    int ta = 0, v0 = 0;
+    while (ta < ext[ca]) {
+      int tb = ta, nv;
+      if (v0 == 0 && size(ta, ta) * nvar <= stage) {
+        nv = nvar;
+        while (tb + 1 < ext[ca] && size(ta, tb + 1) * nvar <= stage) ++tb;
+      } else {
+        nv = (int)std::min<int64_t>(stage / size(ta, ta), nvar - v0);
+        if (nv < 1) return false;
+      }
+      GItem it{};
+      it.m = m;
+      it.comp = comp;
+      it.ca = ca;
+      it.ta = ta;
+      it.tb = tb;
+      it.v0 = v0;
+      it.nv = nv;
+      range(ca, ta, tb, it.r0[ca], it.r1[ca]);
+      it.r0[cb] = rb0;
+      it.r1[cb] = rb1;
+      it.r0[cc] = rc0;
+      it.r1[cc] = rc1;
+      for (int d = 0; d < 3; ++d) it.tab[d] = tab[d];
+      its.push_back(it);
+      v0 += nv;
+      if (v0 >= nvar) {
+        v0 = 0;
+        ta = tb + 1;
+      }
+    }
+    out.insert(out.end(), its.begin(), its.end());
+    return true;
   }
-  return size <= stage;
-}
+};
 
 bool tolat(double x, int64_t scale, int64_t& out) {
   const double y = x * (double)scale;
@@ -651,18 +773,40 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
   std::vector<int> rbox_off(1, 0);
   std::vector<GBox> boxes;
   std::vector<std::vector<GBox>> keys;
+  // the resampling plan: per patch its work items (the boxes of the regions
+  // read through the padded buffer; a resampled box that exceeds the tables
+  // or the stage is flagged direct instead)
+  GfillPlan plan;
+  std::vector<GItem> gitems;
+  std::vector<int> gitem_off(1, 0);
   for (int p = 0; p < npatch; ++p) {
     int e = S->build_boxes(p, c.nguard, keys, &reads[p]);
     if (e) return e;
     e = S->build_boxes(p, 2, keys, nullptr);
     if (e) return e;
     for (int k = 0; k < 108; ++k) {
+      const int comp = k / 27 - 1;
+      const bool padded = k % 27 != 13 && !(keys[k].size() == 1 && keys[k][0].same && c.torder < 2);
       for (GBox g : keys[k]) {
-        g.direct = (!g.same && !staged_resampling_fits(S->P[p], S->P[g.q], k / 27 - 1, g, c.prec)) ? 1 : 0;
+        const int m = (int)boxes.size();
+        g.direct = 0;
+        if (!g.same) {
+          const size_t before = gitems.size();
+          if (!plan.box(S->P[p], S->P[g.q], comp, g, m, c.prec, gitems)) g.direct = 1;
+          if (!padded) gitems.resize(before);
+        } else if (padded) {
+          GItem it{};
+          it.m = m;
+          it.comp = comp;
+          it.nv = comp < 0 ? 5 : 1;
+          it.tab[0] = it.tab[1] = it.tab[2] = -1;
+          gitems.push_back(it);
+        }
         boxes.push_back(g);
       }
       rbox_off.push_back((int)boxes.size());
     }
+    gitem_off.push_back((int)gitems.size());
   }
   {
     // the fused kernel keeps the time brackets of a patch's guard boxes in LDS
@@ -801,6 +945,37 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
   D.nb_off = (const int*)up(nb_off.data(), sizeof(int) * nb_off.size());
   D.nb_idx = (const int*)up(nb_idx.data(), sizeof(int) * std::max<size_t>(1, nb_idx.size()));
   D.rbox_off = (const int*)up(rbox_off.data(), sizeof(int) * rbox_off.size());
+  D.gitem_off = (const int*)up(gitem_off.data(), sizeof(int) * gitem_off.size());
+  D.gitems = (const GItem*)up(gitems.data(), sizeof(GItem) * std::max<size_t>(1, gitems.size()));
+  {
+    // the table pool in the set's precision
+    const size_t ne = std::max<size_t>(1, plan.pool.size());
+    if (s->f32) {
+      std::vector<GTab<float>> t(ne);
+      for (size_t i = 0; i < plan.pool.size(); ++i) {
+        t[i].i0 = plan.pool[i].i0;
+        t[i].cnt = plan.pool[i].cnt;
+        for (int m = 0; m < GMAXC; ++m) {
+          t[i].w[m] = (float)plan.pool[i].w[m];
+          t[i].off[m] = (float)plan.pool[i].off[m];
+        }
+      }
+      D.gtab = up(t.data(), sizeof(GTab<float>) * ne);
+    } else {
+      std::vector<GTab<double>> t(ne);
+      for (size_t i = 0; i < plan.pool.size(); ++i) {
+        t[i].i0 = plan.pool[i].i0;
+        t[i].cnt = plan.pool[i].cnt;
+        for (int m = 0; m < GMAXC; ++m) {
+          t[i].w[m] = plan.pool[i].w[m];
+          t[i].off[m] = plan.pool[i].off[m];
+        }
+      }
+      D.gtab = up(t.data(), sizeof(GTab<double>) * ne);
+    }
+  }
+  if (getenv("DSP_DEBUG"))
+    fprintf(stderr, "dsp_create: %zu guard resampling items, %zu table entries\n", gitems.size(), plan.pool.size());
   D.boxes = (const GBox*)up(boxes.data(), sizeof(GBox) * std::max<size_t>(1, boxes.size()));
   D.brk = (Bracket*)A(sizeof(Bracket) * std::max<size_t>(1, boxes.size()));
   {
