@@ -37,7 +37,7 @@ struct GBox {
 // of staged source values
 constexpr int GMAXT = 72;
 constexpr int GMAXC = 4;
-constexpr int GSTAGE_BYTES = 24576;
+constexpr int GSTAGE_BYTES = 16384;
 
 // Per-axis overlap table entry of one target index of a resampled box: the
 // first overlapped source index, the number of overlapped indices, their

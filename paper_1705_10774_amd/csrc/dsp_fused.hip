@@ -277,11 +277,16 @@ __device__ __forceinline__ void tlerp_batched(const T* slots, const Bracket& br,
   }
 }
 
+// Limited slope of a staged source cell along one axis: the minmod of the
+// two one-sided differences when both neighbours exist, the one-sided
+// difference at the source's edge, 0 for a single cell.  Branch-free: a
+// missing neighbour is read as the cell itself (vm or vp = v0), so its
+// difference is exactly 0 and a + b is the other one.
 template <class T>
-__device__ __forceinline__ T minmod_slope(T vm, T v0, T vp) {
+__device__ __forceinline__ T limited_slope(T vm, T v0, T vp, bool both) {
   const T a = v0 - vm, b = vp - v0;
-  if (a * b <= T(0)) return T(0);
-  return (fabs(a) < fabs(b)) ? a : b;
+  const T mm = (a * b <= T(0)) ? T(0) : ((fabs(a) < fabs(b)) ? a : b);
+  return both ? mm : a + b;
 }
 
 // q = r / d for 0 <= r < 2^22 and 1 <= d < 2^11 without an integer division:
@@ -420,14 +425,14 @@ __device__ void gfill_item(const DevSet& S, GfillSmem<T>& sm, const T* __restric
             const int ii = X.i0 + a;
             const T wx = X.w[a], ox = X.off[a];
             const int o = rowb + ii;
-            const T c0 = st[o];
             const bool xm = ii - 1 >= 0, xp = ii + 1 <= nq - 1;
-            const T gx = (xm && xp) ? minmod_slope(st[o - 1], c0, st[o + 1])
-                         : xp ? st[o + 1] - c0 : (xm ? c0 - st[o - 1] : T(0));
-            const T gy = (ym && yp) ? minmod_slope(st[o - sx], c0, st[o + sx])
-                         : yp ? st[o + sx] - c0 : (ym ? c0 - st[o - sx] : T(0));
-            const T gz = (zm && zp) ? minmod_slope(st[o - sxy], c0, st[o + sxy])
-                         : zp ? st[o + sxy] - c0 : (zm ? c0 - st[o - sxy] : T(0));
+            const T c0 = st[o];
+            const T xl = st[o - (xm ? 1 : 0)], xr = st[o + (xp ? 1 : 0)];
+            const T yl = st[o - (ym ? sx : 0)], yr = st[o + (yp ? sx : 0)];
+            const T zl = st[o - (zm ? sxy : 0)], zr = st[o + (zp ? sxy : 0)];
+            const T gx = limited_slope(xl, c0, xr, xm && xp);
+            const T gy = limited_slope(yl, c0, yr, ym && yp);
+            const T gz = limited_slope(zl, c0, zr, zm && zp);
             acc = acc + (wx * wyz) * (((c0 + ox * gx) + oy * gy) + oz * gz);
           }
         }
@@ -461,10 +466,10 @@ __device__ void gfill_item(const DevSet& S, GfillSmem<T>& sm, const T* __restric
             const int f = F.i0 + side;
             const int o = (f - rn) * sn + (u - ru) * su + (w - rw) * sw;
             const T c0 = st[o];
-            const T gu = (um && up) ? minmod_slope(st[o - su], c0, st[o + su])
-                         : up ? st[o + su] - c0 : (um ? c0 - st[o - su] : T(0));
-            const T gw = (wm && wp) ? minmod_slope(st[o - sw], c0, st[o + sw])
-                         : wp ? st[o + sw] - c0 : (wm ? c0 - st[o - sw] : T(0));
+            const T ul = st[o - (um ? su : 0)], ur = st[o + (up ? su : 0)];
+            const T wl = st[o - (wm ? sw : 0)], wr = st[o + (wp ? sw : 0)];
+            const T gu = limited_slope(ul, c0, ur, um && up);
+            const T gw = limited_slope(wl, c0, wr, wm && wp);
             lin2 = lin2 + F.w[side] * ((c0 + ou * gu) + ow * gw);
           }
           acc = acc + (wu * ww) * lin2;
