@@ -256,7 +256,11 @@ def main():
     pst = s.stats()
     s.close()
     plain_rate = pst[0] / (t1 - t0)
-    out["fp64_plain"] = {"value": plain_rate, "sample": "cfg2, t 0 -> 4 dt_base", "updates": pst[0]}
+    out["fp64_plain"] = {"value": plain_rate, "sample": "cfg2, t 0 -> 4 dt_base", "updates": pst[0],
+                         "note": "the plain method: the host picks one ready patch at a time and launches its "
+                                 "fill, Courant, step and publish kernels, synchronising for every dt; bound by "
+                                 "launch and round-trip latency, not by the kernels (slower than the CPU oracle "
+                                 "on 16 cores), so the speedup over it measures the batching, not kernel quality"}
     out["speedup_batched_fp32_vs_plain_fp64"] = {"cfg2": out["cfg2_fp32"]["value"] / plain_rate,
                                                  "cfg2_fp64_batched": out["fp64_batched"]["value"] / plain_rate}
     s = dsp.PatchSet.from_problem(pr2, dt_mode=I.DT_GLOBAL_QUANT, prec=I.F32)

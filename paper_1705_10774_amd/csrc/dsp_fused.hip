@@ -300,6 +300,16 @@ __device__ __forceinline__ int small_div(int r, int d, float inv) {
   return q;
 }
 
+// Quotient r / d of the index decoding: a compile-time patch size (FN > 0)
+// divides by constants, a run-time one through the reciprocal (small_div).
+template <int FN>
+__device__ __forceinline__ int qdiv(int r, int d, float inv) {
+  if constexpr (FN > 0)
+    return r / d;
+  else
+    return small_div(r, d, inv);
+}
+
 constexpr int GFILL_ROWS = 512;  // patch rows of the resampling grid (a row strides over the ready list)
 constexpr int GFILL_COLS = 32;   // workgroups per patch row (a column strides over the patch's items)
 
@@ -563,32 +573,54 @@ __device__ __forceinline__ T interior_sum(const DevSet& S, const PatchCtx<T>& c,
 // Padded coordinates of entry r of the two-layer guard shell around an n^3
 // interior (N = n + 4): the two full planes below, the rings of the n
 // interior planes, the two full planes above.
-__device__ __forceinline__ void shell_cell(int r, int n, int& i, int& j, int& k) {
+// Reciprocals of the shell's divisors (N = n + 4, N^2, the ring N^2 - n^2)
+struct ShellRcp {
+  float iN, iN2, iring;
+};
+__device__ __forceinline__ ShellRcp shell_rcp(int n) {
+  const int N = n + 4;
+  return {1.0f / (float)N, 1.0f / (float)(N * N), 1.0f / (float)(N * N - n * n)};
+}
+template <int FN>
+__device__ __forceinline__ void shell_cell(int r, int n, const ShellRcp& rc, int& i, int& j, int& k) {
   const int N = n + 4, N2 = N * N, ring = N2 - n * n;
   if (r < 2 * N2 || r >= 2 * N2 + n * ring) {
     const int q = r < 2 * N2 ? r : r - n * ring;  // planes -2, -1 | n, n + 1
-    k = q / N2 - 2 + (r < 2 * N2 ? 0 : n);
-    const int m = q % N2;
-    j = m / N - 2;
-    i = m % N - 2;
+    const int kq = qdiv<FN>(q, N2, rc.iN2);
+    k = kq - 2 + (r < 2 * N2 ? 0 : n);
+    const int m = q - kq * N2;
+    const int jq = qdiv<FN>(m, N, rc.iN);
+    j = jq - 2;
+    i = m - jq * N - 2;
     return;
   }
   const int q = r - 2 * N2;
-  k = q / ring;
-  int m = q % ring;
+  k = qdiv<FN>(q, ring, rc.iring);
+  int m = q - k * ring;
   if (m < 2 * N) {  // rows -2, -1
-    j = m / N - 2;
-    i = m % N - 2;
+    const int jq = qdiv<FN>(m, N, rc.iN);
+    j = jq - 2;
+    i = m - jq * N - 2;
   } else if (m < 2 * N + 4 * n) {  // rows 0 .. n-1: two cells on each side
     m -= 2 * N;
-    j = m / 4;
-    const int s = m % 4;
+    j = m >> 2;
+    const int s = m & 3;
     i = s < 2 ? s - 2 : n + s - 2;
   } else {  // rows n, n + 1
     m -= 2 * N + 4 * n;
-    j = n + m / N;
-    i = m % N - 2;
+    const int jq = qdiv<FN>(m, N, rc.iN);
+    j = n + jq;
+    i = m - jq * N - 2;
   }
+}
+
+// Interior cell cid of an n^3 patch (x fastest), rn = 1 / n
+template <int FN>
+__device__ __forceinline__ void interior_cell(int cid, int n, float rn, int& i, int& j, int& k) {
+  const int jk = qdiv<FN>(cid, n, rn);
+  i = cid - jk * n;
+  k = qdiv<FN>(jk, n, rn);
+  j = jk - k * n;
 }
 
 // largest value over the workgroup (red: one slot per wavefront)
@@ -625,13 +657,17 @@ __global__ __launch_bounds__(256) void k_courant(DevSet S, const int* __restrict
   const int n = c.n, N = n + 4;
   const int first = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
   T ms = T(0);
+  const float rn = 1.0f / (float)n;
+  const ShellRcp rc = shell_rcp(n);
   for (int cid = first; cid < n * n * n; cid += stride) {
-    const T v = interior_sum(S, c, cid % n, (cid / n) % n, cid / (n * n));
+    int i, j, k;
+    interior_cell<0>(cid, n, rn, i, j, k);
+    const T v = interior_sum(S, c, i, j, k);
     ms = v > ms ? v : ms;
   }
   for (int r = first; r < N * N * N - n * n * n; r += stride) {
     int i, j, k;
-    shell_cell(r, n, i, j, k);
+    shell_cell<0>(r, n, rc, i, j, k);
     T w[8], bxl, byl, bzl;
     load_cell(c, rt, i, j, k, T(S.gamma), T(0), w, bxl, byl, bzl);
     const T v = cell_sum(S, w);
@@ -655,16 +691,20 @@ __device__ __forceinline__ double fused_local_dt(const DevSet& S, const PatchCtx
   // number is monotonic, so this is the largest of the per-cell rates.
   const int n = FN ? FN : c.n, N = n + 4;
   T ms = T(0);
+  const float rn = 1.0f / (float)n;
+  const ShellRcp rc = shell_rcp(n);
 #pragma unroll 4
   for (int cid = tid; cid < n * n * n; cid += nthr) {
-    const T v = interior_sum(S, c, cid % n, (cid / n) % n, cid / (n * n));
+    int i, j, k;
+    interior_cell<FN>(cid, n, rn, i, j, k);
+    const T v = interior_sum(S, c, i, j, k);
     ms = v > ms ? v : ms;
   }
   const int nshell = N * N * N - n * n * n;
 #pragma unroll 2
   for (int r = tid; r < nshell; r += nthr) {
     int i, j, k;
-    shell_cell(r, n, i, j, k);
+    shell_cell<FN>(r, n, rc, i, j, k);
     T w[8], bxl, byl, bzl;
     load_cell<T, Exact<T>, FN>(c, rt, i, j, k, T(S.gamma), T(0), w, bxl, byl, bzl);
     const T v = cell_sum(S, w);
@@ -750,6 +790,14 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
   const int TX = x1 - x0, TY = y1 - y0;
   const int CX = TX + 4, CY = TY + 4, PX = TX + 2;
   const bool lastx = (x1 == n), lasty = (y1 == n), firstx = (x0 == 0), firsty = (y0 == 0);
+  // index decoding of the face and edge phases: with a compile-time patch
+  // size the divisors are constants; otherwise quotients through their
+  // single-precision reciprocals (small_div), uniform over the workgroup
+  auto uniform_rcp = [](int d) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(1.0f / (float)d)));
+  };
+  const float iTX = uniform_rcp(TX), iTX1 = uniform_rcp(TX + 1), iTX2 = uniform_rcp(TX + 2);
+  auto qd = [&](int r, int d, float inv) -> int { return qdiv<FN>(r, d, inv); };
   const int box0 = S.rbox_off[c.p * 108];
   const int nbox = S.rbox_off[c.p * 108 + 108] - box0;
   const int64_t V = S.slice_len[c.p];
@@ -903,7 +951,7 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
       int cix, cjx;  // cell (i, j) right/upper of the face
       if (d == 0) {
         e = m;
-        const int fl = e % (TX + 1), jr = e / (TX + 1);
+        const int jr = qd(e, TX + 1, iTX1), fl = e - jr * (TX + 1);
         pa = fl + jr * PX;
         pb = pa + 1;
         cix = x0 + fl;
@@ -913,7 +961,7 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
         bface = sm.bf[0][fa];
       } else {
         e = m - nxf;
-        const int ir = e % (TX + 2), gl = e / (TX + 2);
+        const int gl = qd(e, TX + 2, iTX2), ir = e - gl * (TX + 2);
         pa = ir + gl * PX;
         pb = pa + PX;
         cix = x0 - 1 + ir;
@@ -980,7 +1028,8 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
       const int ney = (z >= 0) ? (TX + 1) * TY : 0;
       for (int m = tid; m < nez + nex + ney; m += NTHR) {
         if (m < nez) {  // E_z in plane z at (x-face f, y-face g)
-          const int f = x0 + m % (TX + 1), g = y0 + m / (TX + 1);
+          const int mq = qd(m, TX + 1, iTX1);
+          const int f = x0 + (m - mq * (TX + 1)), g = y0 + mq;
           const T A = -sm.a.f.fx[6][XF(f, g)], B = -sm.a.f.fx[6][XF(f, g - 1)];
           const T C = sm.a.f.fy[5][YF(f, g)], D = sm.a.f.fy[5][YF(f - 1, g)];
           const T v = edge(A, B, C, D, sm.a.f.fx[5][XF(f, g)], sm.a.f.fx[5][XF(f, g - 1)],
@@ -989,7 +1038,8 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
           sm.b.e.ez[m] = v;
         } else if (m < nez + nex) {  // E_x at z-face z, (x-cell i, y-face g)
           const int e = m - nez;
-          const int i = x0 + e % TX, g = y0 + e / TX;
+          const int eq = qd(e, TX, iTX);
+          const int i = x0 + (e - eq * TX), g = y0 + eq;
           const T A = -sm.a.f.fy[7][YF(i, g)], B = -sm.py[1][YF(i, g)];
           const T C = sm.fz[2][P(i, g)], D = sm.fz[2][P(i, g - 1)];
           const T v = edge(A, B, C, D, sm.a.f.fy[6][YF(i, g)], sm.py[0][YF(i, g)], sm.fz[0][P(i, g)],
@@ -998,7 +1048,8 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
           sm.b.e.ex[e] = v;
         } else {  // E_y at z-face z, (x-face f, y-cell j)
           const int e = m - nez - nex;
-          const int f = x0 + e % (TX + 1), j = y0 + e / (TX + 1);
+          const int eq = qd(e, TX + 1, iTX1);
+          const int f = x0 + (e - eq * (TX + 1)), j = y0 + eq;
           const T A = -sm.fz[1][P(f, j)], B = -sm.fz[1][P(f - 1, j)];
           const T C = sm.a.f.fx[7][XF(f, j)], D = sm.px[1][XF(f, j)];
           const T v = edge(A, B, C, D, sm.fz[0][P(f, j)], sm.fz[0][P(f - 1, j)], sm.a.f.fx[5][XF(f, j)],
@@ -1142,6 +1193,14 @@ __device__ __forceinline__ void step2_tile(const DevSet& S, Step2Smem<T>& sm, T*
   const int TX = x1 - x0, TY = y1 - y0;
   const int CX = TX + 4, CY = TY + 4, PX = TX + 2, PY = TY + 2;
   const bool lastx = (x1 == n), lasty = (y1 == n), firstx = (x0 == 0), firsty = (y0 == 0);
+  // index decoding of the face and edge phases: with a compile-time patch
+  // size the divisors are constants; otherwise quotients through their
+  // single-precision reciprocals (small_div), uniform over the workgroup
+  auto uniform_rcp = [](int d) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(1.0f / (float)d)));
+  };
+  const float iTX = uniform_rcp(TX), iTX1 = uniform_rcp(TX + 1), iTX2 = uniform_rcp(TX + 2), iPX = uniform_rcp(PX);
+  auto qd = [&](int r, int d, float inv) -> int { return qdiv<FN>(r, d, inv); };
   const int box0 = S.rbox_off[c.p * 108];
   const int nbox = S.rbox_off[c.p * 108 + 108] - box0;
   const int64_t V = S.slice_len[c.p];
@@ -1291,14 +1350,14 @@ __device__ __forceinline__ void step2_tile(const DevSet& S, Step2Smem<T>& sm, T*
         T bface;
         if (d == 0) {
           e = m;
-          const int fl = e % (TX + 1), jr = e / (TX + 1);
+          const int jr = qd(e, TX + 1, iTX1), fl = e - jr * (TX + 1);
           pa = fl + jr * PX;
           pb = pa + 1;
           cix = x0 + fl;
           cjx = y0 - 1 + jr;
         } else {
           e = m - nxf;
-          const int ir = e % (TX + 2), gl = e / (TX + 2);
+          const int gl = qd(e, TX + 2, iTX2), ir = e - gl * (TX + 2);
           pa = ir + gl * PX;
           pb = pa + PX;
           cix = x0 - 1 + ir;
@@ -1343,7 +1402,7 @@ __device__ __forceinline__ void step2_tile(const DevSet& S, Step2Smem<T>& sm, T*
         F[5 + t2][e] = f[6];
       } else {
         const int q = m - nxf - nyf;  // predictor cell of the face's upper cell
-        const int qa = q % PX, qb = q / PX;
+        const int qb = qd(q, PX, iPX), qa = q - qb * PX;
         const int cix = x0 - 1 + qa, cjx = y0 - 1 + qb;
         const int cq = (qa + 1) + (qb + 1) * CX;
 #pragma unroll
@@ -1421,7 +1480,8 @@ __device__ __forceinline__ void step2_tile(const DevSet& S, Step2Smem<T>& sm, T*
       const int ney = (z >= 0) ? (TX + 1) * TY : 0;
       for (int m = lane; m < nez + nex + ney; m += NTHR2) {
         if (m < nez) {  // E_z in plane z at (x-face f, y-face g)
-          const int f = x0 + m % (TX + 1), g = y0 + m / (TX + 1);
+          const int mq = qd(m, TX + 1, iTX1);
+          const int f = x0 + (m - mq * (TX + 1)), g = y0 + mq;
           const T A = -sm.fx[6][XF(f, g)], B = -sm.fx[6][XF(f, g - 1)];
           const T C = sm.fy[5][YF(f, g)], D = sm.fy[5][YF(f - 1, g)];
           sm.b.e.ez[m] = edge(A, B, C, D, sm.fx[5][XF(f, g)], sm.fx[5][XF(f, g - 1)], sm.fy[6][YF(f, g)],
@@ -1429,7 +1489,8 @@ __device__ __forceinline__ void step2_tile(const DevSet& S, Step2Smem<T>& sm, T*
                               sm.ecc[pz][2][P(f - 1, g)], sm.ecc[pz][2][P(f, g)]);
         } else if (m < nez + nex) {  // E_x at z-face z, (x-cell i, y-face g)
           const int e = m - nez;
-          const int i = x0 + e % TX, g = y0 + e / TX;
+          const int eq = qd(e, TX, iTX);
+          const int i = x0 + (e - eq * TX), g = y0 + eq;
           const T A = -sm.fy[7][YF(i, g)], B = -sm.py[1][YF(i, g)];
           const T C = sm.fz[6][P(i, g)], D = sm.fz[6][P(i, g - 1)];
           sm.b.e.ex[e] = edge(A, B, C, D, sm.fy[6][YF(i, g)], sm.py[0][YF(i, g)], sm.fz[7][P(i, g)],
@@ -1437,7 +1498,8 @@ __device__ __forceinline__ void step2_tile(const DevSet& S, Step2Smem<T>& sm, T*
                               sm.ecc[pz][0][P(i, g - 1)], sm.ecc[pz][0][P(i, g)]);
         } else {  // E_y at z-face z, (x-face f, y-cell j)
           const int e = m - nez - nex;
-          const int f = x0 + e % (TX + 1), j = y0 + e / (TX + 1);
+          const int eq = qd(e, TX + 1, iTX1);
+          const int f = x0 + (e - eq * (TX + 1)), j = y0 + eq;
           const T A = -sm.fz[5][P(f, j)], B = -sm.fz[5][P(f - 1, j)];
           const T C = sm.fx[7][XF(f, j)], D = sm.px[1][XF(f, j)];
           sm.b.e.ey[e] = edge(A, B, C, D, sm.fz[7][P(f, j)], sm.fz[7][P(f - 1, j)], sm.fx[5][XF(f, j)],

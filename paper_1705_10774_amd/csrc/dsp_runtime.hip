@@ -922,7 +922,7 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
   D.torder = c.torder;
   auto up = [&](const void* h, size_t bytes) -> void* {
     void* d = A(bytes);
-    if (d && bytes) (void)hipMemcpy(d, h, bytes, hipMemcpyHostToDevice);
+    if (d && bytes && h) (void)hipMemcpy(d, h, bytes, hipMemcpyHostToDevice);  // empty tables: nothing to copy
     return d;
   };
   D.n = (const int*)up(hn.data(), sizeof(int) * npatch);
@@ -946,7 +946,8 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
   D.nb_idx = (const int*)up(nb_idx.data(), sizeof(int) * std::max<size_t>(1, nb_idx.size()));
   D.rbox_off = (const int*)up(rbox_off.data(), sizeof(int) * rbox_off.size());
   D.gitem_off = (const int*)up(gitem_off.data(), sizeof(int) * gitem_off.size());
-  D.gitems = (const GItem*)up(gitems.data(), sizeof(GItem) * std::max<size_t>(1, gitems.size()));
+  if (gitems.empty()) gitems.resize(1);  // a placeholder: no patch lists an item
+  D.gitems = (const GItem*)up(gitems.data(), sizeof(GItem) * gitems.size());
   {
     // the table pool in the set's precision
     const size_t ne = std::max<size_t>(1, plan.pool.size());

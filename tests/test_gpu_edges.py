@@ -44,3 +44,17 @@ def test_advance_to_current_time_is_a_no_op():
     st2, kh2 = s.read_schedule()
     assert np.array_equal(st1, st2) and np.array_equal(kh1, kh2)
     s.close()
+
+
+@pytest.mark.parametrize("npd", [1, 2], ids=["single-patch", "equal-patches"])
+def test_create_leaves_no_hip_error(npd):
+    """Creating a set with no resampling plan and (one patch) no neighbour
+    list leaves no pending HIP error for the caller's next call."""
+    import torch
+    from paper_1705_10774_amd import dsp
+    dsp.load()
+    s = dsp.PatchSet.from_problem(turb(npd, 8))
+    x = torch.ones(4, device="cuda") * 2.0
+    torch.cuda.synchronize()
+    assert float(x.sum()) == 8.0
+    s.close()

@@ -130,7 +130,7 @@ def test_uniform_state_bitwise(prec, mode):
     t = 4.0 / 64 if mode == I.DT_LOCAL else 0.1
     U, steps, kh, st = gpu_run(pr, t_end=t)
     U0 = pr.U0 if prec == I.F64 else pr.U0.astype(np.float32).astype(np.float64)
-    assert st[13] >= 8
+    assert steps.min() >= 4  # (rounds are not a measure here: the queue runs them in one launch)
     assert np.array_equal(U, U0)
 
 
