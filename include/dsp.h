@@ -236,6 +236,20 @@ enum { DSP_DISPATCH_ROUNDS = 0, DSP_DISPATCH_QUEUE = 1 };
 int dsp_set_dispatch(dsp_set* set, int32_t mode, int32_t workers);
 /* Current mode, whether the queue mode is available, and its workgroups. */
 int dsp_get_dispatch(const dsp_set* set, int32_t* mode, int32_t* queue_available, int32_t* workers);
+
+/* Output cadence (Sec. 3E: each task writes its output when its time passes
+ * its next output time, then advances that time by the interval).  From this
+ * call on, every patch update whose new time t is a multiple of out_dt copies
+ * the patch's new slice into frame (t / out_dt - 1) mod nframes of frames_dev:
+ * a device array (current device, caller-owned, kept alive while the cadence
+ * is set) of nframes frames, each the whole set in the host layout and the
+ * set's precision (total values as for dsp_read_state).  Each patch writes its
+ * own part of a frame when it reaches that time, independently of the others
+ * (there is no barrier).  out_dt must be a positive multiple of dt_base: with
+ * quantised steps every patch then reaches each output time exactly.  Needs
+ * the LOCAL or GLOBAL_QUANT mode (DSP_EINVAL otherwise).  frames_dev null or
+ * nframes <= 0 turns the cadence off. */
+int dsp_set_output(dsp_set* set, double out_dt, void* frames_dev, int32_t nframes);
 /* Autotuner: times LOCAL advances of t_probe (a multiple of dt_base) from the
  * set's current state with each candidate dispatch (rounds; the queue with
  * all, three quarters and half of the workgroups, when available), restores

@@ -123,7 +123,33 @@ struct DevSet {
   // non-empty rounds
   const int* live;
   int* rounds;
+  // output cadence (Sec. 3E): a patch whose new time is a multiple of
+  // out_ticks copies its new slice into frame (ticks / out_ticks - 1) mod
+  // out_nframes of out_frames (host layout, host_off[p] values into the
+  // frame, out_words 32-bit words per value); out_frames null: off
+  void* out_frames;
+  int64_t out_ticks;
+  int out_nframes;
+  int out_words;
+  int64_t out_frame_values;
+  const int64_t* host_off;
 };
+
+// Frame of patch p's output at its new time ticks, or -1: no output then.
+__device__ __forceinline__ int output_frame(const DevSet& S, int64_t ticks) {
+  if (!S.out_frames || ticks <= 0 || ticks % S.out_ticks != 0) return -1;
+  return (int)((ticks / S.out_ticks - 1) % S.out_nframes);
+}
+
+// Copy of the current slice of patch p into output frame f by the threads
+// [tid, nthr) of a group.
+__device__ inline void output_copy(const DevSet& S, int p, int f, const void* slots, int tid, int nthr) {
+  const int64_t w = S.out_words;
+  const int64_t nw = S.slice_len[p] * w;
+  const uint32_t* src = (const uint32_t*)slots + (S.slot_off[p] + (int64_t)S.cur[p] * S.slice_len[p]) * w;
+  uint32_t* dst = (uint32_t*)S.out_frames + ((int64_t)f * S.out_frame_values + S.host_off[p]) * w;
+  for (int64_t e = tid; e < nw; e += nthr) dst[e] = src[e];
+}
 
 // entries of a round launch: the host's count, or the device-counted length
 // of the ready list when the rounds run without host round trips
@@ -223,7 +249,8 @@ void launch_adjoint_step(const DevSet& S, const int* list, int count, int nmax, 
 void launch_brackets(const DevSet& S, const int* list, int count, hipStream_t s);
 void launch_dt(const DevSet& S, const int* list, int count, const StepPtr& st, const double* smax, hipStream_t s,
                int dt_kind, double t_end, int clip);
-void launch_publish(const DevSet& S, const int* list, int count, const StepPtr& st, hipStream_t s);
+void launch_publish(const DevSet& S, const int* list, int count, const StepPtr& st, hipStream_t s,
+                    const void* slots = nullptr);
 void launch_reset_times(const DevSet& S, unsigned long long* cnt, hipStream_t s);
 void launch_scan(const DevSet& S, int64_t T_end, int* list, int* counters, hipStream_t s, int* clear = nullptr);
 template <class T> void launch_stats(const DevSet& S, const T* slots, double* out, hipStream_t s);

@@ -1767,6 +1767,18 @@ __global__ __launch_bounds__(NTHR2) void k_persist(DevSet S, QueueState Q, float
     // ---- Courant level and the fused step (record entry w)
     step2_tile<float, FN>(S, sm.step, slots, pad, pad_stride, st, w, p, 0, 1, 1);
     __syncthreads();
+    // ---- output cadence: the new slice into its frame before it is published
+    if (S.out_frames) {
+      const int f = output_frame(S, S.ticks[p] + st.dtk[w]);
+      if (f >= 0) {
+        const int64_t V = S.slice_len[p];
+        const int64_t w4 = S.out_words;
+        const uint32_t* src = (const uint32_t*)slots + (S.slot_off[p] + (int64_t)((S.cur[p] + 1) % S.nslots) * V) * w4;
+        uint32_t* dst = (uint32_t*)S.out_frames + ((int64_t)f * S.out_frame_values + S.host_off[p]) * w4;
+        for (int64_t e = tid; e < V * w4; e += NTHR2) dst[e] = src[e];
+      }
+      __syncthreads();  // every wave has read cur before thread 0 advances it
+    }
     // ---- publish, give the patch back, count it when it has arrived
     if (tid == 0) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // the new slice and the step record

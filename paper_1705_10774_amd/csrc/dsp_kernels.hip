@@ -654,6 +654,19 @@ __global__ void k_publish(DevSet S, const int* __restrict__ list, int count, Ste
   publish_patch(S, list[b], st, b);
 }
 
+// k_output: the output cadence (Sec. 3E).  A listed patch whose new time is
+// a multiple of the output interval copies its new slice into the frame of
+// that time (after k_publish, so the slice is current).
+
+__global__ void k_output(DevSet S, const int* __restrict__ list, int count, const void* __restrict__ slots) {
+  const int b = blockIdx.y;
+  if (b >= live_count(S, count)) return;
+  const int p = list[b];
+  const int f = output_frame(S, S.ticks[p]);
+  if (f < 0) return;
+  output_copy(S, p, f, slots, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
 // ---------------------------------------------------------------------------
 // k_scan: readiness of every patch (Eq. (1), with the grace) and the ready list.
 
@@ -888,8 +901,11 @@ void launch_reset_times(const DevSet& S, unsigned long long* cnt, hipStream_t s)
   hipLaunchKernelGGL(k_reset_times, dim3((S.npatch + 255) / 256), dim3(256), 0, s, S, cnt);
 }
 
-void launch_publish(const DevSet& S, const int* list, int count, const StepPtr& st, hipStream_t s) {
+void launch_publish(const DevSet& S, const int* list, int count, const StepPtr& st, hipStream_t s,
+                    const void* slots) {
   hipLaunchKernelGGL(k_publish, dim3((count + 255) / 256), dim3(256), 0, s, S, list, count, st);
+  if (S.out_frames && slots)
+    hipLaunchKernelGGL(k_output, dim3(64, count), dim3(256), 0, s, S, list, count, slots);
 }
 
 void launch_scan(const DevSet& S, int64_t T_end, int* list, int* counters, hipStream_t s, int* clear) {

@@ -884,6 +884,8 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
   s->st.dt = (double*)A(sizeof(double) * npatch);
   s->d_hostbuf = (double*)A(sizeof(double) * (size_t)s->total_values);
   s->d_host_off = (int64_t*)A(sizeof(int64_t) * (npatch + 1));
+  s->D.host_off = s->d_host_off;
+  s->D.out_words = (int)(tsz / 4);
   s->d_stats = (double*)A(sizeof(double) * 9 * npatch);
   if (s->alloc_failed) return fail(DSP_ENOMEM, "device allocation failed: " + s->alloc_msg);
 
@@ -1183,7 +1185,7 @@ static int run_global(dsp_set* s, double t_end, int64_t T, int max_steps) {
       }
     }
     s->update_batch(0, s->np, 1, t_end, max_steps < 0 ? 1 : 0, s->d_list);
-    launch_publish(s->D, s->d_list, s->np, s->st, s->stream);
+    launch_publish(s->D, s->d_list, s->np, s->st, s->stream, s->slots);
     s->rounds++;
     nstep++;
     (void)hipMemsetAsync(s->d_counters, 0, sizeof(int) * 2, s->stream);
@@ -1215,7 +1217,7 @@ static int run_local_device(dsp_set* s, double t_end, int64_t T, int64_t& rounds
       s->D.live = cur;
       launch_scan(s->D, T, s->d_list, cur, s->stream, pair[(r + 1) & 1]);
       s->update_batch(0, s->np, 0, t_end, 0, s->d_list);
-      launch_publish(s->D, s->d_list, s->np, s->st, s->stream);
+      launch_publish(s->D, s->d_list, s->np, s->st, s->stream, s->slots);
     }
     int cnt[2];
     e = read_err(s, cnt, pair[(K - 1) & 1]);
@@ -1309,7 +1311,7 @@ int dsp_advance_to(dsp_set* s, double t_end) {
         }
         for (int off = 0; off < cnt[0]; off += s->B)
           s->update_batch(off, std::min(s->B, cnt[0] - off), 0, t_end, 0, s->d_list);
-        launch_publish(s->D, s->d_list, cnt[0], s->st, s->stream);
+        launch_publish(s->D, s->d_list, cnt[0], s->st, s->stream, s->slots);
         s->rounds++;
       }
     }
@@ -1341,6 +1343,37 @@ int dsp_set_dispatch(dsp_set* s, int32_t mode, int32_t workers) {
     }
   }
   s->dispatch = mode;
+  return 0;
+}
+
+// The captured graph of the persistent dispatcher holds the set's description
+// (kernel arguments): dropped when that changes, captured again on use.
+static void drop_graph(dsp_set* s) {
+  if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+  if (s->graph) (void)hipGraphDestroy(s->graph);
+  s->gexec = nullptr;
+  s->graph = nullptr;
+}
+
+int dsp_set_output(dsp_set* s, double out_dt, void* frames_dev, int32_t nframes) {
+  if (!s) return fail(DSP_EINVAL, "null handle");
+  DevSet& D = s->D;
+  if (!frames_dev || nframes <= 0) {
+    D.out_frames = nullptr;
+  } else {
+    if (s->cfg.dt_mode != DSP_DT_LOCAL && s->cfg.dt_mode != DSP_DT_GLOBAL_QUANT)
+      return fail(DSP_EINVAL, "an output cadence needs the quantised time steps (LOCAL or GLOBAL_QUANT)");
+    // every patch lands on each multiple of dt_base (its step never crosses
+    // a multiple of its own alignment), so a multiple of dt_base is met exactly
+    int64_t m = 0;
+    if (!(out_dt > 0.0) || !tolat(out_dt / s->cfg.dt_base, 1, m) || m < 1)
+      return fail(DSP_EINVAL, "the output interval must be a positive multiple of dt_base");
+    D.out_frames = frames_dev;
+    D.out_ticks = m << s->cfg.kmax;
+    D.out_nframes = nframes;
+    D.out_frame_values = s->total_values;
+  }
+  drop_graph(s);
   return 0;
 }
 
@@ -1425,6 +1458,12 @@ int dsp_autotune(dsp_set* s, double t_probe, const char* cache_path, double* ms_
   int e = hipck(hipMemcpy(tc.data(), s->D.tcur, sizeof(double) * s->np, hipMemcpyDeviceToHost), "time");
   if (e) return e;
   const double t0 = *std::min_element(tc.begin(), tc.end());
+  // no output from the probe runs
+  void* const out0 = s->D.out_frames;
+  if (out0) {
+    s->D.out_frames = nullptr;
+    drop_graph(s);
+  }
   // save the state
   std::vector<std::pair<void*, size_t>> items = mutable_state(s);
   std::vector<void*> saved(items.size(), nullptr);
@@ -1462,6 +1501,10 @@ int dsp_autotune(dsp_set* s, double t_probe, const char* cache_path, double* ms_
     if (saved[m]) (void)hipFree(saved[m]);
   }
   s->rounds = rounds0;
+  if (out0) {
+    s->D.out_frames = out0;
+    drop_graph(s);
+  }
   if (e) {
     (void)dsp_set_dispatch(s, mode0, workers0);
     return e;
@@ -1532,7 +1575,7 @@ int dsp_advance_to_plain(dsp_set* s, double t_end) {
     e = hipck(hipMemcpyAsync(s->d_single, &best, sizeof(int), hipMemcpyHostToDevice, s->stream), "list");
     if (e) break;
     s->update_batch(0, 1, 0, t_end, 0, s->d_single);
-    launch_publish(s->D, s->d_single, 1, s->st, s->stream);
+    launch_publish(s->D, s->d_single, 1, s->st, s->stream, s->slots);
     s->rounds++;
     int64_t dtk = 0;
     e = hipck(hipMemcpyAsync(&dtk, s->st.dtk, sizeof(int64_t), hipMemcpyDeviceToHost, s->stream), "dt");

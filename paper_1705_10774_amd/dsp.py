@@ -26,7 +26,8 @@ DSP_DT_LOCAL, DSP_DT_GLOBAL_QUANT, DSP_DT_GLOBAL_EXACT, DSP_DT_FIXED = 0, 1, 2, 
 EXPORTS = ["dsp_create", "dsp_init", "dsp_init_device", "dsp_advance_to", "dsp_advance_to_plain", "dsp_read_state",
            "dsp_read_schedule", "dsp_stats", "dsp_kernel_time", "dsp_kernel_stats", "dsp_fixed_steps_fwd",
            "dsp_fixed_steps_adj", "dsp_save_snapshot", "dsp_load_snapshot", "dsp_hlld_faces",
-           "dsp_hlld_faces_noalloc", "dsp_set_dispatch", "dsp_get_dispatch", "dsp_autotune", "dsp_destroy",
+           "dsp_hlld_faces_noalloc", "dsp_set_dispatch", "dsp_get_dispatch", "dsp_autotune", "dsp_set_output",
+           "dsp_destroy",
            "dsp_last_error"]
 DSP_DISPATCH_ROUNDS, DSP_DISPATCH_QUEUE = 0, 1
 
@@ -89,6 +90,7 @@ def load():
     L.dsp_set_dispatch.argtypes = [vp, C.c_int32, C.c_int32]
     L.dsp_get_dispatch.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.dsp_autotune.argtypes = [vp, C.c_double, C.c_char_p, dp]
+    L.dsp_set_output.argtypes = [vp, C.c_double, vp, C.c_int32]
     L.dsp_destroy.argtypes = [vp]
     L.dsp_destroy.restype = None
     L.dsp_last_error.restype = C.c_char_p
@@ -254,6 +256,10 @@ def dsp_autotune(h, t_probe, cache_path=None):
     return out
 
 
+def dsp_set_output(h, out_dt, frames_ptr, nframes):
+    _check(load().dsp_set_output(h, float(out_dt), frames_ptr, int(nframes)))
+
+
 def dsp_destroy(h):
     if h:
         load().dsp_destroy(h)
@@ -324,6 +330,20 @@ class PatchSet:
 
     def load(self, path):
         dsp_load_snapshot(self.h, path)
+
+    def set_output(self, out_dt, nframes):
+        """Output cadence: returns the device tensor [nframes, values] (the
+        set's precision, host layout) that each patch fills with its slice at
+        every multiple of out_dt; nframes = 0 turns it off."""
+        import torch
+        if nframes <= 0:
+            dsp_set_output(self.h, out_dt, None, 0)
+            self._frames = None
+            return None
+        frames = torch.full((nframes, self.nvals), float("nan"), dtype=self._dtype(), device="cuda")
+        dsp_set_output(self.h, out_dt, frames.data_ptr(), nframes)
+        self._frames = frames  # kept alive while the cadence is set
+        return frames
 
     # ---- fixed-dt steps and their adjoint (device tensors in the host layout)
 
