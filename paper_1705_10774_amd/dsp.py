@@ -143,11 +143,40 @@ def _torch_stream():
 
 # --- functions with the C names ------------------------------------------------
 
-def dsp_create(cfg, patches, stream=None):
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class dsp_allocator(C.Structure):
+    _fields_ = [("ctx", C.c_void_p), ("alloc", _ALLOC_FN), ("free", _FREE_FN)]
+
+
+def torch_allocator():
+    """A dsp_allocator over torch's caching allocator (current device and
+    stream).  The returned object must outlive every set created with it."""
+    import torch
+
+    def alloc(ctx, nbytes):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes))
+        except RuntimeError:  # out of memory: dsp_create reports DSP_ENOMEM
+            return None
+
+    def free(ctx, ptr):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    a, f = _ALLOC_FN(alloc), _FREE_FN(free)
+    st = dsp_allocator(None, a, f)
+    st._keep = (a, f)  # the callbacks live as long as the structure
+    return st
+
+
+def dsp_create(cfg, patches, stream=None, allocator=None):
     c = make_config(cfg)
     d = make_descs(patches)
     h = C.c_void_p()
-    _check(load().dsp_create(C.byref(c), d, len(patches), stream, None, C.byref(h)))
+    _check(load().dsp_create(C.byref(c), d, len(patches), stream,
+                             C.byref(allocator) if allocator is not None else None, C.byref(h)))
     return h
 
 
@@ -268,17 +297,20 @@ def dsp_destroy(h):
 class PatchSet:
     """A patch set on the GPU (owns a dsp_set handle)."""
 
-    def __init__(self, cfg, patches, stream="torch"):
+    def __init__(self, cfg, patches, stream="torch", allocator=None):
+        """allocator: None (hipMalloc), or "torch" (torch's caching allocator,
+        so the set's device memory shows in torch's memory statistics)."""
         self.cfg, self.patches = cfg, list(patches)
         self.nvals = int(sum(5 * p.n ** 3 + 3 * p.n * p.n * (p.n + 1) for p in self.patches))
         s = _torch_stream() if stream == "torch" else stream
-        self.h = dsp_create(cfg, self.patches, s)
+        self._alloc = torch_allocator() if allocator == "torch" else allocator
+        self.h = dsp_create(cfg, self.patches, s, self._alloc)
 
     @classmethod
-    def from_problem(cls, prob, **over):
+    def from_problem(cls, prob, allocator=None, **over):
         import dataclasses
         cfg = dataclasses.replace(prob.cfg, **over) if over else prob.cfg
-        s = cls(cfg, prob.patches)
+        s = cls(cfg, prob.patches, allocator=allocator)
         s.init(prob.U0)
         return s
 

@@ -494,7 +494,7 @@ def cfg4_smr(prec=F64, t_end=0.01, dt_base=None, levels=3, n=16):
 
 
 def cfg5_adjoint(prec=F64, npd=4, n=16, nsteps=32, dt=1.6e-3, seed_init=1005,
-                 seed_target=2005, B=(0.6, 0.4, 0.2), V=(0.3, 0.2, 0.1)):
+                 seed_target=2005, B=(0.6, 0.4, 0.2), V=(0.3, 0.2, 0.1), dp=True):
     """4^3 patches of 16^3; rho = 1, p = 0.6, uniform oblique B and uniform
     flow V; smooth perturbations of rho and v (1 <= |k| <= 3, max |.| = 1e-3);
     target density rho* = 1 + the same recipe with another seed; fixed dt.
@@ -502,7 +502,8 @@ def cfg5_adjoint(prec=F64, npd=4, n=16, nsteps=32, dt=1.6e-3, seed_init=1005,
     limit, the mean flow keeps every face mass flux away from zero, and the
     (fixed) pressure carries its own smooth perturbation so that no limited
     slope starts at exactly zero: the fixed-dt map is then smooth at the
-    initial state."""
+    initial state.  B = (1, 0, 0), V = 0, dp = False give the background
+    as specified (uniform p = 0.6, fluid at rest)."""
     patches = cartesian(npd, n)
 
     def smooth(seed, ncomp):
@@ -525,7 +526,7 @@ def cfg5_adjoint(prec=F64, npd=4, n=16, nsteps=32, dt=1.6e-3, seed_init=1005,
     target = smooth(seed_target, 1)[0]
     rho = [1.0 + pert[0][i] for i in range(len(patches))]
     vel = [[V[d] + pert[1 + d][i] for d in range(3)] for i in range(len(patches))]
-    pres = [0.6 * (1.0 + a) for a in smooth(3005, 1)[0]]
+    pres = [0.6 * (1.0 + a) for a in smooth(3005, 1)[0]] if dp else [np.full((q.n,) * 3, 0.6) for q in patches]
     U = assemble(patches, rho, vel, pres, _uniform_b(patches, B), 5.0 / 3.0)
     cfg = Config(dt_mode=DT_FIXED, dt_fixed=dt, prec=prec, kmax=30)
     return Problem("cfg5_adjoint", cfg, patches, U, nsteps * dt, nsteps=nsteps,

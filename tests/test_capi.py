@@ -30,12 +30,16 @@ def test_library_exports_every_symbol():
         assert hasattr(L, name), name
 
 
+STRUCTS = (("dsp_config", dsp.dsp_config), ("dsp_patch_desc", dsp.dsp_patch_desc),
+           ("dsp_allocator", dsp.dsp_allocator))
+
+
 def test_struct_layout_matches_header(tmp_path):
     """Size and every field offset of the binding's structures against the C
     compiler's layout of include/dsp.h."""
     import subprocess
     lines = []
-    for cname, ct in (("dsp_config", dsp.dsp_config), ("dsp_patch_desc", dsp.dsp_patch_desc)):
+    for cname, ct in STRUCTS:
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
         for f, _ in ct._fields_:
             lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
@@ -46,7 +50,7 @@ def test_struct_layout_matches_header(tmp_path):
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
     want = []
-    for cname, ct in (("dsp_config", dsp.dsp_config), ("dsp_patch_desc", dsp.dsp_patch_desc)):
+    for cname, ct in STRUCTS:
         want.append(f"{cname} size {C.sizeof(ct)}")
         for f, _ in ct._fields_:
             want.append(f"{cname} {f} {getattr(ct, f).offset}")

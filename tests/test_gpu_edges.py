@@ -58,3 +58,29 @@ def test_create_leaves_no_hip_error(npd):
     torch.cuda.synchronize()
     assert float(x.sum()) == 8.0
     s.close()
+
+
+def test_torch_caching_allocator():
+    """A set whose device memory comes from torch's caching allocator (the
+    allocator hook of dsp_create): its memory shows in torch's statistics
+    while it lives and goes back when it is closed, and it runs bit for bit
+    as a set on hipMalloc memory."""
+    import torch
+    from paper_1705_10774_amd import dsp
+    dsp.load()
+    pr = turb(2, 8)
+    T = 2 * pr.cfg.dt_base
+    torch.cuda.synchronize()
+    m0 = torch.cuda.memory_allocated()
+    s = dsp.PatchSet.from_problem(pr, allocator="torch")
+    assert torch.cuda.memory_allocated() - m0 >= 3 * s.nvals * 8  # the three FP64 ring slots at least
+    s.advance_to(T)
+    Ua = s.read_state()
+    s.close()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == m0
+    s = dsp.PatchSet.from_problem(pr)
+    s.advance_to(T)
+    Ub = s.read_state()
+    s.close()
+    assert np.array_equal(Ua, Ub)
