@@ -94,6 +94,8 @@ struct DevSet {
   int64_t* steps;
   uint64_t* khash;
   int8_t* klog;  // [npatch * klog_cap]
+  // readiness scan order: patch ids by decreasing n (ties by id)
+  const int* scan_order;
   // neighbours (Eq. (1)) and guard boxes
   const int* nb_off;
   const int* nb_idx;

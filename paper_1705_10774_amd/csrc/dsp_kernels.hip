@@ -672,14 +672,18 @@ __global__ void k_output(DevSet S, const int* __restrict__ list, int count, cons
 
 __global__ void k_scan(DevSet S, int64_t T_end, int* __restrict__ list, int* __restrict__ counters,
                        int* __restrict__ clear) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   // the other counter pair, which the next round's scan uses (the round
   // before this one has finished reading it)
-  if (clear && p == 0) {
+  if (clear && i == 0) {
     clear[0] = 0;
     clear[1] = 0;
   }
-  if (p >= S.npatch) return;
+  if (i >= S.npatch) return;
+  // patches in decreasing size: the ready list then starts with the longest
+  // updates, whose workgroups are dispatched first (the order of a round
+  // does not change its result)
+  const int p = S.scan_order[i];
   if (*S.err) return;  // an error stops the scheduling: later rounds find nothing to do
   if (S.frozen[p]) return;  // boundary patches never update
   const int64_t t = S.ticks[p];

@@ -944,6 +944,12 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
   D.steps = (int64_t*)A(sizeof(int64_t) * npatch);
   D.khash = (uint64_t*)A(sizeof(uint64_t) * npatch);
   D.klog = (int8_t*)A((size_t)npatch * s->klog_cap);
+  {
+    std::vector<int> order(npatch);
+    for (int p = 0; p < npatch; ++p) order[p] = p;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return s->P[a].n > s->P[b].n; });
+    D.scan_order = (const int*)up(order.data(), sizeof(int) * npatch);
+  }
   D.nb_off = (const int*)up(nb_off.data(), sizeof(int) * nb_off.size());
   D.nb_idx = (const int*)up(nb_idx.data(), sizeof(int) * std::max<size_t>(1, nb_idx.size()));
   D.rbox_off = (const int*)up(rbox_off.data(), sizeof(int) * rbox_off.size());
