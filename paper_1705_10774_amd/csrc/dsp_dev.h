@@ -125,6 +125,9 @@ struct DevSet {
   // non-empty rounds
   const int* live;
   int* rounds;
+  // largest ready list of a round (0: no limit); the round kernels are then
+  // launched for at most scan_cap entries
+  int scan_cap;
   // output cadence (Sec. 3E): a patch whose new time is a multiple of
   // out_ticks copies its new slice into frame (ticks / out_ticks - 1) mod
   // out_nframes of out_frames (host layout, host_off[p] values into the

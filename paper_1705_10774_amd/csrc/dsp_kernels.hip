@@ -726,6 +726,10 @@ __global__ void k_scan(DevSet S, int64_t T_end, int* __restrict__ list, int* __r
     }
   }
   const int slot = atomicAdd(counters, 1);
+  // a capped round takes the first scan_cap ready patches; the others stay
+  // ready for the next round (with g = 0 the order of the updates does not
+  // change the result)
+  if (S.scan_cap > 0 && slot >= S.scan_cap) return;
   list[slot] = p;
 }
 #endif  // DSP_TU_COMMON

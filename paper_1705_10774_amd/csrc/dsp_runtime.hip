@@ -1209,6 +1209,8 @@ static int run_global(dsp_set* s, double t_end, int64_t T, int max_steps) {
 // ready-list length that the scan writes on the device; the host reads the
 // counters and the error flags once per chunk.  Rounds queued after the last
 // patch reached t_end find an empty ready list and do nothing.
+constexpr int kRoundCap = 1024;
+
 static int run_local_device(dsp_set* s, double t_end, int64_t T, int64_t& rounds_done) {
   const int K = 16;
   // two counter pairs, used by alternate rounds: each scan clears the pair
@@ -1217,13 +1219,22 @@ static int run_local_device(dsp_set* s, double t_end, int64_t T, int64_t& rounds
   int e = hipck(hipMemsetAsync(s->d_counters + 2, 0, sizeof(int) * 6, s->stream), "rounds");
   if (e) return e;
   s->D.rounds = s->d_counters + 2;
+  // Without a grace, a round takes at most kRoundCap ready patches: its
+  // kernels are then launched for that many entries, not for every patch of
+  // a large set (whose surplus workgroups would only exit).  With a grace
+  // the result depends on which patches share a round, so rounds stay whole.
+  const char* cap_env = getenv("DSP_ROUND_CAP");  // a smaller cap (tests of the deferral)
+  const int cap_max = cap_env ? std::max(1, atoi(cap_env)) : kRoundCap;
+  const int cap = (s->cfg.grace == 0.0 && s->np > cap_max) ? cap_max : 0;
+  const int count = cap ? cap : s->np;
+  s->D.scan_cap = cap;
   while (!e) {
     for (int r = 0; r < K; ++r) {  // K is even: every chunk starts on pair 0
       int* const cur = pair[r & 1];
       s->D.live = cur;
       launch_scan(s->D, T, s->d_list, cur, s->stream, pair[(r + 1) & 1]);
-      s->update_batch(0, s->np, 0, t_end, 0, s->d_list);
-      launch_publish(s->D, s->d_list, s->np, s->st, s->stream, s->slots);
+      s->update_batch(0, count, 0, t_end, 0, s->d_list);
+      launch_publish(s->D, s->d_list, count, s->st, s->stream, s->slots);
     }
     int cnt[2];
     e = read_err(s, cnt, pair[(K - 1) & 1]);
@@ -1233,6 +1244,7 @@ static int run_local_device(dsp_set* s, double t_end, int64_t T, int64_t& rounds
   }
   s->D.live = nullptr;
   s->D.rounds = nullptr;
+  s->D.scan_cap = 0;
   int r = 0;
   const int e2 = hipck(hipMemcpy(&r, s->d_counters + 2, sizeof(int), hipMemcpyDeviceToHost), "rounds");
   rounds_done = r;

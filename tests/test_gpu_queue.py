@@ -147,3 +147,26 @@ def test_autotune_restores_state_and_selects(tmp_path):
     assert np.all(ms2 == -1) and s.dispatch()[0] == mode
     s.close()
     print("autotune ms", ms, "chosen", mode, workers)
+
+
+@pytest.mark.parametrize("cap", [1, 5])
+def test_capped_rounds_equal_whole_rounds(cap, monkeypatch):
+    """Rounds that take at most `cap` ready patches (the rest wait for the
+    next round; large sets are capped this way) give the same bits as whole
+    rounds, in FP64 and with a resolution jump."""
+    dsp = _dsp()
+    outs = []
+    for env in (None, str(cap)):
+        if env is None:
+            monkeypatch.delenv("DSP_ROUND_CAP", raising=False)
+        else:
+            monkeypatch.setenv("DSP_ROUND_CAP", env)
+        for pr in (_spread(), I.uneven(npd=4, seed_sizes=1013, seed_rho=2013, prec=I.F64, box=0.25, name="m",
+                                       dt_base=2.0 ** -11)):
+            s = dsp.PatchSet.from_problem(pr, prec=I.F64)
+            s.advance_to(4 * pr.cfg.dt_base)
+            outs.append((s.read_state(), *s.read_schedule(), s.stats()[13]))
+            s.close()
+    for a, b in zip(outs[:2], outs[2:]):
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    assert outs[2][3] > outs[0][3]  # the capped run took more rounds
