@@ -192,32 +192,6 @@ __device__ T cross_value(const DevSet& S, const T* slots, const Bracket& br, int
   });
 }
 
-// Source index range [r0, r1] per axis that the resampling of the target
-// elements with lattice positions from Xlo to Xhi (component comp, target cell
-// size tdx) reads from patch q, slope neighbours included.
-__device__ inline void cross_source_range(const DevSet& S, int q, int comp, const int64_t* Xlo, const int64_t* Xhi,
-                                          int64_t tdx, int* r0, int* r1) {
-  const int n = S.n[q];
-  const int64_t sdx = S.dxl[q], len = S.len[q];
-  for (int d = 0; d < 3; ++d) {
-    int64_t A = (d == comp) ? Xlo[d] : Xlo[d] - tdx / 2;
-    int64_t B = (d == comp) ? Xhi[d] : Xhi[d] + tdx / 2;
-    A -= S.lo[3 * q + d];
-    B -= S.lo[3 * q + d];
-    A = A < 0 ? 0 : (A > len ? len : A);
-    B = B < 0 ? 0 : (B > len ? len : B);
-    if (d == comp) {  // the two faces bracketing the target face
-      int f0 = (int)(A / sdx), f1 = (int)(B / sdx) + 1;
-      r0[d] = f0 < 0 ? 0 : (f0 > n ? n : f0);
-      r1[d] = f1 < 0 ? 0 : (f1 > n ? n : f1);
-    } else {  // overlapped cells and their slope neighbours
-      int c0 = (int)(A / sdx) - 1, c1 = (int)((B - 1) / sdx) + 1;
-      r0[d] = c0 < 0 ? 0 : (c0 > n - 1 ? n - 1 : c0);
-      r1[d] = c1 < 0 ? 0 : (c1 > n - 1 ? n - 1 : c1);
-    }
-  }
-}
-
 template <class T, class G>
 __device__ T cross_value_from(const DevSet& S, int q, int comp, const int64_t* X, int64_t tdx, G&& get) {
   const int n = S.n[q];
