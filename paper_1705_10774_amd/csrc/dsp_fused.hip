@@ -311,7 +311,7 @@ __device__ __forceinline__ int qdiv(int r, int d, float inv) {
 }
 
 constexpr int GFILL_ROWS = 512;  // patch rows of the resampling grid (a row strides over the ready list)
-constexpr int GFILL_COLS = 32;   // workgroups per patch row (a column strides over the patch's items)
+constexpr int GFILL_COLS = 16;   // workgroups per patch row (a column strides over the patch's items)
 
 // Work item it of patch p into its padded buffer dst, by the whole
 // workgroup (every thread calls it).  The time bracket of the item's box is
