@@ -319,10 +319,10 @@ constexpr int GFILL_COLS = 16;   // workgroups per patch row (a column strides o
 // stage); a copy item uses no LDS and has none.
 template <class T>
 __device__ void gfill_item(const DevSet& S, GfillSmem<T>& sm, const T* __restrict__ slots, T* __restrict__ dst,
-                           int p, const GItem& it) {
+                           int p, const GItem& it, int tid) {
   constexpr int GSTAGE = GSTAGE_BYTES / (int)sizeof(T);
   const int comp = it.comp;
-  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int nthr = blockDim.x;
   const int n = S.n[p], N = n + 4;
   // padded-buffer offset (32 bits: a padded patch holds fewer than 2^31 values)
   const int N2 = N * N;
@@ -501,7 +501,7 @@ __global__ __launch_bounds__(256) void k_gfill(DevSet S, const int* __restrict__
     const int p = list[b];
     const int i1 = S.gitem_off[p + 1];
     for (int it = S.gitem_off[p] + blockIdx.x; it < i1; it += gridDim.x)
-      gfill_item<T>(S, sm, slots, pad + (int64_t)b * pad_stride, p, S.gitems[it]);
+      gfill_item<T>(S, sm, slots, pad + (int64_t)b * pad_stride, p, S.gitems[it], threadIdx.x);
   }
 }
 
@@ -1177,11 +1177,10 @@ __device__ __forceinline__ int mod3(int z) { return (z + 3) % 3; }
 template <class T, int FN>
 __device__ __forceinline__ void step2_tile(const DevSet& S, Step2Smem<T>& sm, T* __restrict__ slots,
                                            const T* __restrict__ pad, int64_t pad_stride, const StepPtr& st,
-                                           int bidx, int p, int tile, int tpa, int fuse_dt) {
+                                           int bidx, int p, int tile, int tpa, int fuse_dt, int tid) {
   static_assert(sizeof(T) == 4, "the wide step kernel is the single-precision variant");
   static_assert(FN >= 0 && FN <= MT, "a fixed patch size is one tile");
   using M = FastF32;
-  const int tid = threadIdx.x;
   PatchCtx<T> c;
   c.p = p;
   const int n = c.n = FN ? FN : S.n[c.p];
@@ -1574,7 +1573,7 @@ __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict
   const int bidx = (wg / (8 * T2)) * 8 + (wg % 8);
   const int tile = (wg / 8) % T2;
   if (bidx >= live_count(S, count)) return;
-  step2_tile<T, FN>(S, sm, slots, pad, pad_stride, st, bidx, list[bidx], tile, tpa, fuse_dt);
+  step2_tile<T, FN>(S, sm, slots, pad, pad_stride, st, bidx, list[bidx], tile, tpa, fuse_dt, threadIdx.x);
 }
 
 #ifdef DSP_TU_F32
@@ -1752,6 +1751,11 @@ __global__ __launch_bounds__(NTHR2) void k_persist(DevSet S, QueueState Q, float
     __syncthreads();
     const int p = s_p;
     if (p < 0) break;
+    // the thread index made opaque for each patch: what the guard fill and
+    // the step derive from it is recomputed per patch, not hoisted out of the
+    // worker loop and held (spilled) across it
+    int ltid = tid;
+    DSP_OPAQUE(ltid);
     // ---- brackets of the patch's guard boxes at its time
     const int box0 = S.rbox_off[p * 108], nbox = S.rbox_off[p * 108 + 108] - box0;
     for (int m = tid; m < nbox; m += NTHR2) S.brk[box0 + m] = bracket(S, S.boxes[box0 + m].q, S.ticks[p], S.tcur[p]);
@@ -1760,12 +1764,12 @@ __global__ __launch_bounds__(NTHR2) void k_persist(DevSet S, QueueState Q, float
     if constexpr (FN == 0) {  // a fixed size (FN > 0) means no resampled region
       if (gfill) {
         for (int it = S.gitem_off[p]; it < S.gitem_off[p + 1]; ++it)
-          gfill_item<float>(S, sm.gf, slots, pad + (int64_t)w * pad_stride, p, S.gitems[it]);
+          gfill_item<float>(S, sm.gf, slots, pad + (int64_t)w * pad_stride, p, S.gitems[it], ltid);
         __syncthreads();
       }
     }
     // ---- Courant level and the fused step (record entry w)
-    step2_tile<float, FN>(S, sm.step, slots, pad, pad_stride, st, w, p, 0, 1, 1);
+    step2_tile<float, FN>(S, sm.step, slots, pad, pad_stride, st, w, p, 0, 1, 1, ltid);
     __syncthreads();
     // ---- output cadence: the new slice into its frame before it is published
     if (S.out_frames) {
