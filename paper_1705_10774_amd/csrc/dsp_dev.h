@@ -56,11 +56,13 @@ template <class T> struct GTab {
 // along the other two, variables [v0, v0 + nv); its staged source indices
 // are r0 .. r1 per axis.  tab[d]: pool entry of target index 0 of the box's
 // axis-d table.  Planned on the host at create (the geometry is static).
+// The first word is m (read first when the item is prefetched).
 struct GItem {
   int m, comp;
   int ca, ta, tb, v0, nv;
   int r0[3], r1[3];
   int tab[3];
+  int nq;  // cells per edge of the source patch
 };
 
 struct Bracket;

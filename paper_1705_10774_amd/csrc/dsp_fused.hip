@@ -313,13 +313,75 @@ __device__ __forceinline__ int qdiv(int r, int d, float inv) {
 constexpr int GFILL_ROWS = 512;  // patch rows of the resampling grid (a row strides over the ready list)
 constexpr int GFILL_COLS = 16;   // workgroups per patch row (a column strides over the patch's items)
 
-// Work item it of patch p into its padded buffer dst, by the whole
-// workgroup (every thread calls it).  The time bracket of the item's box is
-// in S.brk.  A resampling item ends with a barrier (the next item reuses the
-// stage); a copy item uses no LDS and has none.
-template <class T>
-__device__ void gfill_item(const DevSet& S, GfillSmem<T>& sm, const T* __restrict__ slots, T* __restrict__ dst,
-                           int p, const GItem& it, int tid) {
+// Metadata of a work item prefetched into registers, one 32-bit word per
+// lane: the item (lanes from 0) in one register; its box (lanes from 0) and
+// the round's time bracket of the box (lanes from 32) in another, loaded once
+// the item's box index has arrived.  The words come back as scalars
+// (readlane) when the item starts.  A workgroup so fetches the next item's
+// metadata while it works on the current one, instead of waiting at the start
+// of every item on the chain item -> box and bracket -> staged values.
+constexpr int GI_WORDS = (int)(sizeof(GItem) / 4), GB_WORDS = (int)(sizeof(GBox) / 4);
+constexpr int BR_WORDS = (int)(sizeof(Bracket) / 4);
+static_assert(GI_WORDS <= 64 && GB_WORDS <= 32 && BR_WORDS <= 32, "one word per lane of a wavefront");
+__device__ __forceinline__ int gmeta_item(const DevSet& S, int i, int lane) {
+  return lane < GI_WORDS ? ((const int*)(S.gitems + i))[lane] : 0;
+}
+__device__ __forceinline__ int gmeta_box(const DevSet& S, int m, int lane) {
+  if (lane < GB_WORDS) return ((const int*)(S.boxes + m))[lane];
+  if (lane >= 32 && lane < 32 + BR_WORDS) return ((const int*)(S.brk + m))[lane - 32];
+  return 0;
+}
+__device__ __forceinline__ GItem gmeta_unpack_item(int reg) {
+  int w[GI_WORDS];
+#pragma unroll
+  for (int k = 0; k < GI_WORDS; ++k) w[k] = __builtin_amdgcn_readlane(reg, k);
+  GItem r;
+  __builtin_memcpy(&r, w, sizeof(GItem));
+  return r;
+}
+// the parts of the box that the resampling reads
+struct GBoxLo {
+  int lo[3], hi[3], shift[3];
+};
+__device__ __forceinline__ GBoxLo gmeta_unpack_box(int reg) {
+  GBoxLo r;
+  constexpr int lo = offsetof(GBox, lo) / 4, hi = offsetof(GBox, hi) / 4, sh = offsetof(GBox, shift) / 4;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    r.lo[d] = __builtin_amdgcn_readlane(reg, lo + d);
+    r.hi[d] = __builtin_amdgcn_readlane(reg, hi + d);
+    r.shift[d] = __builtin_amdgcn_readlane(reg, sh + d);
+  }
+  return r;
+}
+__device__ __forceinline__ Bracket gmeta_unpack_bracket(int reg) {
+  auto i64 = [&](int o) {
+    const int w = 32 + o / 4;
+    return (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(reg, w + 1) << 32) |
+                     (uint32_t)__builtin_amdgcn_readlane(reg, w));
+  };
+  auto f64 = [&](int o) {
+    const int w = 32 + o / 4;
+    return __hiloint2double(__builtin_amdgcn_readlane(reg, w + 1), __builtin_amdgcn_readlane(reg, w));
+  };
+  Bracket r;
+  r.oa = i64(offsetof(Bracket, oa));
+  r.ob = i64(offsetof(Bracket, ob));
+  r.oc = i64(offsetof(Bracket, oc));
+  r.w = f64(offsetof(Bracket, w));
+  r.wc = f64(offsetof(Bracket, wc));
+  return r;
+}
+
+// Work item it of patch p (box G, time bracket br) into its padded buffer
+// dst, by the whole workgroup (every thread calls it).  mid() runs once the
+// item's source values are staged (a copy item: at its start), to start
+// loads for the next item.  A resampling item ends with a barrier (the next
+// item reuses the stage); a copy item uses no LDS and has none.
+template <class T, class Mid>
+__device__ __forceinline__ void gfill_item(const DevSet& S, GfillSmem<T>& sm, const T* __restrict__ slots,
+                                           T* __restrict__ dst, int p, const GItem& it, const GBoxLo& G,
+                                           const Bracket& br, int tid, Mid&& mid) {
   constexpr int GSTAGE = GSTAGE_BYTES / (int)sizeof(T);
   const int comp = it.comp;
   const int nthr = blockDim.x;
@@ -331,11 +393,10 @@ __device__ void gfill_item(const DevSet& S, GfillSmem<T>& sm, const T* __restric
     const int sx = N + (comp == 0), sy = N + (comp == 1);
     return 5 * N2 * N + comp * N2 * (N + 1) + ((k + 2) * sy + (j + 2)) * sx + (i + 2);
   };
-  const GBox G = S.boxes[it.m];
-  const Bracket br = S.brk[it.m];  // the round's bracket of this box (k_brackets)
   const int ext[3] = {G.hi[0] - G.lo[0] + 1, G.hi[1] - G.lo[1] + 1, G.hi[2] - G.lo[2] + 1};
-  const int q = G.q, nq = S.n[q];
+  const int nq = it.nq;
   if (it.tab[0] < 0) {  // a same-resolution box of a padded region: a time-interpolated copy
+    mid();
     const int cnt = ext[0] * ext[1] * ext[2];
     const float ie0 = 1.0f / (float)ext[0], ie1 = 1.0f / (float)ext[1], ie2 = 1.0f / (float)ext[2];
     auto decode = [&](int e, int& var, int& i, int& j, int& k) {
@@ -374,7 +435,7 @@ __device__ void gfill_item(const DevSet& S, GfillSmem<T>& sm, const T* __restric
     for (int e = tid; e < l0 + l1 + l2; e += nthr) {
       const int d = e < l0 ? 0 : (e < l0 + l1 ? 1 : 2);
       const int t = e - (d > 0 ? l0 : 0) - (d > 1 ? l1 : 0) + (d == ca ? ta : 0);
-      sm.tab[d][t] = pool[it.tab[d] + t];
+      sm.tab[d][t] = pool[(d == 0 ? it.tab[0] : (d == 1 ? it.tab[1] : it.tab[2])) + t];
     }
   }
   const int r00 = it.r0[0], r01 = it.r0[1], r02 = it.r0[2];
@@ -383,6 +444,7 @@ __device__ void gfill_item(const DevSet& S, GfillSmem<T>& sm, const T* __restric
   const int v0 = it.v0, nv = it.nv;
   if (nv * sblk > GSTAGE) {  // the host plans every item to fit
     if (tid == 0) atomicOr(S.err, ERR_STATE);
+    mid();
     return;
   }
   {
@@ -399,6 +461,7 @@ __device__ void gfill_item(const DevSet& S, GfillSmem<T>& sm, const T* __restric
         [&](int e, T v) { sm.stage[e] = v; });
   }
   __syncthreads();
+  mid();
   // target elements of the chunk: ta..tb along the chunk axis, all of the
   // others (per-axis indices kept in scalars: no private arrays indexed at
   // run time in the hot loop)
@@ -491,6 +554,29 @@ __device__ void gfill_item(const DevSet& S, GfillSmem<T>& sm, const T* __restric
   __syncthreads();  // the next item reuses the tables and the stage
 }
 
+// Work items i0, i0 + step, ... below i1 of patch p into its padded buffer
+// dst, by the whole workgroup: each item's metadata is prefetched during the
+// item before it (the item word at its start, box and bracket once its
+// source values are staged).  The brackets of the patch's boxes are in S.brk.
+template <class T>
+__device__ void gfill_items(const DevSet& S, GfillSmem<T>& sm, const T* __restrict__ slots, T* __restrict__ dst,
+                            int p, int i0, int i1, int step, int tid) {
+  if (i0 >= i1) return;
+  const int lane = tid & 63;
+  int ra = gmeta_item(S, i0, lane);
+  int rb = gmeta_box(S, __builtin_amdgcn_readlane(ra, 0), lane);
+  for (int i = i0; i < i1; i += step) {
+    const GItem it = gmeta_unpack_item(ra);
+    const GBoxLo G = gmeta_unpack_box(rb);
+    const Bracket br = gmeta_unpack_bracket(rb);
+    const bool more = i + step < i1;
+    if (more) ra = gmeta_item(S, i + step, lane);
+    gfill_item<T>(S, sm, slots, dst, p, it, G, br, tid, [&]() {
+      if (more) rb = gmeta_box(S, __builtin_amdgcn_readlane(ra, 0), lane);
+    });
+  }
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void k_gfill(DevSet S, const int* __restrict__ list, int count,
                                                const T* __restrict__ slots, T* __restrict__ pad,
@@ -499,9 +585,8 @@ __global__ __launch_bounds__(256) void k_gfill(DevSet S, const int* __restrict__
   const int live = live_count(S, count);
   for (int b = blockIdx.y; b < live; b += gridDim.y) {
     const int p = list[b];
-    const int i1 = S.gitem_off[p + 1];
-    for (int it = S.gitem_off[p] + blockIdx.x; it < i1; it += gridDim.x)
-      gfill_item<T>(S, sm, slots, pad + (int64_t)b * pad_stride, p, S.gitems[it], threadIdx.x);
+    gfill_items<T>(S, sm, slots, pad + (int64_t)b * pad_stride, p, S.gitem_off[p] + blockIdx.x,
+                   S.gitem_off[p + 1], gridDim.x, threadIdx.x);
   }
 }
 
@@ -1763,8 +1848,8 @@ __global__ __launch_bounds__(NTHR2) void k_persist(DevSet S, QueueState Q, float
     // ---- guard regions resampled across resolutions, into this worker's padded buffer
     if constexpr (FN == 0) {  // a fixed size (FN > 0) means no resampled region
       if (gfill) {
-        for (int it = S.gitem_off[p]; it < S.gitem_off[p + 1]; ++it)
-          gfill_item<float>(S, sm.gf, slots, pad + (int64_t)w * pad_stride, p, S.gitems[it], ltid);
+        gfill_items<float>(S, sm.gf, slots, pad + (int64_t)w * pad_stride, p, S.gitem_off[p], S.gitem_off[p + 1], 1,
+                           ltid);
         __syncthreads();
       }
     }

@@ -625,6 +625,7 @@ struct GfillPlan {
       it.r0[cc] = rc0;
       it.r1[cc] = rc1;
       for (int d = 0; d < 3; ++d) it.tab[d] = tab[d];
+      it.nq = nq;
       its.push_back(it);
       v0 += nv;
       if (v0 >= nvar) {
@@ -800,6 +801,7 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
           it.comp = comp;
           it.nv = comp < 0 ? 5 : 1;
           it.tab[0] = it.tab[1] = it.tab[2] = -1;
+          it.nq = S->P[g.q].n;
           gitems.push_back(it);
         }
         boxes.push_back(g);
