@@ -1425,7 +1425,10 @@ __device__ __forceinline__ void step2_tile(const DevSet& S, Step2Smem<T>& sm, T*
     if constexpr (PIPE) {
       if (ld) raw_issue<T, FN>(n, sm.rt, ci, cj, z + 2, raw);
     }
-    const int nface = nxf + nyf + (z >= 0 ? nzf : 0);
+    // the z-faces start on a wavefront boundary, so that no wavefront
+    // evaluates both kinds of face (the HLLD flux twice)
+    const int zf0 = (nxf + nyf + 63) & ~63;
+    const int nface = z >= 0 ? zf0 + nzf : nxf + nyf;
     for (int m = lane; m < nface; m += NTHR2) {
       T l[7], r[7], bn, f[8];
       if (m < nxf + nyf) {
@@ -1484,8 +1487,8 @@ __device__ __forceinline__ void step2_tile(const DevSet& S, Step2Smem<T>& sm, T*
         F[5 + d][e] = f[7];  // the normal field has no flux: the slot holds the upwind speed
         F[5 + t1][e] = f[5];
         F[5 + t2][e] = f[6];
-      } else {
-        const int q = m - nxf - nyf;  // predictor cell of the face's upper cell
+      } else if (m >= zf0) {
+        const int q = m - zf0;  // predictor cell of the face's upper cell
         const int qb = qd(q, PX, iPX), qa = q - qb * PX;
         const int cix = x0 - 1 + qa, cjx = y0 - 1 + qb;
         const int cq = (qa + 1) + (qb + 1) * CX;
@@ -1562,7 +1565,10 @@ __device__ __forceinline__ void step2_tile(const DevSet& S, Step2Smem<T>& sm, T*
       const int nez = (z >= 0 && z < n) ? (TX + 1) * (TY + 1) : 0;
       const int nex = (z >= 0) ? TX * (TY + 1) : 0;
       const int ney = (z >= 0) ? (TX + 1) * TY : 0;
-      for (int m = lane; m < nez + nex + ney; m += NTHR2) {
+      // each kind of edge starts on a wavefront boundary (no wavefront runs
+      // two of the branches)
+      const int ex0 = (nez + 63) & ~63, ey0 = ex0 + ((nex + 63) & ~63);
+      for (int m = lane; m < ey0 + ney; m += NTHR2) {
         if (m < nez) {  // E_z in plane z at (x-face f, y-face g)
           const int mq = qd(m, TX + 1, iTX1);
           const int f = x0 + (m - mq * (TX + 1)), g = y0 + mq;
@@ -1571,8 +1577,8 @@ __device__ __forceinline__ void step2_tile(const DevSet& S, Step2Smem<T>& sm, T*
           sm.b.e.ez[m] = edge(A, B, C, D, sm.fx[5][XF(f, g)], sm.fx[5][XF(f, g - 1)], sm.fy[6][YF(f, g)],
                               sm.fy[6][YF(f - 1, g)], sm.ecc[pz][2][P(f - 1, g - 1)], sm.ecc[pz][2][P(f, g - 1)],
                               sm.ecc[pz][2][P(f - 1, g)], sm.ecc[pz][2][P(f, g)]);
-        } else if (m < nez + nex) {  // E_x at z-face z, (x-cell i, y-face g)
-          const int e = m - nez;
+        } else if (m >= ex0 && m < ex0 + nex) {  // E_x at z-face z, (x-cell i, y-face g)
+          const int e = m - ex0;
           const int eq = qd(e, TX, iTX);
           const int i = x0 + (e - eq * TX), g = y0 + eq;
           const T A = -sm.fy[7][YF(i, g)], B = -sm.py[1][YF(i, g)];
@@ -1580,8 +1586,8 @@ __device__ __forceinline__ void step2_tile(const DevSet& S, Step2Smem<T>& sm, T*
           sm.b.e.ex[e] = edge(A, B, C, D, sm.fy[6][YF(i, g)], sm.py[0][YF(i, g)], sm.fz[7][P(i, g)],
                               sm.fz[7][P(i, g - 1)], sm.ecc[pzm][0][P(i, g - 1)], sm.ecc[pzm][0][P(i, g)],
                               sm.ecc[pz][0][P(i, g - 1)], sm.ecc[pz][0][P(i, g)]);
-        } else {  // E_y at z-face z, (x-face f, y-cell j)
-          const int e = m - nez - nex;
+        } else if (m >= ey0) {  // E_y at z-face z, (x-face f, y-cell j)
+          const int e = m - ey0;
           const int eq = qd(e, TX + 1, iTX1);
           const int f = x0 + (e - eq * (TX + 1)), j = y0 + eq;
           const T A = -sm.fz[5][P(f, j)], B = -sm.fz[5][P(f - 1, j)];
