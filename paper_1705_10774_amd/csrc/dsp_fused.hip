@@ -1111,7 +1111,10 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
       const int nez = (z >= 0 && z < n) ? (TX + 1) * (TY + 1) : 0;
       const int nex = (z >= 0) ? TX * (TY + 1) : 0;
       const int ney = (z >= 0) ? (TX + 1) * TY : 0;
-      for (int m = tid; m < nez + nex + ney; m += NTHR) {
+      // each kind of edge starts on a wavefront boundary (no wavefront runs
+      // two of the branches)
+      const int ex0 = (nez + 63) & ~63, ey0 = ex0 + ((nex + 63) & ~63);
+      for (int m = tid; m < ey0 + ney; m += NTHR) {
         if (m < nez) {  // E_z in plane z at (x-face f, y-face g)
           const int mq = qd(m, TX + 1, iTX1);
           const int f = x0 + (m - mq * (TX + 1)), g = y0 + mq;
@@ -1121,8 +1124,8 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
                            sm.a.f.fy[6][YF(f, g)], sm.a.f.fy[6][YF(f - 1, g)], sm.ecc[pz][2][P(f - 1, g - 1)],
                            sm.ecc[pz][2][P(f, g - 1)], sm.ecc[pz][2][P(f - 1, g)], sm.ecc[pz][2][P(f, g)]);
           sm.b.e.ez[m] = v;
-        } else if (m < nez + nex) {  // E_x at z-face z, (x-cell i, y-face g)
-          const int e = m - nez;
+        } else if (m >= ex0 && m < ex0 + nex) {  // E_x at z-face z, (x-cell i, y-face g)
+          const int e = m - ex0;
           const int eq = qd(e, TX, iTX);
           const int i = x0 + (e - eq * TX), g = y0 + eq;
           const T A = -sm.a.f.fy[7][YF(i, g)], B = -sm.py[1][YF(i, g)];
@@ -1131,8 +1134,8 @@ __global__ __launch_bounds__(NTHR) void k_step(DevSet S, const int* __restrict__
                            sm.fz[0][P(i, g - 1)], sm.ecc[pzm][0][P(i, g - 1)], sm.ecc[pzm][0][P(i, g)],
                            sm.ecc[pz][0][P(i, g - 1)], sm.ecc[pz][0][P(i, g)]);
           sm.b.e.ex[e] = v;
-        } else {  // E_y at z-face z, (x-face f, y-cell j)
-          const int e = m - nez - nex;
+        } else if (m >= ey0) {  // E_y at z-face z, (x-face f, y-cell j)
+          const int e = m - ey0;
           const int eq = qd(e, TX + 1, iTX1);
           const int f = x0 + (e - eq * (TX + 1)), j = y0 + eq;
           const T A = -sm.fz[1][P(f, j)], B = -sm.fz[1][P(f - 1, j)];
