@@ -459,6 +459,28 @@ def uneven(npd=16, seed_sizes=1003, seed_rho=2003, prec=F32, box=1.0, name="cfg3
                    extra={"sizes": ns.tolist()})
 
 
+def uneven_smooth(npd=3, sizes=(4, 16), seed_sizes=1021, prec=F64, box=0.1875, dt_base=2.0 ** -11,
+                  nsteps_base=4, name="uneven_smooth"):
+    """npd^3 equal-size patches with n drawn uniformly from `sizes` (wide
+    resolution jumps between neighbours) carrying a smooth periodic state:
+    rho = 1 + 0.2 sin(kx) sin(ky) sin(kz), v = 0.1 (cos ky, cos kz, cos kx),
+    p = 0.6, B = (0.5, 0.3, 0.2), k = 2 pi / box.  Runs to nsteps_base * dt_base."""
+    rs = np.random.Generator(np.random.PCG64(seed_sizes))
+    ns = rs.choice(np.array(sizes), size=npd ** 3)
+    patches = cartesian(npd, ns, box=box)
+    kw = 2.0 * math.pi / box
+    rho, vel, pres = [], [], []
+    for q in patches:
+        x, y, z = cell_coords(q)
+        Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+        rho.append(1.0 + 0.2 * np.sin(kw * X) * np.sin(kw * Y) * np.sin(kw * Z))
+        vel.append([0.1 * np.cos(kw * Y), 0.1 * np.cos(kw * Z), 0.1 * np.cos(kw * X)])
+        pres.append(np.full(X.shape, 0.6))
+    U = assemble(patches, rho, vel, pres, _uniform_b(patches, (0.5, 0.3, 0.2)), 5.0 / 3.0)
+    cfg = Config(dt_mode=DT_LOCAL, dt_base=dt_base, prec=prec, kmax=30, box_hi=(box, box, box))
+    return Problem(name, cfg, patches, U, nsteps_base * dt_base, extra={"sizes": ns.tolist()})
+
+
 def cfg3_uneven(prec=F32):
     return uneven(prec=prec)
 

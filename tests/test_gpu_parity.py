@@ -290,6 +290,38 @@ def test_cross_resolution_schedule_and_state(mini_oracle_full, prec):
     assert el <= (1e-9 if prec == I.F64 else 1e-4)
 
 
+def wide_jumps(prec):
+    # 3^3 patches of n in {4, 20} and the same size, smooth state: neighbours
+    # of unequal n differ by a factor 5 in resolution (a coarse guard cell
+    # overlaps five fine source cells per axis, beyond the staged resampling's
+    # tables), so those guard boxes take the direct resampling kernel
+    return I.uneven_smooth(npd=3, sizes=(4, 20), prec=prec)
+
+
+@pytest.fixture(scope="module")
+def wide_oracle(orc):
+    pr = wide_jumps(I.F64)
+    return orc_run(orc, pr, t_end=8 * pr.cfg.dt_base)
+
+
+@pytest.mark.parametrize("prec", [I.F64, I.F32])
+def test_wide_resolution_jumps(wide_oracle, prec):
+    """Resolution jumps of a factor 5 (guard boxes resampled straight from
+    the source slices, one thread per element) over 8 dt_base."""
+    pr = wide_jumps(prec)
+    ns = pr.extra["sizes"]
+    assert 4 in ns and 20 in ns
+    T = 8 * pr.cfg.dt_base
+    Ug, sg, kg, stg = gpu_run(pr, t_end=T)
+    Uo, so, ko, sto = wide_oracle
+    assert np.array_equal(sg, so) and np.array_equal(kg, ko)
+    err = rel_l1(Ug, Uo, pr.patches)
+    el = elem_rel(Ug, Uo, pr.patches)
+    print("wide jumps rel L1", prec, err, "element-wise", el, "steps", int(sg.sum()))
+    assert err <= (1e-10 if prec == I.F64 else 1e-4)
+    assert el <= (1e-10 if prec == I.F64 else 1e-4)
+
+
 @pytest.fixture(scope="module")
 def smr_oracle_full(orc):
     """The oracle's configuration 4 (centred blast) over its whole run."""
