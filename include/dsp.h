@@ -223,11 +223,13 @@ int dsp_fixed_steps_adj(dsp_set* set, const void* ckpt_dev, const void* lamT_dev
  * workgroups take ready patches from a device queue, update and publish
  * them and push the neighbours that became ready, launched as a captured
  * hipGraph (queue seed + persistent kernel) replayed by each advance.  The
- * queue mode is available for single-precision sets of patches of at most
- * 16^3 cells (one tile per patch) without a grace; with g = 0 both modes give
- * bitwise the same results.  New sets start in the queue mode when it is
- * available (environment DSP_DISPATCH=rounds overrides).  Every wait of the
- * persistent kernel is bounded (DSP_QUEUE_TIMEOUT_S, default 30 s; then
+ * queue mode is available for single-precision sets without a grace whose
+ * resampled guard boxes fit the staged resampling; a workgroup updates the
+ * tiles of a larger patch (more than 16 cells per edge) one after another.
+ * With g = 0 both modes give bitwise the same results.  New sets of patches
+ * of at most 16^3 cells start in the queue mode when it is available, others
+ * in the rounds (environment DSP_DISPATCH=rounds overrides).  Every wait of
+ * the persistent kernel is bounded (DSP_QUEUE_TIMEOUT_S, default 30 s; then
  * DSP_ESTATE). */
 enum { DSP_DISPATCH_ROUNDS = 0, DSP_DISPATCH_QUEUE = 1 };
 /* Select the dispatch mode (DSP_EINVAL: the queue mode is not available for

@@ -65,6 +65,10 @@ struct GItem {
   int nq;  // cells per edge of the source patch
 };
 
+// Largest tile edge of the step kernels (output cells): a patch of n cells
+// per edge is cut into ceil(n / MT)^2 column tiles.
+constexpr int MT = 16;
+
 struct Bracket;
 
 struct DevSet {
@@ -245,10 +249,11 @@ int launch_fused(const DevSet& S, const int* list, int count, int nmin, int nmax
 // grace): clears the queue (grid over max(cap, npatch)), then seeds it with
 // the patches ready at the start; k_persist runs with `workers` workgroups
 // until every patch has reached *Q.tend.  fn: 16 for sets of equal 16^3
-// patches without resampled guard regions, else 0.
+// patches without resampled guard regions, else 0; multi: some patch has
+// more than one tile (a worker then runs its tiles in turn).
 void launch_queue_seed(const DevSet& S, const QueueState& Q, hipStream_t s);
 void launch_persist(const DevSet& S, const QueueState& Q, float* slots, float* pad, int64_t pad_stride,
-                    const StepPtr& st, int workers, int fn, bool gfill, hipStream_t s);
+                    const StepPtr& st, int workers, int fn, bool multi, bool gfill, hipStream_t s);
 template <class T>
 void launch_adjoint_step(const DevSet& S, const int* list, int count, int nmax, const WorkPtr<T>& W,
                          const WorkPtr<T>& L, const StepPtr& st, const T* lam_next, T* lam_prev,

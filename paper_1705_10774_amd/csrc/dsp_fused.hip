@@ -26,7 +26,6 @@
 
 namespace dsp {
 
-constexpr int MT = 16;                   // largest tile edge (output cells)
 constexpr int MCX = MT + 4;              // columns per edge incl. 2-cell halo
 constexpr int MCOL = MCX * MCX;          // 400 column threads at most
 constexpr int MPX = MT + 2;              // predictor cells per edge
@@ -1677,9 +1676,9 @@ __global__ __launch_bounds__(NTHR2) void k_step2(DevSet S, const int* __restrict
 // persistent launch of `workers` workgroups (one per CU: the step needs the
 // whole LDS) replaces the rounds.  A worker takes a ticket, waits until the
 // ticket's ring slot holds a patch, updates it (guard brackets, resampled
-// guard regions, Courant level, the fused step), publishes it, and tests the
-// patch and its neighbours for readiness (Eq. (1) with g = 0), pushing each
-// that became ready.
+// guard regions, Courant level, the fused step of each of its tiles in
+// turn), publishes it, and tests the patch and its neighbours for readiness
+// (Eq. (1) with g = 0), pushing each that became ready.
 //
 // Exactly-once push: a patch is pushed only by the thread that owns it, and
 // ownership moves from idle to queued with a compare-and-swap.  The owner
@@ -1801,7 +1800,7 @@ __global__ void k_queue_seed(DevSet S, QueueState Q) {
 
 // S.brk_ready = 1 (each worker computes its patch's brackets first) and
 // S.live = nullptr, as set by launch_persist.
-template <int FN>
+template <int FN, bool MULTI>
 __global__ __launch_bounds__(NTHR2) void k_persist(DevSet S, QueueState Q, float* __restrict__ slots,
                                                    float* __restrict__ pad, int64_t pad_stride, StepPtr st,
                                                    int gfill) {
@@ -1862,9 +1861,23 @@ __global__ __launch_bounds__(NTHR2) void k_persist(DevSet S, QueueState Q, float
         __syncthreads();
       }
     }
-    // ---- Courant level and the fused step (record entry w)
-    step2_tile<float, FN>(S, sm.step, slots, pad, pad_stride, st, w, p, 0, 1, 1, ltid);
-    __syncthreads();
+    // ---- Courant level and the fused step (record entry w), tile by tile:
+    // the first tile takes the Courant rate over the whole padded patch and
+    // writes the step record, which the other tiles read
+    // (MULTI: the set has patches of more than one tile; otherwise the one
+    // tile runs without the loop around it)
+    if constexpr (MULTI) {
+      const int nt = (S.n[p] + MT - 1) / MT;
+      for (int tile = 0; tile < nt * nt; ++tile) {
+        int ttid = ltid;  // opaque per tile as well (nothing held across the tile loop)
+        DSP_OPAQUE(ttid);
+        step2_tile<float, FN>(S, sm.step, slots, pad, pad_stride, st, w, p, tile, nt, tile == 0 ? 1 : 0, ttid);
+        __syncthreads();
+      }
+    } else {
+      step2_tile<float, FN>(S, sm.step, slots, pad, pad_stride, st, w, p, 0, 1, 1, ltid);
+      __syncthreads();
+    }
     // ---- output cadence: the new slice into its frame before it is published
     if (S.out_frames) {
       const int f = output_frame(S, S.ticks[p] + st.dtk[w]);
@@ -1904,15 +1917,18 @@ void launch_queue_seed(const DevSet& S, const QueueState& Q, hipStream_t s) {
 }
 
 void launch_persist(const DevSet& S0, const QueueState& Q, float* slots, float* pad, int64_t pad_stride,
-                    const StepPtr& st, int workers, int fn, bool gfill, hipStream_t s) {
+                    const StepPtr& st, int workers, int fn, bool multi, bool gfill, hipStream_t s) {
   DevSet S = S0;
   S.brk_ready = 1;
   S.live = nullptr;
   if (fn == 16)
-    hipLaunchKernelGGL((k_persist<16>), dim3(workers), dim3(NTHR2), 0, s, S, Q, slots, pad, pad_stride, st,
+    hipLaunchKernelGGL((k_persist<16, false>), dim3(workers), dim3(NTHR2), 0, s, S, Q, slots, pad, pad_stride, st,
+                       gfill ? 1 : 0);
+  else if (multi)
+    hipLaunchKernelGGL((k_persist<0, true>), dim3(workers), dim3(NTHR2), 0, s, S, Q, slots, pad, pad_stride, st,
                        gfill ? 1 : 0);
   else
-    hipLaunchKernelGGL((k_persist<0>), dim3(workers), dim3(NTHR2), 0, s, S, Q, slots, pad, pad_stride, st,
+    hipLaunchKernelGGL((k_persist<0, false>), dim3(workers), dim3(NTHR2), 0, s, S, Q, slots, pad, pad_stride, st,
                        gfill ? 1 : 0);
 }
 

@@ -1027,13 +1027,15 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
   D.algo_bytes = s->d_cnt + 3;
   if (s->alloc_failed) return fail(DSP_ENOMEM, "device allocation failed: " + s->alloc_msg);
   {
-    // persistent dispatcher: single-precision sets of one-tile patches in
-    // LOCAL mode without a grace, whose resampled boxes all stage (the worker
-    // has no separate direct pass), on the fused path
+    // persistent dispatcher: single-precision sets in LOCAL mode without a
+    // grace, whose resampled boxes all stage (the worker has no separate
+    // direct pass), on the fused path.  A worker runs the tiles of a patch in
+    // turn, so sets of one-tile patches start in the queue and sets with
+    // larger patches in the rounds (which run a patch's tiles side by side).
     int dev = 0, cus = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    s->queue_ok = s->fused && s->f32 && c.dt_mode == DSP_DT_LOCAL && c.grace == 0.0 && s->nmax <= 16 &&
+    s->queue_ok = s->fused && s->f32 && c.dt_mode == DSP_DT_LOCAL && c.grace == 0.0 &&
                   !D.any_direct && cus > 0;
     if (s->queue_ok) {
       s->workers = std::min(cus, std::min(npatch, s->B));  // one workgroup per CU: the step takes the LDS
@@ -1057,7 +1059,8 @@ int dsp_create(const dsp_config* cfg, const dsp_patch_desc* pd, int32_t npatch, 
       if (hipHostMalloc((void**)&s->tend_host, sizeof(int64_t), hipHostMallocDefault) != hipSuccess)
         return fail(DSP_ENOMEM, "pinned host allocation failed");
       const char* dm = getenv("DSP_DISPATCH");
-      s->dispatch = (dm && std::string(dm) == "rounds") ? DSP_DISPATCH_ROUNDS : DSP_DISPATCH_QUEUE;
+      s->dispatch =
+          ((dm && std::string(dm) == "rounds") || s->nmax > MT) ? DSP_DISPATCH_ROUNDS : DSP_DISPATCH_QUEUE;
     }
   }
   int e = hipck(hipMemcpy(s->d_host_off, s->host_off.data(), sizeof(int64_t) * (npatch + 1), hipMemcpyHostToDevice),
@@ -1272,7 +1275,7 @@ static int run_queue(dsp_set* s, int64_t T) {
     if (e) return e;
     launch_queue_seed(s->D, s->Q, s->gstream);
     launch_persist(s->D, s->Q, (float*)s->slots, (float*)s->work_pad, s->pad_stride, s->st, s->workers, s->queue_fn,
-                   s->any_generic, s->gstream);
+                   s->nmax > MT, s->any_generic, s->gstream);
     e = hipck(hipStreamEndCapture(s->gstream, &s->graph), "hipStreamEndCapture");
     if (!e) e = hipck(hipGraphInstantiate(&s->gexec, s->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
     if (e) return e;

@@ -45,12 +45,17 @@ def test_queue_available_and_default():
     s.close()
     assert avail and workers >= 1
     assert mode == (dsp.DSP_DISPATCH_ROUNDS if os.environ.get("DSP_DISPATCH") == "rounds" else dsp.DSP_DISPATCH_QUEUE)
-    # not available: double precision, or patches of more than one tile
+    # not available: double precision
     s = dsp.PatchSet.from_problem(_spread(), prec=I.F64)
     assert not s.dispatch()[1]
     with pytest.raises(dsp.DspError):
         s.set_dispatch(dsp.DSP_DISPATCH_QUEUE)
     s.close()
+    # patches of more than one tile: available, but new sets start in the rounds
+    s = dsp.PatchSet.from_problem(_mini(I.F32))
+    mode, avail, workers = s.dispatch()
+    s.close()
+    assert avail and mode == dsp.DSP_DISPATCH_ROUNDS
 
 
 @pytest.mark.parametrize("n", [8, 16])
@@ -91,6 +96,32 @@ def test_queue_resolution_jumps_bitwise(orc):
     assert len(set(a[1].tolist())) >= 3
     for x, y in zip(a[:4], b[:4]):
         assert np.array_equal(x, y)
+    Uo, so, ko, _ = orc_run(orc, pr, t_end=T, prec=I.F64)
+    assert np.array_equal(b[1], so) and np.array_equal(b[2], ko)
+    assert rel_l1(b[0], Uo, pr.patches) <= 1e-4
+
+
+def _mini(prec):
+    # configuration 3 in small: 4^3 patches of n in {16, 24, 32}
+    return I.uneven(npd=4, seed_sizes=1013, seed_rho=2013, prec=prec, box=0.25, name="cfg3_mini",
+                    dt_base=2.0 ** -11)
+
+
+def test_queue_multi_tile_bitwise(orc):
+    """Patches of 24^3 and 32^3 (four tiles each, run one after another by
+    the worker, the first with the Courant level of the whole patch) beside
+    16^3 ones, with resampled guard regions: the queue gives the rounds'
+    bits, and the oracle's schedule."""
+    dsp = _dsp()
+    pr = _mini(I.F32)
+    T = 2 * pr.cfg.dt_base
+    a = _run(pr, dsp.DSP_DISPATCH_ROUNDS, T)
+    b = _run(pr, dsp.DSP_DISPATCH_QUEUE, T)
+    assert len(set(a[1].tolist())) >= 3
+    for x, y in zip(a[:4], b[:4]):
+        assert np.array_equal(x, y)
+    assert a[4][0] == b[4][0] and a[4][10] == b[4][10] and a[4][11] == b[4][11]
+    assert b[5][1] == 1  # one persistent launch
     Uo, so, ko, _ = orc_run(orc, pr, t_end=T, prec=I.F64)
     assert np.array_equal(b[1], so) and np.array_equal(b[2], ko)
     assert rel_l1(b[0], Uo, pr.patches) <= 1e-4
