@@ -107,16 +107,17 @@ def _mini(prec):
                     dt_base=2.0 ** -11)
 
 
-def test_queue_multi_tile_bitwise(orc):
+@pytest.mark.parametrize("workers", [0, 7])
+def test_queue_multi_tile_bitwise(orc, workers):
     """Patches of 24^3 and 32^3 (four tiles each, run one after another by
     the worker, the first with the Courant level of the whole patch) beside
     16^3 ones, with resampled guard regions: the queue gives the rounds'
-    bits, and the oracle's schedule."""
+    bits, and the oracle's schedule (one worker per CU, and 7 workers)."""
     dsp = _dsp()
     pr = _mini(I.F32)
     T = 2 * pr.cfg.dt_base
     a = _run(pr, dsp.DSP_DISPATCH_ROUNDS, T)
-    b = _run(pr, dsp.DSP_DISPATCH_QUEUE, T)
+    b = _run(pr, dsp.DSP_DISPATCH_QUEUE, T, workers=workers)
     assert len(set(a[1].tolist())) >= 3
     for x, y in zip(a[:4], b[:4]):
         assert np.array_equal(x, y)
