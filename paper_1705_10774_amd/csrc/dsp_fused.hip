@@ -310,7 +310,7 @@ __device__ __forceinline__ int qdiv(int r, int d, float inv) {
 }
 
 constexpr int GFILL_ROWS = 512;  // patch rows of the resampling grid (a row strides over the ready list)
-constexpr int GFILL_COLS = 16;   // workgroups per patch row (a column strides over the patch's items)
+constexpr int GFILL_COLS = 24;   // workgroups per patch row (a column strides over the patch's items)
 
 // Metadata of a work item prefetched into registers, one 32-bit word per
 // lane: the item (lanes from 0) in one register; its box (lanes from 0) and
